@@ -1,0 +1,239 @@
+/*
+ * abm.h -- C ABI of the MI355X agent-step library (libabm.so).
+ *
+ * One mechanical step of N spherical agents, the hot path of the agent-based
+ * engine described in "High-Performance and Scalable Agent-Based Simulation
+ * with BioDynaMo" (arXiv 2301.06984):
+ *   - uniform grid with an O(1) box lookup from the position and a 3x3x3 box
+ *     search (Section 3.1), boxes ranked in gap-free Morton order
+ *     (Section 4.2, steps D-E) and agents sorted into array-based box lists;
+ *   - the pairwise sphere-sphere collision force and the displacement it
+ *     causes, with a force threshold (Section 5; force law: see below);
+ *   - the skip of the force computation for static agents (Section 5);
+ *   - agents re-laid out along the Morton curve every sort_every steps
+ *     (Section 4.2, step G);
+ *   - a batched form (many independent simulations per launch) and a
+ *     reverse-mode (adjoint) form of the step.
+ *
+ * Force law (the paper defers to the Cortex3D method and does not print it):
+ *   f(delta, rho) = k * delta - gamma * sqrt(rho * delta),
+ *   delta = r_i + r_j - |x_i - x_j| > 0, rho = r_i r_j / (r_i + r_j),
+ *   F_i = sum_j f * (x_i - x_j) / |x_i - x_j| over the neighbours j (|x_i - x_j| < R).
+ * Displacement: if |F_i| > f_adh then Delta_i = mu F_i clamped to |Delta_i| <= delta_max,
+ * else 0; all agents move after all forces are known (Jacobi update).
+ *
+ * Conventions for every function:
+ *   - returns ABM_OK (0) or a negative ABM_E_* code; nothing throws across the ABI;
+ *     abm_last_error() gives a message for the calling thread's last failure;
+ *   - "device" pointers are HIP device memory on the current device; "host"
+ *     pointers are ordinary host memory;
+ *   - the caller owns every device buffer (inputs, workspace, outputs); the
+ *     library never allocates device memory (graph objects aside) and keeps
+ *     raw pointers into the workspace until abm_destroy();
+ *   - `stream` is a hipStream_t (0 = the null stream); all work is enqueued on
+ *     it asynchronously; a context is bound to its stream and is not
+ *     thread-safe;
+ *   - positions are n x 3 row-major, diameters n; their element type is
+ *     float (ABM_F32) or double (ABM_F64) as params.precision says;
+ *     geometric tests and forces are evaluated in double in both modes, the
+ *     stored state is rounded to the element type once per step.
+ */
+#ifndef ABM_H
+#define ABM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ABM_ABI_VERSION 1
+#define ABM_EXTENT_SCRATCH_BYTES 1024
+
+enum abm_status {
+    ABM_OK = 0,
+    ABM_E_INVAL = -1,        /* bad argument, size or alignment */
+    ABM_E_NONFINITE = -2,    /* a non-finite input or state value */
+    ABM_E_GRID = -3,         /* grid larger than 2^21 boxes per axis, 2^32 boxes, or the box capacity */
+    ABM_E_WORKSPACE = -4,    /* workspace too small */
+    ABM_E_HIP = -5,          /* HIP runtime failure */
+    ABM_E_STATE = -6,        /* call out of order (e.g. backward before a recorded forward) */
+    ABM_E_UNSUPPORTED = -7   /* feature not available in this configuration */
+};
+
+enum abm_precision { ABM_F32 = 0, ABM_F64 = 1 };
+
+typedef struct abm_params {
+    double k;                  /* repulsion coefficient (default 2) */
+    double gamma;              /* adhesion coefficient (default 1) */
+    double mu;                 /* mobility: displacement per unit force (default 0.1) */
+    double f_adh;              /* force threshold that |F| must exceed to move (default 0) */
+    double delta_max;          /* largest displacement per step (default 3) */
+    double interaction_radius; /* R; 0 = the largest diameter (default 0) */
+    double cell_factor;        /* box edge = cell_factor * R, >= 1 (default 1) */
+    int32_t precision;         /* ABM_F32 or ABM_F64 */
+    int32_t detect_static;     /* skip the force of static agents (Section 5) */
+    int32_t sort_every;        /* re-lay out agents in Morton order every k steps; 0 = never */
+    int32_t block_size;        /* threads per block of the force kernel: 64..1024, multiple of 64; 0 = 256 */
+    int32_t keep_forces;       /* store F_i each step so ABM_FIELD_FORCES can be queried */
+    int32_t reserved;
+} abm_params;
+
+/* Grid extent of a set of positions (Section 3.1), as abm_extent reports it. */
+typedef struct abm_extent {
+    double radius;             /* interaction radius R */
+    double inv_cell;           /* 1 / (cell_factor * R), evaluated in double */
+    int64_t cmin[3];           /* smallest box coordinate floor(x * inv_cell) per axis */
+    int64_t dims[3];           /* boxes per axis */
+    int64_t nboxes;            /* dims[0] * dims[1] * dims[2] */
+} abm_extent;
+
+/* Per-step statistics of the last completed step. */
+typedef struct abm_stats {
+    int64_t step;              /* steps completed */
+    int64_t n_static;          /* agents whose force was skipped */
+    int64_t n_moved;           /* agents with a non-zero displacement */
+    uint32_t error;            /* device error bits (0 = none) */
+    uint32_t reserved;
+} abm_stats;
+
+typedef struct abm_ctx abm_ctx;
+
+/* Fields for abm_query. */
+enum abm_field {
+    ABM_FIELD_POSITIONS = 0,   /* n x 3 element type, by agent id */
+    ABM_FIELD_FORCES = 1,      /* n x 3 double, by agent id (needs keep_forces) */
+    ABM_FIELD_MOVED = 2,       /* n uint8, by agent id: displacement of the last step was non-zero */
+    ABM_FIELD_STATIC = 3,      /* n uint8, by agent id: the force was skipped in the last step */
+    ABM_FIELD_NNZ = 4,         /* n int32, by agent id: non-zero pair terms in the last force evaluation */
+    ABM_FIELD_KEY = 5,         /* n uint32, by agent id: gap-free Morton rank of the agent's box (last grid) */
+    ABM_FIELD_PERM = 6,        /* n uint32: agent ids in (box rank, id) order of the last grid */
+    ABM_FIELD_CELL_START = 7,  /* nboxes + 1 uint32: first slot of each box, last grid (single simulation) */
+    ABM_FIELD_EXTENT = 8,      /* int64[7] per simulation: cmin[3], dims[3], nboxes of the last grid */
+    ABM_FIELD_STORAGE_IDS = 9  /* n uint32: agent id held by each storage slot */
+};
+
+/* Version of this ABI (ABM_ABI_VERSION). */
+int abm_abi_version(void);
+
+/* Fill *p with the defaults listed in abm_params. */
+void abm_default_params(abm_params* p);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char* abm_last_error(void);
+
+/*
+ * Grid extent of n agents (Section 3.1: box = floor(x / edge) per axis).
+ * pos, diam: device, element type per p->precision.  scratch: device, at
+ * least ABM_EXTENT_SCRATCH_BYTES bytes, 8-byte aligned, caller-owned,
+ * clobbered.  Synchronises `stream`.  Errors: ABM_E_INVAL, ABM_E_NONFINITE,
+ * ABM_E_HIP.
+ */
+int abm_extent_of(int64_t n, const void* pos, const void* diam, const abm_params* p, void* scratch,
+                  void* stream, abm_extent* out);
+
+/*
+ * Bytes of device workspace for nsims simulations with the given agent
+ * offsets (host, nsims + 1, offsets[0] = 0) and box capacities (host, nsims:
+ * boxes each simulation's grid may span; see abm_extent.nboxes).
+ */
+int abm_workspace_bytes(int32_t nsims, const int64_t* offsets, const int64_t* box_capacity,
+                        const abm_params* p, int64_t* bytes);
+
+/*
+ * Create a context for one simulation of n agents (Algorithm 1's model
+ * initialisation).  pos (n x 3) and diam (n): device, element type per
+ * p->precision, copied at init.  box_capacity: largest number of grid boxes
+ * the run may need (>= the initial abm_extent.nboxes).  ws: device
+ * workspace of ws_bytes >= abm_workspace_bytes(), 256-byte aligned, kept until
+ * abm_destroy.  Agent ids are 0..n-1 in input order; at step 0 every agent
+ * counts as moved, so none is static.  Errors: ABM_E_INVAL, ABM_E_WORKSPACE,
+ * ABM_E_NONFINITE (diameters not finite and > 0), ABM_E_HIP.
+ */
+int abm_init(abm_ctx** ctx, int64_t n, const void* pos, const void* diam, const abm_params* p,
+             int64_t box_capacity, void* ws, int64_t ws_bytes, void* stream);
+
+/*
+ * Batched form: nsims independent simulations in one context.  offsets
+ * (host, nsims + 1) delimit each simulation's agents in pos/diam; per_sim
+ * (host, nsims) gives each simulation's parameters (precision, sort_every,
+ * block_size, keep_forces and detect_static are taken from per_sim[0]);
+ * box_capacity (host, nsims).  Agent ids are global input indices.  Each
+ * simulation advances exactly as it would alone.
+ */
+int abm_init_batched(abm_ctx** ctx, int32_t nsims, const int64_t* offsets, const void* pos, const void* diam,
+                     const abm_params* per_sim, const int64_t* box_capacity, void* ws, int64_t ws_bytes,
+                     void* stream);
+
+/*
+ * Change the force-law, mobility, threshold or clamp parameters (all
+ * simulations of a batched context take the same values).  Every agent counts
+ * as moved at the next step, so none is static there (Section 5: a changed
+ * attribute unsets static agents).
+ */
+int abm_set_params(abm_ctx* ctx, const abm_params* p);
+
+/*
+ * Enqueue nsteps steps (Algorithm 1's iteration loop): grid build, static
+ * flags, forces, displacement.  Asynchronous; device-detected errors (grid
+ * overflow, non-finite positions) are reported by the next abm_sync/query.
+ */
+int abm_step(abm_ctx* ctx, int32_t nsteps);
+
+/* Wait for the stream; returns the first device error as ABM_E_* (cleared). */
+int abm_sync(abm_ctx* ctx);
+
+/*
+ * Copy a field (enum abm_field) into dst (device if dst_is_device, else
+ * host) of dst_bytes.  Synchronises the stream.
+ */
+int abm_query(abm_ctx* ctx, int32_t field, void* dst, int64_t dst_bytes, int32_t dst_is_device);
+
+/* Statistics of the last completed step (synchronises). */
+int abm_get_stats(abm_ctx* ctx, abm_stats* out);
+
+/*
+ * Checkpoint / resume: abm_state_bytes gives the size; export writes
+ * positions, moved flags, non-zero counts and the step counter to host
+ * memory; import restores them into a context of the same shape.
+ */
+int abm_state_bytes(abm_ctx* ctx, int64_t* bytes);
+int abm_export_state(abm_ctx* ctx, void* dst, int64_t dst_bytes);
+int abm_import_state(abm_ctx* ctx, const void* src, int64_t src_bytes);
+
+/*
+ * Capture nsteps steps into one HIP graph (replaces any earlier graph) and
+ * replay it with abm_graph_launch; a replay advances the context by nsteps.
+ * The context's stream must not be the null stream.  nsteps must be even and
+ * a multiple of sort_every, so that every replay starts from the same
+ * internal buffers.  Errors: ABM_E_INVAL, ABM_E_HIP; abm_graph_launch
+ * without a graph: ABM_E_STATE.
+ */
+int abm_graph_capture(abm_ctx* ctx, int32_t nsteps);
+int abm_graph_launch(abm_ctx* ctx);
+
+/*
+ * Reverse mode of the step x -> x + Delta(F(x); k, gamma) with the neighbour
+ * sets, thresholds and clamp states of every forward step held fixed
+ * (single simulation, detect_static off).
+ *   abm_record_bytes: device bytes needed to record nsteps with a checkpoint
+ *     every ckpt_every steps.
+ *   abm_forward_record: run nsteps steps from the current state, keeping the
+ *     positions of every ckpt_every-th step in rec (device, rec_bytes).
+ *   abm_backward: given dL/dx_T (device, n x 3 double, by id), write
+ *     dL/dx_0 (device, n x 3 double, by id) and dL/d(k, gamma) (device,
+ *     2 double).  Recomputes each checkpoint segment forward, then walks it
+ *     backward.  ABM_E_STATE without a preceding abm_forward_record.
+ */
+int abm_record_bytes(abm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, int64_t* bytes);
+int abm_forward_record(abm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, void* rec, int64_t rec_bytes);
+int abm_backward(abm_ctx* ctx, const void* dL_dxT, void* dL_dx0, void* dL_dparams);
+
+/* Release the context (not the caller's buffers). */
+void abm_destroy(abm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABM_H */

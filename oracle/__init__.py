@@ -65,6 +65,9 @@ def lib():
             st = getattr(L, f"orc_step_{suf}")
             st.restype = C.c_int
             st.argtypes = [i64, P, P, P, P, P, i64, C.POINTER(_Params), P, P]
+            sm = getattr(L, f"orc_sample_{suf}")
+            sm.restype = C.c_int
+            sm.argtypes = [i64, P, P, C.POINTER(_Params), i64, P, P, P, P]
             ad = getattr(L, f"orc_adjoint_{suf}")
             ad.restype = C.c_int
             ad.argtypes = [i64, P, P, C.c_int32, C.POINTER(_Params), P, P, P, P, P]
@@ -204,6 +207,24 @@ def step(state: State, params: Params, want_static: bool = False, want_disp: boo
         raise ValueError(f"orc_step failed ({rc})")
     state.t += 1
     return st, disp
+
+
+def sample_step(pos, diam, ids, params: Params):
+    """First-step force, non-zero count and new position of the agents
+    ``ids``, from the all-pairs definition (no grid)."""
+    pos = np.ascontiguousarray(pos)
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    ns = ids.shape[0]
+    F = np.zeros((ns, 3), np.float64)
+    nnz = np.zeros(ns, np.int32)
+    newp = np.zeros((ns, 3), pos.dtype)
+    fn = getattr(lib(), f"orc_sample_{_suffix(pos)}")
+    pc = params.c()
+    rc = fn(pos.shape[0], _ptr(pos), _ptr(np.ascontiguousarray(diam)), C.byref(pc), ns, _ptr(ids), _ptr(F),
+            _ptr(nnz), _ptr(newp))
+    if rc != 0:
+        raise ValueError(f"orc_sample failed ({rc})")
+    return F, nnz, newp
 
 
 def run(pos, diam, steps: int, params: Params) -> State:

@@ -430,6 +430,62 @@ int64_t neighbors_impl(int64_t n, const T* pos, double R, double inv_h, int64_t*
     return total;
 }
 
+// One step for a few sampled agents from the plain definition: the neighbour
+// set of agent i is every j != i with |x_i - x_j|^2 < R^2, found by scanning
+// all agents in id order (no grid).  No static skipping (a first step).
+template <class T>
+int sample_impl(int64_t n, const T* pos, const T* diam, const orc_params* p, int64_t ns, const int64_t* ids,
+                double* F, int32_t* nnz, T* new_pos) {
+    if (n <= 0 || ns < 0) return -1;
+#ifdef _OPENMP
+    if (p->nthreads > 0) omp_set_num_threads(p->nthreads);
+#endif
+    const std::vector<double> d = promote(n, diam);
+    const double R = radius_of(n, d.data(), p);
+    const double R2 = R * R;
+    for (int64_t s = 0; s < ns; ++s)
+        if (ids[s] < 0 || ids[s] >= n) return -1;
+    for (int64_t s = 0; s < ns; ++s) {
+        const int64_t i = ids[s];
+        const Vec3 xi = load(pos, i);
+        double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+        int64_t cnt = 0;
+#pragma omp parallel for schedule(static) reduction(+ : Fx, Fy, Fz, cnt)
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const Vec3 xj = load(pos, j);
+            if (!(sq3(xi.x - xj.x, xi.y - xj.y, xi.z - xj.z) < R2)) continue;
+            const PairTerm pt = pair_term(xi, d[i], xj, d[j], p->k, p->gamma);
+            if (!pt.contact) continue;
+            Fx += pt.fx;
+            Fy += pt.fy;
+            Fz += pt.fz;
+            if (pt.f != 0.0) ++cnt;
+        }
+        F[3 * s] = Fx;
+        F[3 * s + 1] = Fy;
+        F[3 * s + 2] = Fz;
+        nnz[s] = int32_t(cnt);
+        double ux = 0.0, uy = 0.0, uz = 0.0;
+        if (std::sqrt(sq3(Fx, Fy, Fz)) > p->f_adh) {
+            ux = p->mu * Fx;
+            uy = p->mu * Fy;
+            uz = p->mu * Fz;
+            const double un = std::sqrt(sq3(ux, uy, uz));
+            if (un > p->delta_max) {
+                const double sc = p->delta_max / un;
+                ux *= sc;
+                uy *= sc;
+                uz *= sc;
+            }
+        }
+        new_pos[3 * s] = T(xi.x + ux);
+        new_pos[3 * s + 1] = T(xi.y + uy);
+        new_pos[3 * s + 2] = T(xi.z + uz);
+    }
+    return 0;
+}
+
 // ---- Reverse mode of the step map x -> x + Delta(F(x); k, gamma), with the
 // neighbour sets, thresholds and clamp states of each forward step held fixed.
 // Static skipping is off on this path.
@@ -625,4 +681,15 @@ int orc_max_threads(void) {
 #endif
 }
 
+}  // extern "C"
+
+extern "C" {
+int orc_sample_f64(int64_t n, const double* pos, const double* diam, const orc_params* p, int64_t ns,
+                   const int64_t* ids, double* F, int32_t* nnz, double* new_pos) {
+    return sample_impl(n, pos, diam, p, ns, ids, F, nnz, new_pos);
+}
+int orc_sample_f32(int64_t n, const float* pos, const float* diam, const orc_params* p, int64_t ns,
+                   const int64_t* ids, double* F, int32_t* nnz, float* new_pos) {
+    return sample_impl(n, pos, diam, p, ns, ids, F, nnz, new_pos);
+}
 }  // extern "C"

@@ -1,0 +1,336 @@
+"""Python binding of libabm (the C ABI declared in include/abm.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libabm.so.  PyTorch provides device memory and the stream.  The library must
+be built (``python -m paper_2301_06984_amd.build``); importing this module on
+a machine without it raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabm.so")
+
+ABM_OK, ABM_E_INVAL, ABM_E_NONFINITE, ABM_E_GRID, ABM_E_WORKSPACE, ABM_E_HIP, ABM_E_STATE, ABM_E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+ABM_F32, ABM_F64 = 0, 1
+FIELD = dict(positions=0, forces=1, moved=2, static=3, nnz=4, key=5, perm=6, cell_start=7, extent=8,
+             storage_ids=9)
+EXTENT_SCRATCH_BYTES = 1024
+
+# every symbol include/abm.h declares
+EXPORTS = ["abm_abi_version", "abm_default_params", "abm_last_error", "abm_extent_of", "abm_workspace_bytes",
+           "abm_init", "abm_init_batched", "abm_set_params", "abm_step", "abm_sync", "abm_query",
+           "abm_get_stats", "abm_state_bytes", "abm_export_state", "abm_import_state", "abm_graph_capture",
+           "abm_graph_launch", "abm_record_bytes", "abm_forward_record", "abm_backward", "abm_destroy"]
+
+
+class abm_params(C.Structure):
+    _fields_ = [("k", C.c_double), ("gamma", C.c_double), ("mu", C.c_double), ("f_adh", C.c_double),
+                ("delta_max", C.c_double), ("interaction_radius", C.c_double), ("cell_factor", C.c_double),
+                ("precision", C.c_int32), ("detect_static", C.c_int32), ("sort_every", C.c_int32),
+                ("block_size", C.c_int32), ("keep_forces", C.c_int32), ("reserved", C.c_int32)]
+
+
+class abm_extent(C.Structure):
+    _fields_ = [("radius", C.c_double), ("inv_cell", C.c_double), ("cmin", C.c_int64 * 3),
+                ("dims", C.c_int64 * 3), ("nboxes", C.c_int64)]
+
+
+class abm_stats(C.Structure):
+    _fields_ = [("step", C.c_int64), ("n_static", C.c_int64), ("n_moved", C.c_int64), ("error", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class ABMError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libabm.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2301_06984_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        sig = {
+            "abm_abi_version": (C.c_int, []),
+            "abm_default_params": (None, [C.POINTER(abm_params)]),
+            "abm_last_error": (C.c_char_p, []),
+            "abm_extent_of": (C.c_int, [i64, P, P, C.POINTER(abm_params), P, P, C.POINTER(abm_extent)]),
+            "abm_workspace_bytes": (C.c_int, [i32, P, P, C.POINTER(abm_params), C.POINTER(i64)]),
+            "abm_init": (C.c_int, [C.POINTER(P), i64, P, P, C.POINTER(abm_params), i64, P, i64, P]),
+            "abm_init_batched": (C.c_int, [C.POINTER(P), i32, P, P, P, P, P, P, i64, P]),
+            "abm_set_params": (C.c_int, [P, C.POINTER(abm_params)]),
+            "abm_step": (C.c_int, [P, i32]),
+            "abm_sync": (C.c_int, [P]),
+            "abm_query": (C.c_int, [P, i32, P, i64, i32]),
+            "abm_get_stats": (C.c_int, [P, C.POINTER(abm_stats)]),
+            "abm_state_bytes": (C.c_int, [P, C.POINTER(i64)]),
+            "abm_export_state": (C.c_int, [P, P, i64]),
+            "abm_import_state": (C.c_int, [P, P, i64]),
+            "abm_graph_capture": (C.c_int, [P, i32]),
+            "abm_graph_launch": (C.c_int, [P]),
+            "abm_record_bytes": (C.c_int, [P, i32, i32, C.POINTER(i64)]),
+            "abm_forward_record": (C.c_int, [P, i32, i32, P, i64]),
+            "abm_backward": (C.c_int, [P, P, P, P]),
+            "abm_destroy": (None, [P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int, where: str):
+    if code != ABM_OK:
+        raise ABMError(code, where, lib().abm_last_error().decode())
+
+
+def default_params(**kw) -> abm_params:
+    p = abm_params()
+    lib().abm_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = ABM_F64 if v in ("f64", "float64", "double") else ABM_F32
+        if isinstance(v, bool):
+            v = int(v)
+        setattr(p, k, v)
+    return p
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dtype_of(p: abm_params):
+    return torch.float64 if p.precision == ABM_F64 else torch.float32
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return int(t.data_ptr())
+
+
+def extent_of(pos: torch.Tensor, diam: torch.Tensor, params: abm_params, stream=None) -> abm_extent:
+    """Grid extent of positions on the device (abm_extent_of)."""
+    scratch = torch.empty(EXTENT_SCRATCH_BYTES, dtype=torch.uint8, device=pos.device)
+    out = abm_extent()
+    _check(lib().abm_extent_of(pos.shape[0], _ptr(pos), _ptr(diam), C.byref(params), _ptr(scratch),
+                               _stream_handle(stream), C.byref(out)), "abm_extent_of")
+    return out
+
+
+def box_capacity_for(nboxes: int, slack: float) -> int:
+    return int(min(nboxes * slack + 4096, 2 ** 32 - 2))
+
+
+class Sim:
+    """One simulation: ``Sim(pos, diam, **params)`` with device tensors
+    (n x 3 and n, float32 or float64 per ``precision``)."""
+
+    def __init__(self, pos: torch.Tensor, diam: torch.Tensor, *, box_slack: float = 1.5,
+                 box_capacity: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None, **params):
+        if "precision" not in params:
+            params["precision"] = "f64" if pos.dtype == torch.float64 else "f32"
+        self.params = default_params(**params)
+        dt = _dtype_of(self.params)
+        if pos.dtype != dt or diam.dtype != dt or not pos.is_cuda or not diam.is_cuda:
+            raise TypeError(f"pos and diam must be CUDA tensors of {dt}")
+        self.pos_in = pos.contiguous()
+        self.diam_in = diam.contiguous()
+        self.n = int(pos.shape[0])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ext = extent_of(self.pos_in, self.diam_in, self.params, self.stream)
+        self.extent0 = ext
+        self.box_capacity = int(box_capacity) if box_capacity else box_capacity_for(ext.nboxes, box_slack)
+        offs = (C.c_int64 * 2)(0, self.n)
+        caps = (C.c_int64 * 1)(self.box_capacity)
+        nbytes = C.c_int64()
+        _check(lib().abm_workspace_bytes(1, offs, caps, C.byref(self.params), C.byref(nbytes)), "abm_workspace_bytes")
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=pos.device)
+        self.ctx = C.c_void_p()
+        _check(lib().abm_init(C.byref(self.ctx), self.n, _ptr(self.pos_in), _ptr(self.diam_in), C.byref(self.params),
+                              self.box_capacity, _ptr(self.ws), self.ws.numel(), int(self.stream.cuda_stream)),
+               "abm_init")
+
+    # ---------------------------------------------------------------- stepping
+    def step(self, nsteps: int = 1):
+        _check(lib().abm_step(self.ctx, int(nsteps)), "abm_step")
+
+    def sync(self):
+        _check(lib().abm_sync(self.ctx), "abm_sync")
+
+    def set_params(self, **kw):
+        p = abm_params.from_buffer_copy(self.params)
+        for k, v in kw.items():
+            setattr(p, k, int(v) if isinstance(v, bool) else v)
+        _check(lib().abm_set_params(self.ctx, C.byref(p)), "abm_set_params")
+        self.params = p
+
+    def graph_capture(self, nsteps: int):
+        _check(lib().abm_graph_capture(self.ctx, int(nsteps)), "abm_graph_capture")
+
+    def graph_launch(self):
+        _check(lib().abm_graph_launch(self.ctx), "abm_graph_launch")
+
+    # ---------------------------------------------------------------- queries
+    def query(self, field: str) -> torch.Tensor:
+        dev = self.ws.device
+        n = self.n
+        if field == "positions":
+            out = torch.empty((n, 3), dtype=_dtype_of(self.params), device=dev)
+        elif field == "forces":
+            out = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        elif field in ("moved", "static"):
+            out = torch.empty(n, dtype=torch.uint8, device=dev)
+        elif field == "nnz":
+            out = torch.empty(n, dtype=torch.int32, device=dev)
+        elif field in ("key", "perm", "storage_ids"):
+            out = torch.empty(n, dtype=torch.int32, device=dev)
+        elif field == "cell_start":
+            nb = int(self.query("extent")[:, 6].sum())
+            out = torch.empty(nb + 1, dtype=torch.int32, device=dev)
+        elif field == "extent":
+            out = torch.empty((self.nsims, 7), dtype=torch.int64)
+            _check(lib().abm_query(self.ctx, FIELD[field], out.data_ptr(), out.numel() * 8, 0), "abm_query")
+            return out
+        else:
+            raise ValueError(field)
+        _check(lib().abm_query(self.ctx, FIELD[field], _ptr(out), out.numel() * out.element_size(), 1), "abm_query")
+        if field in ("key", "perm", "storage_ids", "cell_start"):
+            out = out.view(torch.int32)
+        return out
+
+    @property
+    def nsims(self) -> int:
+        return 1
+
+    def positions(self) -> torch.Tensor:
+        return self.query("positions")
+
+    def stats(self) -> dict:
+        s = abm_stats()
+        _check(lib().abm_get_stats(self.ctx, C.byref(s)), "abm_get_stats")
+        return dict(step=s.step, n_static=s.n_static, n_moved=s.n_moved, error=s.error)
+
+    # ---------------------------------------------------------------- checkpoint
+    def export_state(self) -> bytes:
+        nb = C.c_int64()
+        _check(lib().abm_state_bytes(self.ctx, C.byref(nb)), "abm_state_bytes")
+        buf = (C.c_char * nb.value)()
+        _check(lib().abm_export_state(self.ctx, buf, nb.value), "abm_export_state")
+        return bytes(buf)
+
+    def import_state(self, blob: bytes):
+        buf = (C.c_char * len(blob)).from_buffer_copy(blob)
+        _check(lib().abm_import_state(self.ctx, buf, len(blob)), "abm_import_state")
+
+    # ---------------------------------------------------------------- adjoint
+    def forward_record(self, nsteps: int, ckpt_every: int):
+        nb = C.c_int64()
+        _check(lib().abm_record_bytes(self.ctx, int(nsteps), int(ckpt_every), C.byref(nb)), "abm_record_bytes")
+        self.rec = torch.empty(int(nb.value), dtype=torch.uint8, device=self.ws.device)
+        _check(lib().abm_forward_record(self.ctx, int(nsteps), int(ckpt_every), _ptr(self.rec), self.rec.numel()),
+               "abm_forward_record")
+
+    def backward(self, dL_dxT: torch.Tensor):
+        g = dL_dxT.to(torch.float64).contiguous()
+        gx0 = torch.empty_like(g)
+        gp = torch.zeros(2, dtype=torch.float64, device=g.device)
+        _check(lib().abm_backward(self.ctx, _ptr(g), _ptr(gx0), _ptr(gp)), "abm_backward")
+        return gx0, gp
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            lib().abm_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchedSim(Sim):
+    """Many independent simulations in one context: ``BatchedSim(pos, diam,
+    offsets, params=[dict, ...])``; simulation s owns agents
+    offsets[s]:offsets[s+1]."""
+
+    def __init__(self, pos: torch.Tensor, diam: torch.Tensor, offsets: Sequence[int],
+                 params: Optional[Sequence[dict]] = None, *, box_slack: float = 1.5,
+                 stream: Optional[torch.cuda.Stream] = None, common: Optional[dict] = None):
+        offsets = [int(o) for o in offsets]
+        ns = len(offsets) - 1
+        common = dict(common or {})
+        if "precision" not in common:
+            common["precision"] = "f64" if pos.dtype == torch.float64 else "f32"
+        plist = [default_params(**{**common, **(params[s] if params else {})}) for s in range(ns)]
+        self.params = plist[0]
+        self.pos_in = pos.contiguous()
+        self.diam_in = diam.contiguous()
+        self.n = int(pos.shape[0])
+        self._nsims = ns
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        caps = []
+        for s in range(ns):
+            a, b = offsets[s], offsets[s + 1]
+            ext = extent_of(self.pos_in[a:b], self.diam_in[a:b], plist[s], self.stream)
+            caps.append(box_capacity_for(ext.nboxes, box_slack))
+        self.box_capacity = sum(caps)
+        offs = (C.c_int64 * (ns + 1))(*offsets)
+        capa = (C.c_int64 * ns)(*caps)
+        parr = (abm_params * ns)(*plist)
+        nbytes = C.c_int64()
+        _check(lib().abm_workspace_bytes(ns, offs, capa, C.byref(plist[0]), C.byref(nbytes)), "abm_workspace_bytes")
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=pos.device)
+        self.ctx = C.c_void_p()
+        _check(lib().abm_init_batched(C.byref(self.ctx), ns, offs, _ptr(self.pos_in), _ptr(self.diam_in), parr, capa,
+                                      _ptr(self.ws), self.ws.numel(), int(self.stream.cuda_stream)),
+               "abm_init_batched")
+
+    @property
+    def nsims(self) -> int:
+        return self._nsims
+
+
+class StepFn(torch.autograd.Function):
+    """x_T = StepFn.apply(x0, diam, k, gamma, nsteps, ckpt_every, params_dict).
+
+    Runs nsteps steps on the GPU from x0, recording a checkpoint every
+    ckpt_every steps; backward gives dL/dx0, dL/dk and dL/dgamma through the
+    hand-written reverse-mode kernels."""
+
+    @staticmethod
+    def forward(ctx, x0, diam, k, gamma, nsteps: int, ckpt_every: int, params: Optional[dict] = None):
+        kw = dict(params or {})
+        kw.update(k=float(k), gamma=float(gamma), detect_static=False)
+        sim = Sim(x0.detach(), diam.detach(), **kw)
+        sim.forward_record(nsteps, ckpt_every)
+        xT = sim.positions()
+        ctx.sim = sim
+        ctx.dtypes = (x0.dtype, torch.as_tensor(k).dtype, torch.as_tensor(gamma).dtype)
+        return xT
+
+    @staticmethod
+    def backward(ctx, grad_xT):
+        gx0, gp = ctx.sim.backward(grad_xT)
+        sim = ctx.sim
+        ctx.sim = None
+        sim.close()
+        dx, dk, dg = ctx.dtypes
+        return gx0.to(dx), None, gp[0].to(dk), gp[1].to(dg), None, None, None

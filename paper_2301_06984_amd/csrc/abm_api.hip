@@ -1,0 +1,833 @@
+// abm_api.hip -- the C ABI of libabm (declared in include/abm.h): workspace
+// layout, step sequencing (Algorithm 1's iteration as a chain of kernels on
+// one stream), queries, checkpoints, graph capture and the adjoint driver.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/abm.h"
+#include "abm_internal.h"
+
+using namespace abm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail(ABM_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int64_t globals, sims, sim_of, pos4[2], ids[2], flags[2], force[2], key, rmi, sub, tmp, perm, count, cell_start,
+        cellinfo, scan_status, partials, stage, total;
+    uint32_t scan_tiles, partial_cap;
+};
+
+Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, int64_t elem) {
+    Layout L{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.globals = take(sizeof(Globals));
+    L.sims = take(int64_t(sizeof(SimGrid)) * nsims);
+    L.sim_of = nsims > 1 ? take(2 * n) : -1;
+    for (int k = 0; k < 2; ++k) L.pos4[k] = take(4 * elem * n);
+    for (int k = 0; k < 2; ++k) L.ids[k] = take(4 * n);
+    for (int k = 0; k < 2; ++k) L.flags[k] = take(4 * n);
+    for (int k = 0; k < 2; ++k) L.force[k] = keep_forces ? take(24 * n) : -1;
+    L.key = take(4 * n);
+    L.rmi = take(4 * n);
+    L.sub = take(4 * n);
+    L.tmp = take(4 * n);
+    L.perm = take(4 * n);
+    L.count = take(4 * boxes);
+    L.cell_start = take(4 * (boxes + 1));
+    L.cellinfo = take(8 * boxes);
+    L.scan_tiles = uint32_t((boxes + kScanTile - 1) / kScanTile);
+    if (L.scan_tiles == 0) L.scan_tiles = 1;
+    L.scan_status = take(8 * int64_t(L.scan_tiles));
+    L.partial_cap = uint32_t(adj_blocks(uint32_t(n)));
+    L.partials = take(16 * int64_t(L.partial_cap));
+    L.stage = take(24 * n);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct abm_ctx {
+    int precision = ABM_F32;
+    int32_t nsims = 1;
+    int64_t n = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout L{};
+    Buffers<float> bf{};
+    Buffers<double> bd{};
+    std::vector<int64_t> offsets;
+    abm_params params{};
+    // host mirror of the device state
+    int64_t step = 0;
+    int pos_cur = 0;
+    int ids_cur = 0;
+    int grid_ids = 0;        // ids buffer that the last grid's key/perm refer to
+    bool have_grid = false;
+    uint32_t stamp_count = 0;  // device stamp value after the last enqueued step
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int32_t graph_steps = 0;
+    int graph_grid_ids = 0;  // ids buffer of the last captured step's grid
+    // adjoint record
+    bool recorded = false;
+    int32_t rec_steps = 0, rec_ckpt = 0;
+    int64_t rec_start = 0;
+    char* rec = nullptr;
+    int64_t rec_bytes = 0;
+
+    int64_t elem() const { return precision == ABM_F64 ? 8 : 4; }
+    template <class T> Buffers<T>& buf();
+};
+template <> Buffers<float>& abm_ctx::buf<float>() { return bf; }
+template <> Buffers<double>& abm_ctx::buf<double>() { return bd; }
+
+namespace {
+
+template <class T>
+void fill_buffers(abm_ctx* c) {
+    Buffers<T>& b = c->buf<T>();
+    char* w = c->ws;
+    const Layout& L = c->L;
+    b.g = reinterpret_cast<Globals*>(w + L.globals);
+    b.sims = reinterpret_cast<SimGrid*>(w + L.sims);
+    b.sim_of = L.sim_of >= 0 ? reinterpret_cast<const uint16_t*>(w + L.sim_of) : nullptr;
+    b.nsims = c->nsims;
+    b.n = uint32_t(c->n);
+    for (int k = 0; k < 2; ++k) {
+        b.pos4[k] = w + L.pos4[k];
+        b.ids[k] = reinterpret_cast<uint32_t*>(w + L.ids[k]);
+        b.flags[k] = reinterpret_cast<uint32_t*>(w + L.flags[k]);
+        b.force[k] = L.force[k] >= 0 ? reinterpret_cast<double*>(w + L.force[k]) : nullptr;
+    }
+    b.key = reinterpret_cast<uint32_t*>(w + L.key);
+    b.rmi = reinterpret_cast<uint32_t*>(w + L.rmi);
+    b.sub = reinterpret_cast<uint32_t*>(w + L.sub);
+    b.tmp = reinterpret_cast<uint32_t*>(w + L.tmp);
+    b.perm = reinterpret_cast<uint32_t*>(w + L.perm);
+    b.count = reinterpret_cast<uint32_t*>(w + L.count);
+    b.cell_start = reinterpret_cast<uint32_t*>(w + L.cell_start);
+    b.cellinfo = reinterpret_cast<unsigned long long*>(w + L.cellinfo);
+    b.scan_status = reinterpret_cast<unsigned long long*>(w + L.scan_status);
+    b.scan_tiles = L.scan_tiles;
+    b.partials = reinterpret_cast<double*>(w + L.partials);
+    b.partial_cap = L.partial_cap;
+}
+
+bool valid_params(const abm_params* p, std::string* why) {
+    if (!p) return *why = "params is null", false;
+    if (p->precision != ABM_F32 && p->precision != ABM_F64) return *why = "precision must be ABM_F32 or ABM_F64", false;
+    const double v[] = {p->k, p->gamma, p->mu, p->f_adh, p->delta_max, p->interaction_radius, p->cell_factor};
+    for (double x : v)
+        if (!std::isfinite(x)) return *why = "non-finite parameter", false;
+    if (p->delta_max < 0 || p->mu < 0 || p->interaction_radius < 0)
+        return *why = "mu, delta_max and interaction_radius must be >= 0", false;
+    if (p->cell_factor < 1.0) return *why = "cell_factor must be >= 1", false;
+    if (p->sort_every < 0) return *why = "sort_every must be >= 0", false;
+    if (p->block_size != 0 && (p->block_size < 64 || p->block_size > 1024 || p->block_size % 64))
+        return *why = "block_size must be 0 or a multiple of 64 in [64, 1024]", false;
+    return true;
+}
+
+int block_size_of(const abm_params& p) { return p.block_size ? p.block_size : 256; }
+
+// Decode the device error word into a status code.
+int error_code(uint32_t err) {
+    if (err & kErrNonfinite) return fail(ABM_E_NONFINITE, "non-finite position or diameter");
+    if (err & kErrGrid) return fail(ABM_E_GRID, "grid exceeds its box capacity or 2^21 boxes per axis");
+    if (err & kErrBoxOverflow) return fail(ABM_E_GRID, "more than 65535 agents in one box");
+    if (err & kErrInternal) return fail(ABM_E_HIP, "internal index check failed");
+    return ABM_OK;
+}
+
+int read_error(abm_ctx* c, bool clear) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    uint32_t err = 0;
+    Globals* g = reinterpret_cast<Globals*>(c->ws + c->L.globals);
+    HIP_TRY(hipMemcpy(&err, &g->err, sizeof(err), hipMemcpyDeviceToHost));
+    if (err && clear) HIP_TRY(hipMemset(&g->err, 0, sizeof(err)));
+    return error_code(err);
+}
+
+template <class T>
+void enqueue_extent(abm_ctx* c) {
+    const int parity = int(c->step & 1);
+    launch_bbox<T>(c->buf<T>(), c->pos_cur, parity, c->stream);
+}
+
+// Clear the box table and restart the stamps if m more steps would wrap them.
+template <class T>
+void guard_stamps(abm_ctx* c, int64_t m) {
+    if (int64_t(c->stamp_count) + m > int64_t(kStampPeriod)) {
+        launch_clear_cellinfo<T>(c->buf<T>(), c->stream);
+        c->stamp_count = 0;
+    }
+}
+
+template <class T>
+void enqueue_step(abm_ctx* c, bool allow_relayout) {
+    Buffers<T>& b = c->buf<T>();
+    const int parity = int(c->step & 1);
+    launch_setup<T>(b, parity, c->stream);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, c->stream);
+    StepArgs a{};
+    a.parity = parity;
+    a.pos_cur = c->pos_cur;
+    a.ids_cur = c->ids_cur;
+    a.relayout = allow_relayout && c->params.sort_every > 0 && ((c->step + 1) % c->params.sort_every == 0);
+    a.detect_static = c->params.detect_static != 0;
+    a.keep_forces = c->params.keep_forces != 0;
+    a.block_size = block_size_of(c->params);
+    launch_force<T>(b, a, c->stream);
+    c->grid_ids = c->ids_cur;
+    c->have_grid = true;
+    c->pos_cur ^= 1;
+    if (a.relayout) c->ids_cur ^= 1;
+    c->step += 1;
+    c->stamp_count += 1;
+}
+
+template <class T>
+int do_steps(abm_ctx* c, int32_t nsteps, bool allow_relayout) {
+    int32_t left = nsteps;
+    while (left > 0) {
+        const int32_t m = left < int32_t(kStampPeriod) ? left : int32_t(kStampPeriod);
+        guard_stamps<T>(c, m);
+        for (int32_t s = 0; s < m; ++s) enqueue_step<T>(c, allow_relayout);
+        left -= m;
+    }
+    HIP_TRY(hipGetLastError());
+    return ABM_OK;
+}
+
+int check_ctx(abm_ctx* c) {
+    if (!c || !c->ws) return fail(ABM_E_INVAL, "null or destroyed context");
+    return ABM_OK;
+}
+
+template <class T>
+int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* pos, const void* diam,
+              const abm_params* per_sim, const int64_t* box_capacity, void* ws, int64_t ws_bytes, void* stream) {
+    const int64_t n = offsets[nsims];
+    std::vector<SimGrid> sims(nsims);
+    uint64_t boxes = 0;
+    for (int s = 0; s < nsims; ++s) {
+        std::string why;
+        if (!valid_params(&per_sim[s], &why)) return fail(ABM_E_INVAL, "simulation " + std::to_string(s) + ": " + why);
+        if (offsets[s + 1] <= offsets[s]) return fail(ABM_E_INVAL, "every simulation needs at least one agent");
+        if (box_capacity[s] < 1 || box_capacity[s] > 0xFFFFFFFFll)
+            return fail(ABM_E_INVAL, "box capacity must be in [1, 2^32)");
+        boxes += uint64_t(box_capacity[s]);
+        SimGrid& G = sims[s];
+        std::memset(&G, 0, sizeof(G));
+        G.radius = per_sim[s].interaction_radius;
+        G.k = per_sim[s].k;
+        G.gamma = per_sim[s].gamma;
+        G.mu = per_sim[s].mu;
+        G.f_adh = per_sim[s].f_adh;
+        G.delta_max = per_sim[s].delta_max;
+        G.cell_factor = per_sim[s].cell_factor;
+        G.agent_begin = uint32_t(offsets[s]);
+        G.agent_end = uint32_t(offsets[s + 1]);
+        G.cap = uint32_t(box_capacity[s]);
+    }
+    if (boxes >= 0xFFFFFFFFull) return fail(ABM_E_GRID, "total box capacity must be below 2^32");
+    const abm_params& p0 = per_sim[0];
+    const Layout L = make_layout(n, nsims, int64_t(boxes), p0.keep_forces != 0, sizeof(T));
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(ABM_E_INVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(ABM_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    abm_ctx* c = new abm_ctx();
+    c->precision = p0.precision;
+    c->nsims = nsims;
+    c->n = n;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->ws = static_cast<char*>(ws);
+    c->L = L;
+    c->offsets.assign(offsets, offsets + nsims + 1);
+    c->params = p0;
+    fill_buffers<T>(c);
+    Buffers<T>& b = c->buf<T>();
+    b.box_capacity = uint32_t(boxes);
+    hipStream_t s = c->stream;
+    auto bail = [&](int code) {
+        delete c;
+        return code;
+    };
+    // zero what must start at zero: globals, histogram, box table, scan status
+    if (hipMemsetAsync(c->ws + L.globals, 0, sizeof(Globals), s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.count, 0, 4 * boxes, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.cellinfo, 0, 8 * boxes, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.scan_status, 0, 8 * int64_t(L.scan_tiles), s) != hipSuccess ||
+        hipMemcpyAsync(b.sims, sims.data(), sizeof(SimGrid) * nsims, hipMemcpyHostToDevice, s) != hipSuccess)
+        return bail(fail(ABM_E_HIP, "workspace initialisation failed"));
+    std::vector<uint16_t> sim_of;
+    if (nsims > 1) {
+        sim_of.resize(n);
+        for (int q = 0; q < nsims; ++q)
+            for (int64_t i = offsets[q]; i < offsets[q + 1]; ++i) sim_of[i] = uint16_t(q);
+        if (hipMemcpyAsync(c->ws + L.sim_of, sim_of.data(), 2 * n, hipMemcpyHostToDevice, s) != hipSuccess)
+            return bail(fail(ABM_E_HIP, "sim index upload failed"));
+    }
+    launch_pack<T>(b, static_cast<const T*>(pos), static_cast<const T*>(diam), s);
+    launch_radius<T>(b, 0, s);
+    launch_finish_radius<T>(b, s);
+    launch_bbox<T>(b, 0, 0, s);
+    if (hipGetLastError() != hipSuccess) return bail(fail(ABM_E_HIP, "init kernels failed to launch"));
+    const int rc = read_error(c, true);   // also keeps the host arrays alive until the copies are done
+    if (rc != ABM_OK) return bail(rc);
+    *out = c;
+    return ABM_OK;
+}
+
+template <class T>
+int extent_impl(int64_t n, const void* pos, const void* diam, const abm_params* p, void* scratch, hipStream_t s,
+                abm_extent* out) {
+    char* w = static_cast<char*>(scratch);
+    Globals* g = reinterpret_cast<Globals*>(w);
+    SimGrid* G = reinterpret_cast<SimGrid*>(w + 256);
+    SimGrid h{};
+    h.radius = p->interaction_radius;
+    h.cell_factor = p->cell_factor;
+    HIP_TRY(hipMemsetAsync(g, 0, sizeof(Globals), s));
+    HIP_TRY(hipMemcpyAsync(G, &h, sizeof(SimGrid), hipMemcpyHostToDevice, s));
+    launch_extent<T>(static_cast<const T*>(pos), static_cast<const T*>(diam), uint32_t(n), g, G, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    Globals hg{};
+    HIP_TRY(hipMemcpy(&hg, g, sizeof(hg), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&h, G, sizeof(h), hipMemcpyDeviceToHost));
+    if (hg.err) return error_code(hg.err);
+    out->radius = h.radius;
+    out->inv_cell = h.inv_h;
+    out->nboxes = 1;
+    for (int a = 0; a < 3; ++a) {
+        out->cmin[a] = h.bbox[0][a];
+        out->dims[a] = int64_t(h.bbox[0][3 + a]) - int64_t(h.bbox[0][a]) + 1;
+        out->nboxes *= out->dims[a];
+    }
+    return ABM_OK;
+}
+
+template <class T>
+int query_impl(abm_ctx* c, int32_t field, void* dst, int64_t dst_bytes, int32_t dst_is_device) {
+    Buffers<T>& b = c->buf<T>();
+    const int64_t n = c->n;
+    int64_t need = 0;
+    int ids_buf = c->ids_cur;
+    switch (field) {
+        case ABM_FIELD_POSITIONS: need = 3 * n * int64_t(sizeof(T)); break;
+        case ABM_FIELD_FORCES:
+            if (!c->params.keep_forces) return fail(ABM_E_UNSUPPORTED, "forces are kept only with keep_forces");
+            need = 24 * n;
+            break;
+        case ABM_FIELD_MOVED:
+        case ABM_FIELD_STATIC: need = n; break;
+        case ABM_FIELD_NNZ: need = 4 * n; break;
+        case ABM_FIELD_KEY:
+        case ABM_FIELD_PERM:
+            if (!c->have_grid) return fail(ABM_E_STATE, "no grid has been built yet (run a step)");
+            ids_buf = c->grid_ids;
+            need = 4 * n;
+            break;
+        case ABM_FIELD_STORAGE_IDS: need = 4 * n; break;
+        case ABM_FIELD_CELL_START: {
+            if (!c->have_grid) return fail(ABM_E_STATE, "no grid has been built yet (run a step)");
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            uint32_t total = 0;
+            HIP_TRY(hipMemcpy(&total, &b.g->total_boxes, 4, hipMemcpyDeviceToHost));
+            need = 4 * (int64_t(total) + 1);
+            if (dst_bytes < need) return fail(ABM_E_INVAL, "destination too small: need " + std::to_string(need));
+            HIP_TRY(hipMemcpy(dst, b.cell_start, need, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+            return ABM_OK;
+        }
+        case ABM_FIELD_EXTENT: {
+            need = 56 * int64_t(c->nsims);
+            if (dst_bytes < need) return fail(ABM_E_INVAL, "destination too small: need " + std::to_string(need));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            std::vector<SimGrid> sims(c->nsims);
+            HIP_TRY(hipMemcpy(sims.data(), b.sims, sizeof(SimGrid) * c->nsims, hipMemcpyDeviceToHost));
+            std::vector<int64_t> v(7 * c->nsims);
+            for (int s = 0; s < c->nsims; ++s) {
+                for (int a = 0; a < 3; ++a) {
+                    v[7 * s + a] = sims[s].cmin[a];
+                    v[7 * s + 3 + a] = sims[s].dims[a];
+                }
+                v[7 * s + 6] = sims[s].nboxes;
+            }
+            HIP_TRY(hipMemcpy(dst, v.data(), need, dst_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+            return ABM_OK;
+        }
+        default: return fail(ABM_E_INVAL, "unknown field");
+    }
+    if (dst_bytes < need) return fail(ABM_E_INVAL, "destination too small: need " + std::to_string(need));
+    void* target = dst_is_device ? dst : static_cast<void*>(c->ws + c->L.stage);
+    if (field == ABM_FIELD_POSITIONS)
+        launch_unpack_positions<T>(b, c->pos_cur, ids_buf, static_cast<T*>(target), c->stream);
+    else
+        launch_unpack_field<T>(b, c->pos_cur, ids_buf, field, target, c->stream);
+    HIP_TRY(hipGetLastError());
+    const int rc = read_error(c, false);
+    if (rc != ABM_OK) return rc;
+    if (!dst_is_device) HIP_TRY(hipMemcpy(dst, target, need, hipMemcpyDeviceToHost));
+    return ABM_OK;
+}
+
+struct StateHeader {
+    uint64_t magic;
+    int64_t n;
+    int64_t step;
+    int32_t precision;
+    int32_t nsims;
+};
+constexpr uint64_t kStateMagic = 0x3165746174534241ull;  // "ABState1" in little-endian bytes
+
+int64_t state_bytes(abm_ctx* c) { return int64_t(sizeof(StateHeader)) + c->n * (3 * c->elem() + 1 + 4); }
+
+template <class T>
+int import_impl(abm_ctx* c, const void* src, int64_t src_bytes) {
+    if (src_bytes < state_bytes(c)) return fail(ABM_E_INVAL, "state buffer too small");
+    StateHeader h;
+    std::memcpy(&h, src, sizeof(h));
+    if (h.magic != kStateMagic || h.n != c->n || h.precision != c->precision || h.nsims != c->nsims)
+        return fail(ABM_E_INVAL, "state does not match this context");
+    Buffers<T>& b = c->buf<T>();
+    const char* p = static_cast<const char*>(src) + sizeof(h);
+    char* stage = c->ws + c->L.stage;
+    const int64_t pos_b = 3 * c->n * int64_t(sizeof(T));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(stage, p, pos_b, hipMemcpyHostToDevice));
+    launch_load_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const T*>(stage), c->stream);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(stage, p + pos_b, c->n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(stage + align_up(c->n), p + pos_b + c->n, 4 * c->n, hipMemcpyHostToDevice));
+    launch_set_flags<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const uint8_t*>(stage),
+                        reinterpret_cast<const int32_t*>(stage + align_up(c->n)), c->stream);
+    c->step = h.step;
+    enqueue_extent<T>(c);
+    HIP_TRY(hipGetLastError());
+    return read_error(c, true);
+}
+
+template <class T>
+int export_impl(abm_ctx* c, void* dst, int64_t dst_bytes) {
+    if (dst_bytes < state_bytes(c)) return fail(ABM_E_INVAL, "destination too small");
+    StateHeader h{kStateMagic, c->n, c->step, c->precision, c->nsims};
+    std::memcpy(dst, &h, sizeof(h));
+    char* p = static_cast<char*>(dst) + sizeof(h);
+    const int64_t pos_b = 3 * c->n * int64_t(sizeof(T));
+    int rc = query_impl<T>(c, ABM_FIELD_POSITIONS, p, pos_b, 0);
+    if (rc == ABM_OK) rc = query_impl<T>(c, ABM_FIELD_MOVED, p + pos_b, c->n, 0);
+    if (rc == ABM_OK) rc = query_impl<T>(c, ABM_FIELD_NNZ, p + pos_b + c->n, 4 * c->n, 0);
+    return rc;
+}
+
+// ---------------------------------------------------------------- adjoint
+struct RecLayout {
+    int64_t ckpt, seg, xT, lam, lam2, w, total;
+    int32_t nckpt;
+};
+
+RecLayout rec_layout(abm_ctx* c, int32_t nsteps, int32_t ckpt_every) {
+    RecLayout r{};
+    const int64_t pb = align_up(3 * c->n * c->elem());
+    const int64_t db = align_up(24 * c->n);
+    r.nckpt = (nsteps + ckpt_every - 1) / ckpt_every;
+    int64_t off = 0;
+    r.ckpt = off;
+    off += pb * r.nckpt;
+    r.seg = off;
+    off += pb * ckpt_every;
+    r.xT = off;
+    off += pb;
+    r.lam = off;
+    off += db;
+    r.lam2 = off;
+    off += db;
+    r.w = off;
+    off += db;
+    r.total = off;
+    return r;
+}
+
+template <class T>
+int forward_record_impl(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, void* rec, int64_t rec_bytes) {
+    const RecLayout R = rec_layout(c, nsteps, ckpt_every);
+    if (rec_bytes < R.total) return fail(ABM_E_WORKSPACE, "record buffer too small: need " + std::to_string(R.total));
+    Buffers<T>& b = c->buf<T>();
+    char* base = static_cast<char*>(rec);
+    const int64_t pb = align_up(3 * c->n * c->elem());
+    c->recorded = false;
+    c->rec_start = c->step;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        if (s % ckpt_every == 0)
+            launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.ckpt + pb * (s / ckpt_every)),
+                                       c->stream);
+        int rc = do_steps<T>(c, 1, false);
+        if (rc != ABM_OK) return rc;
+    }
+    launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.xT), c->stream);
+    HIP_TRY(hipGetLastError());
+    const int rc = read_error(c, true);
+    if (rc != ABM_OK) return rc;
+    c->recorded = true;
+    c->rec_steps = nsteps;
+    c->rec_ckpt = ckpt_every;
+    c->rec = base;
+    c->rec_bytes = rec_bytes;
+    return ABM_OK;
+}
+
+// Load positions (by id) into the current storage and build the grid for them.
+template <class T>
+void load_and_grid(abm_ctx* c, const T* pos_by_id) {
+    Buffers<T>& b = c->buf<T>();
+    launch_load_positions<T>(b, c->pos_cur, c->ids_cur, pos_by_id, c->stream);
+    launch_bbox<T>(b, c->pos_cur, 0, c->stream);
+    guard_stamps<T>(c, 1);
+    launch_setup<T>(b, 0, c->stream);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, c->stream);
+    c->stamp_count += 1;
+}
+
+template <class T>
+int backward_impl(abm_ctx* c, const double* dL_dxT, double* dL_dx0, double* dL_dparams) {
+    if (!c->recorded) return fail(ABM_E_STATE, "abm_backward needs a preceding abm_forward_record");
+    Buffers<T>& b = c->buf<T>();
+    const RecLayout R = rec_layout(c, c->rec_steps, c->rec_ckpt);
+    char* base = c->rec;
+    const int64_t pb = align_up(3 * c->n * c->elem());
+    double* lam = reinterpret_cast<double*>(base + R.lam);
+    double* lam2 = reinterpret_cast<double*>(base + R.lam2);
+    double* w = reinterpret_cast<double*>(base + R.w);
+    const uint32_t* ids = b.ids[c->ids_cur];
+    const uint32_t n = uint32_t(c->n);
+    hipStream_t s = c->stream;
+    const int64_t end_step = c->step;
+    launch_permute3(ids, n, dL_dxT, lam, false, s);
+    HIP_TRY(hipMemsetAsync(dL_dparams, 0, 2 * sizeof(double), s));
+    const int nblocks = adj_blocks(n);
+    for (int32_t seg = R.nckpt - 1; seg >= 0; --seg) {
+        const int32_t s0 = seg * c->rec_ckpt;
+        const int32_t s1 = std::min(c->rec_steps, s0 + c->rec_ckpt);
+        // recompute the segment forward, keeping every step's positions
+        launch_load_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const T*>(base + R.ckpt + pb * seg), s);
+        launch_mark_moved<T>(b, c->pos_cur, s);
+        c->step = c->rec_start + s0;
+        enqueue_extent<T>(c);
+        for (int32_t t = s0; t < s1; ++t) {
+            launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.seg + pb * (t - s0)), s);
+            int rc = do_steps<T>(c, 1, false);
+            if (rc != ABM_OK) return rc;
+        }
+        // walk the segment backward
+        for (int32_t t = s1 - 1; t >= s0; --t) {
+            load_and_grid<T>(c, reinterpret_cast<const T*>(base + R.seg + pb * (t - s0)));
+            launch_adj_w<T>(b, c->pos_cur, lam, w, s);
+            launch_adj_gather<T>(b, c->pos_cur, lam, w, lam2, s);
+            launch_adj_finish<T>(b, nblocks, dL_dparams, s);
+            std::swap(lam, lam2);
+        }
+    }
+    launch_permute3(ids, n, lam, dL_dx0, true, s);
+    // restore the final state of the recorded run
+    launch_load_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const T*>(base + R.xT), s);
+    c->step = end_step;
+    enqueue_extent<T>(c);
+    HIP_TRY(hipGetLastError());
+    return read_error(c, true);
+}
+
+template <class T>
+int graph_capture_impl(abm_ctx* c, int32_t nsteps) {
+    const int se = c->params.sort_every;
+    if (nsteps % 2 != 0 || (se > 0 && nsteps % se != 0))
+        return fail(ABM_E_INVAL, "graph steps must be even and a multiple of sort_every, so replays start from the same buffers");
+    int32_t relayouts = 0;
+    for (int32_t t = 0; t < nsteps; ++t)
+        if (se > 0 && ((c->step + t + 1) % se == 0)) ++relayouts;
+    if (relayouts % 2 != 0)
+        return fail(ABM_E_INVAL, "graph must contain an even number of re-layout steps");
+    if (nsteps > int32_t(kStampPeriod)) return fail(ABM_E_INVAL, "at most 32767 steps per graph");
+    if (c->graph_exec) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    // make sure no stamp wrap can fall inside a replay: replays start from a cleared table
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int64_t saved_step = c->step;
+    const int saved_pos = c->pos_cur, saved_ids = c->ids_cur;
+    const uint32_t saved_stamp = c->stamp_count;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    launch_clear_cellinfo<T>(c->buf<T>(), c->stream);
+    c->stamp_count = 0;
+    for (int32_t t = 0; t < nsteps; ++t) enqueue_step<T>(c, true);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->graph_grid_ids = c->grid_ids;
+    c->step = saved_step;
+    c->pos_cur = saved_pos;
+    c->ids_cur = saved_ids;
+    c->stamp_count = saved_stamp;
+    if (e != hipSuccess) return fail(ABM_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+    c->graph = g;
+    HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    c->graph_steps = nsteps;
+    return ABM_OK;
+}
+
+int graph_launch_impl(abm_ctx* c) {
+    if (!c->graph_exec) return fail(ABM_E_STATE, "no graph captured");
+    HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+    // a replay advances the state exactly as the captured steps do; buffer
+    // indices return to their start because the step counts are even
+    c->step += c->graph_steps;
+    c->stamp_count = uint32_t(c->graph_steps);
+    c->grid_ids = c->graph_grid_ids;
+    c->have_grid = true;
+    return ABM_OK;
+}
+
+template <class T>
+int dispatch_steps(abm_ctx* c, int32_t nsteps) { return do_steps<T>(c, nsteps, true); }
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+int abm_abi_version(void) { return ABM_ABI_VERSION; }
+
+void abm_default_params(abm_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->k = 2.0;
+    p->gamma = 1.0;
+    p->mu = 0.1;
+    p->f_adh = 0.0;
+    p->delta_max = 3.0;
+    p->interaction_radius = 0.0;
+    p->cell_factor = 1.0;
+    p->precision = ABM_F32;
+    p->detect_static = 0;
+    p->sort_every = 1;
+    p->block_size = 256;
+    p->keep_forces = 0;
+}
+
+const char* abm_last_error(void) { return g_last_error.c_str(); }
+
+int abm_extent_of(int64_t n, const void* pos, const void* diam, const abm_params* p, void* scratch, void* stream,
+                  abm_extent* out) {
+    std::string why;
+    if (!valid_params(p, &why)) return fail(ABM_E_INVAL, why);
+    if (n <= 0 || n > 0xFFFFFFFEll || !pos || !diam || !scratch || !out) return fail(ABM_E_INVAL, "bad arguments");
+    if (reinterpret_cast<uintptr_t>(scratch) % 8) return fail(ABM_E_INVAL, "scratch must be 8-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return p->precision == ABM_F64 ? extent_impl<double>(n, pos, diam, p, scratch, s, out)
+                                   : extent_impl<float>(n, pos, diam, p, scratch, s, out);
+}
+
+int abm_workspace_bytes(int32_t nsims, const int64_t* offsets, const int64_t* box_capacity, const abm_params* p,
+                        int64_t* bytes) {
+    std::string why;
+    if (!valid_params(p, &why)) return fail(ABM_E_INVAL, why);
+    if (nsims < 1 || nsims > 65535 || !offsets || !box_capacity || !bytes) return fail(ABM_E_INVAL, "bad arguments");
+    const int64_t n = offsets[nsims];
+    if (offsets[0] != 0 || n <= 0 || n > 0xFFFFFFFEll) return fail(ABM_E_INVAL, "offsets must start at 0, n in [1, 2^32-1)");
+    int64_t boxes = 0;
+    for (int s = 0; s < nsims; ++s) {
+        if (offsets[s + 1] < offsets[s]) return fail(ABM_E_INVAL, "offsets must be non-decreasing");
+        if (box_capacity[s] < 1) return fail(ABM_E_INVAL, "box capacity must be >= 1");
+        boxes += box_capacity[s];
+    }
+    if (boxes >= 0xFFFFFFFFll) return fail(ABM_E_GRID, "total box capacity must be below 2^32");
+    *bytes = make_layout(n, nsims, boxes, p->keep_forces != 0, p->precision == ABM_F64 ? 8 : 4).total;
+    return ABM_OK;
+}
+
+int abm_init(abm_ctx** ctx, int64_t n, const void* pos, const void* diam, const abm_params* p, int64_t box_capacity,
+             void* ws, int64_t ws_bytes, void* stream) {
+    if (!ctx || !pos || !diam || !p || n <= 0 || n > 0xFFFFFFFEll) return fail(ABM_E_INVAL, "bad arguments");
+    const int64_t offsets[2] = {0, n};
+    return p->precision == ABM_F64
+               ? init_impl<double>(ctx, 1, offsets, pos, diam, p, &box_capacity, ws, ws_bytes, stream)
+               : init_impl<float>(ctx, 1, offsets, pos, diam, p, &box_capacity, ws, ws_bytes, stream);
+}
+
+int abm_init_batched(abm_ctx** ctx, int32_t nsims, const int64_t* offsets, const void* pos, const void* diam,
+                     const abm_params* per_sim, const int64_t* box_capacity, void* ws, int64_t ws_bytes,
+                     void* stream) {
+    if (!ctx || nsims < 1 || nsims > 65535 || !offsets || !pos || !diam || !per_sim || !box_capacity)
+        return fail(ABM_E_INVAL, "bad arguments");
+    if (offsets[0] != 0 || offsets[nsims] > 0xFFFFFFFEll) return fail(ABM_E_INVAL, "bad offsets");
+    for (int s = 0; s < nsims; ++s)
+        if (per_sim[s].precision != per_sim[0].precision) return fail(ABM_E_INVAL, "all simulations need one precision");
+    return per_sim[0].precision == ABM_F64
+               ? init_impl<double>(ctx, nsims, offsets, pos, diam, per_sim, box_capacity, ws, ws_bytes, stream)
+               : init_impl<float>(ctx, nsims, offsets, pos, diam, per_sim, box_capacity, ws, ws_bytes, stream);
+}
+
+int abm_set_params(abm_ctx* c, const abm_params* p) {
+    if (int rc = check_ctx(c)) return rc;
+    std::string why;
+    if (!valid_params(p, &why)) return fail(ABM_E_INVAL, why);
+    if (p->precision != c->precision) return fail(ABM_E_INVAL, "precision cannot change");
+    if (p->keep_forces && c->L.force[0] < 0) return fail(ABM_E_UNSUPPORTED, "workspace has no force buffers");
+    if (p->cell_factor != c->params.cell_factor || p->interaction_radius != c->params.interaction_radius)
+        return fail(ABM_E_UNSUPPORTED, "the grid geometry is fixed at init");
+    const bool force_law_changed = p->k != c->params.k || p->gamma != c->params.gamma || p->mu != c->params.mu ||
+                                   p->f_adh != c->params.f_adh || p->delta_max != c->params.delta_max;
+    launch_set_params(c->precision == ABM_F64 ? c->bd.sims : c->bf.sims, c->nsims, p->k, p->gamma, p->mu, p->f_adh,
+                      p->delta_max, c->stream);
+    if (force_law_changed) {
+        if (c->precision == ABM_F64)
+            launch_mark_moved<double>(c->bd, c->pos_cur, c->stream);
+        else
+            launch_mark_moved<float>(c->bf, c->pos_cur, c->stream);
+    }
+    const int keep = p->keep_forces;
+    c->params.k = p->k;
+    c->params.gamma = p->gamma;
+    c->params.mu = p->mu;
+    c->params.f_adh = p->f_adh;
+    c->params.delta_max = p->delta_max;
+    c->params.detect_static = p->detect_static;
+    c->params.sort_every = p->sort_every;
+    c->params.block_size = p->block_size;
+    c->params.keep_forces = keep;
+    HIP_TRY(hipGetLastError());
+    return ABM_OK;
+}
+
+int abm_step(abm_ctx* c, int32_t nsteps) {
+    if (int rc = check_ctx(c)) return rc;
+    if (nsteps < 0) return fail(ABM_E_INVAL, "nsteps must be >= 0");
+    c->recorded = false;
+    return c->precision == ABM_F64 ? dispatch_steps<double>(c, nsteps) : dispatch_steps<float>(c, nsteps);
+}
+
+int abm_sync(abm_ctx* c) {
+    if (int rc = check_ctx(c)) return rc;
+    return read_error(c, true);
+}
+
+int abm_query(abm_ctx* c, int32_t field, void* dst, int64_t dst_bytes, int32_t dst_is_device) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!dst) return fail(ABM_E_INVAL, "null destination");
+    return c->precision == ABM_F64 ? query_impl<double>(c, field, dst, dst_bytes, dst_is_device)
+                                   : query_impl<float>(c, field, dst, dst_bytes, dst_is_device);
+}
+
+int abm_get_stats(abm_ctx* c, abm_stats* out) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!out) return fail(ABM_E_INVAL, "null output");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    Globals g{};
+    HIP_TRY(hipMemcpy(&g, c->ws + c->L.globals, sizeof(g), hipMemcpyDeviceToHost));
+    out->step = c->step;
+    const int last = int((c->step - 1) & 1);
+    out->n_static = c->step > 0 ? int64_t(g.n_static[last]) : 0;
+    out->n_moved = c->step > 0 ? int64_t(g.n_moved[last]) : 0;
+    out->error = g.err;
+    out->reserved = 0;
+    return ABM_OK;
+}
+
+int abm_state_bytes(abm_ctx* c, int64_t* bytes) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!bytes) return fail(ABM_E_INVAL, "null output");
+    *bytes = state_bytes(c);
+    return ABM_OK;
+}
+
+int abm_export_state(abm_ctx* c, void* dst, int64_t dst_bytes) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!dst) return fail(ABM_E_INVAL, "null destination");
+    return c->precision == ABM_F64 ? export_impl<double>(c, dst, dst_bytes) : export_impl<float>(c, dst, dst_bytes);
+}
+
+int abm_import_state(abm_ctx* c, const void* src, int64_t src_bytes) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!src) return fail(ABM_E_INVAL, "null source");
+    c->recorded = false;
+    return c->precision == ABM_F64 ? import_impl<double>(c, src, src_bytes) : import_impl<float>(c, src, src_bytes);
+}
+
+int abm_graph_capture(abm_ctx* c, int32_t nsteps) {
+    if (int rc = check_ctx(c)) return rc;
+    if (nsteps <= 0) return fail(ABM_E_INVAL, "nsteps must be > 0");
+    return c->precision == ABM_F64 ? graph_capture_impl<double>(c, nsteps) : graph_capture_impl<float>(c, nsteps);
+}
+
+int abm_graph_launch(abm_ctx* c) {
+    if (int rc = check_ctx(c)) return rc;
+    c->recorded = false;
+    return graph_launch_impl(c);
+}
+
+int abm_record_bytes(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, int64_t* bytes) {
+    if (int rc = check_ctx(c)) return rc;
+    if (nsteps < 1 || ckpt_every < 1 || !bytes) return fail(ABM_E_INVAL, "bad arguments");
+    *bytes = rec_layout(c, nsteps, ckpt_every).total;
+    return ABM_OK;
+}
+
+int abm_forward_record(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, void* rec, int64_t rec_bytes) {
+    if (int rc = check_ctx(c)) return rc;
+    if (nsteps < 1 || ckpt_every < 1 || !rec) return fail(ABM_E_INVAL, "bad arguments");
+    if (c->nsims != 1) return fail(ABM_E_UNSUPPORTED, "the adjoint covers a single simulation");
+    if (c->params.detect_static) return fail(ABM_E_UNSUPPORTED, "the adjoint needs detect_static off");
+    if (reinterpret_cast<uintptr_t>(rec) % kAlign) return fail(ABM_E_INVAL, "record buffer must be 256-byte aligned");
+    return c->precision == ABM_F64 ? forward_record_impl<double>(c, nsteps, ckpt_every, rec, rec_bytes)
+                                   : forward_record_impl<float>(c, nsteps, ckpt_every, rec, rec_bytes);
+}
+
+int abm_backward(abm_ctx* c, const void* dL_dxT, void* dL_dx0, void* dL_dparams) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!dL_dxT || !dL_dx0 || !dL_dparams) return fail(ABM_E_INVAL, "null argument");
+    const double* a = static_cast<const double*>(dL_dxT);
+    double* b = static_cast<double*>(dL_dx0);
+    double* p = static_cast<double*>(dL_dparams);
+    return c->precision == ABM_F64 ? backward_impl<double>(c, a, b, p) : backward_impl<float>(c, a, b, p);
+}
+
+void abm_destroy(abm_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->ws = nullptr;
+    delete c;
+}
+
+}  // extern "C"

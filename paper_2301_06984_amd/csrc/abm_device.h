@@ -1,0 +1,123 @@
+// abm_device.h -- device helpers shared by the libabm kernels.
+#pragma once
+
+#include "abm_internal.h"
+
+namespace abm {
+
+template <class T> struct Vec4Of;
+template <> struct Vec4Of<float> { using type = float4; };
+template <> struct Vec4Of<double> { using type = double4; };
+template <class T> using V4 = typename Vec4Of<T>::type;
+
+template <class T>
+__device__ __forceinline__ V4<T>* pos4_ptr(const Buffers<T>& b, int which) {
+    return reinterpret_cast<V4<T>*>(b.pos4[which]);
+}
+
+template <class T>
+__device__ __forceinline__ int sim_index(const Buffers<T>& b, uint32_t i) {
+    return b.sim_of ? int(b.sim_of[i]) : 0;
+}
+
+// Box coordinate floor(x / edge) along one axis, evaluated in double from the
+// stored value (Section 3.1: the box of an agent follows from its position in
+// constant time).  Returns false when the coordinate leaves the int32 range.
+__device__ __forceinline__ bool box_coord(double x, double inv_h, int32_t* c) {
+    const double v = floor(x * inv_h);
+    if (!(v >= -2147483648.0 && v < 2147483647.0)) return false;
+    *c = int32_t(v);
+    return true;
+}
+
+// Gap-free Morton rank of box q inside a dims box (x in the lowest bit of the
+// interleave).  Computed as the number of boxes of the space that precede q in
+// Morton order: walking from the root of the implicit octree down to q, add
+// the in-space boxes of every sibling subtree that comes before q's child.
+// A subtree's in-space boxes are a product of three clamped widths, so no
+// table is needed.  Requires dims[0]*dims[1]*dims[2] < 2^32.
+__device__ __forceinline__ uint32_t gapfree_rank(uint32_t qx, uint32_t qy, uint32_t qz, uint32_t dx, uint32_t dy,
+                                                 uint32_t dz, int levels) {
+    uint32_t r = 0, ox = 0, oy = 0, oz = 0;
+    for (int lev = levels - 1; lev >= 0; --lev) {
+        const uint32_t h = 1u << lev;
+        const uint32_t bx = (qx >> lev) & 1u, by = (qy >> lev) & 1u, bz = (qz >> lev) & 1u;
+        const uint32_t rx = dx - ox, ry = dy - oy, rz = dz - oz;       // >= 1: q lies in this node
+        const uint32_t x0 = min(rx, h), x1 = rx > h ? min(rx - h, h) : 0u;
+        const uint32_t y0 = min(ry, h), y1 = ry > h ? min(ry - h, h) : 0u;
+        const uint32_t z0 = min(rz, h), z1 = rz > h ? min(rz - h, h) : 0u;
+        const uint32_t wz = bz ? z1 : z0;
+        const uint32_t wy = by ? y1 : y0;
+        if (bz) r += (x0 + x1) * (y0 + y1) * z0;
+        if (by) r += (x0 + x1) * y0 * wz;
+        if (bx) r += x0 * wy * wz;
+        ox += bx * h;
+        oy += by * h;
+        oz += bz * h;
+    }
+    return r;
+}
+
+// Row-major box table entry: start slot, agent count, 15-bit stamp, any-moved.
+__device__ __forceinline__ unsigned long long pack_cell(uint32_t start, uint32_t cnt, uint32_t stamp, uint32_t moved) {
+    return (unsigned long long)start | ((unsigned long long)(cnt & 0xFFFFu) << 32) |
+           ((unsigned long long)(stamp & 0x7FFFu) << 48) | ((unsigned long long)(moved & 1u) << 63);
+}
+__device__ __forceinline__ uint32_t cell_start_of(unsigned long long e) { return uint32_t(e); }
+__device__ __forceinline__ uint32_t cell_count_of(unsigned long long e) { return uint32_t(e >> 32) & 0xFFFFu; }
+__device__ __forceinline__ uint32_t cell_stamp_of(unsigned long long e) { return uint32_t(e >> 48) & 0x7FFFu; }
+__device__ __forceinline__ bool cell_moved_of(unsigned long long e) { return (e >> 63) != 0; }
+
+__device__ __forceinline__ void raise_error(Globals* g, uint32_t bits) { atomicOr(&g->err, bits); }
+
+// Blocks are handed to the 8 XCDs round-robin; remap so that each XCD works on
+// one contiguous range of slots (neighbouring slots share their L2).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t launched) {
+    const uint32_t per = launched >> 3;
+    return (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+}
+inline uint32_t xcd_grid(uint32_t blocks) { return (blocks + 7u) & ~7u; }
+
+__device__ __forceinline__ int lane_id() { return int(threadIdx.x & 63u); }
+
+__device__ __forceinline__ int32_t wave_min(int32_t v) {
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// Fold the box coordinates c of the active lanes into the bbox accumulator
+// of their simulation: one set of atomics per wave when the wave's active
+// lanes share one simulation, per lane otherwise.
+__device__ __forceinline__ void bbox_accumulate(SimGrid* sims, int sim, int slot, bool active, const int32_t c[3]) {
+    const unsigned long long act = __ballot(active);
+    if (act == 0) return;
+    const int leader = __ffsll((long long)act) - 1;
+    const int s0 = __shfl(sim, leader, 64);
+    const bool uniform = __ballot(active && sim != s0) == 0;
+    if (uniform) {
+        int32_t lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = wave_min(active ? c[a] : INT32_MAX);
+            hi[a] = wave_max(active ? c[a] : INT32_MIN);
+        }
+        if (lane_id() == leader) {
+            int32_t* bb = sims[s0].bbox[slot];
+            for (int a = 0; a < 3; ++a) {
+                atomicMin(&bb[a], lo[a]);
+                atomicMax(&bb[3 + a], hi[a]);
+            }
+        }
+    } else if (active) {
+        int32_t* bb = sims[sim].bbox[slot];
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&bb[a], c[a]);
+            atomicMax(&bb[3 + a], c[a]);
+        }
+    }
+}
+
+}  // namespace abm

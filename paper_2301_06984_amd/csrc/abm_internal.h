@@ -1,0 +1,154 @@
+// abm_internal.h -- device data structures and kernel launchers of libabm.
+//
+// Layout in HBM (one workspace, carved by abm_api.hip):
+//   per agent, two copies (ping-pong between steps):
+//     pos4   {x, y, z, d} in the element type T (16 B for float, 32 B for double)
+//     ids    persistent agent id held by each storage slot
+//     flags  bit 0 moved, bit 1 static (last step), bits 8.. non-zero pair terms
+//     force  3 doubles (only with keep_forces)
+//   per agent, one copy (rebuilt every step):
+//     key    global box key = box base of the simulation + gap-free Morton rank
+//     rmi    global row-major box index (box base + (qz*dy + qy)*dx + qx)
+//     sub    arrival index of the agent in its box (from the histogram atomics)
+//     tmp    agents in box order, arrival order inside a box
+//     perm   agents in canonical (box rank, id) order
+//   per box (capacity = sum of the per-simulation box capacities):
+//     count       histogram; every scan leaves it zeroed for the next step
+//     cell_start  exclusive prefix sum of count (+1 entry)
+//     cellinfo    row-major box table {start, count, stamp, any-moved}; a box
+//                 whose stamp is not the current step's is empty, so the table
+//                 is never cleared between steps (the timestamp trick of
+//                 Section 3.1)
+//   per scan tile: one 64-bit status word for the decoupled look-back.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace abm {
+
+constexpr uint32_t kMovedBit = 1u;
+constexpr uint32_t kStaticBit = 2u;
+constexpr int kNnzShift = 8;
+constexpr uint32_t kMaxBoxesPerAxis = 1u << 21;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Device error bits (latched, cleared by abm_sync).
+enum : uint32_t {
+    kErrNonfinite = 1u,     // a position or diameter is not finite
+    kErrGrid = 2u,          // grid larger than its capacity or 2^21 boxes per axis
+    kErrBoxOverflow = 4u,   // more than 65535 agents in one box
+    kErrInternal = 8u,      // an index left its range (should never fire)
+};
+
+struct SimGrid {
+    // set at init / set_params
+    double radius;          // interaction radius R
+    double inv_h;           // 1 / (cell_factor * R)
+    double r2;              // R * R
+    double k, gamma, mu, f_adh, delta_max;
+    double cell_factor;
+    uint32_t agent_begin, agent_end;
+    uint32_t cap;           // box capacity of this simulation
+    uint32_t pad0;
+    // set by the per-step setup kernel
+    int32_t cmin[3];
+    uint32_t dims[3];
+    uint32_t nboxes;
+    uint32_t box_base;      // first global box index of this simulation
+    int32_t levels;         // smallest L with 2^L >= max(dims)
+    uint32_t valid;
+    // min x,y,z then max x,y,z of the box coordinates, two accumulators used
+    // alternately: one is read by the step, the other filled by its move kernel
+    int32_t bbox[2][6];
+    uint64_t radius_bits;   // max diameter as ordered bits (init only)
+};
+
+struct Globals {
+    uint32_t err;
+    uint32_t total_boxes;
+    uint32_t stamp;          // of the current step's box table entries (1..32767)
+    uint32_t scan_epoch;     // tag of the current step's scan status words (never 0)
+    unsigned long long scan_ticket;
+    unsigned long long n_static[2];
+    unsigned long long n_moved[2];
+    double grad[2];         // adjoint: dL/dk, dL/dgamma (final reduction)
+};
+
+// Pointers into the workspace, passed by value to kernels.
+template <class T>
+struct Buffers {
+    Globals* g;
+    SimGrid* sims;
+    const uint16_t* sim_of;   // null for a single simulation
+    int32_t nsims;
+    uint32_t n;
+    uint32_t box_capacity;    // sum of per-simulation capacities
+    uint32_t scan_tiles;
+    // per agent
+    void* pos4[2];
+    uint32_t* ids[2];
+    uint32_t* flags[2];
+    double* force[2];         // null without keep_forces
+    uint32_t* key;
+    uint32_t* rmi;
+    uint32_t* sub;
+    uint32_t* tmp;
+    uint32_t* perm;
+    // per box
+    uint32_t* count;
+    uint32_t* cell_start;
+    unsigned long long* cellinfo;
+    unsigned long long* scan_status;
+    double* partials;         // per-block partial sums (adjoint)
+    uint32_t partial_cap;
+};
+
+// Host-side description of which kernels to run for one step.
+struct StepArgs {
+    int parity;             // which bbox accumulator describes the current positions
+    int pos_cur;            // which pos4/flags/force buffer holds the state
+    int ids_cur;            // which ids buffer holds the state
+    bool relayout;          // write the new state in canonical slot order
+    bool detect_static;
+    bool keep_forces;
+    int block_size;
+};
+
+constexpr uint32_t kStampPeriod = 32767;   // 15-bit stamps in the box table
+
+// ---- launchers (grid_kernels.hip)
+template <class T> void launch_pack(const Buffers<T>& b, const T* pos, const T* diam, hipStream_t s);
+template <class T> void launch_radius(const Buffers<T>& b, int pos_cur, hipStream_t s);
+template <class T> void launch_finish_radius(const Buffers<T>& b, hipStream_t s);
+template <class T> void launch_extent(const T* pos, const T* diam, uint32_t n, Globals* g, SimGrid* sim, hipStream_t s);
+template <class T> void launch_mark_moved(const Buffers<T>& b, int pos_cur, hipStream_t s);
+void launch_set_params(SimGrid* sims, int nsims, double k, double gamma, double mu, double f_adh, double delta_max,
+                       hipStream_t s);
+void launch_permute3(const uint32_t* ids, uint32_t n, const double* in, double* out, bool to_id, hipStream_t s);
+template <class T> void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s);
+template <class T> void launch_setup(const Buffers<T>& b, int parity, hipStream_t s);
+template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s);
+template <class T> void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s);
+template <class T> void launch_reset_bbox(const Buffers<T>& b, int parity, hipStream_t s);
+
+// ---- launchers (force_kernels.hip)
+template <class T> void launch_force(const Buffers<T>& b, const StepArgs& a, hipStream_t s);
+template <class T> void launch_unpack_positions(const Buffers<T>& b, int pos_cur, int ids_cur, T* out, hipStream_t s);
+template <class T> void launch_unpack_field(const Buffers<T>& b, int pos_cur, int ids_cur, int field, void* out,
+                                            hipStream_t s);
+template <class T> void launch_load_positions(const Buffers<T>& b, int pos_cur, int ids_cur, const T* in,
+                                              hipStream_t s);
+template <class T> void launch_set_flags(const Buffers<T>& b, int pos_cur, int ids_cur, const uint8_t* moved,
+                                         const int32_t* nnz, hipStream_t s);
+
+// ---- launchers (adjoint_kernels.hip)
+template <class T> void launch_adj_w(const Buffers<T>& b, int pos_cur, const double* lam, double* w, hipStream_t s);
+template <class T> void launch_adj_gather(const Buffers<T>& b, int pos_cur, const double* lam, const double* w,
+                                          double* lam_out, hipStream_t s);
+template <class T> void launch_adj_finish(const Buffers<T>& b, int nblocks, double* dparams, hipStream_t s);
+int adj_blocks(uint32_t n);
+
+}  // namespace abm

@@ -1,0 +1,233 @@
+// force_kernels.hip -- static flags, pair forces, displacement and the
+// Jacobi commit of one step (Section 5, Algorithm 1), plus the copies that
+// move per-agent fields in and out of the internal layout.
+#include "force_loop.h"
+
+namespace abm {
+
+// One thread per slot of the canonical (box rank, id) order, so a wave works
+// on agents that are close in space and shares their neighbour boxes in
+// cache.  Agent i = perm[t] reads its state at storage index i; the new state
+// goes to storage index i, or to slot t when this step re-lays agents out in
+// Morton order (Section 4.2, step G).  The static test (Section 5) runs first:
+// an agent that did not move, had at most one non-zero pair term, and has no
+// moved neighbour within R keeps its force and does not move.  The new
+// positions' box extent is reduced here for the next step's grid.
+template <class T, bool STATIC_ON, bool KEEP_F, bool RELAYOUT>
+__global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32_t launched) {
+    const uint32_t t = xcd_block(launched) * blockDim.x + threadIdx.x;
+    bool active = t < b.n;
+    bool ok = false, is_static = false, moved = false;
+    int sim = 0;
+    int32_t cnew[3] = {0, 0, 0};
+    if (active) {
+        sim = sim_index(b, t);
+        const SimGrid& G = b.sims[sim];
+        const int cur = a.pos_cur, nxt = cur ^ 1;
+        const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
+        V4<T>* __restrict__ pout = pos4_ptr(b, nxt);
+        const uint32_t* __restrict__ fin = b.flags[cur];
+        const bool perm_ok = G.valid && b.perm[t] < b.n;
+        if (G.valid && !perm_ok) raise_error(b.g, kErrInternal);
+        if (!perm_ok) {
+            // grid overflow (reported at sync): keep this slot's state unchanged
+            pout[t] = pin[t];
+            b.flags[nxt][t] = fin[t];
+            if (RELAYOUT) b.ids[a.ids_cur ^ 1][t] = b.ids[a.ids_cur][t];
+            if (KEEP_F)
+                for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(t) + c] = b.force[cur][3 * size_t(t) + c];
+            const V4<T> p = pin[t];
+            ok = box_coord(double(p.x), G.inv_h, &cnew[0]) && box_coord(double(p.y), G.inv_h, &cnew[1]) &&
+                 box_coord(double(p.z), G.inv_h, &cnew[2]);
+        } else {
+            const uint32_t i = b.perm[t];
+            const V4<T> p = pin[i];
+            const uint32_t f = fin[i];
+            const uint32_t out = RELAYOUT ? t : i;
+            uint32_t q[3];
+            if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
+            const uint32_t stamp = b.g->stamp;
+            // at step 0 every agent carries the moved bit, so none is static
+            if (STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u) {
+                const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
+                const double r2 = G.r2;
+                is_static = visit_boxes(b, G, q, stamp, true, [&](uint32_t j) {
+                    if (j == i || !(fin[j] & kMovedBit)) return true;
+                    const V4<T> pj = pin[j];
+                    const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
+                    return !(((ex * ex + ey * ey) + ez * ez) < r2);
+                });
+            }
+            V4<T> np = p;
+            uint32_t nf;
+            if (is_static) {
+                nf = kStaticBit | (f & ~(kMovedBit | kStaticBit));
+                if (KEEP_F)
+                    for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
+            } else {
+                ForceSum acc;
+                force_of<T, false>(b, G, pin, i, p, q, stamp, acc);
+                const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
+                np.x = T(double(p.x) + m.ux);
+                np.y = T(double(p.y) + m.uy);
+                np.z = T(double(p.z) + m.uz);
+                moved = m.ux != 0.0 || m.uy != 0.0 || m.uz != 0.0;
+                const uint32_t nz = acc.nnz < 0xFFFFFFu ? acc.nnz : 0xFFFFFFu;
+                nf = (moved ? kMovedBit : 0u) | (nz << kNnzShift);
+                if (KEEP_F) {
+                    b.force[nxt][3 * size_t(out)] = acc.fx;
+                    b.force[nxt][3 * size_t(out) + 1] = acc.fy;
+                    b.force[nxt][3 * size_t(out) + 2] = acc.fz;
+                }
+            }
+            pout[out] = np;
+            b.flags[nxt][out] = nf;
+            if (RELAYOUT) b.ids[a.ids_cur ^ 1][t] = b.ids[a.ids_cur][i];
+            ok = box_coord(double(np.x), G.inv_h, &cnew[0]) && box_coord(double(np.y), G.inv_h, &cnew[1]) &&
+                 box_coord(double(np.z), G.inv_h, &cnew[2]);
+        }
+        if (!ok) raise_error(b.g, kErrNonfinite);
+    }
+    bbox_accumulate(b.sims, sim, a.parity ^ 1, active && ok, cnew);
+    const unsigned long long ns = __ballot(active && is_static), nm = __ballot(active && moved);
+    if (lane_id() == 0 && (ns | nm)) {
+        if (ns) atomicAdd(&b.g->n_static[a.parity], (unsigned long long)__popcll(ns));
+        if (nm) atomicAdd(&b.g->n_moved[a.parity], (unsigned long long)__popcll(nm));
+    }
+}
+
+template <class T, bool S, bool K, bool R>
+static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
+    const int bs = a.block_size;
+    const uint32_t blocks = (b.n + bs - 1) / bs;
+    const uint32_t launched = xcd_grid(blocks);
+    hipLaunchKernelGGL((k_force<T, S, K, R>), dim3(launched), dim3(bs), 0, s, b, a, launched);
+}
+
+template <class T>
+void launch_force(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
+    const int v = (a.detect_static ? 4 : 0) | (a.keep_forces ? 2 : 0) | (a.relayout ? 1 : 0);
+    switch (v) {
+        case 0: launch_force_v<T, false, false, false>(b, a, s); break;
+        case 1: launch_force_v<T, false, false, true>(b, a, s); break;
+        case 2: launch_force_v<T, false, true, false>(b, a, s); break;
+        case 3: launch_force_v<T, false, true, true>(b, a, s); break;
+        case 4: launch_force_v<T, true, false, false>(b, a, s); break;
+        case 5: launch_force_v<T, true, false, true>(b, a, s); break;
+        case 6: launch_force_v<T, true, true, false>(b, a, s); break;
+        default: launch_force_v<T, true, true, true>(b, a, s); break;
+    }
+}
+
+// ------------------------------------------------------------------ copies
+template <class T>
+__global__ void k_unpack_positions(Buffers<T> b, int cur, int ids_cur, T* __restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n) return;
+    const uint32_t id = b.ids[ids_cur][i];
+    if (id >= b.n) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    const V4<T> p = pos4_ptr(b, cur)[i];
+    out[3 * size_t(id)] = p.x;
+    out[3 * size_t(id) + 1] = p.y;
+    out[3 * size_t(id) + 2] = p.z;
+}
+
+template <class T>
+void launch_unpack_positions(const Buffers<T>& b, int pos_cur, int ids_cur, T* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_unpack_positions<T>, dim3((b.n + 255) / 256), dim3(256), 0, s, b, pos_cur, ids_cur, out);
+}
+
+// field: 1 forces, 2 moved, 3 static, 4 nnz, 5 key, 6 perm, 9 storage ids
+template <class T>
+__global__ void k_unpack_field(Buffers<T> b, int cur, int ids_cur, int field, void* out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n) return;
+    const uint32_t* ids = b.ids[ids_cur];
+    if (field == 6) {   // canonical order of the last grid: slot -> id
+        const uint32_t j = b.perm[i];
+        static_cast<uint32_t*>(out)[i] = j < b.n ? ids[j] : 0xFFFFFFFFu;
+        return;
+    }
+    if (field == 9) {
+        static_cast<uint32_t*>(out)[i] = ids[i];
+        return;
+    }
+    const uint32_t id = ids[i];
+    if (id >= b.n) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    const uint32_t f = b.flags[cur][i];
+    switch (field) {
+        case 1:
+            for (int c = 0; c < 3; ++c) static_cast<double*>(out)[3 * size_t(id) + c] = b.force[cur][3 * size_t(i) + c];
+            break;
+        case 2: static_cast<uint8_t*>(out)[id] = uint8_t(f & kMovedBit); break;
+        case 3: static_cast<uint8_t*>(out)[id] = uint8_t((f & kStaticBit) ? 1 : 0); break;
+        case 4: static_cast<int32_t*>(out)[id] = int32_t(f >> kNnzShift); break;
+        case 5: static_cast<uint32_t*>(out)[id] = b.key[i]; break;
+        default: break;
+    }
+}
+
+template <class T>
+void launch_unpack_field(const Buffers<T>& b, int pos_cur, int ids_cur, int field, void* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_unpack_field<T>, dim3((b.n + 255) / 256), dim3(256), 0, s, b, pos_cur, ids_cur, field, out);
+}
+
+template <class T>
+__global__ void k_load_positions(Buffers<T> b, int cur, int ids_cur, const T* __restrict__ in) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n) return;
+    const uint32_t id = b.ids[ids_cur][i];
+    if (id >= b.n) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    V4<T>* p = pos4_ptr(b, cur);
+    V4<T> v = p[i];
+    v.x = in[3 * size_t(id)];
+    v.y = in[3 * size_t(id) + 1];
+    v.z = in[3 * size_t(id) + 2];
+    if (!isfinite(double(v.x)) || !isfinite(double(v.y)) || !isfinite(double(v.z))) raise_error(b.g, kErrNonfinite);
+    p[i] = v;
+}
+
+template <class T>
+void launch_load_positions(const Buffers<T>& b, int pos_cur, int ids_cur, const T* in, hipStream_t s) {
+    hipLaunchKernelGGL(k_load_positions<T>, dim3((b.n + 255) / 256), dim3(256), 0, s, b, pos_cur, ids_cur, in);
+}
+
+// moved / nnz given by id (import of a checkpoint); storage slot i holds id ids[i]
+template <class T>
+__global__ void k_set_flags(Buffers<T> b, int cur, const uint8_t* __restrict__ moved,
+                            const int32_t* __restrict__ nnz, const uint32_t* __restrict__ ids) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n) return;
+    const uint32_t id = ids[i];
+    if (id >= b.n) return;
+    const uint32_t nz = uint32_t(max(nnz[id], 0));
+    b.flags[cur][i] = (moved[id] ? kMovedBit : 0u) | ((nz < 0xFFFFFFu ? nz : 0xFFFFFFu) << kNnzShift);
+}
+
+template <class T>
+void launch_set_flags(const Buffers<T>& b, int pos_cur, int ids_cur, const uint8_t* moved, const int32_t* nnz,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_set_flags<T>, dim3((b.n + 255) / 256), dim3(256), 0, s, b, pos_cur, moved, nnz,
+                       static_cast<const uint32_t*>(b.ids[ids_cur]));
+}
+
+#define ABM_INSTANTIATE(T)                                                                                   \
+    template void launch_force<T>(const Buffers<T>&, const StepArgs&, hipStream_t);                        \
+    template void launch_unpack_positions<T>(const Buffers<T>&, int, int, T*, hipStream_t);                \
+    template void launch_unpack_field<T>(const Buffers<T>&, int, int, int, void*, hipStream_t);            \
+    template void launch_load_positions<T>(const Buffers<T>&, int, int, const T*, hipStream_t);            \
+    template void launch_set_flags<T>(const Buffers<T>&, int, int, const uint8_t*, const int32_t*, hipStream_t);
+
+ABM_INSTANTIATE(float)
+ABM_INSTANTIATE(double)
+
+}  // namespace abm

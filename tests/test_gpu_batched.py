@@ -1,0 +1,63 @@
+"""Batched form: every simulation of a batch advances exactly as it does alone,
+eagerly and from one captured graph."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import make_sim, note, to_dev
+from paper_2301_06984_amd import abm, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(nsims=24, seed=4):
+    return workloads.c4(nsims=nsims, nmin=50, nmax=3000, seed=seed, steps=10)
+
+
+def test_batched_equals_plain_runs_bitwise():
+    w = small_batch()
+    off = w.offsets
+    note(f"batched {len(off) - 1} sims, n={w.n}")
+    params = [dict(k=2.0 + 0.05 * s, gamma=1.0 - 0.01 * s) for s in range(len(off) - 1)]
+    b = abm.BatchedSim(to_dev(w.pos), to_dev(w.diam), off, params=params, common=dict(detect_static=True))
+    b.step(w.steps)
+    got = b.query("positions").cpu().numpy()
+    nnz = b.query("nnz").cpu().numpy()
+    for s in range(len(off) - 1):
+        a, e = off[s], off[s + 1]
+        sim = make_sim(w.pos[a:e], w.diam[a:e], detect_static=True, **params[s])
+        sim.step(w.steps)
+        np.testing.assert_array_equal(got[a:e], sim.query("positions").cpu().numpy(), err_msg=f"sim {s}")
+        np.testing.assert_array_equal(nnz[a:e], sim.query("nnz").cpu().numpy(), err_msg=f"sim {s}")
+
+
+def test_batched_matches_oracle_per_sim():
+    w = small_batch(nsims=6, seed=5)
+    off = w.offsets
+    note("batched vs oracle")
+    b = abm.BatchedSim(to_dev(w.pos), to_dev(w.diam), off)
+    b.step(3)
+    got = b.query("positions").cpu().numpy()
+    for s in range(len(off) - 1):
+        a, e = off[s], off[s + 1]
+        st = oracle.run(w.pos[a:e], w.diam[a:e], 3, oracle.Params())
+        d = np.abs(got[a:e].astype(np.float64) - st.pos.astype(np.float64))
+        assert np.all(d <= 3 * np.spacing(np.abs(st.pos)).astype(np.float64)), s
+
+
+def test_batched_graph_equals_eager():
+    w = small_batch(nsims=16, seed=6)
+    note("batched graph")
+    eager = abm.BatchedSim(to_dev(w.pos), to_dev(w.diam), w.offsets)
+    eager.step(20)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = abm.BatchedSim(to_dev(w.pos), to_dev(w.diam), w.offsets, stream=s)
+        g.graph_capture(10)
+        g.graph_launch()
+        g.graph_launch()
+        g.sync()
+    np.testing.assert_array_equal(eager.query("positions").cpu().numpy(), g.query("positions").cpu().numpy())
+    ext = g.query("extent").numpy()
+    assert ext.shape == (16, 7) and np.all(ext[:, 6] == np.prod(ext[:, 3:6], axis=1))

@@ -1,0 +1,126 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times: the whole grid against the oracle where it finishes in
+seconds, sampled agents against the all-pairs definition otherwise, and
+properties that hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import assert_grid_equal, gpu_state, make_sim, note, to_dev
+from paper_2301_06984_amd import abm, workloads
+
+pytestmark = pytest.mark.gpu
+
+BENCH = dict(sort_every=1, block_size=256)
+
+
+def check_samples(pos, diam, got_pos, nsamples, seed, params=oracle.Params()):
+    ids = np.random.default_rng(seed).choice(pos.shape[0], nsamples, replace=False)
+    F, nnz, newp = oracle.sample_step(pos, diam, ids, params)
+    d = np.abs(got_pos[ids].astype(np.float64) - newp.astype(np.float64))
+    tol = np.spacing(np.abs(newp)).astype(np.float64) if pos.dtype == np.float32 else \
+        1e-12 * np.maximum(np.abs(newp), float(diam.max()))
+    assert np.all(d <= tol), (d.max(), tol.max())
+    return ids, nnz
+
+
+def test_headline_1e7_first_step():
+    w = workloads.headline()
+    note(f"headline n={w.n} side={w.meta['side']:.1f}")
+    sim = make_sim(w.pos, w.diam, **BENCH)
+    sim.step(1)
+    sim.sync()
+    note("headline grid parity")
+    assert_grid_equal(sim, w.pos, w.diam, oracle.Params())
+    got = sim.query("positions").cpu().numpy()
+    _, nnz = check_samples(w.pos, w.diam, got, 96, 1)
+    gn = sim.query("nnz").cpu().numpy()
+    assert gn.mean() > 0.3
+    note("headline 20 more steps")
+    sim.step(20)
+    sim.sync()
+    x = sim.query("positions").cpu().numpy()
+    assert np.isfinite(x).all()
+
+
+def test_c2_full_parity_and_skip():
+    w = workloads.c2()
+    note(f"c2 n={w.n}")
+    on = make_sim(w.pos, w.diam, detect_static=True, **BENCH)
+    off = make_sim(w.pos, w.diam, detect_static=False, **BENCH)
+    on.step(1)
+    st = oracle.State.initial(w.pos, w.diam)
+    oracle.step(st, oracle.Params(detect_static=True))
+    g = gpu_state(on)
+    np.testing.assert_array_equal(g["nnz"], st.nnz)
+    np.testing.assert_array_equal(g["moved"], st.moved)
+    assert np.all(np.abs(g["pos"].astype(np.float64) - st.pos) <= np.spacing(np.abs(st.pos)).astype(np.float64))
+    exact = np.mean(np.all(g["pos"] == st.pos, axis=1))
+    note(f"c2 first step bit-exact fraction {exact:.6f}")
+    off.step(1)
+    on.step(49)
+    off.step(49)
+    a, b = gpu_state(on), gpu_state(off)
+    np.testing.assert_array_equal(a["pos"], b["pos"])
+    # one more step from the GPU's state, against the oracle from that same state
+    mid = oracle.State(a["pos"].copy(), w.diam.copy(), a["moved"].copy(), a["nnz"].copy(),
+                       np.zeros((w.n, 3)), 50)
+    oracle.step(mid, oracle.Params(detect_static=True))
+    on.step(1)
+    c = gpu_state(on)
+    np.testing.assert_array_equal(c["moved"], mid.moved)
+    assert np.all(np.abs(c["pos"].astype(np.float64) - mid.pos) <= np.spacing(np.abs(mid.pos)).astype(np.float64))
+    frac = on.stats()["n_static"] / w.n
+    note(f"c2 skip fraction at step 51: {frac:.3f}")
+    assert frac > 0.4
+    on.step(49)
+    off.step(50)
+    np.testing.assert_array_equal(gpu_state(on)["pos"], gpu_state(off)["pos"])
+
+
+def test_c3_clustered_first_step_sampled():
+    w = workloads.c3()
+    note(f"c3 n={w.n}")
+    sim = make_sim(w.pos, w.diam, sort_every=w.sort_every, block_size=256)
+    sim.step(1)
+    sim.sync()
+    got = sim.query("positions").cpu().numpy()
+    note("c3 sampled check")
+    _, nnz = check_samples(w.pos, w.diam, got, 24, 3)
+    assert nnz.mean() > 5
+    gn = sim.query("nnz").cpu().numpy()
+    np.testing.assert_array_equal(gn[np.random.default_rng(3).choice(w.n, 24, replace=False)], nnz)
+
+
+def test_c4_batched_graph_sampled_sims():
+    w = workloads.c4()
+    note(f"c4 nsims={len(w.offsets) - 1} n={w.n}")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = abm.BatchedSim(to_dev(w.pos), to_dev(w.diam), w.offsets, stream=s)
+        b.graph_capture(w.steps)
+        b.graph_launch()
+        b.sync()
+        got = b.query("positions").cpu().numpy()
+    for sidx in np.random.default_rng(4).choice(len(w.offsets) - 1, 6, replace=False):
+        a, e = w.offsets[sidx], w.offsets[sidx + 1]
+        note(f"c4 sim {sidx} n={e - a}")
+        sim = make_sim(w.pos[a:e], w.diam[a:e])
+        sim.step(w.steps)
+        np.testing.assert_array_equal(got[a:e], sim.query("positions").cpu().numpy())
+
+
+def test_c5_adjoint_full():
+    w = workloads.c5()
+    note(f"c5 adjoint n={w.n}")
+    sim = make_sim(w.pos, w.diam)
+    sim.forward_record(w.steps, w.meta["ckpt_every"])
+    xT = sim.query("positions").double()
+    t = torch.from_numpy(w.target).cuda()
+    gx0, gp = sim.backward(2.0 * (xT - t) / (3 * w.n))
+    note("c5 oracle adjoint")
+    ref = oracle.adjoint(w.pos, w.diam, w.steps, oracle.Params(), w.target)
+    np.testing.assert_array_equal(xT.cpu().numpy(), ref["posT"].astype(np.float64))
+    np.testing.assert_allclose(gp.cpu().numpy(), [ref["dL_dk"], ref["dL_dgamma"]], rtol=1e-8)
+    assert np.abs(gx0.cpu().numpy() - ref["dL_dx0"]).max() <= 1e-8 * np.abs(ref["dL_dx0"]).max()

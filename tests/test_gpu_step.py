@@ -1,0 +1,213 @@
+"""GPU parity of the plain step against the CPU oracle: grid (keys, order,
+box starts) bit-exact; positions, moved flags and non-zero counts per step;
+forces; static skip; invariances of the GPU path itself."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import assert_grid_equal, gpu_state, make_sim, note, oracle_params, to_dev
+from paper_2301_06984_amd import abm, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    w = workloads.c1()
+    yield "c1-full-f64", w.pos, w.diam
+    w = workloads.c1(n=777, seed=11)
+    yield "c1-ragged-f64", w.pos, w.diam
+    w = workloads.c2(n=30011, seed=12)
+    yield "c2-ragged-f32", w.pos, w.diam
+    p, d = workloads.uniform_cube(5003, 110.0, seed=13, dtype=np.float32)
+    yield "dense-f32", p, d
+    p, d = workloads.uniform_cube(3001, 2000.0, seed=14, dtype=np.float64)
+    yield "sparse-f64", p - 1000.0, d
+
+
+CASES = list(_cases())
+IDS = [c[0] for c in CASES]
+
+
+@pytest.mark.parametrize("name,pos,diam", CASES, ids=IDS)
+def test_first_step_matches_oracle(name, pos, diam):
+    note(f"first step {name} n={pos.shape[0]}")
+    sim = make_sim(pos, diam, keep_forces=True)
+    sim.step(1)
+    sim.sync()
+    assert_grid_equal(sim, pos, diam, oracle.Params())
+    st = oracle.State.initial(pos, diam)
+    oracle.step(st, oracle.Params())
+    g = gpu_state(sim)
+    F = sim.query("forces").cpu().numpy()
+    np.testing.assert_array_equal(g["nnz"], st.nnz)
+    np.testing.assert_array_equal(g["moved"], st.moved)
+    # forces: same pair terms in the same order, so equal up to the last bit of sqrt/divide
+    scale = np.maximum(np.abs(st.force).max(axis=1, keepdims=True), 1.0)
+    assert np.all(np.abs(F - st.force) <= 1e-13 * scale)
+    rel = np.abs(g["pos"].astype(np.float64) - st.pos.astype(np.float64)).max(axis=1)
+    R = float(diam.max())
+    bound = 1e-12 * np.maximum(np.abs(st.pos.astype(np.float64)).max(axis=1), R)
+    if pos.dtype == np.float32:   # one rounding to float: at most one ulp apart
+        bound = np.spacing(np.abs(st.pos).max(axis=1)).astype(np.float64) + 0.0
+    assert np.all(rel <= bound)
+    exact = np.mean(np.all(g["pos"] == st.pos, axis=1))
+    note(f"{name}: bit-exact positions {exact:.6f}")
+
+
+def test_c1_ten_steps_fp64():
+    w = workloads.c1()
+    note("c1 10 steps f64")
+    sim = make_sim(w.pos, w.diam)
+    st = oracle.State.initial(w.pos, w.diam)
+    worst = 0.0
+    for t in range(w.steps):
+        before = sim.query("positions").cpu().numpy()
+        ref = oracle.State(before.copy(), w.diam.copy(), st.moved.copy(), st.nnz.copy(), st.force.copy(), t)
+        oracle.step(ref, oracle.Params())
+        sim.step(1)
+        g = gpu_state(sim)
+        err = np.abs(g["pos"] - ref.pos).max(axis=1) / np.maximum(np.abs(ref.pos).max(axis=1), w.diam.max())
+        worst = max(worst, float(err.max()))
+        assert err.max() <= 1e-12, (t, err.max())
+        np.testing.assert_array_equal(g["moved"], ref.moved)
+        np.testing.assert_array_equal(g["nnz"], ref.nnz)
+        oracle.step(st, oracle.Params())
+    note(f"c1 10-step worst per-step relative error {worst:.3e}")
+    # whole trajectory against the oracle's own trajectory
+    traj = np.abs(sim.query("positions").cpu().numpy() - st.pos).max()
+    note(f"c1 10-step trajectory max abs diff {traj:.3e}")
+    assert traj < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_static_skip_bitwise_and_matches_oracle(precision):
+    w = workloads.c2(n=20000, seed=21)
+    pos = w.pos.astype(np.float64) if precision == "f64" else w.pos
+    diam = w.diam.astype(np.float64) if precision == "f64" else w.diam
+    note(f"static skip {precision}")
+    on = make_sim(pos, diam, detect_static=True)
+    off = make_sim(pos, diam, detect_static=False)
+    ost = oracle.State.initial(pos, diam)
+    fracs = []
+    for t in range(12):
+        on.step(1)
+        off.step(1)
+        a, b = gpu_state(on), gpu_state(off)
+        np.testing.assert_array_equal(a["pos"], b["pos"])
+        np.testing.assert_array_equal(a["moved"], b["moved"])
+        stat, _ = oracle.step(ost, oracle.Params(detect_static=True), want_static=True)
+        gs = on.query("static").cpu().numpy()
+        np.testing.assert_array_equal(gs, stat)
+        np.testing.assert_array_equal(a["nnz"], ost.nnz)
+        assert np.all(np.abs(a["pos"].astype(np.float64) - ost.pos) <= np.spacing(np.abs(ost.pos).astype(pos.dtype)))
+        fracs.append(float(gs.mean()))
+        s = on.stats()
+        assert s["n_static"] == int(gs.sum())
+    note(f"skip fractions {fracs}")
+    assert fracs[0] == 0.0 and min(fracs[1:]) > 0.3
+
+
+def test_determinism_and_layout_invariance():
+    w = workloads.c2(n=25000, seed=31)
+    runs = {}
+    for name, kw in [("a", dict(sort_every=1)), ("b", dict(sort_every=1)), ("never", dict(sort_every=0)),
+                     ("every3", dict(sort_every=3)), ("bs64", dict(block_size=64)), ("bs1024", dict(block_size=1024))]:
+        note(f"layout variant {name}")
+        sim = make_sim(w.pos, w.diam, **kw)
+        sim.step(7)
+        runs[name] = gpu_state(sim)
+    for name, r in runs.items():
+        np.testing.assert_array_equal(r["pos"], runs["a"]["pos"], err_msg=name)
+        np.testing.assert_array_equal(r["nnz"], runs["a"]["nnz"], err_msg=name)
+
+
+def test_checkpoint_resume_bitwise():
+    w = workloads.c2(n=12000, seed=41)
+    note("checkpoint resume")
+    full = make_sim(w.pos, w.diam, detect_static=True)
+    full.step(20)
+    half = make_sim(w.pos, w.diam, detect_static=True)
+    half.step(10)
+    blob = half.export_state()
+    resumed = make_sim(w.pos, w.diam, detect_static=True)
+    resumed.import_state(blob)
+    resumed.step(10)
+    a, b = gpu_state(full), gpu_state(resumed)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    assert resumed.stats()["step"] == 20
+
+
+def test_graph_replay_equals_eager():
+    w = workloads.c2(n=15000, seed=51)
+    note("graph replay")
+    eager = make_sim(w.pos, w.diam, detect_static=True)
+    eager.step(30)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = make_sim(w.pos, w.diam, detect_static=True, stream=s)
+        g.step(10)
+        g.graph_capture(10)
+        g.graph_launch()
+        g.graph_launch()
+        g.sync()
+    a, b = gpu_state(eager), gpu_state(g)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    assert g.stats()["step"] == 30
+
+
+def test_set_params_matches_oracle():
+    w = workloads.c1(n=3000, seed=61)
+    note("set params")
+    sim = make_sim(w.pos, w.diam, detect_static=True)
+    st = oracle.State.initial(w.pos, w.diam)
+    p = oracle.Params(detect_static=True)
+    for _ in range(3):
+        sim.step(1)
+        oracle.step(st, p)
+    sim.set_params(k=3.0, gamma=0.5, f_adh=0.05)
+    st.moved[:] = 1           # a parameter change counts as a move of every agent
+    p = oracle.Params(k=3.0, gamma=0.5, f_adh=0.05, detect_static=True)
+    for _ in range(3):
+        sim.step(1)
+        oracle.step(st, p)
+    g = gpu_state(sim)
+    assert np.abs(g["pos"] - st.pos).max() < 1e-11
+    np.testing.assert_array_equal(g["nnz"], st.nnz)
+
+
+def test_tiny_inputs():
+    for n in (1, 2, 63, 64, 65):
+        note(f"tiny n={n}")
+        p, d = workloads.uniform_cube(n, 20.0, seed=70 + n)
+        sim = make_sim(p, d)
+        sim.step(2)
+        st = oracle.run(p, d, 2, oracle.Params())
+        assert np.abs(sim.query("positions").cpu().numpy() - st.pos).max() < 1e-12
+
+
+def test_errors_are_reported():
+    p, d = workloads.uniform_cube(1000, 60.0, seed=81)
+    bad = p.copy()
+    bad[5, 1] = np.nan
+    note("error: non-finite input")
+    with pytest.raises(abm.ABMError) as e:
+        make_sim(bad, d)
+    assert e.value.code == abm.ABM_E_NONFINITE
+    note("error: grid overflow")
+    sim = make_sim(p, d, box_capacity=1)   # smaller than the grid: every step is refused
+    sim.step(1)
+    with pytest.raises(abm.ABMError) as e:
+        sim.sync()
+    assert e.value.code == abm.ABM_E_GRID
+    note("error: forces not kept / backward before record")
+    sim = make_sim(p, d)
+    sim.step(1)
+    with pytest.raises(abm.ABMError) as e:
+        sim.query("forces")
+    assert e.value.code == abm.ABM_E_UNSUPPORTED
+    with pytest.raises(abm.ABMError) as e:
+        sim.backward(torch.zeros((1000, 3), dtype=torch.float64, device="cuda"))
+    assert e.value.code == abm.ABM_E_STATE

@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the agent step on one MI355X.
+
+Headline: agent-steps/s of the plain step (grid build + static flags + force
++ move, every agent's force computed) on 1e7 spheres in FP32 state, the c2
+construction scaled to 1e7 agents (uniform inner cube + force-free jittered
+lattice shell, cube side 3387.7, d ~ U[8, 12]).  Beside it, on the same GPU:
+the static skip switched on, the batched form (512 simulations, 50 steps in
+one graph launch) and the adjoint form (1e5 spheres, 50 steps forward +
+backward), each as agent-steps/s; the dominant kernel's roofline from HIP
+events around it over the timed region; and the CPU oracle timed on a bounded
+sample of the same workload.
+
+Prints one JSON line (rank 0).  Inputs are resident in HBM before timing.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "agent-steps/s (grid+force+move) at 1e7 agents; batched & adjoint vs plain step"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# Algorithmic bytes per agent of the step: read x, y, z, d; write x, y, z;
+# one 4-byte box key and one 4-byte list index written and read.
+STEP_BYTES = {"f32": 4 * 4 + 3 * 4 + 16, "f64": 4 * 8 + 3 * 8 + 16}
+# ... of the force/move kernel alone: read x, y, z, d and the 4-byte slot
+# index of the agent; write x, y, z.
+FORCE_BYTES = {"f32": 4 * 4 + 4 + 3 * 4, "f64": 4 * 8 + 4 + 3 * 8}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def timed_steps(sim, steps, timing=False):
+    import torch
+    if timing:
+        sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.sync()
+    tm = sim.timing() if timing else None
+    if timing:
+        sim.set_timing(False)
+    return t1 - t0, tm
+
+
+def cpu_baseline(w, budget_s: float):
+    """The oracle (as it is) on the same workload, whole steps until the budget is used."""
+    import numpy as np
+    import oracle
+    st = oracle.State.initial(w.pos, w.diam)
+    p = oracle.Params(detect_static=False)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.step(st, p)
+        steps += 1
+        el = time.perf_counter() - t0
+        log(f"cpu oracle step {steps}: {el:.1f} s")
+        if el >= budget_s or steps >= 3:
+            break
+    cores = oracle.max_threads()
+    del np
+    return dict(value=w.n * steps / el, unit="agent-steps/s", cores=int(cores), kind="oracle",
+                sample=f"{steps} full step(s) of the {w.n}-agent headline workload (FP64 C++ oracle, OpenMP, "
+                       f"{el:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--block-size", type=int, default=256)
+    ap.add_argument("--sort-every", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true", help="skip the skip-on, batched and adjoint legs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--json-out", default=None)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB five times (scales rocprof byte counters)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                          "launches": 5}), flush=True)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the spatial decomposition over GPUs is a design, see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2301_06984_amd import abm, build as hip_build, workloads
+
+    if not os.path.exists(abm.LIB_PATH):
+        hip_build.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # ---------------------------------------------------------------- headline
+    log(f"generating headline workload n={args.n}")
+    w = workloads.headline(n=args.n)
+    pos = torch.from_numpy(w.pos).to(dev)
+    diam = torch.from_numpy(w.diam).to(dev)
+    sim = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size)
+    sim.step(args.warmup)
+    sim.sync()
+    log("timed region")
+    el, tm = timed_steps(sim, args.steps, timing=True)
+    value = w.n * args.steps / el
+    ms_step = 1e3 * el / args.steps
+    phases = {k: tm[k] / tm["steps"] for k in abm.TIMED_PHASES}
+    dominant = max(abm.TIMED_PHASES, key=lambda k: phases[k])
+    prec = w.precision
+    force_bytes = FORCE_BYTES[prec] * w.n
+    ach = force_bytes / (phases["force"] * 1e-3) / 1e9
+    roof = dict(bound="hbm", kernel="k_force (static flags + force + move)", achieved=round(ach, 1),
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
+                bytes_per_agent=FORCE_BYTES[prec], avg_launch_ms=round(phases["force"], 4),
+                dominant_phase=dominant, phase_ms={k: round(v, 4) for k, v in phases.items()},
+                step_bytes_per_agent=STEP_BYTES[prec],
+                step_frac=round(value * STEP_BYTES[prec] / (HBM_PEAK_GBS * 1e9), 4))
+    log(f"headline {value:.3e} agent-steps/s, {ms_step:.3f} ms/step, phases {phases}")
+    del sim
+
+    extras = {}
+    if not args.no_extras:
+        # static skip on (same workload): the shell is force-free and static
+        s2 = abm.Sim(pos, diam, detect_static=True, sort_every=args.sort_every, block_size=args.block_size)
+        s2.step(args.warmup)
+        el2, _ = timed_steps(s2, args.steps)
+        st = s2.stats()
+        extras["skip_on"] = dict(value=w.n * args.steps / el2, unit="agent-steps/s",
+                                 speedup_vs_skip_off=round(el / el2, 3),
+                                 static_fraction_last_step=round(st["n_static"] / w.n, 4))
+        log(f"skip on {extras['skip_on']}")
+        del s2
+        del pos, diam
+        torch.cuda.empty_cache()
+        # batched: 512 simulations, 50 steps in one graph launch
+        wb = workloads.c4()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            b = abm.BatchedSim(torch.from_numpy(wb.pos).to(dev), torch.from_numpy(wb.diam).to(dev), wb.offsets,
+                               stream=s, common=dict(sort_every=1, block_size=args.block_size))
+            b.graph_capture(wb.steps)
+            b.graph_launch()          # warm-up replay
+            b.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.graph_launch()
+            b.sync()
+            elb = time.perf_counter() - t0
+        extras["batched"] = dict(value=wb.n * wb.steps / elb, unit="agent-steps/s", nsims=len(wb.offsets) - 1,
+                                 agents=int(wb.n), steps=wb.steps, launch="one hipGraph replay of 50 steps",
+                                 ratio_vs_plain=round((wb.n * wb.steps / elb) / value, 3))
+        log(f"batched {extras['batched']}")
+        del b
+        torch.cuda.empty_cache()
+        # adjoint: 1e5 spheres, 50 steps, checkpoint every 10, forward + backward
+        wa = workloads.c5()
+        pa = torch.from_numpy(wa.pos).to(dev)
+        da = torch.from_numpy(wa.diam).to(dev)
+        plain = abm.Sim(pa, da, sort_every=0)
+        plain.step(5)
+        elp, _ = timed_steps(plain, wa.steps)
+        adj = abm.Sim(pa, da, sort_every=0)
+        adj.forward_record(wa.steps, 10)      # warm-up
+        xT = adj.positions().double()
+        tgt = torch.from_numpy(wa.target).to(dev)
+        adj.backward(2.0 * (xT - tgt) / (3 * wa.n))
+        adj2 = abm.Sim(pa, da, sort_every=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        adj2.forward_record(wa.steps, 10)
+        xT = adj2.positions().double()
+        gx, gp = adj2.backward(2.0 * (xT - tgt) / (3 * wa.n))
+        torch.cuda.synchronize()
+        ela = time.perf_counter() - t0
+        extras["adjoint"] = dict(value=wa.n * wa.steps / ela, unit="agent-steps/s (forward+backward)",
+                                 agents=wa.n, steps=wa.steps, ckpt_every=10,
+                                 plain_forward=wa.n * wa.steps / elp,
+                                 ratio_vs_plain_forward=round(elp / ela, 3),
+                                 dL_dk=float(gp[0]), dL_dgamma=float(gp[1]))
+        log(f"adjoint {extras['adjoint']}")
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline")
+        cpu = cpu_baseline(w, args.cpu_budget)
+
+    out = {"metric": METRIC, "value": value, "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "headline: 1e7 spheres, c2 construction (uniform inner cube + jittered "
+                                  "force-free lattice shell), side 3387.7, d~U[8,12], seed 2",
+                      "n": w.n, "state": prec, "arithmetic": "f64", "detect_static": False,
+                      "sort_every": args.sort_every, "block_size": args.block_size},
+           "roofline": roof, "cpu_baseline": cpu, **extras}
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,15 @@ typedef struct abm_stats {
     uint32_t reserved;
 } abm_stats;
 
+/* Accumulated kernel times of timed steps (abm_set_timing / abm_get_timing):
+ * ms[0] setup, ms[1] box keys + histogram, ms[2] scan, ms[3] scatter,
+ * ms[4] canonical order + box table, ms[5] static flags + force + move;
+ * ms[6], ms[7] unused (0). */
+typedef struct abm_timing {
+    int64_t steps;
+    double ms[8];
+} abm_timing;
+
 typedef struct abm_ctx abm_ctx;
 
 /* Fields for abm_query. */
@@ -228,6 +237,15 @@ int abm_graph_launch(abm_ctx* ctx);
 int abm_record_bytes(abm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, int64_t* bytes);
 int abm_forward_record(abm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, void* rec, int64_t rec_bytes);
 int abm_backward(abm_ctx* ctx, const void* dL_dxT, void* dL_dx0, void* dL_dparams);
+
+/*
+ * Timing mode: with enable != 0, every step enqueued by abm_step brackets
+ * each of its kernels with HIP events on the context's stream (graph replays
+ * are not timed).  abm_set_timing resets the accumulators; abm_get_timing
+ * synchronises and adds the elapsed times of all timed steps so far.
+ */
+int abm_set_timing(abm_ctx* ctx, int32_t enable);
+int abm_get_timing(abm_ctx* ctx, abm_timing* out);
 
 /* Release the context (not the caller's buffers). */
 void abm_destroy(abm_ctx* ctx);

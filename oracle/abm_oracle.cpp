@@ -18,6 +18,7 @@
 //    none of its neighbours moved in the last iteration and at most one
 //    neighbour force was non-zero.
 //  * Displacement from the summed force with a force threshold (Section 5).
+//  * Sums over neighbours run in canonical (box rank, id) order.
 //  * Parallel-for over agents with a barrier before positions are committed
 //    (Algorithm 1), read as a Jacobi update.
 // The pairwise force law is not given in the paper (Section 5 defers to the
@@ -235,9 +236,13 @@ Vec3 load(const T* pos, int64_t i) { return {double(pos[3 * i]), double(pos[3 * 
 // Visit the candidates of agent i: the agents of the 27 boxes around its box
 // (boxes outside the space are skipped), boxes in lexicographic (dz, dy, dx)
 // order, agents of a box in ascending id.  fn(j) is called for j != i.
+// The candidates are visited in canonical order: ascending (box rank, id),
+// i.e. by their slot in the array-based lists.  Floating-point sums over
+// neighbours therefore have one defined order (the paper leaves it open).
 template <class T, class Fn>
 void for_candidates(const Grid<T>& g, int64_t i, Fn&& fn) {
     const int64_t* q = &g.cell[3 * i];
+    std::vector<uint32_t> slots;
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
@@ -246,11 +251,13 @@ void for_candidates(const Grid<T>& g, int64_t i, Fn&& fn) {
                 for (int a = 0; a < 3; ++a) in = in && qq[a] >= 0 && qq[a] < g.dims[a];
                 if (!in) continue;
                 const int64_t b = g.box_rank(qq);
-                for (uint32_t s = g.cell_start[b]; s < g.cell_start[b + 1]; ++s) {
-                    const uint32_t j = g.perm[s];
-                    if (int64_t(j) != i) fn(int64_t(j));
-                }
+                for (uint32_t s = g.cell_start[b]; s < g.cell_start[b + 1]; ++s) slots.push_back(s);
             }
+    std::sort(slots.begin(), slots.end());
+    for (uint32_t s : slots) {
+        const uint32_t j = g.perm[s];
+        if (int64_t(j) != i) fn(int64_t(j));
+    }
 }
 
 double sq3(double a, double b, double c) { return (a * a + b * b) + c * c; }

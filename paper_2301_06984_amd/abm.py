@@ -27,7 +27,9 @@ EXTENT_SCRATCH_BYTES = 1024
 EXPORTS = ["abm_abi_version", "abm_default_params", "abm_last_error", "abm_extent_of", "abm_workspace_bytes",
            "abm_init", "abm_init_batched", "abm_set_params", "abm_step", "abm_sync", "abm_query",
            "abm_get_stats", "abm_state_bytes", "abm_export_state", "abm_import_state", "abm_graph_capture",
-           "abm_graph_launch", "abm_record_bytes", "abm_forward_record", "abm_backward", "abm_destroy"]
+           "abm_graph_launch", "abm_record_bytes", "abm_forward_record", "abm_backward", "abm_set_timing",
+           "abm_get_timing", "abm_destroy"]
+TIMED_PHASES = ["setup", "keys", "scan", "scatter", "fixup", "force"]
 
 
 class abm_params(C.Structure):
@@ -45,6 +47,10 @@ class abm_extent(C.Structure):
 class abm_stats(C.Structure):
     _fields_ = [("step", C.c_int64), ("n_static", C.c_int64), ("n_moved", C.c_int64), ("error", C.c_uint32),
                 ("reserved", C.c_uint32)]
+
+
+class abm_timing(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("ms", C.c_double * 8)]
 
 
 class ABMError(RuntimeError):
@@ -85,6 +91,8 @@ def lib():
             "abm_record_bytes": (C.c_int, [P, i32, i32, C.POINTER(i64)]),
             "abm_forward_record": (C.c_int, [P, i32, i32, P, i64]),
             "abm_backward": (C.c_int, [P, P, P, P]),
+            "abm_set_timing": (C.c_int, [P, i32]),
+            "abm_get_timing": (C.c_int, [P, C.POINTER(abm_timing)]),
             "abm_destroy": (None, [P]),
         }
         for name, (res, args) in sig.items():
@@ -180,6 +188,17 @@ class Sim:
             setattr(p, k, int(v) if isinstance(v, bool) else v)
         _check(lib().abm_set_params(self.ctx, C.byref(p)), "abm_set_params")
         self.params = p
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().abm_set_timing(self.ctx, int(bool(enable))), "abm_set_timing")
+
+    def timing(self) -> dict:
+        """Accumulated per-kernel times (ms) of the timed steps."""
+        t = abm_timing()
+        _check(lib().abm_get_timing(self.ctx, C.byref(t)), "abm_get_timing")
+        out = {name: t.ms[k] for k, name in enumerate(TIMED_PHASES)}
+        out["steps"] = t.steps
+        return out
 
     def graph_capture(self, nsteps: int):
         _check(lib().abm_graph_capture(self.ctx, int(nsteps)), "abm_graph_capture")

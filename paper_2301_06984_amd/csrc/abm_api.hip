@@ -1,6 +1,7 @@
 // abm_api.hip -- the C ABI of libabm (declared in include/abm.h): workspace
 // layout, step sequencing (Algorithm 1's iteration as a chain of kernels on
 // one stream), queries, checkpoints, graph capture and the adjoint driver.
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -30,9 +31,12 @@ int fail(int code, const std::string& msg) {
 constexpr int64_t kAlign = 256;
 int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// setup, keys, scan, scatter, fixup, force
+constexpr int kTimedPhases = 6;
+
 struct Layout {
-    int64_t globals, sims, sim_of, pos4[2], ids[2], flags[2], force[2], key, rmi, sub, tmp, perm, count, cell_start,
-        cellinfo, scan_status, partials, stage, total;
+    int64_t globals, sims, sim_of, bbox_rep, pos4[2], ids[2], flags[2], force[2], key, rmi, sub, tmp, perm, spos,
+        count, cell_start, cellinfo, scan_status, partials, stage, total;
     uint32_t scan_tiles, partial_cap;
 };
 
@@ -47,6 +51,7 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.globals = take(sizeof(Globals));
     L.sims = take(int64_t(sizeof(SimGrid)) * nsims);
     L.sim_of = nsims > 1 ? take(2 * n) : -1;
+    L.bbox_rep = take(int64_t(sizeof(int32_t)) * 2 * kReplicas * nsims * 6);
     for (int k = 0; k < 2; ++k) L.pos4[k] = take(4 * elem * n);
     for (int k = 0; k < 2; ++k) L.ids[k] = take(4 * n);
     for (int k = 0; k < 2; ++k) L.flags[k] = take(4 * n);
@@ -56,6 +61,7 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.sub = take(4 * n);
     L.tmp = take(4 * n);
     L.perm = take(4 * n);
+    L.spos = take(4 * elem * n);
     L.count = take(4 * boxes);
     L.cell_start = take(4 * (boxes + 1));
     L.cellinfo = take(8 * boxes);
@@ -94,6 +100,11 @@ struct abm_ctx {
     hipGraphExec_t graph_exec = nullptr;
     int32_t graph_steps = 0;
     int graph_grid_ids = 0;  // ids buffer of the last captured step's grid
+    // timing mode: one set of events per step around each kernel
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, kTimedPhases + 1>> ev_pending, ev_free;
+    double ev_ms[kTimedPhases] = {};
+    int64_t ev_steps = 0;
     // adjoint record
     bool recorded = false;
     int32_t rec_steps = 0, rec_ckpt = 0;
@@ -117,6 +128,7 @@ void fill_buffers(abm_ctx* c) {
     b.g = reinterpret_cast<Globals*>(w + L.globals);
     b.sims = reinterpret_cast<SimGrid*>(w + L.sims);
     b.sim_of = L.sim_of >= 0 ? reinterpret_cast<const uint16_t*>(w + L.sim_of) : nullptr;
+    b.bbox_rep = reinterpret_cast<int32_t*>(w + L.bbox_rep);
     b.nsims = c->nsims;
     b.n = uint32_t(c->n);
     for (int k = 0; k < 2; ++k) {
@@ -130,6 +142,7 @@ void fill_buffers(abm_ctx* c) {
     b.sub = reinterpret_cast<uint32_t*>(w + L.sub);
     b.tmp = reinterpret_cast<uint32_t*>(w + L.tmp);
     b.perm = reinterpret_cast<uint32_t*>(w + L.perm);
+    b.spos = w + L.spos;
     b.count = reinterpret_cast<uint32_t*>(w + L.count);
     b.cell_start = reinterpret_cast<uint32_t*>(w + L.cell_start);
     b.cellinfo = reinterpret_cast<unsigned long long*>(w + L.cellinfo);
@@ -189,12 +202,31 @@ void guard_stamps(abm_ctx* c, int64_t m) {
     }
 }
 
+std::array<hipEvent_t, kTimedPhases + 1>* next_events(abm_ctx* c) {
+    if (c->ev_free.empty()) {
+        std::array<hipEvent_t, kTimedPhases + 1> e{};
+        for (auto& x : e)
+            if (hipEventCreate(&x) != hipSuccess) return nullptr;
+        c->ev_free.push_back(e);
+    }
+    c->ev_pending.push_back(c->ev_free.back());
+    c->ev_free.pop_back();
+    return &c->ev_pending.back();
+}
+
 template <class T>
-void enqueue_step(abm_ctx* c, bool allow_relayout) {
+void enqueue_step(abm_ctx* c, bool allow_relayout, bool timed = false) {
     Buffers<T>& b = c->buf<T>();
     const int parity = int(c->step & 1);
+    std::array<hipEvent_t, kTimedPhases + 1>* ev = timed ? next_events(c) : nullptr;
+    hipEvent_t* marks[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (ev) {
+        (void)hipEventRecord((*ev)[0], c->stream);
+        for (int k = 0; k < 4; ++k) marks[k] = &(*ev)[2 + k];
+    }
     launch_setup<T>(b, parity, c->stream);
-    launch_grid<T>(b, c->pos_cur, c->ids_cur, c->stream);
+    if (ev) (void)hipEventRecord((*ev)[1], c->stream);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, c->stream, ev ? marks : nullptr);
     StepArgs a{};
     a.parity = parity;
     a.pos_cur = c->pos_cur;
@@ -204,6 +236,7 @@ void enqueue_step(abm_ctx* c, bool allow_relayout) {
     a.keep_forces = c->params.keep_forces != 0;
     a.block_size = block_size_of(c->params);
     launch_force<T>(b, a, c->stream);
+    if (ev) (void)hipEventRecord((*ev)[kTimedPhases], c->stream);
     c->grid_ids = c->ids_cur;
     c->have_grid = true;
     c->pos_cur ^= 1;
@@ -218,7 +251,7 @@ int do_steps(abm_ctx* c, int32_t nsteps, bool allow_relayout) {
     while (left > 0) {
         const int32_t m = left < int32_t(kStampPeriod) ? left : int32_t(kStampPeriod);
         guard_stamps<T>(c, m);
-        for (int32_t s = 0; s < m; ++s) enqueue_step<T>(c, allow_relayout);
+        for (int32_t s = 0; s < m; ++s) enqueue_step<T>(c, allow_relayout, c->timing);
         left -= m;
     }
     HIP_TRY(hipGetLastError());
@@ -756,8 +789,13 @@ int abm_get_stats(abm_ctx* c, abm_stats* out) {
     HIP_TRY(hipMemcpy(&g, c->ws + c->L.globals, sizeof(g), hipMemcpyDeviceToHost));
     out->step = c->step;
     const int last = int((c->step - 1) & 1);
-    out->n_static = c->step > 0 ? int64_t(g.n_static[last]) : 0;
-    out->n_moved = c->step > 0 ? int64_t(g.n_moved[last]) : 0;
+    int64_t ns = 0, nm = 0;
+    for (int r = 0; r < kReplicas; ++r) {
+        ns += int64_t(g.stats[last][r][0]);
+        nm += int64_t(g.stats[last][r][1]);
+    }
+    out->n_static = c->step > 0 ? ns : 0;
+    out->n_moved = c->step > 0 ? nm : 0;
     out->error = g.err;
     out->reserved = 0;
     return ABM_OK;
@@ -821,9 +859,43 @@ int abm_backward(abm_ctx* c, const void* dL_dxT, void* dL_dx0, void* dL_dparams)
     return c->precision == ABM_F64 ? backward_impl<double>(c, a, b, p) : backward_impl<float>(c, a, b, p);
 }
 
+int abm_set_timing(abm_ctx* c, int32_t enable) {
+    if (int rc = check_ctx(c)) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto& e : c->ev_pending) c->ev_free.push_back(e);
+    c->ev_pending.clear();
+    for (double& m : c->ev_ms) m = 0.0;
+    c->ev_steps = 0;
+    c->timing = enable != 0;
+    return ABM_OK;
+}
+
+int abm_get_timing(abm_ctx* c, abm_timing* out) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!out) return fail(ABM_E_INVAL, "null output");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto& e : c->ev_pending) {
+        for (int k = 0; k < kTimedPhases; ++k) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+            c->ev_ms[k] += ms;
+        }
+        c->ev_steps += 1;
+        c->ev_free.push_back(e);
+    }
+    c->ev_pending.clear();
+    out->steps = c->ev_steps;
+    for (int k = 0; k < kTimedPhases; ++k) out->ms[k] = c->ev_ms[k];
+    for (int k = kTimedPhases; k < 8; ++k) out->ms[k] = 0.0;
+    return ABM_OK;
+}
+
 void abm_destroy(abm_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto* v : {&c->ev_pending, &c->ev_free})
+        for (auto& e : *v)
+            for (auto& x : e) (void)hipEventDestroy(x);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     c->ws = nullptr;

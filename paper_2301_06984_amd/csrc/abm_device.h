@@ -89,34 +89,130 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
     return v;
 }
 
-// Fold the box coordinates c of the active lanes into the bbox accumulator
-// of their simulation: one set of atomics per wave when the wave's active
-// lanes share one simulation, per lane otherwise.
-__device__ __forceinline__ void bbox_accumulate(SimGrid* sims, int sim, int slot, bool active, const int32_t c[3]) {
+__device__ __forceinline__ void bbox_atomic(int32_t* t, const int32_t lo[3], const int32_t hi[3]) {
+    for (int a = 0; a < 3; ++a) {
+        atomicMin(&t[a], lo[a]);
+        atomicMax(&t[3 + a], hi[a]);
+    }
+}
+
+// Fold the box coordinates c of the active threads of a block into the
+// accumulator target(sim) (6 ints: min x,y,z then max x,y,z).  Waves reduce
+// in registers, the block combines its waves in LDS, and one set of atomics
+// per simulation present in the block goes out, so that same-address
+// atomics stay few.  Every thread of the block must call this once.
+template <class Target>
+__device__ void bbox_fold_block(int sim, bool active, const int32_t c[3], Target target) {
+    __shared__ int32_t s_box[16][6];
+    __shared__ int s_sim[16];
+    const int wave = int(threadIdx.x >> 6);
+    const int nwaves = int((blockDim.x + 63u) >> 6);
     const unsigned long long act = __ballot(active);
-    if (act == 0) return;
-    const int leader = __ffsll((long long)act) - 1;
-    const int s0 = __shfl(sim, leader, 64);
-    const bool uniform = __ballot(active && sim != s0) == 0;
-    if (uniform) {
+    int s0 = -1;
+    bool uniform = false;
+    if (act) {
+        const int leader = __ffsll((long long)act) - 1;
+        s0 = __shfl(sim, leader, 64);
+        uniform = __ballot(active && sim != s0) == 0;
+    }
+    if (act && uniform) {
         int32_t lo[3], hi[3];
         for (int a = 0; a < 3; ++a) {
             lo[a] = wave_min(active ? c[a] : INT32_MAX);
             hi[a] = wave_max(active ? c[a] : INT32_MIN);
         }
-        if (lane_id() == leader) {
-            int32_t* bb = sims[s0].bbox[slot];
+        if (lane_id() == 0) {
+            s_sim[wave] = s0;
             for (int a = 0; a < 3; ++a) {
-                atomicMin(&bb[a], lo[a]);
-                atomicMax(&bb[3 + a], hi[a]);
+                s_box[wave][a] = lo[a];
+                s_box[wave][3 + a] = hi[a];
             }
         }
-    } else if (active) {
-        int32_t* bb = sims[sim].bbox[slot];
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&bb[a], c[a]);
-            atomicMax(&bb[3 + a], c[a]);
+    } else {
+        if (active) bbox_atomic(target(sim), c, c);
+        if (lane_id() == 0) s_sim[wave] = -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int cur = -1;
+        int32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int w = 0; w < nwaves; ++w) {
+            const int s = s_sim[w];
+            if (s < 0) continue;
+            if (s != cur) {
+                if (cur >= 0) bbox_atomic(target(cur), lo, hi);
+                cur = s;
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = s_box[w][a];
+                    hi[a] = s_box[w][3 + a];
+                }
+            } else {
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = min(lo[a], s_box[w][a]);
+                    hi[a] = max(hi[a], s_box[w][3 + a]);
+                }
+            }
         }
+        if (cur >= 0) bbox_atomic(target(cur), lo, hi);
+    }
+}
+
+// Replica of the bbox accumulator that this block folds into.
+template <class T>
+__device__ __forceinline__ int32_t* bbox_replica(const Buffers<T>& b, int slot, int sim) {
+    const uint32_t r = blockIdx.x % kReplicas;
+    return b.bbox_rep + ((size_t(slot) * kReplicas + r) * size_t(b.nsims) + size_t(sim)) * 6;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(v, d, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Largest value per simulation, folded like bbox_fold_block.
+template <class Target>
+__device__ void max_fold_block(int sim, bool active, unsigned long long v, Target target) {
+    __shared__ unsigned long long s_val[16];
+    __shared__ int s_sim[16];
+    const int wave = int(threadIdx.x >> 6);
+    const int nwaves = int((blockDim.x + 63u) >> 6);
+    const unsigned long long act = __ballot(active);
+    int s0 = -1;
+    bool uniform = false;
+    if (act) {
+        const int leader = __ffsll((long long)act) - 1;
+        s0 = __shfl(sim, leader, 64);
+        uniform = __ballot(active && sim != s0) == 0;
+    }
+    if (act && uniform) {
+        const unsigned long long m = wave_max_u64(active ? v : 0ull);
+        if (lane_id() == 0) {
+            s_sim[wave] = s0;
+            s_val[wave] = m;
+        }
+    } else {
+        if (active) atomicMax(target(sim), v);
+        if (lane_id() == 0) s_sim[wave] = -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int cur = -1;
+        unsigned long long m = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            const int s = s_sim[w];
+            if (s < 0) continue;
+            if (s != cur) {
+                if (cur >= 0) atomicMax(target(cur), m);
+                cur = s;
+                m = s_val[w];
+            } else {
+                m = s_val[w] > m ? s_val[w] : m;
+            }
+        }
+        if (cur >= 0) atomicMax(target(cur), m);
     }
 }
 

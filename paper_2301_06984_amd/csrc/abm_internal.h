@@ -12,6 +12,7 @@
 //     sub    arrival index of the agent in its box (from the histogram atomics)
 //     tmp    agents in box order, arrival order inside a box
 //     perm   agents in canonical (box rank, id) order
+//     spos   {x, y, z, d} of the agents in canonical order (sign of d = moved)
 //   per box (capacity = sum of the per-simulation box capacities):
 //     count       histogram; every scan leaves it zeroed for the next step
 //     cell_start  exclusive prefix sum of count (+1 entry)
@@ -34,6 +35,10 @@ constexpr uint32_t kMaxBoxesPerAxis = 1u << 21;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
+// Reductions over all agents (box extent, step statistics) fold into this
+// many copies of their accumulator, chosen by block index, so that
+// same-address atomics stay few; the per-step setup kernel combines them.
+constexpr int kReplicas = 64;
 
 // Device error bits (latched, cleared by abm_sync).
 enum : uint32_t {
@@ -60,8 +65,8 @@ struct SimGrid {
     uint32_t box_base;      // first global box index of this simulation
     int32_t levels;         // smallest L with 2^L >= max(dims)
     uint32_t valid;
-    // min x,y,z then max x,y,z of the box coordinates, two accumulators used
-    // alternately: one is read by the step, the other filled by its move kernel
+    // min x,y,z then max x,y,z of the box coordinates (extent queries only;
+    // the step keeps its accumulators in Buffers::bbox_rep)
     int32_t bbox[2][6];
     uint64_t radius_bits;   // max diameter as ordered bits (init only)
 };
@@ -72,9 +77,8 @@ struct Globals {
     uint32_t stamp;          // of the current step's box table entries (1..32767)
     uint32_t scan_epoch;     // tag of the current step's scan status words (never 0)
     unsigned long long scan_ticket;
-    unsigned long long n_static[2];
-    unsigned long long n_moved[2];
-    double grad[2];         // adjoint: dL/dk, dL/dgamma (final reduction)
+    // per step parity and replica: agents skipped as static, agents moved
+    unsigned long long stats[2][kReplicas][2];
 };
 
 // Pointers into the workspace, passed by value to kernels.
@@ -97,6 +101,7 @@ struct Buffers {
     uint32_t* sub;
     uint32_t* tmp;
     uint32_t* perm;
+    void* spos;               // V4<T> per slot of the canonical order; sign of d = moved
     // per box
     uint32_t* count;
     uint32_t* cell_start;
@@ -104,6 +109,9 @@ struct Buffers {
     unsigned long long* scan_status;
     double* partials;         // per-block partial sums (adjoint)
     uint32_t partial_cap;
+    // box extent accumulators [2 slots][kReplicas][nsims][6]: one slot is
+    // read by a step's setup, the other filled by its move kernel
+    int32_t* bbox_rep;
 };
 
 // Host-side description of which kernels to run for one step.
@@ -130,7 +138,8 @@ void launch_set_params(SimGrid* sims, int nsims, double k, double gamma, double 
 void launch_permute3(const uint32_t* ids, uint32_t n, const double* in, double* out, bool to_id, hipStream_t s);
 template <class T> void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s);
 template <class T> void launch_setup(const Buffers<T>& b, int parity, hipStream_t s);
-template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s);
+template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s,
+                                    hipEvent_t* const* marks = nullptr);
 template <class T> void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s);
 template <class T> void launch_reset_bbox(const Buffers<T>& b, int parity, hipStream_t s);
 

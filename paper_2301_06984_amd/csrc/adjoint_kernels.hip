@@ -26,13 +26,14 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, co
     if (t < b.n && i >= b.n) raise_error(b.g, kErrInternal);
     if (i < b.n) {
         const SimGrid& G = b.sims[sim_index(b, t)];
-        const V4<T>* pin = pos4_ptr(b, cur);
-        const V4<T> p = pin[i];
+        const V4<T> p = spos_ptr(b)[t];
         uint32_t q[3];
         double wi[3] = {0.0, 0.0, 0.0};
         if (G.valid && box_of<T>(G, p, q)) {
+            unsigned long long e[27];
+            load_boxes(b, G, q, b.g->stamp, e);
             ForceSum acc;
-            force_of<T, true>(b, G, pin, i, p, q, b.g->stamp, acc);
+            force_of<T, true>(b, G, t, p, e, acc);
             const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
             if (m.moves) {
                 const double li[3] = {lam[3 * size_t(i)], lam[3 * size_t(i) + 1], lam[3 * size_t(i) + 2]};
@@ -76,26 +77,30 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= b.n) return;
     const SimGrid& G = b.sims[sim_index(b, t)];
-    const V4<T>* pin = pos4_ptr(b, cur);
     const uint32_t m = b.perm[t];
     if (m >= b.n) {
         raise_error(b.g, kErrInternal);
         return;
     }
-    const V4<T> p = pin[m];
+    const V4<T> p = spos_ptr(b)[t];
+    const V4<T>* __restrict__ sp = spos_ptr(b);
     uint32_t q[3];
     double acc[3] = {lam[3 * size_t(m)], lam[3 * size_t(m) + 1], lam[3 * size_t(m) + 2]};
     if (G.valid && box_of<T>(G, p, q)) {
+        unsigned long long e[27];
+        load_boxes(b, G, q, b.g->stamp, e);
         const double xm = double(p.x), ym = double(p.y), zm = double(p.z);
-        const double rm = 0.5 * double(p.w);
+        const double rm = 0.5 * fabs(double(p.w));
         const double wm[3] = {w[3 * size_t(m)], w[3 * size_t(m) + 1], w[3 * size_t(m) + 2]};
-        visit_boxes(b, G, q, b.g->stamp, false, [&](uint32_t j) {
-            if (j == m) return true;
-            const V4<T> pj = pin[j];
-            const double e[3] = {xm - double(pj.x), ym - double(pj.y), zm - double(pj.z)};
-            const double s2 = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+        visit_slots(e, false, [&](uint32_t u) {
+            if (u == t || u >= b.n) return true;
+            const uint32_t j = b.perm[u];
+            if (j >= b.n) return true;
+            const V4<T> pj = sp[u];
+            const double ev3[3] = {xm - double(pj.x), ym - double(pj.y), zm - double(pj.z)};
+            const double s2 = (ev3[0] * ev3[0] + ev3[1] * ev3[1]) + ev3[2] * ev3[2];
             if (!(s2 < G.r2)) return true;
-            const double rj = 0.5 * double(pj.w), S = rm + rj;
+            const double rj = 0.5 * fabs(double(pj.w)), S = rm + rj;
             if (!(s2 > 0.0) || !(s2 < S * S)) return true;
             const double dist = sqrt(s2);
             const double delta = S - dist, rho = (rm * rj) / S;
@@ -104,8 +109,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
             const double gd = f / dist;
             const double gprime = -(fp * dist + f) / (dist * dist);
             const double v[3] = {wm[0] - w[3 * size_t(j)], wm[1] - w[3 * size_t(j) + 1], wm[2] - w[3 * size_t(j) + 2]};
-            const double ev = e[0] * v[0] + e[1] * v[1] + e[2] * v[2];
-            for (int a = 0; a < 3; ++a) acc[a] += gd * v[a] + gprime / dist * e[a] * ev;
+            const double ev = ev3[0] * v[0] + ev3[1] * v[1] + ev3[2] * v[2];
+            for (int a = 0; a < 3; ++a) acc[a] += gd * v[a] + gprime / dist * ev3[a] * ev;
             return true;
         });
     } else {

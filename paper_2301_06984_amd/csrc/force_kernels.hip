@@ -41,23 +41,16 @@ __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32
                  box_coord(double(p.z), G.inv_h, &cnew[2]);
         } else {
             const uint32_t i = b.perm[t];
-            const V4<T> p = pin[i];
+            V4<T> p = spos_ptr(b)[t];      // own state, from the slot-ordered copy
             const uint32_t f = fin[i];
             const uint32_t out = RELAYOUT ? t : i;
             uint32_t q[3];
             if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
-            const uint32_t stamp = b.g->stamp;
+            unsigned long long e[27];
+            load_boxes(b, G, q, b.g->stamp, e);
             // at step 0 every agent carries the moved bit, so none is static
-            if (STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u) {
-                const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
-                const double r2 = G.r2;
-                is_static = visit_boxes(b, G, q, stamp, true, [&](uint32_t j) {
-                    if (j == i || !(fin[j] & kMovedBit)) return true;
-                    const V4<T> pj = pin[j];
-                    const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
-                    return !(((ex * ex + ey * ey) + ez * ez) < r2);
-                });
-            }
+            if (STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u) is_static = no_moved_neighbour(b, G, t, p, e);
+            p.w = T(fabs(double(p.w)));
             V4<T> np = p;
             uint32_t nf;
             if (is_static) {
@@ -66,7 +59,7 @@ __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32
                     for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
             } else {
                 ForceSum acc;
-                force_of<T, false>(b, G, pin, i, p, q, stamp, acc);
+                force_of<T, false>(b, G, t, p, e, acc);
                 const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
                 np.x = T(double(p.x) + m.ux);
                 np.y = T(double(p.y) + m.uy);
@@ -88,11 +81,13 @@ __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32
         }
         if (!ok) raise_error(b.g, kErrNonfinite);
     }
-    bbox_accumulate(b.sims, sim, a.parity ^ 1, active && ok, cnew);
-    const unsigned long long ns = __ballot(active && is_static), nm = __ballot(active && moved);
-    if (lane_id() == 0 && (ns | nm)) {
-        if (ns) atomicAdd(&b.g->n_static[a.parity], (unsigned long long)__popcll(ns));
-        if (nm) atomicAdd(&b.g->n_moved[a.parity], (unsigned long long)__popcll(nm));
+    bbox_fold_block(sim, active && ok, cnew, [&](int sm) { return bbox_replica(b, a.parity ^ 1, sm); });
+    const int ns = __syncthreads_count(active && is_static);
+    const int nm = __syncthreads_count(active && moved);
+    if (threadIdx.x == 0 && (ns | nm)) {
+        unsigned long long* st = b.g->stats[a.parity][blockIdx.x % kReplicas];
+        if (ns) atomicAdd(&st[0], (unsigned long long)ns);
+        if (nm) atomicAdd(&st[1], (unsigned long long)nm);
     }
 }
 

@@ -1,47 +1,22 @@
 // force_loop.h -- the 27-box neighbour walk and the pair force, shared by the
 // step kernel and the reverse-mode kernels.
+//
+// The walk reads the slot-ordered copy `spos` that the grid build writes:
+// slot u holds {x, y, z, d} of the u-th agent in canonical (box rank, id)
+// order, with the sign of d set when that agent moved in the last step.  A
+// box's agents are a contiguous slot range, so a candidate costs one load.
 #pragma once
 
 #include "abm_device.h"
 
 namespace abm {
 
-// Visit the agents of the 27 boxes around box q (boxes outside the space are
-// skipped; Section 3.1), boxes in lexicographic (dz, dy, dx) order and the
-// agents of a box in canonical (id) order.  Boxes whose table entry carries
-// another step's stamp are empty.  With only_moved, boxes without a moved
-// agent are skipped too.  fn(storage index) returns false to stop the walk;
-// visit_boxes then returns false.
-template <class T, class Fn>
-__device__ __forceinline__ bool visit_boxes(const Buffers<T>& b, const SimGrid& G, const uint32_t q[3],
-                                            uint32_t stamp, bool only_moved, Fn&& fn) {
-    const uint32_t dx = G.dims[0], dy = G.dims[1], dz = G.dims[2];
-    const uint32_t st15 = stamp & 0x7FFFu;
-    for (int oz = -1; oz <= 1; ++oz) {
-        const int64_t z = int64_t(q[2]) + oz;
-        if (z < 0 || z >= int64_t(dz)) continue;
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int64_t y = int64_t(q[1]) + oy;
-            if (y < 0 || y >= int64_t(dy)) continue;
-            const uint32_t row = G.box_base + (uint32_t(z) * dy + uint32_t(y)) * dx;
-            for (int ox = -1; ox <= 1; ++ox) {
-                const int64_t x = int64_t(q[0]) + ox;
-                if (x < 0 || x >= int64_t(dx)) continue;
-                const unsigned long long e = b.cellinfo[row + uint32_t(x)];
-                if (cell_stamp_of(e) != st15) continue;
-                if (only_moved && !cell_moved_of(e)) continue;
-                const uint32_t s0 = cell_start_of(e), s1 = s0 + cell_count_of(e);
-                for (uint32_t u = s0; u < s1; ++u) {
-                    const uint32_t j = b.perm[u];
-                    if (j < b.n && !fn(j)) return false;
-                }
-            }
-        }
-    }
-    return true;
+template <class T>
+__device__ __forceinline__ const V4<T>* spos_ptr(const Buffers<T>& b) {
+    return reinterpret_cast<const V4<T>*>(b.spos);
 }
 
-// Box coordinates of a stored position relative to the simulation's grid.
+// Box coordinates of a position relative to the simulation's grid.
 template <class T>
 __device__ __forceinline__ bool box_of(const SimGrid& G, const V4<T>& p, uint32_t q[3]) {
     int32_t c[3];
@@ -57,6 +32,44 @@ __device__ __forceinline__ bool box_of(const SimGrid& G, const V4<T>& p, uint32_
     return in;
 }
 
+// Table entries of the 27 boxes around box q (Section 3.1: the query box and
+// its 26 neighbours), in lexicographic (dz, dy, dx) order.  All 27 loads are
+// issued before any is used.  Boxes outside the space, and boxes whose entry
+// carries another step's stamp (empty this step), read as 0.
+template <class T>
+__device__ __forceinline__ void load_boxes(const Buffers<T>& b, const SimGrid& G, const uint32_t q[3],
+                                           uint32_t stamp, unsigned long long e[27]) {
+    const uint32_t dx = G.dims[0], dy = G.dims[1], dz = G.dims[2];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+        const int ox = k % 3 - 1, oy = (k / 3) % 3 - 1, oz = k / 9 - 1;
+        const int64_t x = int64_t(q[0]) + ox, y = int64_t(q[1]) + oy, z = int64_t(q[2]) + oz;
+        const bool in = x >= 0 && x < int64_t(dx) && y >= 0 && y < int64_t(dy) && z >= 0 && z < int64_t(dz);
+        const uint32_t idx = G.box_base + (uint32_t(z) * dy + uint32_t(y)) * dx + uint32_t(x);
+        e[k] = in ? b.cellinfo[idx] : 0ull;
+    }
+    const uint32_t st15 = stamp & 0x7FFFu;
+#pragma unroll
+    for (int k = 0; k < 27; ++k)
+        if (cell_stamp_of(e[k]) != st15) e[k] = 0ull;
+}
+
+// Visit the slots of the boxes in e (in order; agents of a box in canonical
+// order).  With only_moved, boxes without a moved agent are skipped.  fn(slot)
+// returns false to stop; visit_slots then returns false.
+template <class Fn>
+__device__ __forceinline__ bool visit_slots(const unsigned long long e[27], bool only_moved, Fn&& fn) {
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+        const unsigned long long v = e[k];
+        if (only_moved && !cell_moved_of(v)) continue;
+        const uint32_t s0 = cell_start_of(v), s1 = s0 + cell_count_of(v);
+        for (uint32_t u = s0; u < s1; ++u)
+            if (!fn(u)) return false;
+    }
+    return true;
+}
+
 struct ForceSum {
     double fx = 0.0, fy = 0.0, fz = 0.0;   // F_i
     double kx = 0.0, ky = 0.0, kz = 0.0;   // dF_i/dk    = sum_j delta_ij u_ij
@@ -67,21 +80,22 @@ struct ForceSum {
 // F_i over the neighbours j (|e|^2 < R^2) in contact (0 < |e| < r_i + r_j):
 // f = k delta - gamma sqrt(rho delta) along e / |e| (the force-law reading of
 // Section 5).  Evaluated in double, without fused multiply-adds (the library
-// is built with contraction off), in the visiting order of visit_boxes.
+// is built with contraction off), in the visiting order of visit_slots.
+// `self` is the agent's own slot.
 template <class T, bool PARAM_GRADS>
-__device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, const V4<T>* __restrict__ pos,
-                                         uint32_t i, const V4<T>& p, const uint32_t q[3], uint32_t stamp,
-                                         ForceSum& acc) {
+__device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, uint32_t self, const V4<T>& p,
+                                         const unsigned long long e[27], ForceSum& acc) {
+    const V4<T>* __restrict__ sp = spos_ptr(b);
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
-    const double ri = 0.5 * double(p.w);
+    const double ri = 0.5 * fabs(double(p.w));
     const double r2 = G.r2, k = G.k, gamma = G.gamma;
-    visit_boxes(b, G, q, stamp, false, [&](uint32_t j) {
-        if (j == i) return true;
-        const V4<T> pj = pos[j];
+    visit_slots(e, false, [&](uint32_t u) {
+        if (u == self || u >= b.n) return true;
+        const V4<T> pj = sp[u];
         const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
         const double s2 = (ex * ex + ey * ey) + ez * ez;
         if (!(s2 < r2)) return true;
-        const double rj = 0.5 * double(pj.w);
+        const double rj = 0.5 * fabs(double(pj.w));
         const double S = ri + rj;
         if (!(s2 > 0.0) || !(s2 < S * S)) return true;
         const double dist = sqrt(s2);
@@ -104,6 +118,23 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
             acc.gz -= sr * uz;
         }
         return true;
+    });
+}
+
+// Static test of Section 5 for an agent that itself did not move and had at
+// most one non-zero pair term: true if no agent within R of it moved.
+template <class T>
+__device__ __forceinline__ bool no_moved_neighbour(const Buffers<T>& b, const SimGrid& G, uint32_t self,
+                                                   const V4<T>& p, const unsigned long long e[27]) {
+    const V4<T>* __restrict__ sp = spos_ptr(b);
+    const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
+    const double r2 = G.r2;
+    return visit_slots(e, true, [&](uint32_t u) {
+        if (u == self || u >= b.n) return true;
+        const V4<T> pj = sp[u];
+        if (!(pj.w < T(0))) return true;   // the sign of d carries the moved flag
+        const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
+        return !(((ex * ex + ey * ey) + ez * ez) < r2);
     });
 }
 

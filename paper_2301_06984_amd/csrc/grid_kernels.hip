@@ -44,10 +44,16 @@ void launch_pack(const Buffers<T>& b, const T* pos, const T* diam, hipStream_t s
 template <class T>
 __global__ void k_radius(Buffers<T> b, int cur) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= b.n) return;
-    const double d = double(pos4_ptr(b, cur)[i].w);
-    if (d > 0.0 && isfinite(d))
-        atomicMax(&b.sims[sim_index(b, i)].radius_bits, (unsigned long long)__double_as_longlong(d));
+    bool active = i < b.n;
+    int sim = 0;
+    unsigned long long v = 0;
+    if (active) {
+        sim = sim_index(b, i);
+        const double d = double(pos4_ptr(b, cur)[i].w);
+        active = d > 0.0 && isfinite(d);
+        v = (unsigned long long)__double_as_longlong(d);
+    }
+    max_fold_block(sim, active, v, [&](int s) { return &b.sims[s].radius_bits; });
 }
 
 template <class T>
@@ -74,20 +80,29 @@ void launch_finish_radius(const Buffers<T>& b, hipStream_t s) {
     hipLaunchKernelGGL(k_finish_radius, dim3((b.nsims + 255) / 256), dim3(256), 0, s, b.sims, b.nsims);
 }
 
-__global__ void k_reset_bbox(SimGrid* sims, int nsims, int slot);
-
 // Extent of caller-layout positions (n x 3 + diameters) for sizing a grid:
-// largest diameter, then box coordinates in the first bbox accumulator.
+// largest diameter, then box coordinates into SimGrid::bbox[0].
 template <class T>
 __global__ void k_extent_radius(const T* __restrict__ diam, uint32_t n, Globals* g, SimGrid* sim) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double d = double(diam[i]);
-    if (!(d > 0.0) || !isfinite(d)) {
-        raise_error(g, kErrNonfinite);
-        return;
+    bool active = i < n;
+    unsigned long long v = 0;
+    if (active) {
+        const double d = double(diam[i]);
+        if (!(d > 0.0) || !isfinite(d)) {
+            raise_error(g, kErrNonfinite);
+            active = false;
+        }
+        v = (unsigned long long)__double_as_longlong(d);
     }
-    atomicMax(&sim->radius_bits, (unsigned long long)__double_as_longlong(d));
+    max_fold_block(0, active, v, [&](int) { return &sim->radius_bits; });
+}
+
+__global__ void k_extent_reset(SimGrid* sim) {
+    for (int a = 0; a < 3; ++a) {
+        sim->bbox[0][a] = INT32_MAX;
+        sim->bbox[0][3 + a] = INT32_MIN;
+    }
 }
 
 template <class T>
@@ -105,7 +120,7 @@ __global__ void k_extent_bbox(const T* __restrict__ pos, uint32_t n, Globals* g,
             active = false;
         }
     }
-    bbox_accumulate(sim, 0, 0, active, c);
+    bbox_fold_block(0, active, c, [&](int) { return sim->bbox[0]; });
 }
 
 template <class T>
@@ -113,7 +128,7 @@ void launch_extent(const T* pos, const T* diam, uint32_t n, Globals* g, SimGrid*
     const uint32_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_extent_radius<T>, dim3(blocks), dim3(256), 0, s, diam, n, g, sim);
     hipLaunchKernelGGL(k_finish_radius, dim3(1), dim3(64), 0, s, sim, 1);
-    hipLaunchKernelGGL(k_reset_bbox, dim3(1), dim3(64), 0, s, sim, 1, 0);
+    hipLaunchKernelGGL(k_extent_reset, dim3(1), dim3(1), 0, s, sim);
     hipLaunchKernelGGL(k_extent_bbox<T>, dim3(blocks), dim3(256), 0, s, pos, n, g, sim);
 }
 
@@ -147,18 +162,22 @@ void launch_set_params(SimGrid* sims, int nsims, double k, double gamma, double 
                        delta_max);
 }
 
-__global__ void k_reset_bbox(SimGrid* sims, int nsims, int slot) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsims) return;
+// Set every replica of one bbox slot to the empty box.
+__global__ void k_reset_bbox(int32_t* rep, int nsims, int slot) {
+    const size_t per = size_t(kReplicas) * size_t(nsims);
+    const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= per) return;
+    int32_t* t = rep + (size_t(slot) * per + e) * 6;
     for (int a = 0; a < 3; ++a) {
-        sims[s].bbox[slot][a] = INT32_MAX;
-        sims[s].bbox[slot][3 + a] = INT32_MIN;
+        t[a] = INT32_MAX;
+        t[3 + a] = INT32_MIN;
     }
 }
 
 template <class T>
 void launch_reset_bbox(const Buffers<T>& b, int parity, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_bbox, dim3((b.nsims + 255) / 256), dim3(256), 0, s, b.sims, b.nsims, parity);
+    const uint32_t per = uint32_t(kReplicas) * uint32_t(b.nsims);
+    hipLaunchKernelGGL(k_reset_bbox, dim3((per + 255) / 256), dim3(256), 0, s, b.bbox_rep, b.nsims, parity);
 }
 
 template <class T>
@@ -178,12 +197,12 @@ __global__ void k_bbox(Buffers<T> b, int cur, int slot) {
             active = false;
         }
     }
-    bbox_accumulate(b.sims, sim, slot, active, c);
+    bbox_fold_block(sim, active, c, [&](int s) { return bbox_replica(b, slot, s); });
 }
 
 template <class T>
 void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_bbox, dim3((b.nsims + 255) / 256), dim3(256), 0, s, b.sims, b.nsims, parity);
+    launch_reset_bbox<T>(b, parity, s);
     const uint32_t blocks = (b.n + 255) / 256;
     hipLaunchKernelGGL(k_bbox<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, parity);
 }
@@ -195,18 +214,35 @@ void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s) {
 // move kernel and the step statistics.
 constexpr int kSetupThreads = 1024;
 
-__global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int nsims, int parity,
-                                                           uint32_t box_capacity) {
+__global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int32_t* rep, int nsims,
+                                                           int parity, uint32_t box_capacity) {
     __shared__ uint32_t s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
     if (threadIdx.x == 0) s_carry = 0;
+    // the other accumulator slot and this step's statistics start empty
+    const size_t per = size_t(kReplicas) * size_t(nsims);
+    for (size_t e = threadIdx.x; e < per; e += kSetupThreads) {
+        int32_t* t = rep + (size_t(parity ^ 1) * per + e) * 6;
+        for (int a = 0; a < 3; ++a) {
+            t[a] = INT32_MAX;
+            t[3 + a] = INT32_MIN;
+        }
+    }
+    for (int e = int(threadIdx.x); e < kReplicas * 2; e += kSetupThreads) g->stats[parity][e >> 1][e & 1] = 0ull;
     __syncthreads();
     for (int chunk = 0; chunk < nsims; chunk += kSetupThreads) {
         const int s = chunk + int(threadIdx.x);
         uint32_t nb = 0;
         if (s < nsims) {
             SimGrid& G = sims[s];
-            const int32_t* bb = G.bbox[parity];
+            int32_t bb[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
+            for (int r = 0; r < kReplicas; ++r) {
+                const int32_t* t = rep + ((size_t(parity) * kReplicas + r) * size_t(nsims) + s) * 6;
+                for (int a = 0; a < 3; ++a) {
+                    bb[a] = min(bb[a], t[a]);
+                    bb[3 + a] = max(bb[3 + a], t[3 + a]);
+                }
+            }
             bool ok = true;
             uint64_t total = 1;
             int levels = 0;
@@ -226,10 +262,6 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
             G.nboxes = ok ? uint32_t(total) : 0u;
             nb = G.nboxes;
             if (!ok) raise_error(g, kErrGrid);
-            for (int a = 0; a < 3; ++a) {
-                G.bbox[parity ^ 1][a] = INT32_MAX;
-                G.bbox[parity ^ 1][3 + a] = INT32_MIN;
-            }
         }
         // block exclusive scan of nb
         uint32_t x = nb;
@@ -261,14 +293,13 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
         // step's scan status words
         g->stamp = g->stamp + 1;
         g->scan_epoch = (g->scan_epoch % 0x3FFFFFFFu) + 1;
-        g->n_static[parity] = 0;
-        g->n_moved[parity] = 0;
     }
 }
 
 template <class T>
 void launch_setup(const Buffers<T>& b, int parity, hipStream_t s) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, b.g, b.sims, b.nsims, parity, b.box_capacity);
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, b.g, b.sims, b.bbox_rep, b.nsims, parity,
+                       b.box_capacity);
 }
 
 // ------------------------------------------------------------------ keys
@@ -312,18 +343,21 @@ __device__ __forceinline__ uint32_t wave_inclusive(uint32_t x) {
 }
 
 // Exclusive scan of count[0, total) into cell_start[0, total], zeroing count.
-// Tiles take their position from a ticket, so a tile only waits on tiles that
-// already run; each tile publishes its aggregate, then its inclusive prefix
-// (status word: epoch | flag | value), and sums its predecessors' words.
+// Tile b covers boxes [b * kScanTile, (b + 1) * kScanTile).  Tiles run in
+// launch order, so a tile only waits on tiles that were dispatched before it;
+// each tile publishes its aggregate, then its inclusive prefix (status word:
+// epoch | flag | value), and sums its predecessors' words (decoupled
+// look-back).  Global loads and stores are striped across the block and
+// transposed through LDS, so every wave touches whole cache lines.
+__device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
+
 __global__ __launch_bounds__(kScanThreads) void k_scan(Globals* g, uint32_t* __restrict__ count,
                                                         uint32_t* __restrict__ cell_start,
                                                         unsigned long long* status, uint32_t ntiles) {
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
     __shared__ uint32_t s_wave[kScanThreads / 64];
     __shared__ uint32_t s_prefix;
-    if (threadIdx.x == 0) s_tile = uint32_t(atomicAdd(&g->scan_ticket, 1ull) % ntiles);
-    __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = blockIdx.x;
     const uint32_t total = g->total_boxes;
     const uint32_t epoch = g->scan_epoch;
     const uint32_t needed = (total + kScanTile - 1) / kScanTile;
@@ -332,19 +366,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Globals* g, uint32_t* __r
         return;
     }
     if (tile >= needed) return;   // no tile waits on a later one
-    const uint32_t first = tile * kScanTile + threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    if (first + kScanItems <= total) {
-        const uint4* src = reinterpret_cast<const uint4*>(count + first);
-        for (int k = 0; k < kScanItems / 4; ++k) {
-            const uint4 u = src[k];
-            v[4 * k] = u.x; v[4 * k + 1] = u.y; v[4 * k + 2] = u.z; v[4 * k + 3] = u.w;
+    const uint32_t base = tile * kScanTile;
+    // striped load: uint4 number k * threads + tid of the tile
+    for (int k = 0; k < kScanItems / 4; ++k) {
+        const uint32_t e4 = uint32_t(k) * kScanThreads + threadIdx.x;
+        const uint32_t g0 = base + 4 * e4;
+        uint32_t c4[4];
+        if (g0 + 4 <= total) {
+            const uint4 u = reinterpret_cast<const uint4*>(count)[g0 >> 2];
+            c4[0] = u.x; c4[1] = u.y; c4[2] = u.z; c4[3] = u.w;
+        } else {
+            for (int c = 0; c < 4; ++c) c4[c] = g0 + c < total ? count[g0 + c] : 0u;
         }
-    } else {
-        for (int k = 0; k < kScanItems; ++k) v[k] = first + k < total ? count[first + k] : 0u;
+        for (int c = 0; c < 4; ++c) s_data[lds_pad(4 * e4 + c)] = c4[c];
     }
+    __syncthreads();
+    uint32_t v[kScanItems];
     uint32_t sum = 0;
-    for (int k = 0; k < kScanItems; ++k) sum += v[k];
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = s_data[lds_pad(threadIdx.x * kScanItems + k)];
+        sum += v[k];
+    }
     const uint32_t incl = wave_inclusive(sum);
     const int wave = int(threadIdx.x >> 6);
     if (lane_id() == 63) s_wave[wave] = incl;
@@ -354,58 +396,81 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Globals* g, uint32_t* __r
         if (w < wave) wave_off += s_wave[w];
         agg += s_wave[w];
     }
-    if (threadIdx.x == 0) {
-        const unsigned long long tag = (unsigned long long)(epoch & 0x3FFFFFFFu) << 34;
+    // Look-back by the first wave: lane l reads the status of the l-th
+    // predecessor; the window advances 64 tiles at a time until it contains
+    // an inclusive prefix, and every tile up to that one has published.
+    if (wave == 0) {
+        const int lane = lane_id();
+        const uint32_t ep = epoch & 0x3FFFFFFFu;
+        const unsigned long long tag = (unsigned long long)ep << 34;
         uint32_t prefix = 0;
         if (tile == 0) {
-            __hip_atomic_store(&status[0], tag | (2ull << 32) | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&status[0], tag | (2ull << 32) | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(&status[tile], tag | (1ull << 32) | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            int64_t p = int64_t(tile) - 1;
+            if (lane == 0)
+                __hip_atomic_store(&status[tile], tag | (1ull << 32) | agg, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            int64_t back = int64_t(tile) - 1;
             uint32_t spins = 0;
-            while (p >= 0) {
-                const unsigned long long w =
-                    __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t flag = uint32_t(w >> 32) & 3u;
-                if (uint32_t(w >> 34) != (epoch & 0x3FFFFFFFu) || flag == 0) {
-                    if (++spins > (1u << 26)) {   // a predecessor never published: give up loudly
-                        raise_error(g, kErrInternal);
+            while (true) {
+                const int64_t p = back - lane;
+                uint32_t flag = 2u, val = 0u;   // before the first tile: an inclusive prefix of 0
+                if (p >= 0) {
+                    const unsigned long long w =
+                        __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    flag = uint32_t(w >> 34) == ep ? (uint32_t(w >> 32) & 3u) : 0u;
+                    val = uint32_t(w);
+                }
+                const unsigned long long incl_m = __ballot(flag == 2u);
+                const unsigned long long ready = __ballot(flag != 0u);
+                const int stop = incl_m ? __ffsll((long long)incl_m) - 1 : 63;
+                const unsigned long long need = (2ull << stop) - 1ull;
+                if ((ready & need) != need) {
+                    if (++spins > (1u << 24)) {   // a predecessor never published: give up loudly
+                        if (lane == 0) raise_error(g, kErrInternal);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
                     continue;
                 }
-                prefix += uint32_t(w);
-                if (flag == 2) break;
-                --p;
+                uint32_t part = lane <= stop ? val : 0u;
+                for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+                prefix += part;
+                if (incl_m) break;
+                back -= 64;
             }
-            __hip_atomic_store(&status[tile], tag | (2ull << 32) | (prefix + agg), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&status[tile], tag | (2ull << 32) | (prefix + agg), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_prefix = prefix;
-        if (tile == needed - 1) cell_start[total] = prefix + agg;
+        if (lane == 0) {
+            s_prefix = prefix;
+            if (tile == needed - 1) cell_start[total] = prefix + agg;
+        }
     }
     __syncthreads();
+    // blocked exclusive prefixes back into LDS, then striped stores
     uint32_t run = s_prefix + wave_off + incl - sum;
-    if (first + kScanItems <= total) {
-        uint4* dst = reinterpret_cast<uint4*>(cell_start + first);
-        uint4* zero = reinterpret_cast<uint4*>(count + first);
-        for (int k = 0; k < kScanItems / 4; ++k) {
-            uint4 o;
-            o.x = run; run += v[4 * k];
-            o.y = run; run += v[4 * k + 1];
-            o.z = run; run += v[4 * k + 2];
-            o.w = run; run += v[4 * k + 3];
-            dst[k] = o;
-            zero[k] = make_uint4(0u, 0u, 0u, 0u);
-        }
-    } else {
-        for (int k = 0; k < kScanItems; ++k) {
-            if (first + k < total) {
-                cell_start[first + k] = run;
-                count[first + k] = 0u;
-            }
-            run += v[k];
+    for (int k = 0; k < kScanItems; ++k) {
+        s_data[lds_pad(threadIdx.x * kScanItems + k)] = run;
+        run += v[k];
+    }
+    __syncthreads();
+    for (int k = 0; k < kScanItems / 4; ++k) {
+        const uint32_t e4 = uint32_t(k) * kScanThreads + threadIdx.x;
+        const uint32_t g0 = base + 4 * e4;
+        uint32_t o[4];
+        for (int c = 0; c < 4; ++c) o[c] = s_data[lds_pad(4 * e4 + c)];
+        if (g0 + 4 <= total) {
+            reinterpret_cast<uint4*>(cell_start)[g0 >> 2] = make_uint4(o[0], o[1], o[2], o[3]);
+            reinterpret_cast<uint4*>(count)[g0 >> 2] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (int c = 0; c < 4; ++c)
+                if (g0 + c < total) {
+                    cell_start[g0 + c] = o[c];
+                    count[g0 + c] = 0u;
+                }
         }
     }
 }
@@ -468,6 +533,9 @@ __global__ void k_fixup(Buffers<T> b, int cur, int ids_cur) {
         return;
     }
     b.perm[st + r] = i;
+    V4<T> p = pos4_ptr(b, cur)[i];
+    if (fl[i] & kMovedBit) p.w = -p.w;
+    reinterpret_cast<V4<T>*>(b.spos)[st + r] = p;
     if (r == 0) {
         uint32_t cnt = en - st;
         if (cnt > 0xFFFFu) {
@@ -495,13 +563,20 @@ void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s) {
 }
 
 template <class T>
-void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s) {
+void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s, hipEvent_t* const* marks) {
     const uint32_t blocks = (b.n + 255) / 256;
+    auto mark = [&](int k) {
+        if (marks) (void)hipEventRecord(*marks[k], s);
+    };
     hipLaunchKernelGGL(k_keys<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur);
+    mark(0);
     hipLaunchKernelGGL(k_scan, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start,
                        b.scan_status, b.scan_tiles);
+    mark(1);
     hipLaunchKernelGGL(k_scatter<T>, dim3(blocks), dim3(256), 0, s, b);
+    mark(2);
     hipLaunchKernelGGL(k_fixup<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, ids_cur);
+    mark(3);
 }
 
 #define ABM_INSTANTIATE(T)                                                                                 \
@@ -513,7 +588,7 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s) {
     template void launch_bbox<T>(const Buffers<T>&, int, int, hipStream_t);                              \
     template void launch_reset_bbox<T>(const Buffers<T>&, int, hipStream_t);                             \
     template void launch_setup<T>(const Buffers<T>&, int, hipStream_t);                                  \
-    template void launch_grid<T>(const Buffers<T>&, int, int, hipStream_t);                              \
+    template void launch_grid<T>(const Buffers<T>&, int, int, hipStream_t, hipEvent_t* const*);         \
     template void launch_clear_cellinfo<T>(const Buffers<T>&, hipStream_t);
 
 ABM_INSTANTIATE(float)

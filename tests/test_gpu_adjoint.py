@@ -55,18 +55,27 @@ def test_adjoint_fd_fp64():
         x = sim.query("positions").cpu().numpy()
         return float(np.mean((x - target) ** 2))
 
+    # Central differences at h and h/4; their difference estimates the FD
+    # truncation error (large near grazing contacts, where f'(delta) ~ delta^-1/2).
     for name, idx in (("k", 0), ("gamma", 1)):
         base = 2.0 if name == "k" else 1.0
-        h = 1e-6 * base
-        fd = (L(**{name: base + h}) - L(**{name: base - h})) / (2 * h)
-        assert abs(fd - gp[idx]) <= 1e-6 * abs(fd) + 1e-12, (name, fd, gp[idx])
+
+        def fd_at(h):
+            return (L(**{name: base + h}) - L(**{name: base - h})) / (2 * h)
+
+        f1, f4 = fd_at(1e-6 * base), fd_at(0.25e-6 * base)
+        tol = 1e-7 * abs(f4) + 2.0 * abs(f1 - f4) + 1e-10
+        assert abs(f4 - gp[idx]) <= tol, (name, f1, f4, gp[idx])
     g = np.random.default_rng(3)
     for c in g.choice(pos.size, 16, replace=False):
-        pp = pos.copy().ravel(); pp[c] += 1e-6
-        pm = pos.copy().ravel(); pm[c] -= 1e-6
-        fd = (L(pp.reshape(-1, 3)) - L(pm.reshape(-1, 3))) / 2e-6
+        def fd_x(h):
+            pp = pos.copy().ravel(); pp[c] += h
+            pm = pos.copy().ravel(); pm[c] -= h
+            return (L(pp.reshape(-1, 3)) - L(pm.reshape(-1, 3))) / (2 * h)
+
+        f1, f4 = fd_x(1e-6), fd_x(0.25e-6)
         an = gx0.ravel()[c]
-        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-9, (c, fd, an)
+        assert abs(f4 - an) <= 1e-6 * abs(an) + 2.0 * abs(f1 - f4) + 1e-9, (c, f1, f4, an)
 
 
 def test_stepfn_autograd():

@@ -20,6 +20,8 @@ template <class T>
 __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, const double* __restrict__ lam,
                                                         double* __restrict__ w) {
     __shared__ double s_k[kAdjThreads], s_g[kAdjThreads];
+    extern __shared__ __align__(16) unsigned char s_walk[];
+    const WalkLds L = walk_lds(s_walk);
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     double gk = 0.0, gg = 0.0;
     const uint32_t i = t < b.n ? b.perm[t] : 0xFFFFFFFFu;
@@ -30,10 +32,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, co
         uint32_t q[3];
         double wi[3] = {0.0, 0.0, 0.0};
         if (G.valid && box_of<T>(G, p, q)) {
-            unsigned long long e[27];
-            load_boxes(b, G, q, b.g->stamp, e);
+            unsigned long long e[8];
+            load_ranges(b, G, q, b.g->stamp, e);
             ForceSum acc;
-            force_of<T, true>(b, G, t, p, e, acc);
+            force_of<T, true>(b, G, t, p, e, L, acc);
             const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
             if (m.moves) {
                 const double li[3] = {lam[3 * size_t(i)], lam[3 * size_t(i) + 1], lam[3 * size_t(i) + 2]};
@@ -87,12 +89,12 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
     uint32_t q[3];
     double acc[3] = {lam[3 * size_t(m)], lam[3 * size_t(m) + 1], lam[3 * size_t(m) + 2]};
     if (G.valid && box_of<T>(G, p, q)) {
-        unsigned long long e[27];
-        load_boxes(b, G, q, b.g->stamp, e);
+        unsigned long long e[8];
+        load_ranges(b, G, q, b.g->stamp, e);
         const double xm = double(p.x), ym = double(p.y), zm = double(p.z);
         const double rm = 0.5 * fabs(double(p.w));
         const double wm[3] = {w[3 * size_t(m)], w[3 * size_t(m) + 1], w[3 * size_t(m) + 2]};
-        visit_slots(e, false, [&](uint32_t u) {
+        visit_ranges(e, [&](uint32_t u) {
             if (u == t || u >= b.n) return true;
             const uint32_t j = b.perm[u];
             if (j >= b.n) return true;
@@ -166,7 +168,8 @@ void launch_permute3(const uint32_t* ids, uint32_t n, const double* in, double* 
 
 template <class T>
 void launch_adj_w(const Buffers<T>& b, int pos_cur, const double* lam, double* w, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_w<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), 0, s, b, pos_cur, lam, w);
+    hipLaunchKernelGGL(k_adj_w<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b, pos_cur,
+                       lam, w);
 }
 
 template <class T>

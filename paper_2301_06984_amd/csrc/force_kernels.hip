@@ -13,15 +13,19 @@ namespace abm {
 // an agent that did not move, had at most one non-zero pair term, and has no
 // moved neighbour within R keeps its force and does not move.  The new
 // positions' box extent is reduced here for the next step's grid.
-template <class T, bool STATIC_ON, bool KEEP_F, bool RELAYOUT>
+template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT>
 __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32_t launched) {
+    extern __shared__ __align__(16) unsigned char s_walk[];
+    const WalkLds L = walk_lds(s_walk);
     const uint32_t t = xcd_block(launched) * blockDim.x + threadIdx.x;
     bool active = t < b.n;
     bool ok = false, is_static = false, moved = false;
     int sim = 0;
     int32_t cnew[3] = {0, 0, 0};
+    const bool KEEP_F = a.keep_forces;
     if (active) {
-        sim = sim_index(b, t);
+        // one simulation: its parameters are the same for every lane
+        sim = BATCHED ? sim_index(b, t) : 0;
         const SimGrid& G = b.sims[sim];
         const int cur = a.pos_cur, nxt = cur ^ 1;
         const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
@@ -46,10 +50,10 @@ __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32
             const uint32_t out = RELAYOUT ? t : i;
             uint32_t q[3];
             if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
-            unsigned long long e[27];
-            load_boxes(b, G, q, b.g->stamp, e);
+            unsigned long long e[8];
+            load_ranges(b, G, q, b.g->stamp, e);
             // at step 0 every agent carries the moved bit, so none is static
-            if (STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u) is_static = no_moved_neighbour(b, G, t, p, e);
+            if (STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u) is_static = no_moved_neighbour(b, G, t, p, e, L);
             p.w = T(fabs(double(p.w)));
             V4<T> np = p;
             uint32_t nf;
@@ -59,7 +63,7 @@ __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32
                     for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
             } else {
                 ForceSum acc;
-                force_of<T, false>(b, G, t, p, e, acc);
+                force_of<T, false>(b, G, t, p, e, L, acc);
                 const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
                 np.x = T(double(p.x) + m.ux);
                 np.y = T(double(p.y) + m.uy);
@@ -96,12 +100,12 @@ static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s
     const int bs = a.block_size;
     const uint32_t blocks = (b.n + bs - 1) / bs;
     const uint32_t launched = xcd_grid(blocks);
-    hipLaunchKernelGGL((k_force<T, S, K, R>), dim3(launched), dim3(bs), 0, s, b, a, launched);
+    hipLaunchKernelGGL((k_force<T, S, K, R>), dim3(launched), dim3(bs), walk_lds_bytes(bs), s, b, a, launched);
 }
 
 template <class T>
 void launch_force(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
-    const int v = (a.detect_static ? 4 : 0) | (a.keep_forces ? 2 : 0) | (a.relayout ? 1 : 0);
+    const int v = (b.sim_of ? 4 : 0) | (a.detect_static ? 2 : 0) | (a.relayout ? 1 : 0);
     switch (v) {
         case 0: launch_force_v<T, false, false, false>(b, a, s); break;
         case 1: launch_force_v<T, false, false, true>(b, a, s); break;

@@ -3,10 +3,10 @@
 //   bbox     box extent of the agents (per simulation)
 //   setup    dims, box counts and box bases of every simulation
 //   keys     box key of every agent + histogram (atomics)
-//   scan     single-pass exclusive scan with decoupled look-back
+//   scan     exclusive scan of the box counts (tile sums, their scan, rescan)
 //   scatter  agents into box order (arrival order inside a box)
 //   fixup    canonical (box, id) order inside each box + row-major box table
-#include "abm_device.h"
+#include "force_loop.h"
 
 namespace abm {
 
@@ -342,32 +342,17 @@ __device__ __forceinline__ uint32_t wave_inclusive(uint32_t x) {
     return x;
 }
 
-// Exclusive scan of count[0, total) into cell_start[0, total], zeroing count.
-// Tile b covers boxes [b * kScanTile, (b + 1) * kScanTile).  Tiles run in
-// launch order, so a tile only waits on tiles that were dispatched before it;
-// each tile publishes its aggregate, then its inclusive prefix (status word:
-// epoch | flag | value), and sums its predecessors' words (decoupled
-// look-back).  Global loads and stores are striped across the block and
-// transposed through LDS, so every wave touches whole cache lines.
+// Exclusive scan of count[0, total) into cell_start[0, total], zeroing count,
+// in three passes over tiles of kScanTile boxes: per-tile sums, a one-block
+// scan of the tile sums, and a per-tile rescan that adds the tile's prefix.
+// Global loads and stores are striped across the block and transposed
+// through LDS, so every wave touches whole cache lines.
 __device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan(Globals* g, uint32_t* __restrict__ count,
-                                                        uint32_t* __restrict__ cell_start,
-                                                        unsigned long long* status, uint32_t ntiles) {
-    __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
-    __shared__ uint32_t s_wave[kScanThreads / 64];
-    __shared__ uint32_t s_prefix;
-    const uint32_t tile = blockIdx.x;
-    const uint32_t total = g->total_boxes;
-    const uint32_t epoch = g->scan_epoch;
-    const uint32_t needed = (total + kScanTile - 1) / kScanTile;
-    if (needed > ntiles) {
-        if (tile == 0 && threadIdx.x == 0) raise_error(g, kErrInternal);
-        return;
-    }
-    if (tile >= needed) return;   // no tile waits on a later one
-    const uint32_t base = tile * kScanTile;
-    // striped load: uint4 number k * threads + tid of the tile
+// Load tile `tile` of count into LDS (striped), return this thread's blocked
+// 16 values.
+__device__ __forceinline__ void load_tile(const uint32_t* __restrict__ count, uint32_t base, uint32_t total,
+                                          uint32_t* s_data, uint32_t v[kScanItems]) {
     for (int k = 0; k < kScanItems / 4; ++k) {
         const uint32_t e4 = uint32_t(k) * kScanThreads + threadIdx.x;
         const uint32_t g0 = base + 4 * e4;
@@ -381,77 +366,82 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Globals* g, uint32_t* __r
         for (int c = 0; c < 4; ++c) s_data[lds_pad(4 * e4 + c)] = c4[c];
     }
     __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) v[k] = s_data[lds_pad(threadIdx.x * kScanItems + k)];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Globals* g, const uint32_t* __restrict__ count,
+                                                               uint32_t* __restrict__ tile_sum, uint32_t ntiles) {
+    __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
+    __shared__ uint32_t s_wave[kScanThreads / 64];
+    const uint32_t total = g->total_boxes;
+    const uint32_t tile = blockIdx.x;
+    if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
     uint32_t v[kScanItems];
+    load_tile(count, tile * kScanTile, total, s_data, v);
     uint32_t sum = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = s_data[lds_pad(threadIdx.x * kScanItems + k)];
-        sum += v[k];
+    for (int k = 0; k < kScanItems; ++k) sum += v[k];
+    for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+    if (lane_id() == 0) s_wave[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) t += s_wave[w];
+        tile_sum[tile] = t;
     }
+}
+
+// One block: exclusive scan of the tile sums in place; cell_start[total] = sum.
+constexpr int kTileScanThreads = 1024;
+__global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uint32_t* __restrict__ tile_sum,
+                                                                  uint32_t* __restrict__ cell_start,
+                                                                  uint32_t ntiles) {
+    __shared__ uint32_t s_wave[kTileScanThreads / 64];
+    __shared__ uint32_t s_carry;
+    const uint32_t total = g->total_boxes;
+    const uint32_t needed = (total + kScanTile - 1) / kScanTile;
+    if (needed > ntiles) {
+        if (threadIdx.x == 0) raise_error(g, kErrInternal);
+        return;
+    }
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < needed; base += kTileScanThreads) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t x = i < needed ? tile_sum[i] : 0u;
+        const uint32_t incl = wave_inclusive(x);
+        const int wave = int(threadIdx.x >> 6);
+        if (lane_id() == 63) s_wave[wave] = incl;
+        __syncthreads();
+        uint32_t off = s_carry;
+        for (int w = 0; w < wave; ++w) off += s_wave[w];
+        if (i < needed) tile_sum[i] = off + incl - x;
+        __syncthreads();
+        if (threadIdx.x == kTileScanThreads - 1) s_carry = off + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total > 0) cell_start[total] = s_carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, uint32_t* __restrict__ count,
+                                                             uint32_t* __restrict__ cell_start,
+                                                             const uint32_t* __restrict__ tile_prefix,
+                                                             uint32_t ntiles) {
+    __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
+    __shared__ uint32_t s_wave[kScanThreads / 64];
+    const uint32_t total = g->total_boxes;
+    const uint32_t tile = blockIdx.x;
+    if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
+    const uint32_t base = tile * kScanTile;
+    uint32_t v[kScanItems];
+    load_tile(count, base, total, s_data, v);
+    uint32_t sum = 0;
+    for (int k = 0; k < kScanItems; ++k) sum += v[k];
     const uint32_t incl = wave_inclusive(sum);
     const int wave = int(threadIdx.x >> 6);
     if (lane_id() == 63) s_wave[wave] = incl;
     __syncthreads();
-    uint32_t wave_off = 0, agg = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) {
-        if (w < wave) wave_off += s_wave[w];
-        agg += s_wave[w];
-    }
-    // Look-back by the first wave: lane l reads the status of the l-th
-    // predecessor; the window advances 64 tiles at a time until it contains
-    // an inclusive prefix, and every tile up to that one has published.
-    if (wave == 0) {
-        const int lane = lane_id();
-        const uint32_t ep = epoch & 0x3FFFFFFFu;
-        const unsigned long long tag = (unsigned long long)ep << 34;
-        uint32_t prefix = 0;
-        if (tile == 0) {
-            if (lane == 0)
-                __hip_atomic_store(&status[0], tag | (2ull << 32) | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0)
-                __hip_atomic_store(&status[tile], tag | (1ull << 32) | agg, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            int64_t back = int64_t(tile) - 1;
-            uint32_t spins = 0;
-            while (true) {
-                const int64_t p = back - lane;
-                uint32_t flag = 2u, val = 0u;   // before the first tile: an inclusive prefix of 0
-                if (p >= 0) {
-                    const unsigned long long w =
-                        __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                    flag = uint32_t(w >> 34) == ep ? (uint32_t(w >> 32) & 3u) : 0u;
-                    val = uint32_t(w);
-                }
-                const unsigned long long incl_m = __ballot(flag == 2u);
-                const unsigned long long ready = __ballot(flag != 0u);
-                const int stop = incl_m ? __ffsll((long long)incl_m) - 1 : 63;
-                const unsigned long long need = (2ull << stop) - 1ull;
-                if ((ready & need) != need) {
-                    if (++spins > (1u << 24)) {   // a predecessor never published: give up loudly
-                        if (lane == 0) raise_error(g, kErrInternal);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                uint32_t part = lane <= stop ? val : 0u;
-                for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
-                prefix += part;
-                if (incl_m) break;
-                back -= 64;
-            }
-            if (lane == 0)
-                __hip_atomic_store(&status[tile], tag | (2ull << 32) | (prefix + agg), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane == 0) {
-            s_prefix = prefix;
-            if (tile == needed - 1) cell_start[total] = prefix + agg;
-        }
-    }
-    __syncthreads();
-    // blocked exclusive prefixes back into LDS, then striped stores
-    uint32_t run = s_prefix + wave_off + incl - sum;
+    uint32_t run = tile_prefix[tile] + incl - sum;
+    for (int w = 0; w < wave; ++w) run += s_wave[w];
     for (int k = 0; k < kScanItems; ++k) {
         s_data[lds_pad(threadIdx.x * kScanItems + k)] = run;
         run += v[k];
@@ -501,7 +491,8 @@ template <class T>
 __global__ void k_fixup(Buffers<T> b, int cur, int ids_cur) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= b.n) return;
-    if (!b.sims[sim_index(b, t)].valid) return;   // a simulation's slots are its agents' range
+    const SimGrid& G = b.sims[sim_index(b, t)];   // a simulation's slots are its agents' range
+    if (!G.valid) return;
     const uint32_t i = b.tmp[t];
     if (i >= b.n) {
         raise_error(b.g, kErrInternal);
@@ -518,15 +509,12 @@ __global__ void k_fixup(Buffers<T> b, int cur, int ids_cur) {
         return;
     }
     const uint32_t* ids = b.ids[ids_cur];
-    const uint32_t* fl = b.flags[cur];
     const uint32_t myid = ids[i];
-    const uint32_t stamp = b.g->stamp;
-    uint32_t r = 0, moved = 0;
+    uint32_t r = 0;
     for (uint32_t u = st; u < en; ++u) {
         const uint32_t j = b.tmp[u];
         if (j >= b.n) continue;
         r += ids[j] < myid ? 1u : 0u;
-        moved |= fl[j] & kMovedBit;
     }
     if (st + r >= b.n) {
         raise_error(b.g, kErrInternal);
@@ -534,15 +522,27 @@ __global__ void k_fixup(Buffers<T> b, int cur, int ids_cur) {
     }
     b.perm[st + r] = i;
     V4<T> p = pos4_ptr(b, cur)[i];
-    if (fl[i] & kMovedBit) p.w = -p.w;
+    const V4<T> pq = p;
+    if (b.flags[cur][i] & kMovedBit) p.w = -p.w;
     reinterpret_cast<V4<T>*>(b.spos)[st + r] = p;
     if (r == 0) {
-        uint32_t cnt = en - st;
-        if (cnt > 0xFFFFu) {
-            raise_error(b.g, kErrBoxOverflow);
-            cnt = 0xFFFFu;
+        // the first agent of each box writes its super-box's slot range
+        // (every box of the super-box writes the same entry)
+        uint32_t q[3];
+        if (!box_of<T>(G, pq, q)) {
+            raise_error(b.g, kErrInternal);
+            return;
         }
-        b.cellinfo[b.rmi[i]] = pack_cell(st, cnt, stamp, moved);
+        uint32_t r0, nin;
+        super_rank_range(G, q, c - G.box_base, &r0, &nin);
+        const uint32_t k0 = G.box_base + r0;
+        const uint32_t s0 = b.cell_start[k0], s1 = b.cell_start[k0 + nin];
+        uint32_t cnt = s1 - s0;
+        if (cnt > kMaxSuperCount) {
+            raise_error(b.g, kErrBoxOverflow);
+            cnt = kMaxSuperCount;
+        }
+        b.cellinfo[super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1)] = pack_super(s0, cnt, b.g->stamp);
     }
 }
 
@@ -570,8 +570,13 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s, h
     };
     hipLaunchKernelGGL(k_keys<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur);
     mark(0);
-    hipLaunchKernelGGL(k_scan, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start,
-                       b.scan_status, b.scan_tiles);
+    uint32_t* tile_sum = reinterpret_cast<uint32_t*>(b.scan_status);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, tile_sum,
+                       b.scan_tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kTileScanThreads), 0, s, b.g, tile_sum, b.cell_start,
+                       b.scan_tiles);
+    hipLaunchKernelGGL(k_scan_down, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start,
+                       tile_sum, b.scan_tiles);
     mark(1);
     hipLaunchKernelGGL(k_scatter<T>, dim3(blocks), dim3(256), 0, s, b);
     mark(2);

@@ -34,6 +34,29 @@ STEP_BYTES = {"f32": 4 * 4 + 3 * 4 + 16, "f64": 4 * 8 + 3 * 8 + 16}
 FORCE_BYTES = {"f32": 4 * 4 + 4 + 3 * 4, "f64": 4 * 8 + 4 + 3 * 8}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_headline_traffic.json")
+
+
+def measured_traffic(n, prec, block_size):
+    """HBM bytes per force launch from the committed FETCH_SIZE/WRITE_SIZE
+    counter runs (scaled by a plain copy's reading), or None when the kernel
+    sources changed since the counters were taken or the configuration
+    differs from the profiled one (1e7 agents, FP32 state, 256 threads)."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for name in rec["sources"]:
+            with open(os.path.join(ROOT, "paper_2301_06984_amd", "csrc", name), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    if h.hexdigest() != rec["source_sha256"] or n != 10_000_000 or prec != "f32" or block_size != 256:
+        return None
+    return float(rec["traffic_bytes"])
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -134,8 +157,11 @@ def main():
     prec = w.precision
     force_bytes = FORCE_BYTES[prec] * w.n
     ach = force_bytes / (phases["force"] * 1e-3) / 1e9
+    traffic = measured_traffic(w.n, prec, args.block_size)
     roof = dict(bound="hbm", kernel="k_force (static flags + force + move)", achieved=round(ach, 1),
-                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
+                traffic=None if traffic is None else round(traffic), traffic_unit="bytes per launch",
+                algorithmic_bytes=force_bytes,
                 bytes_per_agent=FORCE_BYTES[prec], avg_launch_ms=round(phases["force"], 4),
                 dominant_phase=dominant, phase_ms={k: round(v, 4) for k, v in phases.items()},
                 step_bytes_per_agent=STEP_BYTES[prec],

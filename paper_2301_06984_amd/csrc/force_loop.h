@@ -197,23 +197,32 @@ template <class T, bool PARAM_GRADS>
 __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, uint32_t self, const V4<T>& p,
                                          const unsigned long long e[8], const WalkLds& L, ForceSum& acc) {
     const V4<T>* __restrict__ sp = spos_ptr(b);
-    const uint32_t tid = threadIdx.x, bs = blockDim.x;
+    const uint32_t tid = threadIdx.x, bs = blockDim.x, last = b.n - 1;
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
     const double ri = 0.5 * fabs(double(p.w));
     const double r2 = G.r2, k = G.k, gamma = G.gamma;
     const float r2pad = padded_r2(r2);
     uint32_t n = 0;
     auto drain = [&]() {
+        // exact neighbour + contact test, keeping the survivors in place; the
+        // positions of a group of four are requested before any is tested
         uint32_t m = 0;
-        for (uint32_t x = 0; x < n; ++x) {   // exact neighbour + contact test
-            const uint32_t u = L.queue[x * bs + tid];
-            const V4<T> pj = sp[u];
-            const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
-            const double s2 = (ex * ex + ey * ey) + ez * ez;
-            const double S = ri + 0.5 * fabs(double(pj.w));
-            if (s2 < r2 && s2 > 0.0 && s2 < S * S) {
-                L.queue[m * bs + tid] = u;
-                ++m;
+        for (uint32_t x0 = 0; x0 < n; x0 += 4) {
+            V4<T> pj[4];
+            uint32_t uq[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                uq[c] = L.queue[min(x0 + c, n - 1) * bs + tid];
+                pj[c] = sp[uq[c]];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double ex = xi - double(pj[c].x), ey = yi - double(pj[c].y), ez = zi - double(pj[c].z);
+                const double s2 = (ex * ex + ey * ey) + ez * ez;
+                const double S = ri + 0.5 * fabs(double(pj[c].w));
+                const bool keep = x0 + c < n && s2 < r2 && s2 > 0.0 && s2 < S * S;
+                L.queue[m * bs + tid] = uq[c];
+                m += keep ? 1u : 0u;
             }
         }
         for (uint32_t x = 0; x < m; ++x) {   // pair terms, in slot order
@@ -244,13 +253,37 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
         }
         n = 0;
     };
-    stream_slots(e, L, [&](uint32_t u) {
-        if (u != self && u < b.n && maybe_within<T>(p, sp[u], r2pad)) {
-            L.queue[n * bs + tid] = u;
-            if (++n == uint32_t(kQueueCap)) drain();
+    // pass 1: stream the candidates through the pre-test, the next
+    // candidate's position requested one iteration ahead
+    uint32_t total = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        total += super_count(e[q]);
+        L.rng[q * bs + tid] = e[q];
+    }
+    int kr = -1;
+    uint32_t u = 0, end = 0;
+    auto advance = [&]() {
+        while (u >= end && kr < 7) {
+            ++kr;
+            const unsigned long long v = L.rng[kr * bs + tid];
+            u = super_start(v);
+            end = u + super_count(v);
         }
-        return true;
-    });
+    };
+    advance();
+    V4<T> pn = sp[min(u, last)];
+    for (uint32_t j = 0; j < total; ++j) {
+        const uint32_t uc = u;
+        const V4<T> pc = pn;
+        ++u;
+        advance();
+        pn = sp[min(u, last)];
+        const bool pass = uc != self && maybe_within<T>(p, pc, r2pad);
+        L.queue[n * bs + tid] = uc;   // n < kQueueCap here
+        n += pass ? 1u : 0u;
+        if (n == uint32_t(kQueueCap)) drain();
+    }
     drain();
 }
 

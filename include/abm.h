@@ -54,7 +54,8 @@ enum abm_status {
     ABM_OK = 0,
     ABM_E_INVAL = -1,        /* bad argument, size or alignment */
     ABM_E_NONFINITE = -2,    /* a non-finite input or state value */
-    ABM_E_GRID = -3,         /* grid larger than 2^21 boxes per axis, 2^32 boxes, or the box capacity */
+    ABM_E_GRID = -3,         /* grid larger than 2^21 boxes per axis, 2^32 boxes, 2^29 super-boxes (aligned
+                                2x2x2 blocks of boxes), or the box capacity */
     ABM_E_WORKSPACE = -4,    /* workspace too small */
     ABM_E_HIP = -5,          /* HIP runtime failure */
     ABM_E_STATE = -6,        /* call out of order (e.g. backward before a recorded forward) */
@@ -117,7 +118,8 @@ enum abm_field {
     ABM_FIELD_NNZ = 4,         /* n int32, by agent id: non-zero pair terms in the last force evaluation */
     ABM_FIELD_KEY = 5,         /* n uint32, by agent id: gap-free Morton rank of the agent's box (last grid) */
     ABM_FIELD_PERM = 6,        /* n uint32: agent ids in (box rank, id) order of the last grid */
-    ABM_FIELD_CELL_START = 7,  /* nboxes + 1 uint32: first slot of each box, last grid (single simulation) */
+    ABM_FIELD_CELL_START = 7,  /* nboxes + 1 uint32: first slot of each box, last grid (single simulation;
+                                  ABM_E_UNSUPPORTED for a batched context) */
     ABM_FIELD_EXTENT = 8,      /* int64[7] per simulation: cmin[3], dims[3], nboxes of the last grid */
     ABM_FIELD_STORAGE_IDS = 9  /* n uint32: agent id held by each storage slot */
 };

@@ -1,6 +1,7 @@
 // abm_api.hip -- the C ABI of libabm (declared in include/abm.h): workspace
 // layout, step sequencing (Algorithm 1's iteration as a chain of kernels on
 // one stream), queries, checkpoints, graph capture and the adjoint driver.
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -35,7 +36,7 @@ int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 constexpr int kTimedPhases = 6;
 
 struct Layout {
-    int64_t globals, sims, sim_of, bbox_rep, pos4[2], ids[2], flags[2], force[2], key, rmi, sub, tmp, perm, spos,
+    int64_t globals, sims, sim_of, bbox_rep, pos4[2], ids[2], flags[2], force[2], key, sub, rec, perm, sflags, spos,
         count, cell_start, cellinfo, scan_status, partials, stage, total;
     uint32_t scan_tiles, partial_cap;
 };
@@ -57,14 +58,14 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     for (int k = 0; k < 2; ++k) L.flags[k] = take(4 * n);
     for (int k = 0; k < 2; ++k) L.force[k] = keep_forces ? take(24 * n) : -1;
     L.key = take(4 * n);
-    L.rmi = take(4 * n);
     L.sub = take(4 * n);
-    L.tmp = take(4 * n);
+    L.rec = take(16 * n);
+    L.sflags = take(4 * n);
     L.perm = take(4 * n);
-    L.spos = take(4 * elem * n);
+    L.spos = take(4 * elem * (n + kSposPad));
     L.count = take(4 * boxes);
     L.cell_start = take(4 * (boxes + 1));
-    L.cellinfo = take(8 * boxes);
+    L.cellinfo = take(16 * boxes);
     L.scan_tiles = uint32_t((boxes + kScanTile - 1) / kScanTile);
     if (L.scan_tiles == 0) L.scan_tiles = 1;
     L.scan_status = take(8 * int64_t(L.scan_tiles));
@@ -138,14 +139,14 @@ void fill_buffers(abm_ctx* c) {
         b.force[k] = L.force[k] >= 0 ? reinterpret_cast<double*>(w + L.force[k]) : nullptr;
     }
     b.key = reinterpret_cast<uint32_t*>(w + L.key);
-    b.rmi = reinterpret_cast<uint32_t*>(w + L.rmi);
     b.sub = reinterpret_cast<uint32_t*>(w + L.sub);
-    b.tmp = reinterpret_cast<uint32_t*>(w + L.tmp);
+    b.rec = reinterpret_cast<uint4*>(w + L.rec);
+    b.sflags = reinterpret_cast<uint32_t*>(w + L.sflags);
     b.perm = reinterpret_cast<uint32_t*>(w + L.perm);
     b.spos = w + L.spos;
     b.count = reinterpret_cast<uint32_t*>(w + L.count);
     b.cell_start = reinterpret_cast<uint32_t*>(w + L.cell_start);
-    b.cellinfo = reinterpret_cast<unsigned long long*>(w + L.cellinfo);
+    b.cellinfo = reinterpret_cast<uint4*>(w + L.cellinfo);
     b.scan_status = reinterpret_cast<unsigned long long*>(w + L.scan_status);
     b.scan_tiles = L.scan_tiles;
     b.partials = reinterpret_cast<double*>(w + L.partials);
@@ -173,7 +174,6 @@ int block_size_of(const abm_params& p) { return p.block_size ? p.block_size : 25
 int error_code(uint32_t err) {
     if (err & kErrNonfinite) return fail(ABM_E_NONFINITE, "non-finite position or diameter");
     if (err & kErrGrid) return fail(ABM_E_GRID, "grid exceeds its box capacity or 2^21 boxes per axis");
-    if (err & kErrBoxOverflow) return fail(ABM_E_GRID, "more than 65535 agents in one box");
     if (err & kErrInternal) return fail(ABM_E_HIP, "internal index check failed");
     return ABM_OK;
 }
@@ -224,14 +224,14 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, bool timed = false) {
         (void)hipEventRecord((*ev)[0], c->stream);
         for (int k = 0; k < 4; ++k) marks[k] = &(*ev)[2 + k];
     }
-    launch_setup<T>(b, parity, c->stream);
-    if (ev) (void)hipEventRecord((*ev)[1], c->stream);
-    launch_grid<T>(b, c->pos_cur, c->ids_cur, c->stream, ev ? marks : nullptr);
     StepArgs a{};
     a.parity = parity;
     a.pos_cur = c->pos_cur;
     a.ids_cur = c->ids_cur;
     a.relayout = allow_relayout && c->params.sort_every > 0 && ((c->step + 1) % c->params.sort_every == 0);
+    launch_setup<T>(b, parity, c->stream);
+    if (ev) (void)hipEventRecord((*ev)[1], c->stream);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, a.relayout, c->stream, ev ? marks : nullptr);
     a.detect_static = c->params.detect_static != 0;
     a.keep_forces = c->params.keep_forces != 0;
     a.block_size = block_size_of(c->params);
@@ -315,7 +315,8 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     // zero what must start at zero: globals, histogram, box table, scan status
     if (hipMemsetAsync(c->ws + L.globals, 0, sizeof(Globals), s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.count, 0, 4 * boxes, s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.cellinfo, 0, 8 * boxes, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.cellinfo, 0, 16 * boxes, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.spos, 0, 4 * c->elem() * (n + kSposPad), s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.scan_status, 0, 8 * int64_t(L.scan_tiles), s) != hipSuccess ||
         hipMemcpyAsync(b.sims, sims.data(), sizeof(SimGrid) * nsims, hipMemcpyHostToDevice, s) != hipSuccess)
         return bail(fail(ABM_E_HIP, "workspace initialisation failed"));
@@ -390,14 +391,37 @@ int query_impl(abm_ctx* c, int32_t field, void* dst, int64_t dst_bytes, int32_t 
             break;
         case ABM_FIELD_STORAGE_IDS: need = 4 * n; break;
         case ABM_FIELD_CELL_START: {
+            // box starts are not kept by the step (it counts super-boxes);
+            // they are rebuilt here from the boxes of the last grid's slots
             if (!c->have_grid) return fail(ABM_E_STATE, "no grid has been built yet (run a step)");
+            if (c->nsims != 1) return fail(ABM_E_UNSUPPORTED, "box starts are kept for a single simulation only");
             HIP_TRY(hipStreamSynchronize(c->stream));
-            uint32_t total = 0;
-            HIP_TRY(hipMemcpy(&total, &b.g->total_boxes, 4, hipMemcpyDeviceToHost));
-            need = 4 * (int64_t(total) + 1);
+            SimGrid G;
+            HIP_TRY(hipMemcpy(&G, b.sims, sizeof(SimGrid), hipMemcpyDeviceToHost));
+            if (!G.valid) return fail(ABM_E_GRID, "the last grid is not valid");
+            const int64_t nbox = G.nboxes;
+            need = 4 * (nbox + 1);
             if (dst_bytes < need) return fail(ABM_E_INVAL, "destination too small: need " + std::to_string(need));
-            HIP_TRY(hipMemcpy(dst, b.cell_start, need, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
-            return ABM_OK;
+            uint32_t* ranks = reinterpret_cast<uint32_t*>(c->ws + c->L.stage);
+            launch_box_ranks<T>(b, c->grid_ids, ranks, false, c->stream);
+            HIP_TRY(hipGetLastError());
+            if (dst_is_device) {
+                launch_cell_start(ranks, uint32_t(n), 0u, uint32_t(nbox), static_cast<uint32_t*>(dst), c->stream);
+                HIP_TRY(hipGetLastError());
+            } else {
+                // through the rest of the staging area, in chunks
+                uint32_t* part = ranks + n;
+                const int64_t chunk = (24 * n - 4 * n) / 4;
+                for (int64_t r0 = 0; r0 <= nbox; r0 += chunk) {
+                    const int64_t m = std::min<int64_t>(chunk, nbox + 1 - r0);
+                    launch_cell_start(ranks, uint32_t(n), uint32_t(r0), uint32_t(m - 1), part, c->stream);
+                    HIP_TRY(hipGetLastError());
+                    HIP_TRY(hipMemcpyAsync(static_cast<uint32_t*>(dst) + r0, part, 4 * m, hipMemcpyDeviceToHost,
+                                           c->stream));
+                }
+            }
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            return read_error(c, false);
         }
         case ABM_FIELD_EXTENT: {
             need = 56 * int64_t(c->nsims);
@@ -422,6 +446,8 @@ int query_impl(abm_ctx* c, int32_t field, void* dst, int64_t dst_bytes, int32_t 
     void* target = dst_is_device ? dst : static_cast<void*>(c->ws + c->L.stage);
     if (field == ABM_FIELD_POSITIONS)
         launch_unpack_positions<T>(b, c->pos_cur, ids_buf, static_cast<T*>(target), c->stream);
+    else if (field == ABM_FIELD_KEY)
+        launch_box_ranks<T>(b, ids_buf, static_cast<uint32_t*>(target), true, c->stream);
     else
         launch_unpack_field<T>(b, c->pos_cur, ids_buf, field, target, c->stream);
     HIP_TRY(hipGetLastError());
@@ -544,7 +570,7 @@ void load_and_grid(abm_ctx* c, const T* pos_by_id) {
     launch_bbox<T>(b, c->pos_cur, 0, c->stream);
     guard_stamps<T>(c, 1);
     launch_setup<T>(b, 0, c->stream);
-    launch_grid<T>(b, c->pos_cur, c->ids_cur, c->stream);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, false, c->stream);
     c->stamp_count += 1;
 }
 

@@ -58,16 +58,6 @@ __device__ __forceinline__ uint32_t gapfree_rank(uint32_t qx, uint32_t qy, uint3
     return r;
 }
 
-// Row-major box table entry: start slot, agent count, 15-bit stamp, any-moved.
-__device__ __forceinline__ unsigned long long pack_cell(uint32_t start, uint32_t cnt, uint32_t stamp, uint32_t moved) {
-    return (unsigned long long)start | ((unsigned long long)(cnt & 0xFFFFu) << 32) |
-           ((unsigned long long)(stamp & 0x7FFFu) << 48) | ((unsigned long long)(moved & 1u) << 63);
-}
-__device__ __forceinline__ uint32_t cell_start_of(unsigned long long e) { return uint32_t(e); }
-__device__ __forceinline__ uint32_t cell_count_of(unsigned long long e) { return uint32_t(e >> 32) & 0xFFFFu; }
-__device__ __forceinline__ uint32_t cell_stamp_of(unsigned long long e) { return uint32_t(e >> 48) & 0x7FFFu; }
-__device__ __forceinline__ bool cell_moved_of(unsigned long long e) { return (e >> 63) != 0; }
-
 __device__ __forceinline__ void raise_error(Globals* g, uint32_t bits) { atomicOr(&g->err, bits); }
 
 // Blocks are handed to the 8 XCDs round-robin; remap so that each XCD works on

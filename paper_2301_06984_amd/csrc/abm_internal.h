@@ -1,5 +1,11 @@
 // abm_internal.h -- device data structures and kernel launchers of libabm.
 //
+// Boxes of edge h = cell_factor * R are grouped into super-boxes, the aligned
+// 2x2x2 blocks S = q >> 1.  The 8 boxes of a super-box are 8 consecutive
+// Morton codes, so in the canonical (box rank, id) order a super-box's agents
+// are one contiguous slot range, sorted by octant (x bit lowest) and then id.
+// The grid build therefore counts and scans super-boxes, not boxes.
+//
 // Layout in HBM (one workspace, carved by abm_api.hip):
 //   per agent, two copies (ping-pong between steps):
 //     pos4   {x, y, z, d} in the element type T (16 B for float, 32 B for double)
@@ -7,20 +13,21 @@
 //     flags  bit 0 moved, bit 1 static (last step), bits 8.. non-zero pair terms
 //     force  3 doubles (only with keep_forces)
 //   per agent, one copy (rebuilt every step):
-//     key    global box key = box base of the simulation + gap-free Morton rank
-//     rmi    global row-major box index (box base + (qz*dy + qy)*dx + qx)
-//     sub    arrival index of the agent in its box (from the histogram atomics)
-//     tmp    agents in box order, arrival order inside a box
+//     key    (global super-box index << 3) | octant of the agent's box
+//     sub    arrival index of the agent in its super-box (histogram atomics)
+//     rec    agents in super-box order, arrival order inside a super-box:
+//            {storage index, id, super-box start, count << 4 | octant << 1 | moved}
 //     perm   agents in canonical (box rank, id) order
+//     sflags flags of the agents in canonical order
 //     spos   {x, y, z, d} of the agents in canonical order (sign of d = moved)
-//   per box (capacity = sum of the per-simulation box capacities):
+//   per super-box (capacity = sum of the per-simulation box capacities):
 //     count       histogram; every scan leaves it zeroed for the next step
 //     cell_start  exclusive prefix sum of count (+1 entry)
-//     cellinfo    row-major box table {start, count, stamp, any-moved}; a box
-//                 whose stamp is not the current step's is empty, so the table
-//                 is never cleared between steps (the timestamp trick of
-//                 Section 3.1)
-//   per scan tile: one 64-bit status word for the decoupled look-back.
+//     cellinfo    row-major super-box table, 16 B per entry (SuperEntry); an
+//                 entry whose stamp is not the current step's is empty, so
+//                 the table is never cleared between steps (the timestamp
+//                 trick of Section 3.1)
+//   per scan tile: one 64-bit word (tile sums).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,7 +51,6 @@ constexpr int kReplicas = 64;
 enum : uint32_t {
     kErrNonfinite = 1u,     // a position or diameter is not finite
     kErrGrid = 2u,          // grid larger than its capacity or 2^21 boxes per axis
-    kErrBoxOverflow = 4u,   // more than 65535 agents in one box
     kErrInternal = 8u,      // an index left its range (should never fire)
 };
 
@@ -62,9 +68,13 @@ struct SimGrid {
     int32_t cmin[3];
     uint32_t dims[3];
     uint32_t nboxes;
-    uint32_t box_base;      // first global box index of this simulation
+    uint32_t box_base;      // first global box index of this simulation (rank queries)
     int32_t levels;         // smallest L with 2^L >= max(dims)
     uint32_t valid;
+    uint32_t sdims[3];      // super-boxes per axis: (dims + 1) >> 1
+    uint32_t nsuper;        // sdims[0] * sdims[1] * sdims[2]
+    uint32_t sbase;         // first global super-box index of this simulation
+    int32_t slevels;        // smallest L with 2^L >= max(sdims)
     // min x,y,z then max x,y,z of the box coordinates (extent queries only;
     // the step keeps its accumulators in Buffers::bbox_rep)
     int32_t bbox[2][6];
@@ -73,8 +83,8 @@ struct SimGrid {
 
 struct Globals {
     uint32_t err;
-    uint32_t total_boxes;
-    uint32_t stamp;          // of the current step's box table entries (1..32767)
+    uint32_t total_super;    // super-boxes of all simulations in this step's grid
+    uint32_t stamp;          // of the current step's super-box table entries (1..32767)
     uint32_t scan_epoch;     // tag of the current step's scan status words (never 0)
     unsigned long long scan_ticket;
     // per step parity and replica: agents skipped as static, agents moved
@@ -97,15 +107,15 @@ struct Buffers {
     uint32_t* flags[2];
     double* force[2];         // null without keep_forces
     uint32_t* key;
-    uint32_t* rmi;
     uint32_t* sub;
-    uint32_t* tmp;
+    uint4* rec;               // per arrival slot: {storage index, id, super-box start, count << 4 | octant << 1 | moved}
     uint32_t* perm;
+    uint32_t* sflags;         // flags of the agents in canonical order (grid build)
     void* spos;               // V4<T> per slot of the canonical order; sign of d = moved
-    // per box
+    // per super-box
     uint32_t* count;
     uint32_t* cell_start;
-    unsigned long long* cellinfo;
+    uint4* cellinfo;
     unsigned long long* scan_status;
     double* partials;         // per-block partial sums (adjoint)
     uint32_t partial_cap;
@@ -125,7 +135,12 @@ struct StepArgs {
     int block_size;
 };
 
-constexpr uint32_t kStampPeriod = 32767;   // 15-bit stamps in the box table
+constexpr uint32_t kStampPeriod = 32767;   // 15-bit stamps in the super-box table
+// Entries past the end of the slot-ordered position array (read, never used,
+// by the neighbour walk).
+constexpr int kSposPad = 4;
+// Super-box keys carry the octant in their low 3 bits.
+constexpr uint32_t kMaxSuperBoxes = 1u << 29;
 
 // ---- launchers (grid_kernels.hip)
 template <class T> void launch_pack(const Buffers<T>& b, const T* pos, const T* diam, hipStream_t s);
@@ -138,9 +153,12 @@ void launch_set_params(SimGrid* sims, int nsims, double k, double gamma, double 
 void launch_permute3(const uint32_t* ids, uint32_t n, const double* in, double* out, bool to_id, hipStream_t s);
 template <class T> void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s);
 template <class T> void launch_setup(const Buffers<T>& b, int parity, hipStream_t s);
-template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s,
+template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, hipStream_t s,
                                     hipEvent_t* const* marks = nullptr);
 template <class T> void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s);
+template <class T> void launch_box_ranks(const Buffers<T>& b, int ids_cur, uint32_t* out, bool by_id, hipStream_t s);
+void launch_cell_start(const uint32_t* slot_rank, uint32_t n, uint32_t first_box, uint32_t nbox, uint32_t* out,
+                       hipStream_t s);
 template <class T> void launch_reset_bbox(const Buffers<T>& b, int parity, hipStream_t s);
 
 // ---- launchers (force_kernels.hip)

@@ -32,10 +32,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, co
         uint32_t q[3];
         double wi[3] = {0.0, 0.0, 0.0};
         if (G.valid && box_of<T>(G, p, q)) {
-            unsigned long long e[8];
-            load_ranges(b, G, q, b.g->stamp, e);
+            const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
             ForceSum acc;
-            force_of<T, true>(b, G, t, p, e, L, acc);
+            force_of<T, true>(b, G, p, P, L, acc);
             const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
             if (m.moves) {
                 const double li[3] = {lam[3 * size_t(i)], lam[3 * size_t(i) + 1], lam[3 * size_t(i) + 2]};
@@ -76,6 +75,8 @@ template <class T>
 __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cur, const double* __restrict__ lam,
                                                              const double* __restrict__ w,
                                                              double* __restrict__ lam_out) {
+    extern __shared__ __align__(16) unsigned char s_walk[];
+    const WalkLds L = walk_lds(s_walk);
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= b.n) return;
     const SimGrid& G = b.sims[sim_index(b, t)];
@@ -89,12 +90,11 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
     uint32_t q[3];
     double acc[3] = {lam[3 * size_t(m)], lam[3 * size_t(m) + 1], lam[3 * size_t(m) + 2]};
     if (G.valid && box_of<T>(G, p, q)) {
-        unsigned long long e[8];
-        load_ranges(b, G, q, b.g->stamp, e);
+        const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
         const double xm = double(p.x), ym = double(p.y), zm = double(p.z);
         const double rm = 0.5 * fabs(double(p.w));
         const double wm[3] = {w[3 * size_t(m)], w[3 * size_t(m) + 1], w[3 * size_t(m) + 2]};
-        visit_ranges(e, [&](uint32_t u) {
+        stream_pieces(L, P, [&](uint32_t u) {
             if (u == t || u >= b.n) return true;
             const uint32_t j = b.perm[u];
             if (j >= b.n) return true;
@@ -175,7 +175,8 @@ void launch_adj_w(const Buffers<T>& b, int pos_cur, const double* lam, double* w
 template <class T>
 void launch_adj_gather(const Buffers<T>& b, int pos_cur, const double* lam, const double* w, double* lam_out,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_gather<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), 0, s, b, pos_cur, lam, w, lam_out);
+    hipLaunchKernelGGL(k_adj_gather<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b,
+                       pos_cur, lam, w, lam_out);
 }
 
 template <class T>

@@ -5,19 +5,46 @@
 
 namespace abm {
 
+// Simulations whose box extents one block of the step kernel folds in LDS
+// (further ones, in blocks spanning many small simulations, go straight to
+// the global accumulators).
+constexpr int kMaxBlockSims = 4;
+
 // One thread per slot of the canonical (box rank, id) order, so a wave works
 // on agents that are close in space and shares their neighbour boxes in
-// cache.  Agent i = perm[t] reads its state at storage index i; the new state
+// cache.  The grid build left the agent's position (spos) and flags (sflags)
+// at its slot t; the agent's storage index is i = perm[t].  The new state
 // goes to storage index i, or to slot t when this step re-lays agents out in
-// Morton order (Section 4.2, step G).  The static test (Section 5) runs first:
-// an agent that did not move, had at most one non-zero pair term, and has no
-// moved neighbour within R keeps its force and does not move.  The new
-// positions' box extent is reduced here for the next step's grid.
+// Morton order (Section 4.2, step G; the grid build then already wrote the
+// ids in slot order).  The static test (Section 5) runs first: an agent that
+// did not move, had at most one non-zero pair term, and has no moved
+// neighbour within R keeps its force and does not move.  The new positions'
+// box extent is reduced here for the next step's grid: each wave folds into
+// the block's LDS copy, and the block's last wave to finish adds it to the
+// global accumulators, so no wave waits for the others.
+#ifndef ABM_FORCE_WAVES_PER_EU
+#define ABM_FORCE_WAVES_PER_EU 1
+#endif
 template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT>
-__global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32_t launched) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_WAVES_PER_EU))) void k_force(
+    Buffers<T> b, StepArgs a, uint32_t launched) {
     extern __shared__ __align__(16) unsigned char s_walk[];
+    __shared__ int32_t s_box[kMaxBlockSims][6];
+    __shared__ int s_sims[kMaxBlockSims];
+    __shared__ uint32_t s_cnt[3];   // static, moved, waves done
     const WalkLds L = walk_lds(s_walk);
     const uint32_t t = xcd_block(launched) * blockDim.x + threadIdx.x;
+    // the block's slots belong to at most kMaxBlockSims simulations (the
+    // first and last slot bound them); their LDS accumulators start empty
+    const uint32_t t0 = xcd_block(launched) * blockDim.x;
+    const int sim0 = BATCHED && t0 < b.n ? sim_index(b, t0) : 0;
+    if (threadIdx.x < kMaxBlockSims * 6) {
+        const int k = int(threadIdx.x) % 6;
+        s_box[threadIdx.x / 6][k] = k < 3 ? INT32_MAX : INT32_MIN;
+    }
+    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0u;
+    if (threadIdx.x < kMaxBlockSims) s_sims[threadIdx.x] = -1;
+    __syncthreads();
     bool active = t < b.n;
     bool ok = false, is_static = false, moved = false;
     int sim = 0;
@@ -28,15 +55,12 @@ __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32
         sim = BATCHED ? sim_index(b, t) : 0;
         const SimGrid& G = b.sims[sim];
         const int cur = a.pos_cur, nxt = cur ^ 1;
-        const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
         V4<T>* __restrict__ pout = pos4_ptr(b, nxt);
-        const uint32_t* __restrict__ fin = b.flags[cur];
-        const bool perm_ok = G.valid && b.perm[t] < b.n;
-        if (G.valid && !perm_ok) raise_error(b.g, kErrInternal);
-        if (!perm_ok) {
+        if (!G.valid) {
             // grid overflow (reported at sync): keep this slot's state unchanged
+            const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
             pout[t] = pin[t];
-            b.flags[nxt][t] = fin[t];
+            b.flags[nxt][t] = b.flags[cur][t];
             if (RELAYOUT) b.ids[a.ids_cur ^ 1][t] = b.ids[a.ids_cur][t];
             if (KEEP_F)
                 for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(t) + c] = b.force[cur][3 * size_t(t) + c];
@@ -44,16 +68,22 @@ __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32
             ok = box_coord(double(p.x), G.inv_h, &cnew[0]) && box_coord(double(p.y), G.inv_h, &cnew[1]) &&
                  box_coord(double(p.z), G.inv_h, &cnew[2]);
         } else {
-            const uint32_t i = b.perm[t];
-            V4<T> p = spos_ptr(b)[t];      // own state, from the slot-ordered copy
-            const uint32_t f = fin[i];
+            V4<T> p = spos_ptr(b)[t];   // own state, from the slot-ordered copy
+            const uint32_t f = b.sflags[t];
+            uint32_t i = t;
+            if (!RELAYOUT || KEEP_F) {
+                i = b.perm[t];
+                if (i >= b.n) {
+                    raise_error(b.g, kErrInternal);
+                    i = t;
+                }
+            }
             const uint32_t out = RELAYOUT ? t : i;
             uint32_t q[3];
             if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
-            unsigned long long e[8];
-            load_ranges(b, G, q, b.g->stamp, e);
+            const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
             // at step 0 every agent carries the moved bit, so none is static
-            if (STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u) is_static = no_moved_neighbour(b, G, t, p, e, L);
+            if (STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u) is_static = no_moved_neighbour(b, G, t, p, P, L);
             p.w = T(fabs(double(p.w)));
             V4<T> np = p;
             uint32_t nf;
@@ -63,7 +93,7 @@ __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32
                     for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
             } else {
                 ForceSum acc;
-                force_of<T, false>(b, G, t, p, e, L, acc);
+                force_of<T, false>(b, G, p, P, L, acc);
                 const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
                 np.x = T(double(p.x) + m.ux);
                 np.y = T(double(p.y) + m.uy);
@@ -79,19 +109,64 @@ __global__ __launch_bounds__(1024) void k_force(Buffers<T> b, StepArgs a, uint32
             }
             pout[out] = np;
             b.flags[nxt][out] = nf;
-            if (RELAYOUT) b.ids[a.ids_cur ^ 1][t] = b.ids[a.ids_cur][i];
             ok = box_coord(double(np.x), G.inv_h, &cnew[0]) && box_coord(double(np.y), G.inv_h, &cnew[1]) &&
                  box_coord(double(np.z), G.inv_h, &cnew[2]);
         }
         if (!ok) raise_error(b.g, kErrNonfinite);
     }
-    bbox_fold_block(sim, active && ok, cnew, [&](int sm) { return bbox_replica(b, a.parity ^ 1, sm); });
-    const int ns = __syncthreads_count(active && is_static);
-    const int nm = __syncthreads_count(active && moved);
-    if (threadIdx.x == 0 && (ns | nm)) {
-        unsigned long long* st = b.g->stats[a.parity][blockIdx.x % kReplicas];
-        if (ns) atomicAdd(&st[0], (unsigned long long)ns);
-        if (nm) atomicAdd(&st[1], (unsigned long long)nm);
+    // ---- box extent and statistics: wave, then block (LDS atomics), then
+    // the last wave of the block adds the block's result to the replicas
+    const bool contrib = active && ok;
+    const unsigned long long any = __ballot(contrib);
+    const uint32_t ns = uint32_t(__popcll(__ballot(active && is_static)));
+    const uint32_t nm = uint32_t(__popcll(__ballot(active && moved)));
+    const int lead = any ? __ffsll((long long)any) - 1 : 0;
+    const int wsim = __shfl(sim, lead, 64);
+    const bool uniform = __ballot(contrib && sim != wsim) == 0;
+    if (uniform) {
+        int32_t lo[3], hi[3];
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = wave_min(contrib ? cnew[c] : INT32_MAX);
+            hi[c] = wave_max(contrib ? cnew[c] : INT32_MIN);
+        }
+        const int slot = wsim - sim0;
+        if (lane_id() == 0 && any) {
+            if (slot >= 0 && slot < kMaxBlockSims) {
+                s_sims[slot] = wsim;
+                for (int c = 0; c < 3; ++c) {
+                    atomicMin(&s_box[slot][c], lo[c]);
+                    atomicMax(&s_box[slot][3 + c], hi[c]);
+                }
+            } else {
+                bbox_atomic(bbox_replica(b, a.parity ^ 1, wsim), lo, hi);
+            }
+        }
+    } else if (contrib) {
+        // several simulations in one wave (batched, small simulations)
+        bbox_atomic(bbox_replica(b, a.parity ^ 1, sim), cnew, cnew);
+    }
+    if (lane_id() == 0) {
+        if (ns) atomicAdd(&s_cnt[0], ns);
+        if (nm) atomicAdd(&s_cnt[1], nm);
+        __threadfence_block();
+        const uint32_t nwaves = (blockDim.x + 63u) >> 6;
+        if (atomicAdd(&s_cnt[2], 1u) == nwaves - 1) {
+            __threadfence_block();
+            for (int k = 0; k < kMaxBlockSims; ++k) {
+                const int sk = atomicAdd(&s_sims[k], 0);
+                if (sk < 0) continue;
+                int32_t lo[3], hi[3];
+                for (int c = 0; c < 3; ++c) {
+                    lo[c] = atomicAdd(&s_box[k][c], 0);
+                    hi[c] = atomicAdd(&s_box[k][3 + c], 0);
+                }
+                bbox_atomic(bbox_replica(b, a.parity ^ 1, sk), lo, hi);
+            }
+            const uint32_t ts = atomicAdd(&s_cnt[0], 0u), tm = atomicAdd(&s_cnt[1], 0u);
+            unsigned long long* st = b.g->stats[a.parity][blockIdx.x % kReplicas];
+            if (ts) atomicAdd(&st[0], (unsigned long long)ts);
+            if (tm) atomicAdd(&st[1], (unsigned long long)tm);
+        }
     }
 }
 
@@ -139,7 +214,7 @@ void launch_unpack_positions(const Buffers<T>& b, int pos_cur, int ids_cur, T* o
     hipLaunchKernelGGL(k_unpack_positions<T>, dim3((b.n + 255) / 256), dim3(256), 0, s, b, pos_cur, ids_cur, out);
 }
 
-// field: 1 forces, 2 moved, 3 static, 4 nnz, 5 key, 6 perm, 9 storage ids
+// field: 1 forces, 2 moved, 3 static, 4 nnz, 6 perm, 9 storage ids
 template <class T>
 __global__ void k_unpack_field(Buffers<T> b, int cur, int ids_cur, int field, void* out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -167,7 +242,6 @@ __global__ void k_unpack_field(Buffers<T> b, int cur, int ids_cur, int field, vo
         case 2: static_cast<uint8_t*>(out)[id] = uint8_t(f & kMovedBit); break;
         case 3: static_cast<uint8_t*>(out)[id] = uint8_t((f & kStaticBit) ? 1 : 0); break;
         case 4: static_cast<int32_t*>(out)[id] = int32_t(f >> kNnzShift); break;
-        case 5: static_cast<uint32_t*>(out)[id] = b.key[i]; break;
         default: break;
     }
 }

@@ -4,14 +4,26 @@
 // Agents sit in slots of the canonical (box rank, id) order; the grid build
 // writes the slot-ordered copy `spos` ({x, y, z, d}, sign of d = moved in the
 // last step).  The walk covers the 3x3x3 boxes of Section 3.1 through
-// super-boxes: the aligned 2x2x2 block S = q >> 1 of boxes is 8 consecutive
-// Morton codes, so its agents are one contiguous slot range, kept in a
-// row-major super-box table (the `cellinfo` array) stamped with the step.
-// Along each axis the boxes q-1..q+1 lie in two super-boxes, so 8 ranges
-// cover the 27 boxes.  The ranges are disjoint; visited in ascending start
-// they yield every neighbour in ascending slot order, the canonical order of
-// the sums.  Agents of the 8 super-boxes outside the 27 boxes are rejected by
-// the distance test like any other non-neighbour.
+// super-boxes, the aligned 2x2x2 blocks S = q >> 1 of boxes: a super-box is 8
+// consecutive Morton codes, so its agents are one contiguous slot range,
+// sorted by octant.  Along each axis the boxes q-1..q+1 lie in two
+// super-boxes, so 8 super-boxes hold the 27 boxes.  Of one of the two along
+// an axis only one half is needed; the super-box table keeps the agent
+// counts at the octant boundaries 2, 4 and 6, so the y and z halves that are
+// not needed are cut off where that leaves one slot range per super-box
+// (z halves always, y halves when z is cut too), leaving at most 8 slot
+// ranges ("pieces") over 4 x 3 x 3 boxes plus two 2 x 1 x 2 blocks.  Agents
+// of the boxes outside the 27 are rejected by the distance test like any
+// other non-neighbour.
+//
+// The 8 super-boxes are visited in Morton order, which is slot order, without
+// sorting: two super-boxes of the 2x2x2 block that differ along a set of axes
+// compare by the highest interleaved bit in which their codes differ, and for
+// axis a that is bit 3 t_a + a, t_a the number of trailing one bits of the
+// block's lower coordinate on that axis.  So the block's Morton order is a
+// 3-bit count whose digits are the axes ranked by 3 t_a + a.  Pieces within a
+// super-box are in octant order, hence the walk yields every neighbour in
+// ascending slot order, the canonical order of the sums.
 #pragma once
 
 #include "abm_device.h"
@@ -23,34 +35,29 @@ __device__ __forceinline__ const V4<T>* spos_ptr(const Buffers<T>& b) {
     return reinterpret_cast<const V4<T>*>(b.spos);
 }
 
-// Super-box table entry: start slot (high 32 bits), 15-bit stamp, 17-bit count.
-__device__ __forceinline__ unsigned long long pack_super(uint32_t start, uint32_t cnt, uint32_t stamp) {
-    return ((unsigned long long)start << 32) | ((unsigned long long)(stamp & 0x7FFFu) << 17) |
-           (unsigned long long)(cnt & 0x1FFFFu);
+// Super-box table entry (16 B):
+//   x  first slot of the super-box
+//   y  number of its agents
+//   z  agents in octants < 2 (bits 0..15) and in octants < 4 (bits 16..31)
+//   w  agents in octants < 6 (bits 0..15), any agent moved in the last step
+//      (bit 16), 15-bit stamp of the step that wrote the entry (bits 17..31)
+// With more than kMaxSplitCount agents the octant counts are not kept and
+// the whole range is walked.
+constexpr uint32_t kMaxSplitCount = 0xFFFFu;
+
+__device__ __forceinline__ uint4 pack_super(uint32_t start, uint32_t total, uint32_t c2, uint32_t c4, uint32_t c6,
+                                            bool moved, uint32_t stamp) {
+    if (total > kMaxSplitCount) c2 = c4 = c6 = 0u;
+    return make_uint4(start, total, (c2 & 0xFFFFu) | (c4 << 16),
+                      (c6 & 0xFFFFu) | (moved ? 1u << 16 : 0u) | ((stamp & 0x7FFFu) << 17));
 }
-__device__ __forceinline__ uint32_t super_start(unsigned long long e) { return uint32_t(e >> 32); }
-__device__ __forceinline__ uint32_t super_count(unsigned long long e) { return uint32_t(e) & 0x1FFFFu; }
-__device__ __forceinline__ uint32_t super_stamp(unsigned long long e) { return (uint32_t(e) >> 17) & 0x7FFFu; }
-constexpr uint32_t kMaxSuperCount = 0x1FFFFu;
+__device__ __forceinline__ uint32_t super_stamp(const uint4& e) { return e.w >> 17; }
 
 __device__ __forceinline__ uint32_t super_dim(uint32_t d) { return (d + 1u) >> 1; }
 
-// Row-major index of super-box (sx, sy, sz) in the simulation's table.
+// Global index of super-box (sx, sy, sz) in the row-major table.
 __device__ __forceinline__ uint32_t super_index(const SimGrid& G, uint32_t sx, uint32_t sy, uint32_t sz) {
-    return G.box_base + (sz * super_dim(G.dims[1]) + sy) * super_dim(G.dims[0]) + sx;
-}
-
-// Ranks of the boxes of q's super-box: [r0, r0 + nin), given q's rank r.
-// With w_a in {1, 2} the super-box's in-space width along axis a and b_a the
-// low bit of q_a, q's position inside it in Morton order is
-// b_x + b_y w_x + b_z w_x w_y.
-__device__ __forceinline__ void super_rank_range(const SimGrid& G, const uint32_t q[3], uint32_t r, uint32_t* r0,
-                                                 uint32_t* nin) {
-    uint32_t w[3];
-    for (int a = 0; a < 3; ++a) w[a] = (G.dims[a] - (q[a] & ~1u)) > 1u ? 2u : 1u;
-    const uint32_t pre = (q[0] & 1u) + (q[1] & 1u) * w[0] + (q[2] & 1u) * w[0] * w[1];
-    *r0 = r - pre;
-    *nin = w[0] * w[1] * w[2];
+    return G.sbase + (sz * G.sdims[1] + sy) * G.sdims[0] + sx;
 }
 
 // Box coordinates of a position relative to the simulation's grid.
@@ -69,92 +76,134 @@ __device__ __forceinline__ bool box_of(const SimGrid& G, const V4<T>& p, uint32_
     return in;
 }
 
-__device__ __forceinline__ void cswap(unsigned long long& a, unsigned long long& b) {
-    const unsigned long long lo = a < b ? a : b, hi = a < b ? b : a;
-    a = lo;
-    b = hi;
-}
-
-// The 8 super-box ranges around box q, sorted by start slot; empty or
-// out-of-space super-boxes read as 0 (no slots).
-template <class T>
-__device__ __forceinline__ void load_ranges(const Buffers<T>& b, const SimGrid& G, const uint32_t q[3],
-                                            uint32_t stamp, unsigned long long e[8]) {
-    const uint32_t sd[3] = {super_dim(G.dims[0]), super_dim(G.dims[1]), super_dim(G.dims[2])};
-    uint32_t lo[3];
-    for (int a = 0; a < 3; ++a) lo[a] = (q[a] >> 1) - 1u + (q[a] & 1u);   // may wrap: then out of range
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const uint32_t sx = lo[0] + (k & 1), sy = lo[1] + ((k >> 1) & 1), sz = lo[2] + (k >> 2);
-        const bool in = sx < sd[0] && sy < sd[1] && sz < sd[2];
-        e[k] = in ? b.cellinfo[G.box_base + (sz * sd[1] + sy) * sd[0] + sx] : 0ull;
-    }
-    const uint32_t st15 = stamp & 0x7FFFu;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (super_stamp(e[k]) != st15) e[k] = 0ull;
-    cswap(e[0], e[2]); cswap(e[1], e[3]); cswap(e[4], e[6]); cswap(e[5], e[7]);
-    cswap(e[0], e[4]); cswap(e[1], e[5]); cswap(e[2], e[6]); cswap(e[3], e[7]);
-    cswap(e[0], e[1]); cswap(e[2], e[3]); cswap(e[4], e[5]); cswap(e[6], e[7]);
-    cswap(e[2], e[4]); cswap(e[3], e[5]);
-    cswap(e[1], e[4]); cswap(e[3], e[6]);
-    cswap(e[1], e[2]); cswap(e[3], e[4]); cswap(e[5], e[6]);
-}
-
-// Visit the slots of the sorted ranges in ascending order.  fn(slot) returns
-// false to stop; visit_ranges then returns false.
-template <class Fn>
-__device__ __forceinline__ bool visit_ranges(const unsigned long long e[8], Fn&& fn) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const uint32_t s0 = super_start(e[k]), s1 = s0 + super_count(e[k]);
-        for (uint32_t u = s0; u < s1; ++u)
-            if (!fn(u)) return false;
-    }
-    return true;
-}
-
-// Per-thread scratch in LDS for the neighbour walk: the 8 sorted ranges and a
-// queue of candidate slots.  Laid out [entry][thread] so that the threads of
-// a wave hit distinct banks.
-constexpr int kQueueCap = 8;
+// Per-thread scratch in LDS for the neighbour walk: the pieces (start slot in
+// the low, end slot in the high 32 bits) and a queue of candidate slots.  Laid
+// out [entry][thread] so that the threads of a wave hit distinct banks.
+// Build-time tuning of the walk (LDS per thread = kMaxPieces * 8 + kQueueCap * 4
+// bytes, which bounds the waves per CU):
+//   ABM_WALK_CHUNK   slots of one piece tested together (1..kSposPad)
+//   ABM_WALK_QUEUE   queue entries (> ABM_WALK_CHUNK)
+//   ABM_WALK_HULL    1: a super-box whose y half is cut but whose z is not
+//                    gives one piece (octants 2h..2h+5) instead of two
+#ifndef ABM_WALK_CHUNK
+#define ABM_WALK_CHUNK 4
+#endif
+#ifndef ABM_WALK_QUEUE
+#define ABM_WALK_QUEUE 10
+#endif
+#ifndef ABM_WALK_HULL
+#define ABM_WALK_HULL 1
+#endif
+constexpr bool kHull = ABM_WALK_HULL != 0;
+constexpr int kMaxPieces = kHull ? 8 : 10;
+constexpr int kQueueCap = ABM_WALK_QUEUE;
+constexpr int kChunk = ABM_WALK_CHUNK;   // slots of one piece tested together in the walk
+static_assert(kChunk >= 1 && kQueueCap > kChunk, "walk tuning");
+static_assert(kChunk <= kSposPad, "the walk reads up to kChunk - 1 slots past a piece");
 struct WalkLds {
-    unsigned long long* rng;   // [8][blockDim]
+    unsigned long long* rng;   // [kMaxPieces][blockDim]
     uint32_t* queue;           // [kQueueCap][blockDim]
 };
-inline size_t walk_lds_bytes(int block) { return size_t(block) * (8 * 8 + kQueueCap * 4); }
+inline size_t walk_lds_bytes(int block) { return size_t(block) * (kMaxPieces * 8 + kQueueCap * 4); }
 
 __device__ __forceinline__ WalkLds walk_lds(void* base) {
     WalkLds w;
     w.rng = static_cast<unsigned long long*>(base);
-    w.queue = reinterpret_cast<uint32_t*>(w.rng + 8 * blockDim.x);
+    w.queue = reinterpret_cast<uint32_t*>(w.rng + kMaxPieces * blockDim.x);
     return w;
 }
 
-// The slots of the sorted ranges as one stream in ascending order.  Each lane
-// advances through its own ranges (read back from LDS), so a wave iterates
-// max(total) times rather than the sum of per-range maxima.  fn(slot) returns
-// false to stop; stream_slots then returns false.
-template <class Fn>
-__device__ __forceinline__ bool stream_slots(const unsigned long long e[8], const WalkLds& L, Fn&& fn) {
+struct Pieces {
+    uint32_t m = 0;       // non-empty pieces, in slot order, in WalkLds::rng
+    uint32_t total = 0;   // slots in all pieces
+    bool moved = false;   // an agent of one of the 8 super-boxes moved in the last step
+};
+
+// Load the pieces around box q (entries of the current stamp only) into this
+// thread's LDS rows.
+template <class T>
+__device__ __forceinline__ Pieces load_pieces(const Buffers<T>& b, const SimGrid& G, const uint32_t q[3],
+                                              uint32_t stamp, const WalkLds& L) {
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
-    uint32_t total = 0;
+    const uint32_t sd0 = G.sdims[0], sd1 = G.sdims[1], sd2 = G.sdims[2];
+    uint32_t lo[3], bq[3], rank_key[3];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        total += super_count(e[k]);
-        L.rng[k * bs + tid] = e[k];
+    for (int a = 0; a < 3; ++a) {
+        bq[a] = q[a] & 1u;
+        lo[a] = (q[a] >> 1) - 1u + bq[a];   // wraps below 0: then out of range
+        rank_key[a] = 3u * uint32_t(__builtin_ctz(~lo[a] | 0x80000000u)) + uint32_t(a);
     }
-    int k = -1;
-    uint32_t u = 0, end = 0;
-    for (uint32_t j = 0; j < total; ++j) {
-        while (u >= end && k < 7) {   // next non-empty range
-            ++k;
-            const unsigned long long v = L.rng[k * bs + tid];
-            u = super_start(v);
-            end = u + super_count(v);
+    // digit of each axis in the Morton order of the 8 super-boxes
+    const uint32_t gx = (rank_key[0] > rank_key[1] ? 1u : 0u) + (rank_key[0] > rank_key[2] ? 1u : 0u);
+    const uint32_t gy = (rank_key[1] > rank_key[0] ? 1u : 0u) + (rank_key[1] > rank_key[2] ? 1u : 0u);
+    const uint32_t gz = (rank_key[2] > rank_key[0] ? 1u : 0u) + (rank_key[2] > rank_key[1] ? 1u : 0u);
+    const bool inx[2] = {lo[0] < sd0, lo[0] + 1u < sd0};
+    const bool iny[2] = {lo[1] < sd1, lo[1] + 1u < sd1};
+    const bool inz[2] = {lo[2] < sd2, lo[2] + 1u < sd2};
+    const uint32_t plane = sd0 * sd1;
+    const uint32_t base = G.sbase + (lo[2] * sd1 + lo[1]) * sd0 + lo[0];   // modulo 2^32; exact when in range
+    const uint32_t st15 = stamp & 0x7FFFu;
+    const uint32_t hy = bq[1] ^ 1u, hz = bq[2] ^ 1u;   // the half needed of a trimmed super-box
+    Pieces P;
+    // the open piece [ps, pe); a piece that starts where it ends extends it
+    uint32_t ps = 0, pe = 0;
+    auto put = [&](uint32_t s0, uint32_t s1) {
+        const bool empty = s1 == s0, cont = s0 == pe;
+        const bool flush = !empty && !cont && pe > ps;
+        L.rng[P.m * bs + tid] = (unsigned long long)ps | ((unsigned long long)pe << 32);   // kept if flushed
+        P.m += flush ? 1u : 0u;
+        ps = (!empty && !cont) ? s0 : ps;
+        pe = empty ? pe : s1;
+        P.total += s1 - s0;
+    };
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t dx = (uint32_t(j) >> gx) & 1u, dy = (uint32_t(j) >> gy) & 1u, dz = (uint32_t(j) >> gz) & 1u;
+        const bool in = inx[dx] && iny[dy] && inz[dz];
+        uint4 e = make_uint4(0u, 0u, 0u, 0u);
+        if (in) e = b.cellinfo[base + dz * plane + dy * sd0 + dx];
+        if (super_stamp(e) != st15) e = make_uint4(0u, 0u, 0u, 0u);
+        P.moved = P.moved || ((e.w >> 16) & 1u);
+        const uint32_t c8 = e.y, c2 = e.z & 0xFFFFu, c4 = e.z >> 16, c6 = e.w & 0xFFFFu;
+        const bool split = c8 <= kMaxSplitCount;
+        const bool ty = split && dy == bq[1], tz = split && dz == bq[2];
+        // octant count bounds of the needed y half in the lower (z bit 0) and
+        // the upper (z bit 1) layer of the super-box
+        const uint32_t ylo0 = hy ? c2 : 0u, yhi0 = hy ? c4 : c2;
+        const uint32_t ylo1 = hy ? c6 : c4, yhi1 = hy ? c8 : c6;
+        uint32_t a0 = 0u, a1 = c8;
+        if (tz) {
+            a0 = ty ? (hz ? ylo1 : ylo0) : (hz ? c4 : 0u);
+            a1 = ty ? (hz ? yhi1 : yhi0) : (hz ? c8 : c4);
+        } else if (ty) {
+            a0 = ylo0;
+            a1 = kHull ? yhi1 : yhi0;
         }
-        if (!fn(u)) return false;
-        ++u;
+        put(e.x + a0, e.x + a1);
+        if (!kHull && ty && !tz) put(e.x + ylo1, e.x + yhi1);
+    }
+    L.rng[P.m * bs + tid] = (unsigned long long)ps | ((unsigned long long)pe << 32);
+    P.m += pe > ps ? 1u : 0u;
+    return P;
+}
+
+// The slots of the pieces as one stream in ascending order; a wave iterates
+// max(total) times rather than the sum of per-piece maxima.  fn(slot)
+// returns false to stop; stream_pieces then returns false.
+template <class Fn>
+__device__ __forceinline__ bool stream_pieces(const WalkLds& L, const Pieces& P, Fn&& fn) {
+    const uint32_t tid = threadIdx.x, bs = blockDim.x;
+    if (P.total == 0) return true;
+    unsigned long long v = L.rng[tid];
+    uint32_t u = uint32_t(v), e = uint32_t(v >> 32), k = 0;
+    for (uint32_t j = 0; j < P.total; ++j) {
+        const uint32_t uc = u++;
+        if (u == e && ++k < P.m) {
+            v = L.rng[k * bs + tid];
+            u = uint32_t(v);
+            e = uint32_t(v >> 32);
+        }
+        if (!fn(uc)) return false;
     }
     return true;
 }
@@ -185,17 +234,18 @@ struct ForceSum {
 // F_i over the neighbours j (|e|^2 < R^2) in contact (0 < |e| < r_i + r_j):
 // f = k delta - gamma sqrt(rho delta) along e / |e| (the force-law reading of
 // Section 5).  Evaluated in double, without fused multiply-adds (the library
-// is built with contraction off), in ascending slot order.  `self` is the
-// agent's own slot.
+// is built with contraction off), in ascending slot order.
 //
-// Pass 1 streams the candidates through the cheap pre-test and queues the
-// survivors; a full queue (and the end) is drained by pass 2, which keeps the
+// Pass 1 takes the candidates kChunk slots of one piece at a time (their
+// positions requested together) through the cheap pre-test and queues the
+// survivors (the agent itself among them: the exact test drops d = 0);
+// a nearly full queue (and the end) is drained by pass 2, which keeps the
 // candidates in contact (exact test, in place) and then adds their terms.
 // Queue order is stream order, so the terms are summed in ascending slot
 // order.
 template <class T, bool PARAM_GRADS>
-__device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, uint32_t self, const V4<T>& p,
-                                         const unsigned long long e[8], const WalkLds& L, ForceSum& acc) {
+__device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, const Pieces& P,
+                                         const WalkLds& L, ForceSum& acc) {
     const V4<T>* __restrict__ sp = spos_ptr(b);
     const uint32_t tid = threadIdx.x, bs = blockDim.x, last = b.n - 1;
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
@@ -213,7 +263,7 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 uq[c] = L.queue[min(x0 + c, n - 1) * bs + tid];
-                pj[c] = sp[uq[c]];
+                pj[c] = sp[min(uq[c], last)];
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -226,7 +276,7 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
             }
         }
         for (uint32_t x = 0; x < m; ++x) {   // pair terms, in slot order
-            const V4<T> pj = sp[L.queue[x * bs + tid]];
+            const V4<T> pj = sp[min(L.queue[x * bs + tid], last)];
             const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
             const double s2 = (ex * ex + ey * ey) + ez * ez;
             const double rj = 0.5 * fabs(double(pj.w));
@@ -253,36 +303,41 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
         }
         n = 0;
     };
-    // pass 1: stream the candidates through the pre-test, the next
-    // candidate's position requested one iteration ahead
-    uint32_t total = 0;
+    if (P.total > 0) {
+        // pass 1, kChunk slots of one piece at a time: [u, u + kChunk) of the
+        // piece [.., e), the next piece already read from LDS.  Slots past
+        // the piece end are read (the slot-ordered array is padded) but
+        // never pass.
+        uint32_t kp = 0, qo = n * bs + tid;   // qo: this thread's next queue entry
+        unsigned long long v = L.rng[tid];
+        unsigned long long nxt = L.rng[min(1u, P.m - 1u) * bs + tid];
+        uint32_t u = uint32_t(v), e = uint32_t(v >> 32);
+        while (kp < P.m) {
+            const V4<T>* __restrict__ pu = sp + u;
+            V4<T> pc[kChunk];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        total += super_count(e[q]);
-        L.rng[q * bs + tid] = e[q];
-    }
-    int kr = -1;
-    uint32_t u = 0, end = 0;
-    auto advance = [&]() {
-        while (u >= end && kr < 7) {
-            ++kr;
-            const unsigned long long v = L.rng[kr * bs + tid];
-            u = super_start(v);
-            end = u + super_count(v);
+            for (int c = 0; c < kChunk; ++c) pc[c] = pu[c];
+            const uint32_t left = e - u;
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c) {
+                // no short-circuit: every lane does the same arithmetic
+                const uint32_t pass = uint32_t(uint32_t(c) < left) & uint32_t(maybe_within<T>(p, pc[c], r2pad));
+                L.queue[qo] = u + c;   // n < kQueueCap here
+                n += pass;
+                qo += pass ? bs : 0u;
+            }
+            u += kChunk;
+            if (u >= e) {
+                ++kp;
+                u = uint32_t(nxt);
+                e = uint32_t(nxt >> 32);
+                nxt = L.rng[min(kp + 1u, P.m - 1u) * bs + tid];
+            }
+            if (n > uint32_t(kQueueCap - kChunk)) {
+                drain();
+                qo = tid;
+            }
         }
-    };
-    advance();
-    V4<T> pn = sp[min(u, last)];
-    for (uint32_t j = 0; j < total; ++j) {
-        const uint32_t uc = u;
-        const V4<T> pc = pn;
-        ++u;
-        advance();
-        pn = sp[min(u, last)];
-        const bool pass = uc != self && maybe_within<T>(p, pc, r2pad);
-        L.queue[n * bs + tid] = uc;   // n < kQueueCap here
-        n += pass ? 1u : 0u;
-        if (n == uint32_t(kQueueCap)) drain();
     }
     drain();
 }
@@ -291,13 +346,13 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
 // most one non-zero pair term: true if no agent within R of it moved.
 template <class T>
 __device__ __forceinline__ bool no_moved_neighbour(const Buffers<T>& b, const SimGrid& G, uint32_t self,
-                                                   const V4<T>& p, const unsigned long long e[8],
-                                                   const WalkLds& L) {
+                                                   const V4<T>& p, const Pieces& P, const WalkLds& L) {
+    if (!P.moved) return true;   // nothing in the 8 super-boxes moved
     const V4<T>* __restrict__ sp = spos_ptr(b);
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
     const double r2 = G.r2;
     const float r2pad = padded_r2(r2);
-    return stream_slots(e, L, [&](uint32_t u) {
+    return stream_pieces(L, P, [&](uint32_t u) {
         if (u == self || u >= b.n) return true;
         const V4<T> pj = sp[u];
         if (!(pj.w < T(0))) return true;   // the sign of d carries the moved flag

@@ -1,11 +1,15 @@
 // grid_kernels.hip -- uniform-grid build of one step (Section 3.1) with boxes
-// in gap-free Morton order (Section 4.2, steps D-F):
+// in gap-free Morton order (Section 4.2, steps D-F), counted per super-box
+// (the aligned 2x2x2 blocks of boxes, whose agents are contiguous in that
+// order):
 //   bbox     box extent of the agents (per simulation)
-//   setup    dims, box counts and box bases of every simulation
-//   keys     box key of every agent + histogram (atomics)
-//   scan     exclusive scan of the box counts (tile sums, their scan, rescan)
-//   scatter  agents into box order (arrival order inside a box)
-//   fixup    canonical (box, id) order inside each box + row-major box table
+//   setup    dims, box and super-box counts and bases of every simulation
+//   keys     super-box key and octant of every agent + histogram (atomics)
+//   scan     exclusive scan of the super-box counts (tile sums, their scan,
+//            rescan)
+//   scatter  agents into super-box order (arrival order inside a super-box)
+//   fixup    canonical (box, id) order inside each super-box + the row-major
+//            super-box table
 #include "force_loop.h"
 
 namespace abm {
@@ -216,7 +220,7 @@ constexpr int kSetupThreads = 1024;
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int32_t* rep, int nsims,
                                                            int parity, uint32_t box_capacity) {
-    __shared__ uint32_t s_wave[kSetupThreads / 64];
+    __shared__ unsigned long long s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
     if (threadIdx.x == 0) s_carry = 0;
     // the other accumulator slot and this step's statistics start empty
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
     __syncthreads();
     for (int chunk = 0; chunk < nsims; chunk += kSetupThreads) {
         const int s = chunk + int(threadIdx.x);
-        uint32_t nb = 0;
+        uint32_t nb = 0, nsup = 0;
         if (s < nsims) {
             SimGrid& G = sims[s];
             int32_t bb[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
@@ -260,34 +264,50 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
             G.levels = levels;
             G.valid = ok ? 1u : 0u;
             G.nboxes = ok ? uint32_t(total) : 0u;
+            uint32_t ns = 1;
+            for (int a = 0; a < 3; ++a) {
+                G.sdims[a] = ok ? super_dim(G.dims[a]) : 1u;
+                ns *= G.sdims[a];
+            }
+            G.slevels = levels > 0 ? levels - 1 : 0;
+            G.nsuper = ok ? ns : 0u;
             nb = G.nboxes;
+            nsup = G.nsuper;
             if (!ok) raise_error(g, kErrGrid);
         }
-        // block exclusive scan of nb
-        uint32_t x = nb;
+        // block exclusive scans of nb (box bases) and nsup (super-box bases)
+        unsigned long long x = (unsigned long long)nb | ((unsigned long long)nsup << 32);
         const int lane = int(threadIdx.x & 63u), wave = int(threadIdx.x >> 6);
         for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t y = __shfl_up(x, d, 64);
+            const unsigned long long y = __shfl_up(x, d, 64);
             if (lane >= d) x += y;
         }
         if (lane == 63) s_wave[wave] = x;
         __syncthreads();
-        uint32_t wave_off = 0;
+        unsigned long long wave_off = 0;
         for (int w = 0; w < wave; ++w) wave_off += s_wave[w];
-        const unsigned long long base = s_carry + wave_off + x - nb;
-        if (s < nsims) sims[s].box_base = uint32_t(base);
+        const unsigned long long own = (unsigned long long)nb | ((unsigned long long)nsup << 32);
+        const unsigned long long off = wave_off + x - own;
+        const unsigned long long bbase = (s_carry & 0xFFFFFFFFull) + (off & 0xFFFFFFFFull);
+        const unsigned long long sbase = (s_carry >> 32) + (off >> 32);
+        if (s < nsims) {
+            sims[s].box_base = uint32_t(bbase);
+            sims[s].sbase = uint32_t(sbase);
+        }
         __syncthreads();
-        if (threadIdx.x == kSetupThreads - 1) s_carry = base + nb;
+        // box counts are bounded by the capacities, whose sum fits 32 bits,
+        // so neither half of the packed sums carries into the other
+        if (threadIdx.x == kSetupThreads - 1) s_carry = ((bbase + nb) & 0xFFFFFFFFull) | ((sbase + nsup) << 32);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        unsigned long long total = s_carry;
-        if (total > box_capacity) {
+        unsigned long long total = s_carry >> 32;
+        if (total > box_capacity || total >= kMaxSuperBoxes) {
             raise_error(g, kErrGrid);
             total = 0;
             for (int s = 0; s < nsims; ++s) sims[s].valid = 0;
         }
-        g->total_boxes = uint32_t(total);
+        g->total_super = uint32_t(total);
         // a fresh stamp marks this step's box table entries (the host clears
         // the table before the 15-bit stamp wraps); a fresh epoch tags this
         // step's scan status words
@@ -303,33 +323,57 @@ void launch_setup(const Buffers<T>& b, int parity, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ keys
+// Super-box key and octant of every agent, and its arrival index in the
+// super-box histogram.  Agents of one super-box tend to be neighbours in
+// storage (the previous step's order), so the lanes of a wave take one
+// atomic per run of equal keys and split its result.
 template <class T>
 __global__ void k_keys(Buffers<T> b, int cur) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= b.n) return;
-    const SimGrid& G = b.sims[sim_index(b, i)];
-    if (!G.valid) return;
-    const V4<T> p = pos4_ptr(b, cur)[i];
-    int32_t c[3];
-    const bool ok = box_coord(double(p.x), G.inv_h, &c[0]) && box_coord(double(p.y), G.inv_h, &c[1]) &&
-                    box_coord(double(p.z), G.inv_h, &c[2]);
-    uint32_t q[3];
-    bool in = ok;
-    for (int a = 0; a < 3; ++a) {
-        const int64_t v = int64_t(c[a]) - int64_t(G.cmin[a]);
-        in = in && v >= 0 && v < int64_t(G.dims[a]);
-        q[a] = uint32_t(v);
+    bool act = false;
+    uint32_t sk = 0;
+    if (i < b.n) {
+        const SimGrid& G = b.sims[sim_index(b, i)];
+        if (G.valid) {
+            const V4<T> p = pos4_ptr(b, cur)[i];
+            int32_t c[3];
+            const bool ok = box_coord(double(p.x), G.inv_h, &c[0]) && box_coord(double(p.y), G.inv_h, &c[1]) &&
+                            box_coord(double(p.z), G.inv_h, &c[2]);
+            uint32_t q[3];
+            bool in = ok;
+            for (int a = 0; a < 3; ++a) {
+                const int64_t v = int64_t(c[a]) - int64_t(G.cmin[a]);
+                in = in && v >= 0 && v < int64_t(G.dims[a]);
+                q[a] = uint32_t(v);
+            }
+            if (!in) {  // the extent is computed from these very positions
+                raise_error(b.g, kErrInternal);
+                b.key[i] = 0xFFFFFFFFu;
+            } else {
+                // super-box rank in gap-free Morton order of the super grid;
+                // the octant (x bit lowest) orders the boxes inside it
+                const uint32_t rank =
+                    gapfree_rank(q[0] >> 1, q[1] >> 1, q[2] >> 1, G.sdims[0], G.sdims[1], G.sdims[2], G.slevels);
+                sk = G.sbase + rank;
+                b.key[i] = (sk << 3) | (q[0] & 1u) | ((q[1] & 1u) << 1) | ((q[2] & 1u) << 2);
+                act = true;
+            }
+        }
     }
-    if (!in) {  // the extent is computed from these very positions
-        raise_error(b.g, kErrInternal);
-        b.key[i] = 0xFFFFFFFFu;
-        return;
-    }
-    const uint32_t rank = gapfree_rank(q[0], q[1], q[2], G.dims[0], G.dims[1], G.dims[2], G.levels);
-    const uint32_t key = G.box_base + rank;
-    b.key[i] = key;
-    b.rmi[i] = G.box_base + (q[2] * G.dims[1] + q[1]) * G.dims[0] + q[0];
-    b.sub[i] = atomicAdd(&b.count[key], 1u);
+    const int lane = lane_id();
+    const uint32_t psk = __shfl_up(sk, 1, 64);
+    const int pact = __shfl_up(act ? 1 : 0, 1, 64);
+    const bool head = act && (lane == 0 || !pact || psk != sk);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long brk = __ballot(!act || head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0..lane
+    const int leader = act ? 63 - __clzll((long long)(heads & upto)) : lane;
+    const unsigned long long above = brk & ~upto;
+    const int next = above ? __ffsll((long long)above) - 1 : 64;
+    uint32_t old = 0;
+    if (head) old = atomicAdd(&b.count[sk], uint32_t(next - lane));
+    old = __shfl(old, leader, 64);
+    if (act) b.sub[i] = old + uint32_t(lane - leader);
 }
 
 // ------------------------------------------------------------------ scan
@@ -373,7 +417,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Globals* g, 
                                                                uint32_t* __restrict__ tile_sum, uint32_t ntiles) {
     __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
     __shared__ uint32_t s_wave[kScanThreads / 64];
-    const uint32_t total = g->total_boxes;
+    const uint32_t total = g->total_super;
     const uint32_t tile = blockIdx.x;
     if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
     uint32_t v[kScanItems];
@@ -397,7 +441,7 @@ __global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uin
                                                                   uint32_t ntiles) {
     __shared__ uint32_t s_wave[kTileScanThreads / 64];
     __shared__ uint32_t s_carry;
-    const uint32_t total = g->total_boxes;
+    const uint32_t total = g->total_super;
     const uint32_t needed = (total + kScanTile - 1) / kScanTile;
     if (needed > ntiles) {
         if (threadIdx.x == 0) raise_error(g, kErrInternal);
@@ -428,7 +472,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, ui
                                                              uint32_t ntiles) {
     __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
     __shared__ uint32_t s_wave[kScanThreads / 64];
-    const uint32_t total = g->total_boxes;
+    const uint32_t total = g->total_super;
     const uint32_t tile = blockIdx.x;
     if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
     const uint32_t base = tile * kScanTile;
@@ -466,83 +510,75 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, ui
 }
 
 // ------------------------------------------------------------------ scatter / fixup
+// The scatter writes, per arrival slot, a record {storage index, agent id,
+// first slot of the super-box, agent count << 4 | octant << 1 | moved}, so
+// that the fixup finds everything it needs in the records of its super-box.
 template <class T>
-__global__ void k_scatter(Buffers<T> b) {
+__global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.n) return;
     if (!b.sims[sim_index(b, i)].valid) return;
     const uint32_t key = b.key[i];
-    if (key >= b.g->total_boxes) {
+    const uint32_t sk = key >> 3;
+    if (sk >= b.g->total_super) {
         raise_error(b.g, kErrInternal);
         return;
     }
-    const uint32_t slot = b.cell_start[key] + b.sub[i];
-    if (slot >= b.n) {
+    const uint32_t st = b.cell_start[sk], en = b.cell_start[sk + 1];
+    const uint32_t slot = st + b.sub[i];
+    if (slot >= en || en > b.n) {
         raise_error(b.g, kErrInternal);
         return;
     }
-    b.tmp[slot] = i;
+    b.rec[slot] = make_uint4(i, b.ids[ids_cur][i], st,
+                             ((en - st) << 4) | ((key & 7u) << 1) | (b.flags[cur][i] & kMovedBit));
 }
 
-// Slot t holds agent tmp[t]; its final slot is the start of its box plus the
-// number of agents of that box with a smaller id.  The first agent of each box
-// writes the box's row-major table entry.
+// Arrival slot t holds agent rec[t].x; its final slot is the start of its
+// super-box plus the number of agents of that super-box that come before it
+// in (octant, id) order.  The first agent of each super-box in that order
+// writes the super-box's table entry.
 template <class T>
-__global__ void k_fixup(Buffers<T> b, int cur, int ids_cur) {
+__global__ void k_fixup(Buffers<T> b, int cur, int ids_next) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= b.n) return;
     const SimGrid& G = b.sims[sim_index(b, t)];   // a simulation's slots are its agents' range
     if (!G.valid) return;
-    const uint32_t i = b.tmp[t];
-    if (i >= b.n) {
+    const uint4 me = b.rec[t];
+    const uint32_t i = me.x, st = me.z, cnt = me.w >> 4;
+    if (i >= b.n || st + cnt > b.n || t < st || t >= st + cnt) {
         raise_error(b.g, kErrInternal);
         return;
     }
-    const uint32_t c = b.key[i];
-    if (c >= b.g->total_boxes) {
-        raise_error(b.g, kErrInternal);
-        return;
-    }
-    const uint32_t st = b.cell_start[c], en = b.cell_start[c + 1];
-    if (en > b.n || st > en) {
-        raise_error(b.g, kErrInternal);
-        return;
-    }
-    const uint32_t* ids = b.ids[ids_cur];
-    const uint32_t myid = ids[i];
-    uint32_t r = 0;
-    for (uint32_t u = st; u < en; ++u) {
-        const uint32_t j = b.tmp[u];
-        if (j >= b.n) continue;
-        r += ids[j] < myid ? 1u : 0u;
-    }
-    if (st + r >= b.n) {
-        raise_error(b.g, kErrInternal);
-        return;
+    // the agent's own state, requested before the walk over its super-box
+    V4<T> p = pos4_ptr(b, cur)[i];
+    const uint32_t fl = b.flags[cur][i];
+    const unsigned long long mine = ((unsigned long long)((me.w >> 1) & 7u) << 32) | me.y;
+    uint32_t r = 0, c2 = 0, c4 = 0, c6 = 0;
+    bool moved = false;
+    for (uint32_t u = st; u < st + cnt; ++u) {
+        const uint4 o = b.rec[u];
+        const uint32_t oc = (o.w >> 1) & 7u;
+        r += (((unsigned long long)oc << 32) | o.y) < mine ? 1u : 0u;
+        c2 += oc < 2u ? 1u : 0u;
+        c4 += oc < 4u ? 1u : 0u;
+        c6 += oc < 6u ? 1u : 0u;
+        moved = moved || (o.w & 1u);
     }
     b.perm[st + r] = i;
-    V4<T> p = pos4_ptr(b, cur)[i];
+    b.sflags[st + r] = fl;
+    if (ids_next >= 0) b.ids[ids_next][st + r] = me.y;   // the step re-lays agents out in this order
     const V4<T> pq = p;
-    if (b.flags[cur][i] & kMovedBit) p.w = -p.w;
+    if (me.w & 1u) p.w = -p.w;
     reinterpret_cast<V4<T>*>(b.spos)[st + r] = p;
     if (r == 0) {
-        // the first agent of each box writes its super-box's slot range
-        // (every box of the super-box writes the same entry)
         uint32_t q[3];
         if (!box_of<T>(G, pq, q)) {
             raise_error(b.g, kErrInternal);
             return;
         }
-        uint32_t r0, nin;
-        super_rank_range(G, q, c - G.box_base, &r0, &nin);
-        const uint32_t k0 = G.box_base + r0;
-        const uint32_t s0 = b.cell_start[k0], s1 = b.cell_start[k0 + nin];
-        uint32_t cnt = s1 - s0;
-        if (cnt > kMaxSuperCount) {
-            raise_error(b.g, kErrBoxOverflow);
-            cnt = kMaxSuperCount;
-        }
-        b.cellinfo[super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1)] = pack_super(s0, cnt, b.g->stamp);
+        b.cellinfo[super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1)] =
+            pack_super(st, cnt, c2, c4, c6, moved, b.g->stamp);
     }
 }
 
@@ -556,14 +592,71 @@ __global__ void k_reset_stamp(Globals* g) { g->stamp = 0; }
 template <class T>
 void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_stamp, dim3(1), dim3(1), 0, s, b.g);
-    const uint64_t n = b.box_capacity;
-    hipLaunchKernelGGL(k_clear_u64, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, s, b.cellinfo, n);
+    const uint64_t n = 2ull * b.box_capacity;   // 16-byte entries
+    hipLaunchKernelGGL(k_clear_u64, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long*>(b.cellinfo), n);
     const uint64_t nt = b.scan_tiles;
     hipLaunchKernelGGL(k_clear_u64, dim3(uint32_t((nt + 255) / 256)), dim3(256), 0, s, b.scan_status, nt);
 }
 
+// ------------------------------------------------------------------ rank queries
+// Gap-free Morton rank (plus the simulation's box base) of the box of every
+// slot of the last grid, from the slot-ordered positions that grid was built
+// from; written per slot, or per agent id.
 template <class T>
-void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s, hipEvent_t* const* marks) {
+__global__ void k_box_ranks(Buffers<T> b, int ids_cur, uint32_t* __restrict__ out, int by_id) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= b.n) return;
+    const SimGrid& G = b.sims[sim_index(b, t)];
+    uint32_t rank = 0xFFFFFFFFu;
+    uint32_t q[3];
+    if (G.valid && box_of<T>(G, spos_ptr(b)[t], q))
+        rank = G.box_base + gapfree_rank(q[0], q[1], q[2], G.dims[0], G.dims[1], G.dims[2], G.levels);
+    if (!by_id) {
+        out[t] = rank;
+        return;
+    }
+    const uint32_t i = b.perm[t];
+    const uint32_t id = i < b.n ? b.ids[ids_cur][i] : 0xFFFFFFFFu;
+    if (id >= b.n) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    out[id] = rank;
+}
+
+template <class T>
+void launch_box_ranks(const Buffers<T>& b, int ids_cur, uint32_t* out, bool by_id, hipStream_t s) {
+    hipLaunchKernelGGL(k_box_ranks<T>, dim3((b.n + 255) / 256), dim3(256), 0, s, b, ids_cur, out, by_id ? 1 : 0);
+}
+
+// out[r] = number of slots whose rank is below first_box + r, r = 0..nbox
+// (slot ranks ascend, so a binary search per box).
+__global__ void k_cell_start(const uint32_t* __restrict__ slot_rank, uint32_t n, uint32_t first_box, uint32_t nbox,
+                             uint32_t* __restrict__ out) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > nbox) return;
+    const uint32_t target = first_box + r;
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (slot_rank[mid] < target)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    out[r] = lo;
+}
+
+void launch_cell_start(const uint32_t* slot_rank, uint32_t n, uint32_t first_box, uint32_t nbox, uint32_t* out,
+                       hipStream_t s) {
+    const uint32_t m = nbox + 1;
+    hipLaunchKernelGGL(k_cell_start, dim3((m + 255) / 256), dim3(256), 0, s, slot_rank, n, first_box, nbox, out);
+}
+
+template <class T>
+void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, hipStream_t s,
+                 hipEvent_t* const* marks) {
     const uint32_t blocks = (b.n + 255) / 256;
     auto mark = [&](int k) {
         if (marks) (void)hipEventRecord(*marks[k], s);
@@ -578,9 +671,9 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s, h
     hipLaunchKernelGGL(k_scan_down, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start,
                        tile_sum, b.scan_tiles);
     mark(1);
-    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, ids_cur);
     mark(2);
-    hipLaunchKernelGGL(k_fixup<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, ids_cur);
+    hipLaunchKernelGGL(k_fixup<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, relayout ? ids_cur ^ 1 : -1);
     mark(3);
 }
 
@@ -593,8 +686,9 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, hipStream_t s, h
     template void launch_bbox<T>(const Buffers<T>&, int, int, hipStream_t);                              \
     template void launch_reset_bbox<T>(const Buffers<T>&, int, hipStream_t);                             \
     template void launch_setup<T>(const Buffers<T>&, int, hipStream_t);                                  \
-    template void launch_grid<T>(const Buffers<T>&, int, int, hipStream_t, hipEvent_t* const*);         \
-    template void launch_clear_cellinfo<T>(const Buffers<T>&, hipStream_t);
+    template void launch_grid<T>(const Buffers<T>&, int, int, bool, hipStream_t, hipEvent_t* const*);   \
+    template void launch_clear_cellinfo<T>(const Buffers<T>&, hipStream_t);                              \
+    template void launch_box_ranks<T>(const Buffers<T>&, int, uint32_t*, bool, hipStream_t);
 
 ABM_INSTANTIATE(float)
 ABM_INSTANTIATE(double)

@@ -61,3 +61,29 @@ def test_batched_graph_equals_eager():
     np.testing.assert_array_equal(eager.query("positions").cpu().numpy(), g.query("positions").cpu().numpy())
     ext = g.query("extent").numpy()
     assert ext.shape == (16, 7) and np.all(ext[:, 6] == np.prod(ext[:, 3:6], axis=1))
+
+
+def test_autotuned_batch_matches_plain_runs():
+    """The tuner's choice (box edge, block size, re-layout cadence) runs the
+    batch exactly as plain contexts with the same knobs, also from a graph."""
+    from paper_2301_06984_amd import tune
+    w = small_batch(nsims=12, seed=7)
+    off = w.offsets
+    note(f"autotune {len(off) - 1} sims, n={w.n}")
+    pos, diam = to_dev(w.pos), to_dev(w.diam)
+    res = tune.autotune_batched(pos, diam, off, graph_steps=10, steps=2, warmup=1,
+                                cell_factors=(1.0, 1.5), block_sizes=(128, 256), sort_every=(1, 2, 5))
+    assert len(res.trials) >= 3 and res.ms_per_step > 0
+    assert 10 % res.params["sort_every"] == 0
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = abm.BatchedSim(pos, diam, off, stream=s, common=res.params)
+        g.graph_capture(10)
+        g.graph_launch()
+        g.sync()
+    got = g.query("positions").cpu().numpy()
+    for q in range(len(off) - 1):
+        a, e = off[q], off[q + 1]
+        sim = make_sim(w.pos[a:e], w.diam[a:e], **res.params)
+        sim.step(10)
+        np.testing.assert_array_equal(got[a:e], sim.query("positions").cpu().numpy(), err_msg=f"sim {q}")

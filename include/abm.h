@@ -77,7 +77,8 @@ typedef struct abm_params {
     int32_t sort_every;        /* re-lay out agents in Morton order every k steps; 0 = never */
     int32_t block_size;        /* threads per block of the force kernel: 64..1024, multiple of 64; 0 = 256 */
     int32_t keep_forces;       /* store F_i each step so ABM_FIELD_FORCES can be queried */
-    int32_t reserved;
+    int32_t walk_chunk;        /* candidates the neighbour walk tests together: 2 or 4; 0 = chosen at init
+                                  from the agents per box (4 at one or more, else 2) */
 } abm_params;
 
 /* Grid extent of a set of positions (Section 3.1), as abm_extent reports it. */

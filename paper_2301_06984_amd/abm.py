@@ -36,7 +36,7 @@ class abm_params(C.Structure):
     _fields_ = [("k", C.c_double), ("gamma", C.c_double), ("mu", C.c_double), ("f_adh", C.c_double),
                 ("delta_max", C.c_double), ("interaction_radius", C.c_double), ("cell_factor", C.c_double),
                 ("precision", C.c_int32), ("detect_static", C.c_int32), ("sort_every", C.c_int32),
-                ("block_size", C.c_int32), ("keep_forces", C.c_int32), ("reserved", C.c_int32)]
+                ("block_size", C.c_int32), ("keep_forces", C.c_int32), ("walk_chunk", C.c_int32)]
 
 
 class abm_extent(C.Structure):

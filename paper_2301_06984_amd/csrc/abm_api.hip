@@ -37,7 +37,7 @@ constexpr int kTimedPhases = 6;
 
 struct Layout {
     int64_t globals, sims, sim_of, bbox_rep, pos4[2], ids[2], flags[2], force[2], key, sub, rec, perm, sflags, spos,
-        count, cell_start, cellinfo, scan_status, partials, stage, total;
+        count, cell_start, cellinfo, tile_off, scan_status, partials, stage, total;
     uint32_t scan_tiles, partial_cap;
 };
 
@@ -66,6 +66,7 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.count = take(4 * boxes);
     L.cell_start = take(4 * (boxes + 1));
     L.cellinfo = take(16 * boxes);
+    L.tile_off = take(4 * boxes);
     L.scan_tiles = uint32_t((boxes + kScanTile - 1) / kScanTile);
     if (L.scan_tiles == 0) L.scan_tiles = 1;
     L.scan_status = take(8 * int64_t(L.scan_tiles));
@@ -89,6 +90,7 @@ struct abm_ctx {
     Buffers<double> bd{};
     std::vector<int64_t> offsets;
     abm_params params{};
+    int walk_chunk = 2;      // candidates the neighbour walk tests together (2 or 4)
     // host mirror of the device state
     int64_t step = 0;
     int pos_cur = 0;
@@ -147,6 +149,7 @@ void fill_buffers(abm_ctx* c) {
     b.count = reinterpret_cast<uint32_t*>(w + L.count);
     b.cell_start = reinterpret_cast<uint32_t*>(w + L.cell_start);
     b.cellinfo = reinterpret_cast<uint4*>(w + L.cellinfo);
+    b.tile_off = reinterpret_cast<uint32_t*>(w + L.tile_off);
     b.scan_status = reinterpret_cast<unsigned long long*>(w + L.scan_status);
     b.scan_tiles = L.scan_tiles;
     b.partials = reinterpret_cast<double*>(w + L.partials);
@@ -165,6 +168,8 @@ bool valid_params(const abm_params* p, std::string* why) {
     if (p->sort_every < 0) return *why = "sort_every must be >= 0", false;
     if (p->block_size != 0 && (p->block_size < 64 || p->block_size > 1024 || p->block_size % 64))
         return *why = "block_size must be 0 or a multiple of 64 in [64, 1024]", false;
+    if (p->walk_chunk != 0 && p->walk_chunk != 2 && p->walk_chunk != 4)
+        return *why = "walk_chunk must be 0, 2 or 4", false;
     return true;
 }
 
@@ -235,6 +240,7 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, bool timed = false) {
     a.detect_static = c->params.detect_static != 0;
     a.keep_forces = c->params.keep_forces != 0;
     a.block_size = block_size_of(c->params);
+    a.walk_chunk = c->walk_chunk;
     launch_force<T>(b, a, c->stream);
     if (ev) (void)hipEventRecord((*ev)[kTimedPhases], c->stream);
     c->grid_ids = c->ids_cur;
@@ -335,6 +341,27 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     if (hipGetLastError() != hipSuccess) return bail(fail(ABM_E_HIP, "init kernels failed to launch"));
     const int rc = read_error(c, true);   // also keeps the host arrays alive until the copies are done
     if (rc != ABM_OK) return bail(rc);
+    // the walk width: 4 where boxes hold one or more agents on average
+    // (longer slot ranges), else 2; from the boxes the agents span now
+    c->walk_chunk = p0.walk_chunk;
+    if (c->walk_chunk == 0) {
+        std::vector<int32_t> rep(size_t(kReplicas) * nsims * 6);
+        if (hipMemcpy(rep.data(), b.bbox_rep, rep.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(ABM_E_HIP, "extent read-back failed"));
+        double boxes_total = 0.0;
+        for (int q = 0; q < nsims; ++q) {
+            int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+            for (int r = 0; r < kReplicas; ++r)
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], rep[(size_t(r) * nsims + q) * 6 + a]);
+                    hi[a] = std::max(hi[a], rep[(size_t(r) * nsims + q) * 6 + 3 + a]);
+                }
+            double nb = 1.0;
+            for (int a = 0; a < 3; ++a) nb *= hi[a] >= lo[a] ? double(hi[a]) - double(lo[a]) + 1.0 : 1.0;
+            boxes_total += nb;
+        }
+        c->walk_chunk = double(n) >= boxes_total ? 4 : 2;
+    }
     *out = c;
     return ABM_OK;
 }
@@ -701,6 +728,7 @@ void abm_default_params(abm_params* p) {
     p->sort_every = 1;
     p->block_size = 256;
     p->keep_forces = 0;
+    p->walk_chunk = 0;
 }
 
 const char* abm_last_error(void) { return g_last_error.c_str(); }
@@ -784,6 +812,8 @@ int abm_set_params(abm_ctx* c, const abm_params* p) {
     c->params.sort_every = p->sort_every;
     c->params.block_size = p->block_size;
     c->params.keep_forces = keep;
+    if (p->walk_chunk) c->walk_chunk = p->walk_chunk;
+    c->params.walk_chunk = p->walk_chunk;
     HIP_TRY(hipGetLastError());
     return ABM_OK;
 }

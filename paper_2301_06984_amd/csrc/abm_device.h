@@ -34,39 +34,48 @@ __device__ __forceinline__ bool box_coord(double x, double inv_h, int32_t* c) {
 // interleave).  Computed as the number of boxes of the space that precede q in
 // Morton order: walking from the root of the implicit octree down to q, add
 // the in-space boxes of every sibling subtree that comes before q's child.
-// A subtree's in-space boxes are a product of three clamped widths, so no
-// table is needed.  Requires dims[0]*dims[1]*dims[2] < 2^32.
+// With r the in-space width of the current node from its origin (per axis),
+// the node spans min(r, 2h) and its lower half min(r, h) boxes, h = 2^level,
+// so a subtree's in-space boxes are a product of three such widths and no
+// table is needed.  Requires dims[0]*dims[1]*dims[2] < 2^32 and
+// 2^levels >= max(dims).
 __device__ __forceinline__ uint32_t gapfree_rank(uint32_t qx, uint32_t qy, uint32_t qz, uint32_t dx, uint32_t dy,
                                                  uint32_t dz, int levels) {
-    uint32_t r = 0, ox = 0, oy = 0, oz = 0;
+    uint32_t r = 0, rx = dx, ry = dy, rz = dz;
     for (int lev = levels - 1; lev >= 0; --lev) {
         const uint32_t h = 1u << lev;
         const uint32_t bx = (qx >> lev) & 1u, by = (qy >> lev) & 1u, bz = (qz >> lev) & 1u;
-        const uint32_t rx = dx - ox, ry = dy - oy, rz = dz - oz;       // >= 1: q lies in this node
-        const uint32_t x0 = min(rx, h), x1 = rx > h ? min(rx - h, h) : 0u;
-        const uint32_t y0 = min(ry, h), y1 = ry > h ? min(ry - h, h) : 0u;
-        const uint32_t z0 = min(rz, h), z1 = rz > h ? min(rz - h, h) : 0u;
-        const uint32_t wz = bz ? z1 : z0;
-        const uint32_t wy = by ? y1 : y0;
-        if (bz) r += (x0 + x1) * (y0 + y1) * z0;
-        if (by) r += (x0 + x1) * y0 * wz;
-        if (bx) r += x0 * wy * wz;
-        ox += bx * h;
-        oy += by * h;
-        oz += bz * h;
+        const uint32_t Wx = min(rx, 2u * h), Wy = min(ry, 2u * h), Wz = min(rz, 2u * h);
+        const uint32_t lx = min(rx, h), ly = min(ry, h), lz = min(rz, h);
+        const uint32_t wy = by ? Wy - ly : ly, wz = bz ? Wz - lz : lz;
+        if (bz) r += Wx * Wy * lz;   // the lower z half of the node
+        if (by) r += Wx * ly * wz;   // the lower y half of q's z half
+        if (bx) r += lx * wy * wz;   // the lower x half of q's y quarter
+        rx -= bx ? h : 0u;
+        ry -= by ? h : 0u;
+        rz -= bz ? h : 0u;
     }
     return r;
 }
 
 __device__ __forceinline__ void raise_error(Globals* g, uint32_t bits) { atomicOr(&g->err, bits); }
 
-// Blocks are handed to the 8 XCDs round-robin; remap so that each XCD works on
-// one contiguous range of slots (neighbouring slots share their L2).
-__device__ __forceinline__ uint32_t xcd_block(uint32_t launched) {
-    const uint32_t per = launched >> 3;
-    return (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+// Blocks are handed to the 8 XCDs round-robin.  Remap them so that each XCD
+// works on runs of `run` consecutive logical blocks (neighbouring slots share
+// that XCD's L2), the runs dealt to the XCDs in turn, so that every XCD gets
+// a share of every region of the slot range (the cost per slot varies with
+// the region).  `launched` is a multiple of 8 * run.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t run) {
+    const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;   // XCD, and its k-th block
+    return ((k / run) * 8u + x) * run + k % run;
 }
-inline uint32_t xcd_grid(uint32_t blocks) { return (blocks + 7u) & ~7u; }
+// Run length for a launch of `blocks` blocks (at most 64, at least one run
+// per XCD).
+inline uint32_t xcd_run(uint32_t blocks) {
+    uint32_t run = blocks / 64u;
+    return run < 1u ? 1u : (run > 64u ? 64u : run);
+}
+inline uint32_t xcd_grid(uint32_t blocks, uint32_t run) { return (blocks + 8u * run - 1u) / (8u * run) * (8u * run); }
 
 __device__ __forceinline__ int lane_id() { return int(threadIdx.x & 63u); }
 

@@ -23,6 +23,7 @@
 //   per super-box (capacity = sum of the per-simulation box capacities):
 //     count       histogram; every scan leaves it zeroed for the next step
 //     cell_start  exclusive prefix sum of count (+1 entry)
+//     tile_off    rank of the first super-box of every tile (2^tlev super-boxes per axis)
 //     cellinfo    row-major super-box table, 16 B per entry (SuperEntry); an
 //                 entry whose stamp is not the current step's is empty, so
 //                 the table is never cleared between steps (the timestamp
@@ -75,6 +76,11 @@ struct SimGrid {
     uint32_t nsuper;        // sdims[0] * sdims[1] * sdims[2]
     uint32_t sbase;         // first global super-box index of this simulation
     int32_t slevels;        // smallest L with 2^L >= max(sdims)
+    // super-boxes are ranked through tiles of 2^tlev super-boxes per axis: the
+    // rank of a tile's first super-box (a table) plus the rank inside the tile
+    int32_t tlev;
+    uint32_t tdims[3];
+    uint32_t ntiles;
     // min x,y,z then max x,y,z of the box coordinates (extent queries only;
     // the step keeps its accumulators in Buffers::bbox_rep)
     int32_t bbox[2][6];
@@ -86,6 +92,7 @@ struct Globals {
     uint32_t total_super;    // super-boxes of all simulations in this step's grid
     uint32_t stamp;          // of the current step's super-box table entries (1..32767)
     uint32_t scan_epoch;     // tag of the current step's scan status words (never 0)
+    uint32_t tiles_dirty;    // some simulation's super grid changed: rebuild the tile table
     unsigned long long scan_ticket;
     // per step parity and replica: agents skipped as static, agents moved
     unsigned long long stats[2][kReplicas][2];
@@ -116,6 +123,7 @@ struct Buffers {
     uint32_t* count;
     uint32_t* cell_start;
     uint4* cellinfo;
+    uint32_t* tile_off;       // per tile (at the simulation's super-box base): rank of its first super-box
     unsigned long long* scan_status;
     double* partials;         // per-block partial sums (adjoint)
     uint32_t partial_cap;
@@ -133,6 +141,7 @@ struct StepArgs {
     bool detect_static;
     bool keep_forces;
     int block_size;
+    int walk_chunk;         // 2 or 4 candidate slots tested together by the neighbour walk
 };
 
 constexpr uint32_t kStampPeriod = 32767;   // 15-bit stamps in the super-box table

@@ -13,6 +13,7 @@
 namespace abm {
 
 constexpr int kAdjThreads = 256;
+constexpr int kAdjChunk = 4;   // candidates the walk of the reverse step tests together
 
 int adj_blocks(uint32_t n) { return int((n + kAdjThreads - 1) / kAdjThreads); }
 
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, co
         if (G.valid && box_of<T>(G, p, q)) {
             const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
             ForceSum acc;
-            force_of<T, true>(b, G, p, P, L, acc);
+            force_of<kAdjChunk, T, true>(b, G, p, P, L, acc);
             const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
             if (m.moves) {
                 const double li[3] = {lam[3 * size_t(i)], lam[3 * size_t(i) + 1], lam[3 * size_t(i) + 2]};

@@ -25,18 +25,19 @@ constexpr int kMaxBlockSims = 4;
 #ifndef ABM_FORCE_WAVES_PER_EU
 #define ABM_FORCE_WAVES_PER_EU 1
 #endif
-template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT>
+template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT, int CH>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_WAVES_PER_EU))) void k_force(
-    Buffers<T> b, StepArgs a, uint32_t launched) {
+    Buffers<T> b, StepArgs a, uint32_t run) {
     extern __shared__ __align__(16) unsigned char s_walk[];
     __shared__ int32_t s_box[kMaxBlockSims][6];
     __shared__ int s_sims[kMaxBlockSims];
     __shared__ uint32_t s_cnt[3];   // static, moved, waves done
     const WalkLds L = walk_lds(s_walk);
-    const uint32_t t = xcd_block(launched) * blockDim.x + threadIdx.x;
+    const uint32_t blk = xcd_block(run);
+    const uint32_t t = blk * blockDim.x + threadIdx.x;
     // the block's slots belong to at most kMaxBlockSims simulations (the
     // first and last slot bound them); their LDS accumulators start empty
-    const uint32_t t0 = xcd_block(launched) * blockDim.x;
+    const uint32_t t0 = blk * blockDim.x;
     const int sim0 = BATCHED && t0 < b.n ? sim_index(b, t0) : 0;
     if (threadIdx.x < kMaxBlockSims * 6) {
         const int k = int(threadIdx.x) % 6;
@@ -82,18 +83,26 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
             uint32_t q[3];
             if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
             const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
-            // at step 0 every agent carries the moved bit, so none is static
-            if (STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u) is_static = no_moved_neighbour(b, G, t, p, P, L);
+            // Static test (Section 5): the agent did not move, had at most one
+            // non-zero pair term, and no agent within R moved.  At step 0
+            // every agent carries the moved bit, so none is static.  With no
+            // moved agent in the 27 boxes it holds at once; otherwise the
+            // force walk itself reports a moved agent within R.
+            const bool cand = STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u;
+            is_static = cand && !P.moved;
             p.w = T(fabs(double(p.w)));
             V4<T> np = p;
-            uint32_t nf;
+            uint32_t nf = 0;
+            ForceSum acc;
+            if (!is_static) {
+                force_of<CH, T, false>(b, G, p, P, L, acc);
+                is_static = cand && !acc.moved_near;
+            }
             if (is_static) {
                 nf = kStaticBit | (f & ~(kMovedBit | kStaticBit));
                 if (KEEP_F)
                     for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
             } else {
-                ForceSum acc;
-                force_of<T, false>(b, G, p, P, L, acc);
                 const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
                 np.x = T(double(p.x) + m.ux);
                 np.y = T(double(p.y) + m.uy);
@@ -170,27 +179,36 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
     }
 }
 
-template <class T, bool S, bool K, bool R>
+template <class T, bool S, bool K, bool R, int CH>
 static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
     const int bs = a.block_size;
     const uint32_t blocks = (b.n + bs - 1) / bs;
-    const uint32_t launched = xcd_grid(blocks);
-    hipLaunchKernelGGL((k_force<T, S, K, R>), dim3(launched), dim3(bs), walk_lds_bytes(bs), s, b, a, launched);
+    const uint32_t run = xcd_run(blocks);
+    hipLaunchKernelGGL((k_force<T, S, K, R, CH>), dim3(xcd_grid(blocks, run)), dim3(bs), walk_lds_bytes(bs), s, b, a,
+                       run);
+}
+
+template <class T, int CH>
+static void launch_force_c(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
+    const int v = (b.sim_of ? 4 : 0) | (a.detect_static ? 2 : 0) | (a.relayout ? 1 : 0);
+    switch (v) {
+        case 0: launch_force_v<T, false, false, false, CH>(b, a, s); break;
+        case 1: launch_force_v<T, false, false, true, CH>(b, a, s); break;
+        case 2: launch_force_v<T, false, true, false, CH>(b, a, s); break;
+        case 3: launch_force_v<T, false, true, true, CH>(b, a, s); break;
+        case 4: launch_force_v<T, true, false, false, CH>(b, a, s); break;
+        case 5: launch_force_v<T, true, false, true, CH>(b, a, s); break;
+        case 6: launch_force_v<T, true, true, false, CH>(b, a, s); break;
+        default: launch_force_v<T, true, true, true, CH>(b, a, s); break;
+    }
 }
 
 template <class T>
 void launch_force(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
-    const int v = (b.sim_of ? 4 : 0) | (a.detect_static ? 2 : 0) | (a.relayout ? 1 : 0);
-    switch (v) {
-        case 0: launch_force_v<T, false, false, false>(b, a, s); break;
-        case 1: launch_force_v<T, false, false, true>(b, a, s); break;
-        case 2: launch_force_v<T, false, true, false>(b, a, s); break;
-        case 3: launch_force_v<T, false, true, true>(b, a, s); break;
-        case 4: launch_force_v<T, true, false, false>(b, a, s); break;
-        case 5: launch_force_v<T, true, false, true>(b, a, s); break;
-        case 6: launch_force_v<T, true, true, false>(b, a, s); break;
-        default: launch_force_v<T, true, true, true>(b, a, s); break;
-    }
+    if (a.walk_chunk == 4)
+        launch_force_c<T, 4>(b, a, s);
+    else
+        launch_force_c<T, 2>(b, a, s);
 }
 
 // ------------------------------------------------------------------ copies

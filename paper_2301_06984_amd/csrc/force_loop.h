@@ -37,19 +37,22 @@ __device__ __forceinline__ const V4<T>* spos_ptr(const Buffers<T>& b) {
 
 // Super-box table entry (16 B):
 //   x  first slot of the super-box
-//   y  number of its agents
+//   y  number of its agents (bits 0..23); bit 24 + o: an agent of octant o
+//      moved in the last step
 //   z  agents in octants < 2 (bits 0..15) and in octants < 4 (bits 16..31)
-//   w  agents in octants < 6 (bits 0..15), any agent moved in the last step
-//      (bit 16), 15-bit stamp of the step that wrote the entry (bits 17..31)
+//   w  agents in octants < 6 (bits 0..15), 15-bit stamp of the step that
+//      wrote the entry (bits 17..31)
 // With more than kMaxSplitCount agents the octant counts are not kept and
-// the whole range is walked.
+// the whole range is walked; kMaxSuperCount agents is the limit (grid error
+// beyond).
 constexpr uint32_t kMaxSplitCount = 0xFFFFu;
+constexpr uint32_t kMaxSuperCount = 0xFFFFFFu;
 
 __device__ __forceinline__ uint4 pack_super(uint32_t start, uint32_t total, uint32_t c2, uint32_t c4, uint32_t c6,
-                                            bool moved, uint32_t stamp) {
+                                            uint32_t moved_octants, uint32_t stamp) {
     if (total > kMaxSplitCount) c2 = c4 = c6 = 0u;
-    return make_uint4(start, total, (c2 & 0xFFFFu) | (c4 << 16),
-                      (c6 & 0xFFFFu) | (moved ? 1u << 16 : 0u) | ((stamp & 0x7FFFu) << 17));
+    return make_uint4(start, (total & kMaxSuperCount) | (moved_octants << 24), (c2 & 0xFFFFu) | (c4 << 16),
+                      (c6 & 0xFFFFu) | ((stamp & 0x7FFFu) << 17));
 }
 __device__ __forceinline__ uint32_t super_stamp(const uint4& e) { return e.w >> 17; }
 
@@ -79,48 +82,35 @@ __device__ __forceinline__ bool box_of(const SimGrid& G, const V4<T>& p, uint32_
 // Per-thread scratch in LDS for the neighbour walk: the pieces (start slot in
 // the low, end slot in the high 32 bits) and a queue of candidate slots.  Laid
 // out [entry][thread] so that the threads of a wave hit distinct banks.
-// Build-time tuning of the walk (LDS per thread = kMaxPieces * 8 + kQueueCap * 4
-// bytes, which bounds the waves per CU):
-//   ABM_WALK_CHUNK   slots of one piece tested together (1..kSposPad)
-//   ABM_WALK_QUEUE   queue entries (> ABM_WALK_CHUNK)
-//   ABM_WALK_HULL    1: a super-box whose y half is cut but whose z is not
-//                    gives one piece (octants 2h..2h+5) instead of two
-#ifndef ABM_WALK_CHUNK
-#define ABM_WALK_CHUNK 4
-#endif
-#ifndef ABM_WALK_QUEUE
-#define ABM_WALK_QUEUE 10
-#endif
-#ifndef ABM_WALK_HULL
-#define ABM_WALK_HULL 1
-#endif
-constexpr bool kHull = ABM_WALK_HULL != 0;
-constexpr int kMaxPieces = kHull ? 8 : 10;
-constexpr int kQueueCap = ABM_WALK_QUEUE;
-constexpr int kChunk = ABM_WALK_CHUNK;   // slots of one piece tested together in the walk
-static_assert(kChunk >= 1 && kQueueCap > kChunk, "walk tuning");
-static_assert(kChunk <= kSposPad, "the walk reads up to kChunk - 1 slots past a piece");
+// LDS per thread of the walk: kPieces * 8 + kQueueCap * 4 bytes, which
+// bounds the waves per CU.  The walk tests CH = 2 or 4 candidate slots of a
+// piece together (4 pays off where boxes hold one or more agents).
+constexpr int kPieces = 8;   // one per super-box of the 2x2x2 block, in Morton order
+constexpr int kQueueCap = 10;
+static_assert(4 <= kSposPad, "the walk reads up to 3 slots past a piece");
 struct WalkLds {
-    unsigned long long* rng;   // [kMaxPieces][blockDim]
+    unsigned long long* rng;   // [kPieces][blockDim]
     uint32_t* queue;           // [kQueueCap][blockDim]
 };
-inline size_t walk_lds_bytes(int block) { return size_t(block) * (kMaxPieces * 8 + kQueueCap * 4); }
+inline size_t walk_lds_bytes(int block) { return size_t(block) * (kPieces * 8 + kQueueCap * 4); }
 
 __device__ __forceinline__ WalkLds walk_lds(void* base) {
     WalkLds w;
     w.rng = static_cast<unsigned long long*>(base);
-    w.queue = reinterpret_cast<uint32_t*>(w.rng + kMaxPieces * blockDim.x);
+    w.queue = reinterpret_cast<uint32_t*>(w.rng + kPieces * blockDim.x);
     return w;
 }
 
 struct Pieces {
-    uint32_t m = 0;       // non-empty pieces, in slot order, in WalkLds::rng
+    uint32_t mask = 0;    // bit j: piece j (Morton position j of its super-box) is not empty
     uint32_t total = 0;   // slots in all pieces
-    bool moved = false;   // an agent of one of the 8 super-boxes moved in the last step
+    bool moved = false;   // an agent of one of the 27 boxes moved in the last step
 };
 
 // Load the pieces around box q (entries of the current stamp only) into this
-// thread's LDS rows.
+// thread's LDS rows, piece j at row j.  The super-boxes are visited in
+// row-major order, so that their table offsets and range tests are fixed
+// per visit; each writes its piece at its Morton position.
 template <class T>
 __device__ __forceinline__ Pieces load_pieces(const Buffers<T>& b, const SimGrid& G, const uint32_t q[3],
                                               uint32_t stamp, const WalkLds& L) {
@@ -133,10 +123,10 @@ __device__ __forceinline__ Pieces load_pieces(const Buffers<T>& b, const SimGrid
         lo[a] = (q[a] >> 1) - 1u + bq[a];   // wraps below 0: then out of range
         rank_key[a] = 3u * uint32_t(__builtin_ctz(~lo[a] | 0x80000000u)) + uint32_t(a);
     }
-    // digit of each axis in the Morton order of the 8 super-boxes
-    const uint32_t gx = (rank_key[0] > rank_key[1] ? 1u : 0u) + (rank_key[0] > rank_key[2] ? 1u : 0u);
-    const uint32_t gy = (rank_key[1] > rank_key[0] ? 1u : 0u) + (rank_key[1] > rank_key[2] ? 1u : 0u);
-    const uint32_t gz = (rank_key[2] > rank_key[0] ? 1u : 0u) + (rank_key[2] > rank_key[1] ? 1u : 0u);
+    // weight of each axis in the Morton position of a super-box of the block
+    const uint32_t wx = 1u << ((rank_key[0] > rank_key[1] ? 1u : 0u) + (rank_key[0] > rank_key[2] ? 1u : 0u));
+    const uint32_t wy = 1u << ((rank_key[1] > rank_key[0] ? 1u : 0u) + (rank_key[1] > rank_key[2] ? 1u : 0u));
+    const uint32_t wz = 1u << ((rank_key[2] > rank_key[0] ? 1u : 0u) + (rank_key[2] > rank_key[1] ? 1u : 0u));
     const bool inx[2] = {lo[0] < sd0, lo[0] + 1u < sd0};
     const bool iny[2] = {lo[1] < sd1, lo[1] + 1u < sd1};
     const bool inz[2] = {lo[2] < sd2, lo[2] + 1u < sd2};
@@ -144,27 +134,22 @@ __device__ __forceinline__ Pieces load_pieces(const Buffers<T>& b, const SimGrid
     const uint32_t base = G.sbase + (lo[2] * sd1 + lo[1]) * sd0 + lo[0];   // modulo 2^32; exact when in range
     const uint32_t st15 = stamp & 0x7FFFu;
     const uint32_t hy = bq[1] ^ 1u, hz = bq[2] ^ 1u;   // the half needed of a trimmed super-box
+    // octants of the super-box at offset d (per axis) that hold boxes of the
+    // 3x3x3 block: all, or only the half on the near side
+    const uint32_t xm[2] = {bq[0] ? 0xFFu : 0xAAu, bq[0] ? 0x55u : 0xFFu};
+    const uint32_t ym[2] = {bq[1] ? 0xFFu : 0xCCu, bq[1] ? 0x33u : 0xFFu};
+    const uint32_t zm[2] = {bq[2] ? 0xFFu : 0xF0u, bq[2] ? 0x0Fu : 0xFFu};
+    uint32_t moved = 0;
     Pieces P;
-    // the open piece [ps, pe); a piece that starts where it ends extends it
-    uint32_t ps = 0, pe = 0;
-    auto put = [&](uint32_t s0, uint32_t s1) {
-        const bool empty = s1 == s0, cont = s0 == pe;
-        const bool flush = !empty && !cont && pe > ps;
-        L.rng[P.m * bs + tid] = (unsigned long long)ps | ((unsigned long long)pe << 32);   // kept if flushed
-        P.m += flush ? 1u : 0u;
-        ps = (!empty && !cont) ? s0 : ps;
-        pe = empty ? pe : s1;
-        P.total += s1 - s0;
-    };
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const uint32_t dx = (uint32_t(j) >> gx) & 1u, dy = (uint32_t(j) >> gy) & 1u, dz = (uint32_t(j) >> gz) & 1u;
-        const bool in = inx[dx] && iny[dy] && inz[dz];
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t dx = uint32_t(c) & 1u, dy = (uint32_t(c) >> 1) & 1u, dz = uint32_t(c) >> 2;
         uint4 e = make_uint4(0u, 0u, 0u, 0u);
-        if (in) e = b.cellinfo[base + dz * plane + dy * sd0 + dx];
+        if (inx[dx] && iny[dy] && inz[dz]) e = b.cellinfo[base + dz * plane + dy * sd0 + dx];
         if (super_stamp(e) != st15) e = make_uint4(0u, 0u, 0u, 0u);
-        P.moved = P.moved || ((e.w >> 16) & 1u);
-        const uint32_t c8 = e.y, c2 = e.z & 0xFFFFu, c4 = e.z >> 16, c6 = e.w & 0xFFFFu;
+        moved |= (e.y >> 24) & xm[dx] & ym[dy] & zm[dz];
+        const uint32_t c8 = e.y & kMaxSuperCount, c2 = e.z & 0xFFFFu, c4 = e.z >> 16, c6 = e.w & 0xFFFFu;
+        // the y (z) half of this super-box is cut when it lies on the far side
         const bool split = c8 <= kMaxSplitCount;
         const bool ty = split && dy == bq[1], tz = split && dz == bq[2];
         // octant count bounds of the needed y half in the lower (z bit 0) and
@@ -175,15 +160,16 @@ __device__ __forceinline__ Pieces load_pieces(const Buffers<T>& b, const SimGrid
         if (tz) {
             a0 = ty ? (hz ? ylo1 : ylo0) : (hz ? c4 : 0u);
             a1 = ty ? (hz ? yhi1 : yhi0) : (hz ? c8 : c4);
-        } else if (ty) {
+        } else if (ty) {   // y cut, z not: one piece over octants 2h..2h+5
             a0 = ylo0;
-            a1 = kHull ? yhi1 : yhi0;
+            a1 = yhi1;
         }
-        put(e.x + a0, e.x + a1);
-        if (!kHull && ty && !tz) put(e.x + ylo1, e.x + yhi1);
+        const uint32_t j = dx * wx + dy * wy + dz * wz;
+        L.rng[j * bs + tid] = (unsigned long long)(e.x + a0) | ((unsigned long long)(e.x + a1) << 32);
+        P.mask |= (a1 > a0 ? 1u : 0u) << j;
+        P.total += a1 - a0;
     }
-    L.rng[P.m * bs + tid] = (unsigned long long)ps | ((unsigned long long)pe << 32);
-    P.m += pe > ps ? 1u : 0u;
+    P.moved = moved != 0u;
     return P;
 }
 
@@ -193,19 +179,79 @@ __device__ __forceinline__ Pieces load_pieces(const Buffers<T>& b, const SimGrid
 template <class Fn>
 __device__ __forceinline__ bool stream_pieces(const WalkLds& L, const Pieces& P, Fn&& fn) {
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
-    if (P.total == 0) return true;
-    unsigned long long v = L.rng[tid];
-    uint32_t u = uint32_t(v), e = uint32_t(v >> 32), k = 0;
-    for (uint32_t j = 0; j < P.total; ++j) {
-        const uint32_t uc = u++;
-        if (u == e && ++k < P.m) {
+    uint32_t M = P.mask;
+    if (!M) return true;
+    uint32_t k = uint32_t(__ffs(M)) - 1u;
+    M &= M - 1u;
+    unsigned long long v = L.rng[k * bs + tid];
+    uint32_t u = uint32_t(v), e = uint32_t(v >> 32);
+    for (;;) {
+        if (!fn(u)) return false;
+        if (++u == e) {
+            if (!M) break;
+            k = uint32_t(__ffs(M)) - 1u;
+            M &= M - 1u;
             v = L.rng[k * bs + tid];
             u = uint32_t(v);
             e = uint32_t(v >> 32);
         }
-        if (!fn(uc)) return false;
     }
     return true;
+}
+
+// The pieces CH slots at a time, with the positions of the next chunk
+// requested before the current one is tested (two register buffers, A and B,
+// take turns).  A chunk is [u, u + CH) of a piece [.., e); the next
+// non-empty piece is already read from LDS.  Slots past the piece end are
+// read (the slot-ordered array is padded) but must not be used:
+// test(pc, u, left) sees the chunk's positions, its first slot and the
+// number of its slots inside the piece, and returns false to stop the walk.
+template <int CH, class T, class Test>
+__device__ __forceinline__ void walk_chunks(const Buffers<T>& b, const Pieces& P, const WalkLds& L, Test&& test) {
+    static_assert(CH >= 1 && CH <= kSposPad && kQueueCap > CH, "walk chunk");
+    if (!P.mask) return;
+    const V4<T>* __restrict__ sp = spos_ptr(b);
+    const uint32_t tid = threadIdx.x, bs = blockDim.x;
+    uint32_t M = P.mask;
+    const uint32_t k0 = uint32_t(__ffs(M)) - 1u;
+    M &= M - 1u;
+    const unsigned long long v0 = L.rng[k0 * bs + tid];
+    unsigned long long nxt = L.rng[(M ? uint32_t(__ffs(M)) - 1u : k0) * bs + tid];
+    const uint32_t safe = uint32_t(v0);   // a slot whose chunk lies in the array
+    // move (uu, ee) to the chunk after it; false at the end of the stream
+    auto advance = [&](uint32_t& uu, uint32_t& ee) -> bool {
+        uu += CH;
+        if (uu < ee) return true;
+        if (!M) return false;
+        uu = uint32_t(nxt);
+        ee = uint32_t(nxt >> 32);
+        M &= M - 1u;
+        if (M) nxt = L.rng[(uint32_t(__ffs(M)) - 1u) * bs + tid];
+        return true;
+    };
+    auto fetch = [&](V4<T>* pc, uint32_t uu, bool has) {
+        const V4<T>* __restrict__ pu = sp + (has ? uu : safe);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) pc[c] = pu[c];
+    };
+    V4<T> pa[CH], pb[CH];
+    uint32_t ua = uint32_t(v0), ea = uint32_t(v0 >> 32);
+    fetch(pa, ua, true);
+    uint32_t ub = ua, eb = ea;
+    bool hb = advance(ub, eb);
+    fetch(pb, ub, hb);
+    for (;;) {
+        if (!test(pa, ua, ea - ua) || !hb) break;
+        ua = ub;
+        ea = eb;
+        const bool ha = advance(ua, ea);
+        fetch(pa, ua, ha);
+        if (!test(pb, ub, eb - ub) || !ha) break;
+        ub = ua;
+        eb = ea;
+        hb = advance(ub, eb);
+        fetch(pb, ub, hb);
+    }
 }
 
 // Conservative single-precision pre-test of |x_i - x_j|^2 < R^2 for float
@@ -229,6 +275,7 @@ struct ForceSum {
     double kx = 0.0, ky = 0.0, kz = 0.0;   // dF_i/dk    = sum_j delta_ij u_ij
     double gx = 0.0, gy = 0.0, gz = 0.0;   // dF_i/dgamma = -sum_j sqrt(rho_ij delta_ij) u_ij
     uint32_t nnz = 0;
+    bool moved_near = false;               // an agent within R (not i) moved in the last step
 };
 
 // F_i over the neighbours j (|e|^2 < R^2) in contact (0 < |e| < r_i + r_j):
@@ -236,14 +283,14 @@ struct ForceSum {
 // Section 5).  Evaluated in double, without fused multiply-adds (the library
 // is built with contraction off), in ascending slot order.
 //
-// Pass 1 takes the candidates kChunk slots of one piece at a time (their
+// Pass 1 takes the candidates CH slots of one piece at a time (their
 // positions requested together) through the cheap pre-test and queues the
 // survivors (the agent itself among them: the exact test drops d = 0);
 // a nearly full queue (and the end) is drained by pass 2, which keeps the
 // candidates in contact (exact test, in place) and then adds their terms.
 // Queue order is stream order, so the terms are summed in ascending slot
 // order.
-template <class T, bool PARAM_GRADS>
+template <int CH, class T, bool PARAM_GRADS>
 __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, const Pieces& P,
                                          const WalkLds& L, ForceSum& acc) {
     const V4<T>* __restrict__ sp = spos_ptr(b);
@@ -270,96 +317,68 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
                 const double ex = xi - double(pj[c].x), ey = yi - double(pj[c].y), ez = zi - double(pj[c].z);
                 const double s2 = (ex * ex + ey * ey) + ez * ez;
                 const double S = ri + 0.5 * fabs(double(pj[c].w));
-                const bool keep = x0 + c < n && s2 < r2 && s2 > 0.0 && s2 < S * S;
+                const bool within = x0 + c < n && s2 < r2;
+                // the sign of d carries the moved flag (the agent itself counts
+                // only where this feeds a static test, and then it did not move)
+                acc.moved_near = acc.moved_near || (within && pj[c].w < T(0));
+                const bool keep = within && s2 > 0.0 && s2 < S * S;
                 L.queue[m * bs + tid] = uq[c];
                 m += keep ? 1u : 0u;
             }
         }
-        for (uint32_t x = 0; x < m; ++x) {   // pair terms, in slot order
-            const V4<T> pj = sp[min(L.queue[x * bs + tid], last)];
-            const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
-            const double s2 = (ex * ex + ey * ey) + ez * ez;
-            const double rj = 0.5 * fabs(double(pj.w));
-            const double S = ri + rj;
-            const double dist = sqrt(s2);
-            const double delta = S - dist;
-            const double rho = (ri * rj) / S;
-            const double sr = sqrt(rho * delta);
-            const double f = k * delta - gamma * sr;
-            const double sc = f / dist;
-            acc.fx += sc * ex;
-            acc.fy += sc * ey;
-            acc.fz += sc * ez;
-            acc.nnz += f != 0.0 ? 1u : 0u;
-            if (PARAM_GRADS) {
-                const double ux = ex / dist, uy = ey / dist, uz = ez / dist;
-                acc.kx += delta * ux;
-                acc.ky += delta * uy;
-                acc.kz += delta * uz;
-                acc.gx -= sr * ux;
-                acc.gy -= sr * uy;
-                acc.gz -= sr * uz;
+        for (uint32_t x0 = 0; x0 < m; x0 += 4) {   // pair terms, in slot order, four positions requested together
+            V4<T> pj4[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pj4[c] = sp[min(L.queue[min(x0 + c, m - 1) * bs + tid], last)];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (x0 + c >= m) break;
+                const V4<T>& pj = pj4[c];
+                const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
+                const double s2 = (ex * ex + ey * ey) + ez * ez;
+                const double rj = 0.5 * fabs(double(pj.w));
+                const double S = ri + rj;
+                const double dist = sqrt(s2);
+                const double delta = S - dist;
+                const double rho = (ri * rj) / S;
+                const double sr = sqrt(rho * delta);
+                const double f = k * delta - gamma * sr;
+                const double sc = f / dist;
+                acc.fx += sc * ex;
+                acc.fy += sc * ey;
+                acc.fz += sc * ez;
+                acc.nnz += f != 0.0 ? 1u : 0u;
+                if (PARAM_GRADS) {
+                    const double ux = ex / dist, uy = ey / dist, uz = ez / dist;
+                    acc.kx += delta * ux;
+                    acc.ky += delta * uy;
+                    acc.kz += delta * uz;
+                    acc.gx -= sr * ux;
+                    acc.gy -= sr * uy;
+                    acc.gz -= sr * uz;
+                }
             }
         }
         n = 0;
     };
-    if (P.total > 0) {
-        // pass 1, kChunk slots of one piece at a time: [u, u + kChunk) of the
-        // piece [.., e), the next piece already read from LDS.  Slots past
-        // the piece end are read (the slot-ordered array is padded) but
-        // never pass.
-        uint32_t kp = 0, qo = n * bs + tid;   // qo: this thread's next queue entry
-        unsigned long long v = L.rng[tid];
-        unsigned long long nxt = L.rng[min(1u, P.m - 1u) * bs + tid];
-        uint32_t u = uint32_t(v), e = uint32_t(v >> 32);
-        while (kp < P.m) {
-            const V4<T>* __restrict__ pu = sp + u;
-            V4<T> pc[kChunk];
+    // pass 1: the pre-test over the walk, survivors queued in slot order
+    uint32_t qo = tid;   // this thread's next queue entry
+    walk_chunks<CH>(b, P, L, [&](const V4<T>* pc, uint32_t u, uint32_t left) {
 #pragma unroll
-            for (int c = 0; c < kChunk; ++c) pc[c] = pu[c];
-            const uint32_t left = e - u;
-#pragma unroll
-            for (int c = 0; c < kChunk; ++c) {
-                // no short-circuit: every lane does the same arithmetic
-                const uint32_t pass = uint32_t(uint32_t(c) < left) & uint32_t(maybe_within<T>(p, pc[c], r2pad));
-                L.queue[qo] = u + c;   // n < kQueueCap here
-                n += pass;
-                qo += pass ? bs : 0u;
-            }
-            u += kChunk;
-            if (u >= e) {
-                ++kp;
-                u = uint32_t(nxt);
-                e = uint32_t(nxt >> 32);
-                nxt = L.rng[min(kp + 1u, P.m - 1u) * bs + tid];
-            }
-            if (n > uint32_t(kQueueCap - kChunk)) {
-                drain();
-                qo = tid;
-            }
+        for (int c = 0; c < CH; ++c) {
+            // no short-circuit: every lane does the same arithmetic
+            const uint32_t pass = uint32_t(uint32_t(c) < left) & uint32_t(maybe_within<T>(p, pc[c], r2pad));
+            L.queue[qo] = u + c;   // n < kQueueCap here
+            n += pass;
+            qo += pass ? bs : 0u;
         }
-    }
-    drain();
-}
-
-// Static test of Section 5 for an agent that itself did not move and had at
-// most one non-zero pair term: true if no agent within R of it moved.
-template <class T>
-__device__ __forceinline__ bool no_moved_neighbour(const Buffers<T>& b, const SimGrid& G, uint32_t self,
-                                                   const V4<T>& p, const Pieces& P, const WalkLds& L) {
-    if (!P.moved) return true;   // nothing in the 8 super-boxes moved
-    const V4<T>* __restrict__ sp = spos_ptr(b);
-    const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
-    const double r2 = G.r2;
-    const float r2pad = padded_r2(r2);
-    return stream_pieces(L, P, [&](uint32_t u) {
-        if (u == self || u >= b.n) return true;
-        const V4<T> pj = sp[u];
-        if (!(pj.w < T(0))) return true;   // the sign of d carries the moved flag
-        if (!maybe_within<T>(p, pj, r2pad)) return true;
-        const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
-        return !(((ex * ex + ey * ey) + ez * ez) < r2);
+        if (n > uint32_t(kQueueCap - CH)) {
+            drain();
+            qo = tid;
+        }
+        return true;
     });
+    drain();
 }
 
 // Displacement rule: Delta = mu F if |F| > f_adh, clamped to delta_max.

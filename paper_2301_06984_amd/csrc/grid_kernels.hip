@@ -217,12 +217,18 @@ void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s) {
 // the shared box arrays.  Also clears the other accumulator for this step's
 // move kernel and the step statistics.
 constexpr int kSetupThreads = 1024;
+constexpr int kTileLevels = 3;    // tiles of 8 x 8 x 8 super-boxes
+constexpr int kTileBlocks = 256;  // grid of the tile-table kernel (it loops)
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int32_t* rep, int nsims,
                                                            int parity, uint32_t box_capacity) {
     __shared__ unsigned long long s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
+    __shared__ uint32_t s_dirty;
+    if (threadIdx.x == 0) {
+        s_carry = 0;
+        s_dirty = 0u;
+    }
     // the other accumulator slot and this step's statistics start empty
     const size_t per = size_t(kReplicas) * size_t(nsims);
     for (size_t e = threadIdx.x; e < per; e += kSetupThreads) {
@@ -237,6 +243,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
     for (int chunk = 0; chunk < nsims; chunk += kSetupThreads) {
         const int s = chunk + int(threadIdx.x);
         uint32_t nb = 0, nsup = 0;
+        bool changed = false;
         if (s < nsims) {
             SimGrid& G = sims[s];
             int32_t bb[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
@@ -266,15 +273,25 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
             G.nboxes = ok ? uint32_t(total) : 0u;
             uint32_t ns = 1;
             for (int a = 0; a < 3; ++a) {
-                G.sdims[a] = ok ? super_dim(G.dims[a]) : 1u;
-                ns *= G.sdims[a];
+                const uint32_t sd = ok ? super_dim(G.dims[a]) : 1u;
+                changed = changed || sd != G.sdims[a];
+                G.sdims[a] = sd;
+                ns *= sd;
             }
             G.slevels = levels > 0 ? levels - 1 : 0;
             G.nsuper = ok ? ns : 0u;
+            G.tlev = G.slevels < kTileLevels ? G.slevels : kTileLevels;
+            uint32_t nt = 1;
+            for (int a = 0; a < 3; ++a) {
+                G.tdims[a] = (G.sdims[a] + (1u << G.tlev) - 1u) >> G.tlev;
+                nt *= G.tdims[a];
+            }
+            G.ntiles = ok ? nt : 0u;
             nb = G.nboxes;
             nsup = G.nsuper;
             if (!ok) raise_error(g, kErrGrid);
         }
+        if (__syncthreads_or(changed ? 1 : 0) && threadIdx.x == 0) s_dirty = 1u;
         // block exclusive scans of nb (box bases) and nsup (super-box bases)
         unsigned long long x = (unsigned long long)nb | ((unsigned long long)nsup << 32);
         const int lane = int(threadIdx.x & 63u), wave = int(threadIdx.x >> 6);
@@ -308,6 +325,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
             for (int s = 0; s < nsims; ++s) sims[s].valid = 0;
         }
         g->total_super = uint32_t(total);
+        g->tiles_dirty = s_dirty;
         // a fresh stamp marks this step's box table entries (the host clears
         // the table before the 15-bit stamp wraps); a fresh epoch tags this
         // step's scan status words
@@ -316,10 +334,41 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
     }
 }
 
+// Rank of the first super-box of every tile, rebuilt when a super grid
+// changed.  Tile t of a simulation (row-major over its tile grid) is stored
+// at the simulation's super-box base + t (tiles are never more than
+// super-boxes).
+__global__ __launch_bounds__(256) void k_tiles(const Globals* g, const SimGrid* __restrict__ sims, int nsims,
+                                               uint32_t* __restrict__ tile_off) {
+    if (!g->tiles_dirty) return;
+    const uint32_t total = g->total_super;
+    for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += gridDim.x * blockDim.x) {
+        // the simulation owning global super-box index gi: the last one whose
+        // base is not above gi (simulations without super-boxes share the
+        // next one's base)
+        int lo = 0, hi = nsims - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sims[mid].sbase <= gi)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const SimGrid& G = sims[lo];
+        if (!G.valid) continue;
+        const uint32_t t = gi - G.sbase;
+        if (t >= G.ntiles) continue;
+        const uint32_t tx = t % G.tdims[0], ty = (t / G.tdims[0]) % G.tdims[1], tz = t / (G.tdims[0] * G.tdims[1]);
+        tile_off[gi] = gapfree_rank(tx << G.tlev, ty << G.tlev, tz << G.tlev, G.sdims[0], G.sdims[1], G.sdims[2],
+                                    G.slevels);
+    }
+}
+
 template <class T>
 void launch_setup(const Buffers<T>& b, int parity, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, b.g, b.sims, b.bbox_rep, b.nsims, parity,
                        b.box_capacity);
+    hipLaunchKernelGGL(k_tiles, dim3(kTileBlocks), dim3(256), 0, s, b.g, b.sims, b.nsims, b.tile_off);
 }
 
 // ------------------------------------------------------------------ keys
@@ -352,8 +401,17 @@ __global__ void k_keys(Buffers<T> b, int cur) {
             } else {
                 // super-box rank in gap-free Morton order of the super grid;
                 // the octant (x bit lowest) orders the boxes inside it
+                // = rank of the tile's first super-box + rank inside the tile
+                const uint32_t tl = uint32_t(G.tlev), tm = (1u << tl) - 1u;
+                uint32_t S[3], w[3];
+                for (int a = 0; a < 3; ++a) {
+                    S[a] = q[a] >> 1;
+                    w[a] = min(tm + 1u, G.sdims[a] - (S[a] & ~tm));
+                }
+                const uint32_t tile =
+                    G.sbase + ((S[2] >> tl) * G.tdims[1] + (S[1] >> tl)) * G.tdims[0] + (S[0] >> tl);
                 const uint32_t rank =
-                    gapfree_rank(q[0] >> 1, q[1] >> 1, q[2] >> 1, G.sdims[0], G.sdims[1], G.sdims[2], G.slevels);
+                    b.tile_off[tile] + gapfree_rank(S[0] & tm, S[1] & tm, S[2] & tm, w[0], w[1], w[2], int(tl));
                 sk = G.sbase + rank;
                 b.key[i] = (sk << 3) | (q[0] & 1u) | ((q[1] & 1u) << 1) | ((q[2] & 1u) << 2);
                 act = true;
@@ -554,16 +612,23 @@ __global__ void k_fixup(Buffers<T> b, int cur, int ids_next) {
     V4<T> p = pos4_ptr(b, cur)[i];
     const uint32_t fl = b.flags[cur][i];
     const unsigned long long mine = ((unsigned long long)((me.w >> 1) & 7u) << 32) | me.y;
-    uint32_t r = 0, c2 = 0, c4 = 0, c6 = 0;
-    bool moved = false;
-    for (uint32_t u = st; u < st + cnt; ++u) {
-        const uint4 o = b.rec[u];
-        const uint32_t oc = (o.w >> 1) & 7u;
-        r += (((unsigned long long)oc << 32) | o.y) < mine ? 1u : 0u;
-        c2 += oc < 2u ? 1u : 0u;
-        c4 += oc < 4u ? 1u : 0u;
-        c6 += oc < 6u ? 1u : 0u;
-        moved = moved || (o.w & 1u);
+    uint32_t r = 0, c2 = 0, c4 = 0, c6 = 0, moved = 0;
+    // the super-box's records, four requested together
+    for (uint32_t u0 = st; u0 < st + cnt; u0 += 4) {
+        uint4 o4[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o4[c] = b.rec[min(u0 + uint32_t(c), st + cnt - 1u)];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint4& o = o4[c];
+            const uint32_t in = u0 + uint32_t(c) < st + cnt ? 1u : 0u;
+            const uint32_t oc = (o.w >> 1) & 7u;
+            r += in & ((((unsigned long long)oc << 32) | o.y) < mine ? 1u : 0u);
+            c2 += in & (oc < 2u ? 1u : 0u);
+            c4 += in & (oc < 4u ? 1u : 0u);
+            c6 += in & (oc < 6u ? 1u : 0u);
+            moved |= (in & o.w) << oc;   // bit oc: an agent of octant oc moved
+        }
     }
     b.perm[st + r] = i;
     b.sflags[st + r] = fl;
@@ -577,6 +642,7 @@ __global__ void k_fixup(Buffers<T> b, int cur, int ids_next) {
             raise_error(b.g, kErrInternal);
             return;
         }
+        if (cnt > kMaxSuperCount) raise_error(b.g, kErrGrid);
         b.cellinfo[super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1)] =
             pack_super(st, cnt, c2, c4, c6, moved, b.g->stamp);
     }

@@ -1,21 +1,23 @@
 """Autotuner for the batched form.
 
-Picks, for one batch of simulations, the three knobs that change the cost of
+Picks, for one batch of simulations, the four knobs that change the cost of
 a step but not its neighbour sets:
 
 * ``cell_factor``  box edge as a multiple of the interaction radius R (>= 1;
   a larger box means fewer boxes and more candidates per box);
 * ``block_size``   threads per block of the force kernel (its LDS walk
   scratch bounds how many blocks fit on a compute unit);
-* ``sort_every``   how often the agents are re-laid out in Morton order.
+* ``sort_every``   how often the agents are re-laid out in Morton order;
+* ``walk_chunk``   candidate slots the neighbour walk tests together (2 or 4).
 
 It times a few steps of the actual batch for each candidate value and does one
-pass of coordinate descent (re-layout cadence first, then block size, then box
+pass of coordinate descent (re-layout cadence, block size, walk width, then box
 edge), keeping the other knobs at the best values found so far.  Re-layout
-cadence and block size leave the results bitwise unchanged.  The box edge
+cadence, block size and walk width leave the results bitwise unchanged.  The box edge
 changes the canonical order and so the order of the force sums, within
-rounding.  A graph-captured replay must cover whole re-layout periods, so
-cadences that do not divide ``graph_steps`` are skipped.
+rounding.  A graph-captured replay must cover an even number of whole
+re-layout periods, so other cadences are skipped when ``graph_steps`` is
+given.
 """
 from __future__ import annotations
 
@@ -31,11 +33,12 @@ Config = Dict[str, float]
 DEFAULT_CELL_FACTORS = (1.0, 1.25, 1.5)
 DEFAULT_BLOCK_SIZES = (128, 256, 512)
 DEFAULT_SORT_EVERY = (1, 2, 5, 10)
+DEFAULT_WALK_CHUNKS = (2, 4)
 
 
 @dataclasses.dataclass
 class TuneResult:
-    params: Config                               # the chosen cell_factor, block_size, sort_every
+    params: Config                               # the chosen cell_factor, block_size, sort_every, walk_chunk
     ms_per_step: float                           # its measured time per step
     trials: List[Tuple[Config, float]]           # every configuration timed, in order
 
@@ -63,27 +66,32 @@ def time_batched(pos: torch.Tensor, diam: torch.Tensor, offsets: Sequence[int], 
 def coordinate_descent(timer: Callable[[Config], float], *, cell_factors: Sequence[float] = DEFAULT_CELL_FACTORS,
                        block_sizes: Sequence[int] = DEFAULT_BLOCK_SIZES,
                        sort_every: Sequence[int] = DEFAULT_SORT_EVERY,
+                       walk_chunks: Sequence[int] = DEFAULT_WALK_CHUNKS,
                        graph_steps: Optional[int] = None) -> TuneResult:
-    """One pass of coordinate descent over the three knobs with cost timer(cfg)."""
+    """One pass of coordinate descent over the four knobs with cost timer(cfg)."""
     if graph_steps is not None:
-        sort_every = [k for k in sort_every if k > 0 and graph_steps % k == 0]
-    if not (cell_factors and block_sizes and sort_every):
+        # a replay must start from the same internal buffers: whole re-layout
+        # periods, an even number of them
+        sort_every = [k for k in sort_every if k > 0 and graph_steps % k == 0 and (graph_steps // k) % 2 == 0]
+    if not (cell_factors and block_sizes and sort_every and walk_chunks):
         raise ValueError("every knob needs at least one candidate value")
     best: Config = dict(cell_factor=float(cell_factors[0]),
                         block_size=int(256 if 256 in block_sizes else block_sizes[0]),
-                        sort_every=int(1 if 1 in sort_every else sort_every[0]))
+                        sort_every=int(1 if 1 in sort_every else sort_every[0]),
+                        walk_chunk=int(walk_chunks[0]))
     seen: Dict[Tuple, float] = {}
     trials: List[Tuple[Config, float]] = []
 
     def cost(cfg: Config) -> float:
-        key = (cfg["cell_factor"], cfg["block_size"], cfg["sort_every"])
+        key = (cfg["cell_factor"], cfg["block_size"], cfg["sort_every"], cfg["walk_chunk"])
         if key not in seen:
             seen[key] = float(timer(dict(cfg)))
             trials.append((dict(cfg), seen[key]))
         return seen[key]
 
     best_ms = cost(best)
-    for knob, values in (("sort_every", sort_every), ("block_size", block_sizes), ("cell_factor", cell_factors)):
+    for knob, values in (("sort_every", sort_every), ("block_size", block_sizes), ("walk_chunk", walk_chunks),
+                         ("cell_factor", cell_factors)):
         for v in values:
             cand = dict(best)
             cand[knob] = type(best[knob])(v)
@@ -98,9 +106,12 @@ def autotune_batched(pos: torch.Tensor, diam: torch.Tensor, offsets: Sequence[in
                      cell_factors: Sequence[float] = DEFAULT_CELL_FACTORS,
                      block_sizes: Sequence[int] = DEFAULT_BLOCK_SIZES,
                      sort_every: Sequence[int] = DEFAULT_SORT_EVERY,
+                     walk_chunks: Sequence[int] = DEFAULT_WALK_CHUNKS,
                      stream: Optional[torch.cuda.Stream] = None, common: Optional[dict] = None) -> TuneResult:
-    """Tune cell_factor, block_size and sort_every for this batch on the GPU.
-    The inputs are copied by every trial context and left unchanged."""
+    """Tune cell_factor, block_size, sort_every and walk_chunk for this batch
+    on the GPU.  The inputs are copied by every trial context and left
+    unchanged."""
     return coordinate_descent(
         lambda cfg: time_batched(pos, diam, offsets, cfg, steps=steps, warmup=warmup, stream=stream, common=common),
-        cell_factors=cell_factors, block_sizes=block_sizes, sort_every=sort_every, graph_steps=graph_steps)
+        cell_factors=cell_factors, block_sizes=block_sizes, sort_every=sort_every, walk_chunks=walk_chunks,
+        graph_steps=graph_steps)

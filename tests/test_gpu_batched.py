@@ -72,9 +72,10 @@ def test_autotuned_batch_matches_plain_runs():
     note(f"autotune {len(off) - 1} sims, n={w.n}")
     pos, diam = to_dev(w.pos), to_dev(w.diam)
     res = tune.autotune_batched(pos, diam, off, graph_steps=10, steps=2, warmup=1,
-                                cell_factors=(1.0, 1.5), block_sizes=(128, 256), sort_every=(1, 2, 5))
+                                cell_factors=(1.0, 1.5), block_sizes=(128, 256), sort_every=(1, 2, 5),
+                                walk_chunks=(2, 4))
     assert len(res.trials) >= 3 and res.ms_per_step > 0
-    assert 10 % res.params["sort_every"] == 0
+    assert 10 % res.params["sort_every"] == 0 and (10 // res.params["sort_every"]) % 2 == 0
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         g = abm.BatchedSim(pos, diam, off, stream=s, common=res.params)

@@ -122,7 +122,11 @@ enum abm_field {
     ABM_FIELD_CELL_START = 7,  /* nboxes + 1 uint32: first slot of each box, last grid (single simulation;
                                   ABM_E_UNSUPPORTED for a batched context) */
     ABM_FIELD_EXTENT = 8,      /* int64[7] per simulation: cmin[3], dims[3], nboxes of the last grid */
-    ABM_FIELD_STORAGE_IDS = 9  /* n uint32: agent id held by each storage slot */
+    ABM_FIELD_STORAGE_IDS = 9, /* n uint32: agent id held by each storage slot */
+    ABM_FIELD_NEIGHBOR_COUNT = 10, /* n uint32, by agent id: |N(i)| = #{j != i : |x_i - x_j|^2 < R^2} on the
+                                      positions of the last grid (Section 3.1's neighbourhood) */
+    ABM_FIELD_NEIGHBORS = 11   /* n x K uint32, by agent id, K = dst_bytes / (4 n): the ids of N(i) in
+                                  ascending order, padded with 0xFFFFFFFF; ABM_E_INVAL if some |N(i)| > K */
 };
 
 /* Version of this ABI (ABM_ABI_VERSION). */

@@ -20,7 +20,7 @@ ABM_OK, ABM_E_INVAL, ABM_E_NONFINITE, ABM_E_GRID, ABM_E_WORKSPACE, ABM_E_HIP, AB
     0, -1, -2, -3, -4, -5, -6, -7
 ABM_F32, ABM_F64 = 0, 1
 FIELD = dict(positions=0, forces=1, moved=2, static=3, nnz=4, key=5, perm=6, cell_start=7, extent=8,
-             storage_ids=9)
+             storage_ids=9, neighbor_count=10, neighbors=11)
 EXTENT_SCRATCH_BYTES = 1024
 
 # every symbol include/abm.h declares
@@ -218,8 +218,11 @@ class Sim:
             out = torch.empty(n, dtype=torch.uint8, device=dev)
         elif field == "nnz":
             out = torch.empty(n, dtype=torch.int32, device=dev)
-        elif field in ("key", "perm", "storage_ids"):
+        elif field in ("key", "perm", "storage_ids", "neighbor_count"):
             out = torch.empty(n, dtype=torch.int32, device=dev)
+        elif field == "neighbors":
+            width = max(1, int(self.query("neighbor_count").max().item()))
+            out = torch.empty((n, width), dtype=torch.int32, device=dev)
         elif field == "cell_start":
             nb = int(self.query("extent")[:, 6].sum())
             out = torch.empty(nb + 1, dtype=torch.int32, device=dev)

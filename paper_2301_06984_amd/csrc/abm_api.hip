@@ -450,6 +450,37 @@ int query_impl(abm_ctx* c, int32_t field, void* dst, int64_t dst_bytes, int32_t 
             HIP_TRY(hipStreamSynchronize(c->stream));
             return read_error(c, false);
         }
+        case ABM_FIELD_NEIGHBOR_COUNT:
+        case ABM_FIELD_NEIGHBORS: {
+            if (!c->have_grid) return fail(ABM_E_STATE, "no grid has been built yet (run a step)");
+            const bool rowsq = field == ABM_FIELD_NEIGHBORS;
+            const int64_t K = rowsq ? dst_bytes / (4 * n) : 0;
+            if (rowsq ? K < 1 : dst_bytes < 4 * n)
+                return fail(ABM_E_INVAL, "destination too small: need at least " + std::to_string(4 * n) + " bytes");
+            if (K > 0xFFFFFFFFll) return fail(ABM_E_INVAL, "row width too large");
+            // device target and one word for the largest count, in the staging area when needed
+            char* stage = c->ws + c->L.stage;
+            uint32_t* worst = reinterpret_cast<uint32_t*>(stage);
+            uint32_t* target = static_cast<uint32_t*>(dst);
+            if (!dst_is_device) {
+                if (4 * n * (rowsq ? K : 1) + 256 > 24 * n)
+                    return fail(ABM_E_UNSUPPORTED, "neighbour rows wider than 5 need a device destination");
+                target = reinterpret_cast<uint32_t*>(stage + 256);
+            }
+            HIP_TRY(hipMemsetAsync(worst, 0, 4, c->stream));
+            launch_neighbors<T>(b, c->grid_ids, rowsq ? nullptr : target, rowsq ? target : nullptr, uint32_t(K), worst,
+                                c->stream);
+            HIP_TRY(hipGetLastError());
+            uint32_t w = 0;
+            HIP_TRY(hipMemcpyAsync(&w, worst, 4, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            if (const int rc = read_error(c, false)) return rc;
+            if (rowsq && w > K)
+                return fail(ABM_E_INVAL, "row width " + std::to_string(K) + " too small: need " + std::to_string(w));
+            if (!dst_is_device)
+                HIP_TRY(hipMemcpy(dst, target, 4 * n * (rowsq ? K : 1), hipMemcpyDeviceToHost));
+            return ABM_OK;
+        }
         case ABM_FIELD_EXTENT: {
             need = 56 * int64_t(c->nsims);
             if (dst_bytes < need) return fail(ABM_E_INVAL, "destination too small: need " + std::to_string(need));

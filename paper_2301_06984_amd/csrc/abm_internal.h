@@ -172,6 +172,8 @@ template <class T> void launch_reset_bbox(const Buffers<T>& b, int parity, hipSt
 
 // ---- launchers (force_kernels.hip)
 template <class T> void launch_force(const Buffers<T>& b, const StepArgs& a, hipStream_t s);
+template <class T> void launch_neighbors(const Buffers<T>& b, int ids_cur, uint32_t* counts, uint32_t* rows,
+                                         uint32_t K, uint32_t* worst, hipStream_t s);
 template <class T> void launch_unpack_positions(const Buffers<T>& b, int pos_cur, int ids_cur, T* out, hipStream_t s);
 template <class T> void launch_unpack_field(const Buffers<T>& b, int pos_cur, int ids_cur, int field, void* out,
                                             hipStream_t s);

@@ -211,6 +211,69 @@ void launch_force(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
         launch_force_c<T, 2>(b, a, s);
 }
 
+// ------------------------------------------------------------------ neighbour sets
+// N(i) of every agent on the positions of the last grid (a query, not part of
+// the step): the walk of the step, the exact test |e|^2 < R^2 in double.
+// rows == nullptr: counts[id] = |N(i)|.  Otherwise row id of `rows` (width
+// K) gets the neighbour ids in ascending order (insertion), and *worst the
+// largest count.
+template <class T>
+__global__ __launch_bounds__(256) void k_neighbors(Buffers<T> b, int ids_cur, uint32_t* __restrict__ counts,
+                                                   uint32_t* __restrict__ rows, uint32_t K, uint32_t* worst) {
+    extern __shared__ __align__(16) unsigned char s_walk[];
+    const WalkLds L = walk_lds(s_walk);
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= b.n) return;
+    const SimGrid& G = b.sims[sim_index(b, t)];
+    const uint32_t* ids = b.ids[ids_cur];
+    const uint32_t i = b.perm[t];
+    const uint32_t id = i < b.n ? ids[i] : 0xFFFFFFFFu;
+    if (id >= b.n) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    const V4<T> p = spos_ptr(b)[t];
+    uint32_t q[3];
+    if (!G.valid || !box_of<T>(G, p, q)) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
+    const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
+    uint32_t cnt = 0;
+    uint32_t* row = rows ? rows + size_t(id) * K : nullptr;
+    stream_pieces(L, P, [&](uint32_t u) {
+        if (u == t) return true;
+        const V4<T> pj = spos_ptr(b)[u];
+        const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
+        if (!(((ex * ex + ey * ey) + ez * ez) < G.r2)) return true;
+        if (row && cnt < K) {
+            const uint32_t j = b.perm[u];
+            const uint32_t jd = j < b.n ? ids[j] : 0xFFFFFFFFu;
+            uint32_t x = cnt;
+            while (x > 0 && row[x - 1] > jd) {
+                row[x] = row[x - 1];
+                --x;
+            }
+            row[x] = jd;
+        }
+        ++cnt;
+        return true;
+    });
+    if (row)
+        for (uint32_t x = cnt; x < K; ++x) row[x] = 0xFFFFFFFFu;
+    else
+        counts[id] = cnt;
+    if (worst) atomicMax(worst, cnt);
+}
+
+template <class T>
+void launch_neighbors(const Buffers<T>& b, int ids_cur, uint32_t* counts, uint32_t* rows, uint32_t K,
+                      uint32_t* worst, hipStream_t s) {
+    hipLaunchKernelGGL(k_neighbors<T>, dim3((b.n + 255) / 256), dim3(256), walk_lds_bytes(256), s, b, ids_cur, counts,
+                       rows, K, worst);
+}
+
 // ------------------------------------------------------------------ copies
 template <class T>
 __global__ void k_unpack_positions(Buffers<T> b, int cur, int ids_cur, T* __restrict__ out) {
@@ -313,6 +376,8 @@ void launch_set_flags(const Buffers<T>& b, int pos_cur, int ids_cur, const uint8
 
 #define ABM_INSTANTIATE(T)                                                                                   \
     template void launch_force<T>(const Buffers<T>&, const StepArgs&, hipStream_t);                        \
+    template void launch_neighbors<T>(const Buffers<T>&, int, uint32_t*, uint32_t*, uint32_t, uint32_t*,   \
+                                      hipStream_t);                                                         \
     template void launch_unpack_positions<T>(const Buffers<T>&, int, int, T*, hipStream_t);                \
     template void launch_unpack_field<T>(const Buffers<T>&, int, int, int, void*, hipStream_t);            \
     template void launch_load_positions<T>(const Buffers<T>&, int, int, const T*, hipStream_t);            \

@@ -47,3 +47,17 @@ def assert_grid_equal(sim: abm.Sim, pos_before: np.ndarray, diam: np.ndarray, pa
     np.testing.assert_array_equal(perm, g["perm"])
     cs = sim.query("cell_start").cpu().numpy().view(np.uint32)
     np.testing.assert_array_equal(cs, g["cell_start"])
+
+
+def assert_neighbors_equal(sim: abm.Sim, pos_before: np.ndarray, diam: np.ndarray, params: oracle.Params):
+    """N(i) of the last GPU grid == the oracle's, as sets of agent ids."""
+    got = sim.query("neighbors").cpu().numpy().view(np.uint32)
+    cnt = sim.query("neighbor_count").cpu().numpy().view(np.uint32)
+    start, ids = oracle.neighbors(pos_before, oracle.radius(diam, params), oracle.inv_cell(diam, params))
+    n = pos_before.shape[0]
+    np.testing.assert_array_equal(cnt, np.diff(start).astype(np.uint32))
+    exp = np.full_like(got, 0xFFFFFFFF)
+    for i in range(n):
+        row = np.sort(ids[start[i]:start[i + 1]])
+        exp[i, :row.size] = row
+    np.testing.assert_array_equal(got, exp)

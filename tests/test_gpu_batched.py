@@ -37,7 +37,19 @@ def test_batched_matches_oracle_per_sim():
     off = w.offsets
     note("batched vs oracle")
     b = abm.BatchedSim(to_dev(w.pos), to_dev(w.diam), off)
-    b.step(3)
+    b.step(1)
+    # neighbour sets of the first grid, per simulation (ids are global)
+    nb = b.query("neighbors").cpu().numpy().view(np.uint32)
+    for s in range(len(off) - 1):
+        a, e = off[s], off[s + 1]
+        p = oracle.Params()
+        start, ids = oracle.neighbors(w.pos[a:e], oracle.radius(w.diam[a:e], p), oracle.inv_cell(w.diam[a:e], p))
+        for i in range(e - a):
+            row = nb[a + i]
+            row = row[row != 0xFFFFFFFF].astype(np.int64) - a
+            np.testing.assert_array_equal(row, np.sort(ids[start[i]:start[i + 1]]).astype(np.int64),
+                                          err_msg=f"sim {s} agent {i}")
+    b.step(2)
     got = b.query("positions").cpu().numpy()
     for s in range(len(off) - 1):
         a, e = off[s], off[s + 1]

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import assert_grid_equal, gpu_state, make_sim, note, oracle_params, to_dev
+from gpu_helpers import assert_grid_equal, assert_neighbors_equal, gpu_state, make_sim, note, oracle_params, to_dev
 from paper_2301_06984_amd import abm, workloads
 
 pytestmark = pytest.mark.gpu
@@ -36,6 +36,7 @@ def test_first_step_matches_oracle(name, pos, diam):
     sim.step(1)
     sim.sync()
     assert_grid_equal(sim, pos, diam, oracle.Params())
+    assert_neighbors_equal(sim, pos, diam, oracle.Params())
     st = oracle.State.initial(pos, diam)
     oracle.step(st, oracle.Params())
     g = gpu_state(sim)

@@ -5,6 +5,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -36,8 +37,9 @@ int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 constexpr int kTimedPhases = 6;
 
 struct Layout {
-    int64_t globals, sims, sim_of, bbox_rep, pos4[2], ids[2], flags[2], force[2], key, sub, rec, perm, sflags, spos,
-        count, cell_start, cellinfo, tile_off, scan_status, partials, stage, total;
+    int64_t globals, sims, sim_of, bbox_rep, pos4[2], ids[2], flags[2], force[2], key, sub, rec, perm, sflags, skey,
+        spos, count, cell_start[2], dirty, darr, dirty_list, mmask, cellinfo, tile_off, scan_status, partials, stage,
+        total;
     uint32_t scan_tiles, partial_cap;
 };
 
@@ -61,10 +63,15 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.sub = take(4 * n);
     L.rec = take(16 * n);
     L.sflags = take(4 * n);
+    L.skey = take(4 * n);
     L.perm = take(4 * n);
     L.spos = take(4 * elem * (n + kSposPad));
     L.count = take(4 * boxes);
-    L.cell_start = take(4 * (boxes + 1));
+    for (int k = 0; k < 2; ++k) L.cell_start[k] = take(4 * (boxes + 1));
+    L.dirty = take(4 * boxes);
+    L.darr = take(4 * boxes);
+    L.dirty_list = take(4 * boxes);
+    L.mmask = take(4 * boxes);
     L.cellinfo = take(16 * boxes);
     L.tile_off = take(4 * boxes);
     L.scan_tiles = uint32_t((boxes + kScanTile - 1) / kScanTile);
@@ -91,6 +98,9 @@ struct abm_ctx {
     std::vector<int64_t> offsets;
     abm_params params{};
     int walk_chunk = 2;      // candidates the neighbour walk tests together (2 or 4)
+    int cs_cur = 0;          // which cell_start copy the next grid build writes (the other holds the last)
+    bool inc_ready = false;  // agents are stored in the last grid's canonical order, positions from the step
+    bool graph_inc_after = false;
     // host mirror of the device state
     int64_t step = 0;
     int pos_cur = 0;
@@ -144,16 +154,31 @@ void fill_buffers(abm_ctx* c) {
     b.sub = reinterpret_cast<uint32_t*>(w + L.sub);
     b.rec = reinterpret_cast<uint4*>(w + L.rec);
     b.sflags = reinterpret_cast<uint32_t*>(w + L.sflags);
+    b.skey = reinterpret_cast<uint32_t*>(w + L.skey);
     b.perm = reinterpret_cast<uint32_t*>(w + L.perm);
     b.spos = w + L.spos;
     b.count = reinterpret_cast<uint32_t*>(w + L.count);
-    b.cell_start = reinterpret_cast<uint32_t*>(w + L.cell_start);
+    b.cell_start = reinterpret_cast<uint32_t*>(w + L.cell_start[c->cs_cur]);
+    b.cell_start_old = reinterpret_cast<uint32_t*>(w + L.cell_start[c->cs_cur ^ 1]);
+    b.dirty = reinterpret_cast<uint32_t*>(w + L.dirty);
+    b.darr = reinterpret_cast<uint32_t*>(w + L.darr);
+    b.dirty_list = reinterpret_cast<uint32_t*>(w + L.dirty_list);
+    b.mmask = reinterpret_cast<uint32_t*>(w + L.mmask);
     b.cellinfo = reinterpret_cast<uint4*>(w + L.cellinfo);
     b.tile_off = reinterpret_cast<uint32_t*>(w + L.tile_off);
     b.scan_status = reinterpret_cast<unsigned long long*>(w + L.scan_status);
     b.scan_tiles = L.scan_tiles;
     b.partials = reinterpret_cast<double*>(w + L.partials);
     b.partial_cap = L.partial_cap;
+}
+
+// After a grid build: its starts become the last grid's.
+template <class T>
+void swap_cell_start(abm_ctx* c) {
+    c->cs_cur ^= 1;
+    Buffers<T>& b = c->buf<T>();
+    b.cell_start = reinterpret_cast<uint32_t*>(c->ws + c->L.cell_start[c->cs_cur]);
+    b.cell_start_old = reinterpret_cast<uint32_t*>(c->ws + c->L.cell_start[c->cs_cur ^ 1]);
 }
 
 bool valid_params(const abm_params* p, std::string* why) {
@@ -204,6 +229,7 @@ void guard_stamps(abm_ctx* c, int64_t m) {
     if (int64_t(c->stamp_count) + m > int64_t(kStampPeriod)) {
         launch_clear_cellinfo<T>(c->buf<T>(), c->stream);
         c->stamp_count = 0;
+        c->inc_ready = false;   // an update build reuses the table entries
     }
 }
 
@@ -234,9 +260,10 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, bool timed = false) {
     a.pos_cur = c->pos_cur;
     a.ids_cur = c->ids_cur;
     a.relayout = allow_relayout && c->params.sort_every > 0 && ((c->step + 1) % c->params.sort_every == 0);
-    launch_setup<T>(b, parity, c->stream);
+    launch_setup<T>(b, parity, c->inc_ready, c->stream);
     if (ev) (void)hipEventRecord((*ev)[1], c->stream);
     launch_grid<T>(b, c->pos_cur, c->ids_cur, a.relayout, c->stream, ev ? marks : nullptr);
+    swap_cell_start<T>(c);
     a.detect_static = c->params.detect_static != 0;
     a.keep_forces = c->params.keep_forces != 0;
     a.block_size = block_size_of(c->params);
@@ -247,6 +274,9 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, bool timed = false) {
     c->have_grid = true;
     c->pos_cur ^= 1;
     if (a.relayout) c->ids_cur ^= 1;
+    // after a re-layout the agents are stored in this grid's canonical order,
+    // so the next grid can be built as an update of this one
+    c->inc_ready = a.relayout;
     c->step += 1;
     c->stamp_count += 1;
 }
@@ -322,6 +352,8 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     if (hipMemsetAsync(c->ws + L.globals, 0, sizeof(Globals), s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.count, 0, 4 * boxes, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.cellinfo, 0, 16 * boxes, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.dirty, 0, 4 * boxes, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.mmask, 0, 4 * boxes, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.spos, 0, 4 * c->elem() * (n + kSposPad), s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.scan_status, 0, 8 * int64_t(L.scan_tiles), s) != hipSuccess ||
         hipMemcpyAsync(b.sims, sims.data(), sizeof(SimGrid) * nsims, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -369,21 +401,25 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
 template <class T>
 int extent_impl(int64_t n, const void* pos, const void* diam, const abm_params* p, void* scratch, hipStream_t s,
                 abm_extent* out) {
+    // scratch: the error word (the only field of Globals the extent kernels
+    // touch) in the first 256 bytes, then one SimGrid
+    static_assert(offsetof(Globals, err) == 0, "the error word leads Globals");
+    static_assert(256 + sizeof(SimGrid) <= ABM_EXTENT_SCRATCH_BYTES, "extent scratch too small");
     char* w = static_cast<char*>(scratch);
     Globals* g = reinterpret_cast<Globals*>(w);
     SimGrid* G = reinterpret_cast<SimGrid*>(w + 256);
     SimGrid h{};
     h.radius = p->interaction_radius;
     h.cell_factor = p->cell_factor;
-    HIP_TRY(hipMemsetAsync(g, 0, sizeof(Globals), s));
+    HIP_TRY(hipMemsetAsync(w, 0, 256, s));
     HIP_TRY(hipMemcpyAsync(G, &h, sizeof(SimGrid), hipMemcpyHostToDevice, s));
     launch_extent<T>(static_cast<const T*>(pos), static_cast<const T*>(diam), uint32_t(n), g, G, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
-    Globals hg{};
-    HIP_TRY(hipMemcpy(&hg, g, sizeof(hg), hipMemcpyDeviceToHost));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, w, sizeof(err), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&h, G, sizeof(h), hipMemcpyDeviceToHost));
-    if (hg.err) return error_code(hg.err);
+    if (err) return error_code(err);
     out->radius = h.radius;
     out->inv_cell = h.inv_h;
     out->nboxes = 1;
@@ -540,6 +576,7 @@ int import_impl(abm_ctx* c, const void* src, int64_t src_bytes) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(stage, p, pos_b, hipMemcpyHostToDevice));
     launch_load_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const T*>(stage), c->stream);
+    c->inc_ready = false;   // positions replaced outside the step
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(stage, p + pos_b, c->n, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(stage + align_up(c->n), p + pos_b + c->n, 4 * c->n, hipMemcpyHostToDevice));
@@ -625,10 +662,13 @@ template <class T>
 void load_and_grid(abm_ctx* c, const T* pos_by_id) {
     Buffers<T>& b = c->buf<T>();
     launch_load_positions<T>(b, c->pos_cur, c->ids_cur, pos_by_id, c->stream);
+    c->inc_ready = false;   // positions replaced outside the step
     launch_bbox<T>(b, c->pos_cur, 0, c->stream);
     guard_stamps<T>(c, 1);
-    launch_setup<T>(b, 0, c->stream);
+    launch_setup<T>(b, 0, false, c->stream);
     launch_grid<T>(b, c->pos_cur, c->ids_cur, false, c->stream);
+    swap_cell_start<T>(c);
+    c->inc_ready = false;
     c->stamp_count += 1;
 }
 
@@ -654,6 +694,7 @@ int backward_impl(abm_ctx* c, const double* dL_dxT, double* dL_dx0, double* dL_d
         const int32_t s1 = std::min(c->rec_steps, s0 + c->rec_ckpt);
         // recompute the segment forward, keeping every step's positions
         launch_load_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const T*>(base + R.ckpt + pb * seg), s);
+        c->inc_ready = false;   // positions replaced outside the step
         launch_mark_moved<T>(b, c->pos_cur, s);
         c->step = c->rec_start + s0;
         enqueue_extent<T>(c);
@@ -674,6 +715,7 @@ int backward_impl(abm_ctx* c, const double* dL_dxT, double* dL_dx0, double* dL_d
     launch_permute3(ids, n, lam, dL_dx0, true, s);
     // restore the final state of the recorded run
     launch_load_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const T*>(base + R.xT), s);
+    c->inc_ready = false;   // positions replaced outside the step
     c->step = end_step;
     enqueue_extent<T>(c);
     HIP_TRY(hipGetLastError());
@@ -704,17 +746,21 @@ int graph_capture_impl(abm_ctx* c, int32_t nsteps) {
     const int64_t saved_step = c->step;
     const int saved_pos = c->pos_cur, saved_ids = c->ids_cur;
     const uint32_t saved_stamp = c->stamp_count;
+    const bool saved_inc = c->inc_ready;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     launch_clear_cellinfo<T>(c->buf<T>(), c->stream);
     c->stamp_count = 0;
+    c->inc_ready = false;   // a replay starts from a cleared table: its first grid is a full build
     for (int32_t t = 0; t < nsteps; ++t) enqueue_step<T>(c, true);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
     c->graph_grid_ids = c->grid_ids;
+    c->graph_inc_after = c->inc_ready;
     c->step = saved_step;
     c->pos_cur = saved_pos;
     c->ids_cur = saved_ids;
     c->stamp_count = saved_stamp;
+    c->inc_ready = saved_inc;   // the captured steps did not run (cell_start parity is back: even steps)
     if (e != hipSuccess) return fail(ABM_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
     c->graph = g;
     HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
@@ -730,6 +776,7 @@ int graph_launch_impl(abm_ctx* c) {
     c->step += c->graph_steps;
     c->stamp_count = uint32_t(c->graph_steps);
     c->grid_ids = c->graph_grid_ids;
+    c->inc_ready = c->graph_inc_after;
     c->have_grid = true;
     return ABM_OK;
 }

@@ -19,10 +19,13 @@
 //            {storage index, id, super-box start, count << 4 | octant << 1 | moved}
 //     perm   agents in canonical (box rank, id) order
 //     sflags flags of the agents in canonical order
+//     skey   keys of the agents in canonical order
 //     spos   {x, y, z, d} of the agents in canonical order (sign of d = moved)
 //   per super-box (capacity = sum of the per-simulation box capacities):
-//     count       histogram; every scan leaves it zeroed for the next step
-//     cell_start  exclusive prefix sum of count (+1 entry)
+//     count       histogram (or count changes); every scan leaves it zeroed
+//     cell_start  exclusive prefix sum of the counts (+1 entry), two copies
+//                 (this grid and the last)
+//     dirty, darr, dirty_list, mmask   bookkeeping of the update build
 //     tile_off    rank of the first super-box of every tile (2^tlev super-boxes per axis)
 //     cellinfo    row-major super-box table, 16 B per entry (SuperEntry); an
 //                 entry whose stamp is not the current step's is empty, so
@@ -38,6 +41,7 @@ namespace abm {
 
 constexpr uint32_t kMovedBit = 1u;
 constexpr uint32_t kStaticBit = 2u;
+constexpr uint32_t kBoxChangedBit = 4u;   // the last step took the agent out of the box it was ranked in
 constexpr int kNnzShift = 8;
 constexpr uint32_t kMaxBoxesPerAxis = 1u << 21;
 constexpr int kScanThreads = 256;
@@ -93,9 +97,14 @@ struct Globals {
     uint32_t stamp;          // of the current step's super-box table entries (1..32767)
     uint32_t scan_epoch;     // tag of the current step's scan status words (never 0)
     uint32_t tiles_dirty;    // some simulation's super grid changed: rebuild the tile table
+    uint32_t inc;            // this step's grid is an update of the last one (see launch_grid)
+    uint32_t epoch;          // counts grid builds (marks this step's changed super-boxes; never 0)
     unsigned long long scan_ticket;
     // per step parity and replica: agents skipped as static, agents moved
     unsigned long long stats[2][kReplicas][2];
+    // changed super-boxes listed in Buffers::dirty_list this step; on a cache
+    // line of its own, away from the fields every thread reads
+    alignas(256) uint32_t ndirty;
 };
 
 // Pointers into the workspace, passed by value to kernels.
@@ -118,10 +127,16 @@ struct Buffers {
     uint4* rec;               // per arrival slot: {storage index, id, super-box start, count << 4 | octant << 1 | moved}
     uint32_t* perm;
     uint32_t* sflags;         // flags of the agents in canonical order (grid build)
+    uint32_t* skey;           // key of the agents in canonical order (grid build)
     void* spos;               // V4<T> per slot of the canonical order; sign of d = moved
     // per super-box
-    uint32_t* count;
-    uint32_t* cell_start;
+    uint32_t* count;          // histogram (full build) or change of the counts (update)
+    uint32_t* cell_start;     // first slot of every super-box, this grid
+    uint32_t* cell_start_old; // ... of the last grid
+    uint32_t* dirty;          // epoch of the last build in which the super-box gained or lost agents
+    uint32_t* darr;           // arrivals so far in a changed super-box
+    uint32_t* dirty_list;     // the changed super-boxes of this build
+    uint32_t* mmask;          // bit o: an agent of octant o moved (update builds; cleared when used)
     uint4* cellinfo;
     uint32_t* tile_off;       // per tile (at the simulation's super-box base): rank of its first super-box
     unsigned long long* scan_status;
@@ -161,7 +176,7 @@ void launch_set_params(SimGrid* sims, int nsims, double k, double gamma, double 
                        hipStream_t s);
 void launch_permute3(const uint32_t* ids, uint32_t n, const double* in, double* out, bool to_id, hipStream_t s);
 template <class T> void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s);
-template <class T> void launch_setup(const Buffers<T>& b, int parity, hipStream_t s);
+template <class T> void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s);
 template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, hipStream_t s,
                                     hipEvent_t* const* marks = nullptr);
 template <class T> void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s);

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
             // grid overflow (reported at sync): keep this slot's state unchanged
             const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
             pout[t] = pin[t];
-            b.flags[nxt][t] = b.flags[cur][t];
+            b.flags[nxt][t] = b.flags[cur][t] | kBoxChangedBit;
             if (RELAYOUT) b.ids[a.ids_cur ^ 1][t] = b.ids[a.ids_cur][t];
             if (KEEP_F)
                 for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(t) + c] = b.force[cur][3 * size_t(t) + c];
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
                 is_static = cand && !acc.moved_near;
             }
             if (is_static) {
-                nf = kStaticBit | (f & ~(kMovedBit | kStaticBit));
+                nf = kStaticBit | (f & ~(kMovedBit | kStaticBit | kBoxChangedBit));
                 if (KEEP_F)
                     for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
             } else {
@@ -117,9 +117,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
                 }
             }
             pout[out] = np;
-            b.flags[nxt][out] = nf;
             ok = box_coord(double(np.x), G.inv_h, &cnew[0]) && box_coord(double(np.y), G.inv_h, &cnew[1]) &&
                  box_coord(double(np.z), G.inv_h, &cnew[2]);
+            // left the box it was ranked in (the next grid build re-ranks it)
+            bool left = !ok;
+            for (int c = 0; c < 3; ++c) left = left || int64_t(cnew[c]) - int64_t(G.cmin[c]) != int64_t(q[c]);
+            b.flags[nxt][out] = nf | (left ? kBoxChangedBit : 0u);
         }
         if (!ok) raise_error(b.g, kErrNonfinite);
     }

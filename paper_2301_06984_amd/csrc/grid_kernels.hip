@@ -217,17 +217,19 @@ void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s) {
 // the shared box arrays.  Also clears the other accumulator for this step's
 // move kernel and the step statistics.
 constexpr int kSetupThreads = 1024;
+constexpr uint32_t kFixupLanes = 8;   // threads per changed super-box in an update build
 constexpr int kTileLevels = 3;    // tiles of 8 x 8 x 8 super-boxes
 constexpr int kTileBlocks = 256;  // grid of the tile-table kernel (it loops)
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int32_t* rep, int nsims,
-                                                           int parity, uint32_t box_capacity) {
+                                                           int parity, uint32_t box_capacity, int allow_inc) {
     __shared__ unsigned long long s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
-    __shared__ uint32_t s_dirty;
+    __shared__ uint32_t s_dirty, s_same;
     if (threadIdx.x == 0) {
         s_carry = 0;
         s_dirty = 0u;
+        s_same = 1u;
     }
     // the other accumulator slot and this step's statistics start empty
     const size_t per = size_t(kReplicas) * size_t(nsims);
@@ -243,9 +245,10 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
     for (int chunk = 0; chunk < nsims; chunk += kSetupThreads) {
         const int s = chunk + int(threadIdx.x);
         uint32_t nb = 0, nsup = 0;
-        bool changed = false;
+        bool changed = false, same = true;
         if (s < nsims) {
             SimGrid& G = sims[s];
+            same = G.valid != 0u;   // the last grid of this simulation was built
             int32_t bb[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
             for (int r = 0; r < kReplicas; ++r) {
                 const int32_t* t = rep + ((size_t(parity) * kReplicas + r) * size_t(nsims) + s) * 6;
@@ -262,6 +265,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
                 const int64_t d = hi - lo + 1;
                 if (hi < lo || d > int64_t(kMaxBoxesPerAxis)) ok = false;
                 const uint32_t du = ok ? uint32_t(d) : 1u;
+                same = same && G.cmin[a] == int32_t(lo) && G.dims[a] == du;
                 G.cmin[a] = int32_t(lo);
                 G.dims[a] = du;
                 total *= du;
@@ -289,9 +293,11 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
             G.ntiles = ok ? nt : 0u;
             nb = G.nboxes;
             nsup = G.nsuper;
+            same = same && ok;
             if (!ok) raise_error(g, kErrGrid);
         }
         if (__syncthreads_or(changed ? 1 : 0) && threadIdx.x == 0) s_dirty = 1u;
+        if (!__syncthreads_and(same ? 1 : 0) && threadIdx.x == 0) s_same = 0u;
         // block exclusive scans of nb (box bases) and nsup (super-box bases)
         unsigned long long x = (unsigned long long)nb | ((unsigned long long)nsup << 32);
         const int lane = int(threadIdx.x & 63u), wave = int(threadIdx.x >> 6);
@@ -326,6 +332,11 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
         }
         g->total_super = uint32_t(total);
         g->tiles_dirty = s_dirty;
+        // an update of the last grid needs the same boxes (extent) and agents
+        // stored in that grid's canonical order (the caller's allow_inc)
+        g->inc = (allow_inc && s_same && total > 0) ? 1u : 0u;
+        g->epoch = g->epoch + 1u ? g->epoch + 1u : 1u;
+        g->ndirty = 0u;
         // a fresh stamp marks this step's box table entries (the host clears
         // the table before the 15-bit stamp wraps); a fresh epoch tags this
         // step's scan status words
@@ -365,63 +376,42 @@ __global__ __launch_bounds__(256) void k_tiles(const Globals* g, const SimGrid* 
 }
 
 template <class T>
-void launch_setup(const Buffers<T>& b, int parity, hipStream_t s) {
+void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, b.g, b.sims, b.bbox_rep, b.nsims, parity,
-                       b.box_capacity);
+                       b.box_capacity, allow_inc ? 1 : 0);
     hipLaunchKernelGGL(k_tiles, dim3(kTileBlocks), dim3(256), 0, s, b.g, b.sims, b.nsims, b.tile_off);
 }
 
 // ------------------------------------------------------------------ keys
-// Super-box key and octant of every agent, and its arrival index in the
-// super-box histogram.  Agents of one super-box tend to be neighbours in
-// storage (the previous step's order), so the lanes of a wave take one
-// atomic per run of equal keys and split its result.
+// Key of a position: (global super-box rank << 3) | octant of its box (x bit
+// lowest).  The super-box rank, in gap-free Morton order of the super grid,
+// is the rank of its tile's first super-box (tile table) plus the rank inside
+// the tile.  false if the position lies outside the grid.
 template <class T>
-__global__ void k_keys(Buffers<T> b, int cur) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = false;
-    uint32_t sk = 0;
-    if (i < b.n) {
-        const SimGrid& G = b.sims[sim_index(b, i)];
-        if (G.valid) {
-            const V4<T> p = pos4_ptr(b, cur)[i];
-            int32_t c[3];
-            const bool ok = box_coord(double(p.x), G.inv_h, &c[0]) && box_coord(double(p.y), G.inv_h, &c[1]) &&
-                            box_coord(double(p.z), G.inv_h, &c[2]);
-            uint32_t q[3];
-            bool in = ok;
-            for (int a = 0; a < 3; ++a) {
-                const int64_t v = int64_t(c[a]) - int64_t(G.cmin[a]);
-                in = in && v >= 0 && v < int64_t(G.dims[a]);
-                q[a] = uint32_t(v);
-            }
-            if (!in) {  // the extent is computed from these very positions
-                raise_error(b.g, kErrInternal);
-                b.key[i] = 0xFFFFFFFFu;
-            } else {
-                // super-box rank in gap-free Morton order of the super grid;
-                // the octant (x bit lowest) orders the boxes inside it
-                // = rank of the tile's first super-box + rank inside the tile
-                const uint32_t tl = uint32_t(G.tlev), tm = (1u << tl) - 1u;
-                uint32_t S[3], w[3];
-                for (int a = 0; a < 3; ++a) {
-                    S[a] = q[a] >> 1;
-                    w[a] = min(tm + 1u, G.sdims[a] - (S[a] & ~tm));
-                }
-                const uint32_t tile =
-                    G.sbase + ((S[2] >> tl) * G.tdims[1] + (S[1] >> tl)) * G.tdims[0] + (S[0] >> tl);
-                const uint32_t rank =
-                    b.tile_off[tile] + gapfree_rank(S[0] & tm, S[1] & tm, S[2] & tm, w[0], w[1], w[2], int(tl));
-                sk = G.sbase + rank;
-                b.key[i] = (sk << 3) | (q[0] & 1u) | ((q[1] & 1u) << 1) | ((q[2] & 1u) << 2);
-                act = true;
-            }
-        }
+__device__ __forceinline__ bool super_key(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, uint32_t* key) {
+    uint32_t q[3];
+    if (!box_of<T>(G, p, q)) return false;
+    const uint32_t tl = uint32_t(G.tlev), tm = (1u << tl) - 1u;
+    uint32_t S[3], w[3];
+    for (int a = 0; a < 3; ++a) {
+        S[a] = q[a] >> 1;
+        w[a] = min(tm + 1u, G.sdims[a] - (S[a] & ~tm));
     }
+    const uint32_t tile = G.sbase + ((S[2] >> tl) * G.tdims[1] + (S[1] >> tl)) * G.tdims[0] + (S[0] >> tl);
+    const uint32_t rank = b.tile_off[tile] + gapfree_rank(S[0] & tm, S[1] & tm, S[2] & tm, w[0], w[1], w[2], int(tl));
+    *key = ((G.sbase + rank) << 3) | (q[0] & 1u) | ((q[1] & 1u) << 1) | ((q[2] & 1u) << 2);
+    return true;
+}
+
+// Lanes of a wave that hold equal values of k come in runs (agents of one
+// super-box are neighbours in storage).  wave_run_add adds each run's length
+// to arr[k] with one atomic and returns every lane's index in arr[k]'s
+// count; wave_run_or ORs each run's bits into arr[k] with one atomic.
+__device__ __forceinline__ uint32_t wave_run_add(uint32_t* arr, bool act, uint32_t k) {
     const int lane = lane_id();
-    const uint32_t psk = __shfl_up(sk, 1, 64);
+    const uint32_t pk = __shfl_up(k, 1, 64);
     const int pact = __shfl_up(act ? 1 : 0, 1, 64);
-    const bool head = act && (lane == 0 || !pact || psk != sk);
+    const bool head = act && (lane == 0 || !pact || pk != k);
     const unsigned long long heads = __ballot(head);
     const unsigned long long brk = __ballot(!act || head);
     const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0..lane
@@ -429,9 +419,98 @@ __global__ void k_keys(Buffers<T> b, int cur) {
     const unsigned long long above = brk & ~upto;
     const int next = above ? __ffsll((long long)above) - 1 : 64;
     uint32_t old = 0;
-    if (head) old = atomicAdd(&b.count[sk], uint32_t(next - lane));
+    if (head) old = atomicAdd(&arr[k], uint32_t(next - lane));
     old = __shfl(old, leader, 64);
-    if (act) b.sub[i] = old + uint32_t(lane - leader);
+    return old + uint32_t(lane - leader);
+}
+
+__device__ __forceinline__ void wave_run_or(uint32_t* arr, bool act, uint32_t k, uint32_t bits) {
+    const int lane = lane_id();
+    const uint32_t pk = __shfl_up(k, 1, 64);
+    const int pact = __shfl_up(act ? 1 : 0, 1, 64);
+    const bool head = act && (lane == 0 || !pact || pk != k);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0..lane
+    // the run of a lane is named by its first lane (inactive lanes: a name of their own)
+    const int run = act ? 63 - __clzll((long long)(heads & upto)) : 64 + lane;
+    // segmented OR towards the run's first lane: after the step with distance
+    // d, a lane holds the OR over [lane, lane + 2d) within its run
+    uint32_t v = act ? bits : 0u;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_down(v, d, 64);
+        const int orun = __shfl_down(run, d, 64);
+        if (lane + d < 64 && orun == run) v |= o;
+    }
+    if (head && v) atomicOr(&arr[k], v);
+}
+
+// Claim super-box sk as changed in this build: true for the one caller that
+// marks it first (it resets the super-box's arrival counter and lists it).
+__device__ __forceinline__ bool claim_changed(Globals* g, uint32_t* dirty, uint32_t* darr, uint32_t sk) {
+    const uint32_t ep = g->epoch;
+    if (atomicExch(&dirty[sk], ep) == ep) return false;
+    darr[sk] = 0u;
+    return true;
+}
+
+// Append the claimed super-boxes of a wave to the list with one atomic.
+__device__ __forceinline__ void list_claimed(Globals* g, uint32_t* list, bool c0, uint32_t k0, bool c1, uint32_t k1) {
+    const unsigned long long b0 = __ballot(c0), b1 = __ballot(c1);
+    if (!(b0 | b1)) return;
+    const int lane = lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const uint32_t n0 = uint32_t(__popcll(b0)), total = n0 + uint32_t(__popcll(b1));
+    const int leader = __ffsll((long long)(b0 | b1)) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&g->ndirty, total);
+    base = __shfl(base, leader, 64);
+    if (c0) list[base + uint32_t(__popcll(b0 & below))] = k0;
+    if (c1) list[base + n0 + uint32_t(__popcll(b1 & below))] = k1;
+}
+
+// Full build: key of every agent and its arrival index in its super-box
+// (histogram atomics).  Update build (the last grid's extent, agents stored in
+// its canonical order): agents that stayed in their box keep their key; the
+// others get a new key, move one count from the old to the new super-box and
+// mark both as changed.  Both: the moved bits per octant of every super-box.
+template <class T>
+__global__ void k_keys(Buffers<T> b, int cur) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool inc = b.g->inc != 0u;
+    bool act = false, c0 = false, c1 = false;
+    uint32_t key = 0, f = 0, old = 0;
+    if (i < b.n) {
+        const SimGrid& G = b.sims[sim_index(b, i)];
+        if (G.valid) {
+            f = b.flags[cur][i];
+            if (inc && !(f & kBoxChangedBit)) {
+                key = b.skey[i];
+                act = true;
+            } else if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
+                act = true;
+                if (inc) {
+                    old = b.skey[i];
+                    if (key != old) {   // left its box: one count moves, both super-boxes change
+                        atomicAdd(&b.count[old >> 3], 0xFFFFFFFFu);
+                        atomicAdd(&b.count[key >> 3], 1u);
+                        c0 = claim_changed(b.g, b.dirty, b.darr, old >> 3);
+                        c1 = claim_changed(b.g, b.dirty, b.darr, key >> 3);
+                    }
+                }
+            } else {   // the extent is computed from these very positions
+                raise_error(b.g, kErrInternal);
+                key = 0xFFFFFFFFu;
+            }
+            b.key[i] = key;
+        }
+    }
+    if (!inc) {
+        const uint32_t sub = wave_run_add(b.count, act, key >> 3);
+        if (act) b.sub[i] = sub;
+    } else {
+        list_claimed(b.g, b.dirty_list, c0, old >> 3, c1, key >> 3);
+        wave_run_or(b.mmask, act && (f & kMovedBit), key >> 3, 1u << (key & 7u));
+    }
 }
 
 // ------------------------------------------------------------------ scan
@@ -451,10 +530,12 @@ __device__ __forceinline__ uint32_t wave_inclusive(uint32_t x) {
 // through LDS, so every wave touches whole cache lines.
 __device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
 
-// Load tile `tile` of count into LDS (striped), return this thread's blocked
-// 16 values.
-__device__ __forceinline__ void load_tile(const uint32_t* __restrict__ count, uint32_t base, uint32_t total,
-                                          uint32_t* s_data, uint32_t v[kScanItems]) {
+// Load tile `tile` of the counts into LDS (striped), return this thread's
+// blocked 16 values.  In an update build the counts are the last grid's
+// (differences of its starts) plus the changes in `count`.
+__device__ __forceinline__ void load_tile(const uint32_t* __restrict__ count, const uint32_t* __restrict__ cs_old,
+                                          bool inc, uint32_t base, uint32_t total, uint32_t* s_data,
+                                          uint32_t v[kScanItems]) {
     for (int k = 0; k < kScanItems / 4; ++k) {
         const uint32_t e4 = uint32_t(k) * kScanThreads + threadIdx.x;
         const uint32_t g0 = base + 4 * e4;
@@ -469,9 +550,22 @@ __device__ __forceinline__ void load_tile(const uint32_t* __restrict__ count, ui
     }
     __syncthreads();
     for (int k = 0; k < kScanItems; ++k) v[k] = s_data[lds_pad(threadIdx.x * kScanItems + k)];
+    if (inc) {
+        const uint32_t g0 = base + threadIdx.x * kScanItems;
+        if (g0 < total) {
+            uint32_t prev = cs_old[g0];
+            for (int k = 0; k < kScanItems; ++k) {
+                if (g0 + k >= total) break;
+                const uint32_t nxt = cs_old[g0 + k + 1];
+                v[k] += nxt - prev;
+                prev = nxt;
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Globals* g, const uint32_t* __restrict__ count,
+                                                               const uint32_t* __restrict__ cs_old,
                                                                uint32_t* __restrict__ tile_sum, uint32_t ntiles) {
     __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
     __shared__ uint32_t s_wave[kScanThreads / 64];
@@ -479,7 +573,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Globals* g, 
     const uint32_t tile = blockIdx.x;
     if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
     uint32_t v[kScanItems];
-    load_tile(count, tile * kScanTile, total, s_data, v);
+    load_tile(count, cs_old, g->inc != 0u, tile * kScanTile, total, s_data, v);
     uint32_t sum = 0;
     for (int k = 0; k < kScanItems; ++k) sum += v[k];
     for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
@@ -525,6 +619,7 @@ __global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uin
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, uint32_t* __restrict__ count,
+                                                             const uint32_t* __restrict__ cs_old,
                                                              uint32_t* __restrict__ cell_start,
                                                              const uint32_t* __restrict__ tile_prefix,
                                                              uint32_t ntiles) {
@@ -535,7 +630,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, ui
     if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
     const uint32_t base = tile * kScanTile;
     uint32_t v[kScanItems];
-    load_tile(count, base, total, s_data, v);
+    load_tile(count, cs_old, g->inc != 0u, base, total, s_data, v);
     uint32_t sum = 0;
     for (int k = 0; k < kScanItems; ++k) sum += v[k];
     const uint32_t incl = wave_inclusive(sum);
@@ -568,14 +663,36 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, ui
 }
 
 // ------------------------------------------------------------------ scatter / fixup
-// The scatter writes, per arrival slot, a record {storage index, agent id,
-// first slot of the super-box, agent count << 4 | octant << 1 | moved}, so
-// that the fixup finds everything it needs in the records of its super-box.
+// Full build: the scatter writes, per arrival slot, a record {storage index,
+// agent id, first slot of the super-box, agent count << 4 | octant << 1 |
+// moved}, so that the fixup finds everything it needs in the records of its
+// super-box.
+//
+// Update build (agents stored in the last grid's canonical order, same
+// extent): an agent of a super-box that neither gained nor lost agents keeps
+// its place among them, so its slot moves by the change of the super-box's
+// start; the first of them also rewrites the super-box's table entry (same
+// octant counts, new start, moved bits and stamp).  Agents of a changed
+// super-box leave a record for the fixup instead.
+
+// The agent at storage index i goes to slot t of the canonical order.
 template <class T>
-__global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
+__device__ __forceinline__ void place_agent(const Buffers<T>& b, int cur, int ids_cur, int ids_next, uint32_t i,
+                                            uint32_t t, uint32_t key, uint32_t fl, V4<T> p) {
+    b.perm[t] = i;
+    b.sflags[t] = fl;
+    b.skey[t] = key;
+    if (ids_next >= 0) b.ids[ids_next][t] = b.ids[ids_cur][i];   // the step re-lays agents out in this order
+    if (fl & kMovedBit) p.w = -p.w;
+    reinterpret_cast<V4<T>*>(b.spos)[t] = p;
+}
+
+template <class T>
+__global__ void k_scatter(Buffers<T> b, int cur, int ids_cur, int ids_next) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.n) return;
-    if (!b.sims[sim_index(b, i)].valid) return;
+    const SimGrid& G = b.sims[sim_index(b, i)];
+    if (!G.valid) return;
     const uint32_t key = b.key[i];
     const uint32_t sk = key >> 3;
     if (sk >= b.g->total_super) {
@@ -583,25 +700,44 @@ __global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
         return;
     }
     const uint32_t st = b.cell_start[sk], en = b.cell_start[sk + 1];
-    const uint32_t slot = st + b.sub[i];
+    const uint32_t fl = b.flags[cur][i];
+    if (b.g->inc && b.dirty[sk] != b.g->epoch) {
+        const uint32_t t = i + st - b.cell_start_old[sk];
+        if (t >= b.n) {
+            raise_error(b.g, kErrInternal);
+            return;
+        }
+        const V4<T> p = pos4_ptr(b, cur)[i];
+        place_agent<T>(b, cur, ids_cur, ids_next, i, t, key, fl, p);
+        if (i == b.cell_start_old[sk]) {
+            uint32_t q[3];
+            if (!box_of<T>(G, p, q)) {
+                raise_error(b.g, kErrInternal);
+                return;
+            }
+            uint4* entry = &b.cellinfo[super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1)];
+            const uint4 e = *entry;
+            const uint32_t mm = b.mmask[sk];
+            b.mmask[sk] = 0u;
+            *entry = make_uint4(st, (e.y & kMaxSuperCount) | (mm << 24), e.z,
+                                (e.w & 0xFFFFu) | ((b.g->stamp & 0x7FFFu) << 17));
+        }
+        return;
+    }
+    const uint32_t slot = st + (b.g->inc ? atomicAdd(&b.darr[sk], 1u) : b.sub[i]);
     if (slot >= en || en > b.n) {
         raise_error(b.g, kErrInternal);
         return;
     }
-    b.rec[slot] = make_uint4(i, b.ids[ids_cur][i], st,
-                             ((en - st) << 4) | ((key & 7u) << 1) | (b.flags[cur][i] & kMovedBit));
+    b.rec[slot] = make_uint4(i, b.ids[ids_cur][i], st, ((en - st) << 4) | ((key & 7u) << 1) | (fl & kMovedBit));
 }
 
-// Arrival slot t holds agent rec[t].x; its final slot is the start of its
-// super-box plus the number of agents of that super-box that come before it
-// in (octant, id) order.  The first agent of each super-box in that order
-// writes the super-box's table entry.
+// Rank of the agent of record slot t inside its super-box (records [st, st +
+// cnt)) by (octant, id); the agent goes to slot st + rank.  The first agent in
+// that order writes the super-box's table entry.
 template <class T>
-__global__ void k_fixup(Buffers<T> b, int cur, int ids_next) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= b.n) return;
-    const SimGrid& G = b.sims[sim_index(b, t)];   // a simulation's slots are its agents' range
-    if (!G.valid) return;
+__device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G, int cur, int ids_cur, int ids_next,
+                                           uint32_t t, bool inc) {
     const uint4 me = b.rec[t];
     const uint32_t i = me.x, st = me.z, cnt = me.w >> 4;
     if (i >= b.n || st + cnt > b.n || t < st || t >= st + cnt) {
@@ -609,7 +745,7 @@ __global__ void k_fixup(Buffers<T> b, int cur, int ids_next) {
         return;
     }
     // the agent's own state, requested before the walk over its super-box
-    V4<T> p = pos4_ptr(b, cur)[i];
+    const V4<T> p = pos4_ptr(b, cur)[i];
     const uint32_t fl = b.flags[cur][i];
     const unsigned long long mine = ((unsigned long long)((me.w >> 1) & 7u) << 32) | me.y;
     uint32_t r = 0, c2 = 0, c4 = 0, c6 = 0, moved = 0;
@@ -630,21 +766,44 @@ __global__ void k_fixup(Buffers<T> b, int cur, int ids_next) {
             moved |= (in & o.w) << oc;   // bit oc: an agent of octant oc moved
         }
     }
-    b.perm[st + r] = i;
-    b.sflags[st + r] = fl;
-    if (ids_next >= 0) b.ids[ids_next][st + r] = me.y;   // the step re-lays agents out in this order
-    const V4<T> pq = p;
-    if (me.w & 1u) p.w = -p.w;
-    reinterpret_cast<V4<T>*>(b.spos)[st + r] = p;
+    const uint32_t sk = b.key[i] >> 3;
+    place_agent<T>(b, cur, ids_cur, ids_next, i, st + r, (sk << 3) | ((me.w >> 1) & 7u), fl, p);
     if (r == 0) {
         uint32_t q[3];
-        if (!box_of<T>(G, pq, q)) {
+        if (!box_of<T>(G, p, q)) {
             raise_error(b.g, kErrInternal);
             return;
         }
         if (cnt > kMaxSuperCount) raise_error(b.g, kErrGrid);
+        if (inc) b.mmask[sk] = 0u;   // the moved bits just recomputed from the records
         b.cellinfo[super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1)] =
             pack_super(st, cnt, c2, c4, c6, moved, b.g->stamp);
+    }
+}
+
+// Full build: one thread per record slot.  Update build: one thread per
+// record slot of the changed super-boxes (the list made by k_keys).
+template <class T>
+__global__ void k_fixup(Buffers<T> b, int cur, int ids_cur, int ids_next) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!b.g->inc) {
+        if (t >= b.n) return;
+        const SimGrid& G = b.sims[sim_index(b, t)];   // a simulation's slots are its agents' range
+        if (!G.valid) return;
+        fixup_slot<T>(b, G, cur, ids_cur, ids_next, t, false);
+        return;
+    }
+    // changed super-boxes of the list, kFixupLanes threads each (more
+    // agents, and more super-boxes than threads, loop)
+    const uint32_t nd = b.g->ndirty;
+    const uint32_t groups = (gridDim.x * blockDim.x) / kFixupLanes, x0 = t % kFixupLanes;
+    for (uint32_t d = t / kFixupLanes; d < nd; d += groups) {
+        const uint32_t sk = b.dirty_list[d];
+        const uint32_t st = b.cell_start[sk], en = b.cell_start[sk + 1];
+        for (uint32_t u = st + x0; u < en; u += kFixupLanes) {
+            const SimGrid& G = b.sims[sim_index(b, u)];
+            fixup_slot<T>(b, G, cur, ids_cur, ids_next, u, true);
+        }
     }
 }
 
@@ -724,22 +883,23 @@ template <class T>
 void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, hipStream_t s,
                  hipEvent_t* const* marks) {
     const uint32_t blocks = (b.n + 255) / 256;
+    const int ids_next = relayout ? ids_cur ^ 1 : -1;
     auto mark = [&](int k) {
         if (marks) (void)hipEventRecord(*marks[k], s);
     };
     hipLaunchKernelGGL(k_keys<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur);
     mark(0);
     uint32_t* tile_sum = reinterpret_cast<uint32_t*>(b.scan_status);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, tile_sum,
-                       b.scan_tiles);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start_old,
+                       tile_sum, b.scan_tiles);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kTileScanThreads), 0, s, b.g, tile_sum, b.cell_start,
                        b.scan_tiles);
-    hipLaunchKernelGGL(k_scan_down, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start,
-                       tile_sum, b.scan_tiles);
+    hipLaunchKernelGGL(k_scan_down, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start_old,
+                       b.cell_start, tile_sum, b.scan_tiles);
     mark(1);
-    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, ids_cur);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, ids_cur, ids_next);
     mark(2);
-    hipLaunchKernelGGL(k_fixup<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, relayout ? ids_cur ^ 1 : -1);
+    hipLaunchKernelGGL(k_fixup<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, ids_cur, ids_next);
     mark(3);
 }
 
@@ -751,7 +911,7 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, h
     template void launch_mark_moved<T>(const Buffers<T>&, int, hipStream_t);                             \
     template void launch_bbox<T>(const Buffers<T>&, int, int, hipStream_t);                              \
     template void launch_reset_bbox<T>(const Buffers<T>&, int, hipStream_t);                             \
-    template void launch_setup<T>(const Buffers<T>&, int, hipStream_t);                                  \
+    template void launch_setup<T>(const Buffers<T>&, int, bool, hipStream_t);                            \
     template void launch_grid<T>(const Buffers<T>&, int, int, bool, hipStream_t, hipEvent_t* const*);   \
     template void launch_clear_cellinfo<T>(const Buffers<T>&, hipStream_t);                              \
     template void launch_box_ranks<T>(const Buffers<T>&, int, uint32_t*, bool, hipStream_t);

@@ -215,3 +215,19 @@ def test_errors_are_reported():
     with pytest.raises(abm.ABMError) as e:
         sim.backward(torch.zeros((1000, 3), dtype=torch.float64, device="cuda"))
     assert e.value.code == abm.ABM_E_STATE
+
+
+@pytest.mark.parametrize("sort_every", [1, 2])
+def test_grid_after_many_steps(sort_every):
+    """Grids built as updates of the last one (agents stored in its order, same
+    extent) equal the oracle's grid of the same positions: keys, order, box
+    starts and neighbour sets, after several steps."""
+    w = workloads.c2(n=40000, seed=81)
+    note(f"grid after steps, sort_every={sort_every}")
+    sim = make_sim(w.pos, w.diam, sort_every=sort_every, detect_static=True)
+    sim.step(7)
+    for _ in range(3):
+        before = sim.query("positions").cpu().numpy()
+        sim.step(1)
+        assert_grid_equal(sim, before, w.diam, oracle.Params())
+    assert_neighbors_equal(sim, before, w.diam, oracle.Params())

@@ -37,8 +37,8 @@ int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 constexpr int kTimedPhases = 6;
 
 struct Layout {
-    int64_t globals, sims, sim_of, bbox_rep, pos4[2], ids[2], flags[2], force[2], key, sub, rec, perm, sflags, skey,
-        spos, count, cell_start[2], dirty, darr, dirty_list, mmask, cellinfo, tile_off, scan_status, partials, stage,
+    int64_t globals, sims, sim_of, bbox_rep, pos4[2], flags[2], skey[2], ids[2], force[2], key, sub, rec, perm, movers,
+        mcount, count, cell_start[2], dirty, dirty_list, aoff, tabidx, cellinfo, tile_off, tile_sums, partials, stage,
         total;
     uint32_t scan_tiles, partial_cap;
 };
@@ -55,28 +55,29 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.sims = take(int64_t(sizeof(SimGrid)) * nsims);
     L.sim_of = nsims > 1 ? take(2 * n) : -1;
     L.bbox_rep = take(int64_t(sizeof(int32_t)) * 2 * kReplicas * nsims * 6);
-    for (int k = 0; k < 2; ++k) L.pos4[k] = take(4 * elem * n);
+    // loose slots [0, 2n) of the grid, positions padded for the walk
+    for (int k = 0; k < 2; ++k) L.pos4[k] = take(4 * elem * (2 * n + kSposPad));
+    for (int k = 0; k < 2; ++k) L.flags[k] = take(4 * 2 * n);
+    for (int k = 0; k < 2; ++k) L.skey[k] = take(4 * 2 * n);
     for (int k = 0; k < 2; ++k) L.ids[k] = take(4 * n);
-    for (int k = 0; k < 2; ++k) L.flags[k] = take(4 * n);
     for (int k = 0; k < 2; ++k) L.force[k] = keep_forces ? take(24 * n) : -1;
     L.key = take(4 * n);
     L.sub = take(4 * n);
     L.rec = take(16 * n);
-    L.sflags = take(4 * n);
-    L.skey = take(4 * n);
     L.perm = take(4 * n);
-    L.spos = take(4 * elem * (n + kSposPad));
+    L.movers = take(4 * n);
+    L.mcount = take(4 * ((n + 255) / 256));
     L.count = take(4 * boxes);
     for (int k = 0; k < 2; ++k) L.cell_start[k] = take(4 * (boxes + 1));
     L.dirty = take(4 * boxes);
-    L.darr = take(4 * boxes);
     L.dirty_list = take(4 * boxes);
-    L.mmask = take(4 * boxes);
+    L.aoff = take(4 * boxes);
+    L.tabidx = take(4 * boxes);
     L.cellinfo = take(16 * boxes);
     L.tile_off = take(4 * boxes);
     L.scan_tiles = uint32_t((boxes + kScanTile - 1) / kScanTile);
     if (L.scan_tiles == 0) L.scan_tiles = 1;
-    L.scan_status = take(8 * int64_t(L.scan_tiles));
+    L.tile_sums = take(12 * int64_t(L.scan_tiles));
     L.partial_cap = uint32_t(adj_blocks(uint32_t(n)));
     L.partials = take(16 * int64_t(L.partial_cap));
     L.stage = take(24 * n);
@@ -101,6 +102,7 @@ struct abm_ctx {
     int cs_cur = 0;          // which cell_start copy the next grid build writes (the other holds the last)
     bool inc_ready = false;  // agents are stored in the last grid's canonical order, positions from the step
     bool graph_inc_after = false;
+    int grid_pos = 0;        // pos4/skey copy holding the last grid's loose slots
     // host mirror of the device state
     int64_t step = 0;
     int pos_cur = 0;
@@ -146,27 +148,30 @@ void fill_buffers(abm_ctx* c) {
     b.n = uint32_t(c->n);
     for (int k = 0; k < 2; ++k) {
         b.pos4[k] = w + L.pos4[k];
-        b.ids[k] = reinterpret_cast<uint32_t*>(w + L.ids[k]);
         b.flags[k] = reinterpret_cast<uint32_t*>(w + L.flags[k]);
+        b.skey[k] = reinterpret_cast<uint32_t*>(w + L.skey[k]);
+        b.ids[k] = reinterpret_cast<uint32_t*>(w + L.ids[k]);
         b.force[k] = L.force[k] >= 0 ? reinterpret_cast<double*>(w + L.force[k]) : nullptr;
     }
     b.key = reinterpret_cast<uint32_t*>(w + L.key);
     b.sub = reinterpret_cast<uint32_t*>(w + L.sub);
     b.rec = reinterpret_cast<uint4*>(w + L.rec);
-    b.sflags = reinterpret_cast<uint32_t*>(w + L.sflags);
-    b.skey = reinterpret_cast<uint32_t*>(w + L.skey);
     b.perm = reinterpret_cast<uint32_t*>(w + L.perm);
-    b.spos = w + L.spos;
+    b.movers = reinterpret_cast<uint32_t*>(w + L.movers);
+    b.mcount = reinterpret_cast<uint32_t*>(w + L.mcount);
+    b.gpos = b.pos4[c->grid_pos];
+    b.gkey = b.skey[c->grid_pos];
     b.count = reinterpret_cast<uint32_t*>(w + L.count);
     b.cell_start = reinterpret_cast<uint32_t*>(w + L.cell_start[c->cs_cur]);
     b.cell_start_old = reinterpret_cast<uint32_t*>(w + L.cell_start[c->cs_cur ^ 1]);
     b.dirty = reinterpret_cast<uint32_t*>(w + L.dirty);
-    b.darr = reinterpret_cast<uint32_t*>(w + L.darr);
+
     b.dirty_list = reinterpret_cast<uint32_t*>(w + L.dirty_list);
-    b.mmask = reinterpret_cast<uint32_t*>(w + L.mmask);
+    b.aoff = reinterpret_cast<uint32_t*>(w + L.aoff);
+    b.tabidx = reinterpret_cast<uint32_t*>(w + L.tabidx);
     b.cellinfo = reinterpret_cast<uint4*>(w + L.cellinfo);
     b.tile_off = reinterpret_cast<uint32_t*>(w + L.tile_off);
-    b.scan_status = reinterpret_cast<unsigned long long*>(w + L.scan_status);
+    b.tile_sums = reinterpret_cast<uint32_t*>(w + L.tile_sums);
     b.scan_tiles = L.scan_tiles;
     b.partials = reinterpret_cast<double*>(w + L.partials);
     b.partial_cap = L.partial_cap;
@@ -179,6 +184,22 @@ void swap_cell_start(abm_ctx* c) {
     Buffers<T>& b = c->buf<T>();
     b.cell_start = reinterpret_cast<uint32_t*>(c->ws + c->L.cell_start[c->cs_cur]);
     b.cell_start_old = reinterpret_cast<uint32_t*>(c->ws + c->L.cell_start[c->cs_cur ^ 1]);
+}
+
+// The grid about to be built (and then queried) holds its loose slots in
+// pos4/skey copy `pos`.
+template <class T>
+void set_grid_pos(abm_ctx* c, int pos) {
+    c->grid_pos = pos;
+    Buffers<T>& b = c->buf<T>();
+    b.gpos = b.pos4[pos];
+    b.gkey = b.skey[pos];
+}
+
+// Super-box starts of the last grid (after its build swapped the copies).
+template <class T>
+const uint32_t* last_grid_starts(abm_ctx* c) {
+    return reinterpret_cast<const uint32_t*>(c->ws + c->L.cell_start[c->cs_cur ^ 1]);
 }
 
 bool valid_params(const abm_params* p, std::string* why) {
@@ -260,14 +281,17 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, bool timed = false) {
     a.pos_cur = c->pos_cur;
     a.ids_cur = c->ids_cur;
     a.relayout = allow_relayout && c->params.sort_every > 0 && ((c->step + 1) % c->params.sort_every == 0);
-    launch_setup<T>(b, parity, c->inc_ready, c->stream);
-    if (ev) (void)hipEventRecord((*ev)[1], c->stream);
-    launch_grid<T>(b, c->pos_cur, c->ids_cur, a.relayout, c->stream, ev ? marks : nullptr);
-    swap_cell_start<T>(c);
     a.detect_static = c->params.detect_static != 0;
     a.keep_forces = c->params.keep_forces != 0;
     a.block_size = block_size_of(c->params);
     a.walk_chunk = c->walk_chunk;
+    a.full_only = !c->inc_ready;
+    set_grid_pos<T>(c, c->pos_cur);
+    launch_setup<T>(b, parity, c->inc_ready, c->stream);
+    if (ev) (void)hipEventRecord((*ev)[1], c->stream);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, a.detect_static, c->stream, ev ? marks : nullptr);
+    swap_cell_start<T>(c);
+    a.cs = last_grid_starts<T>(c);
     launch_force<T>(b, a, c->stream);
     if (ev) (void)hipEventRecord((*ev)[kTimedPhases], c->stream);
     c->grid_ids = c->ids_cur;
@@ -303,6 +327,8 @@ template <class T>
 int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* pos, const void* diam,
               const abm_params* per_sim, const int64_t* box_capacity, void* ws, int64_t ws_bytes, void* stream) {
     const int64_t n = offsets[nsims];
+    // loose slots [0, 2n) and the padded step grid stay below 2^32
+    if (n > (int64_t(1) << 31) - (int64_t(1) << 20)) return fail(ABM_E_INVAL, "at most 2^31 - 2^20 agents");
     std::vector<SimGrid> sims(nsims);
     uint64_t boxes = 0;
     for (int s = 0; s < nsims; ++s) {
@@ -348,14 +374,16 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
         delete c;
         return code;
     };
-    // zero what must start at zero: globals, histogram, box table, scan status
+    // zero what must start at zero: globals, histogram, box table, change
+    // marks, table indices; and the positions with their padding (read,
+    // never used, by the walk)
     if (hipMemsetAsync(c->ws + L.globals, 0, sizeof(Globals), s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.count, 0, 4 * boxes, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.cellinfo, 0, 16 * boxes, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.dirty, 0, 4 * boxes, s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.mmask, 0, 4 * boxes, s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.spos, 0, 4 * c->elem() * (n + kSposPad), s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.scan_status, 0, 8 * int64_t(L.scan_tiles), s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.tabidx, 0, 4 * boxes, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.pos4[0], 0, 4 * c->elem() * (2 * n + kSposPad), s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.pos4[1], 0, 4 * c->elem() * (2 * n + kSposPad), s) != hipSuccess ||
         hipMemcpyAsync(b.sims, sims.data(), sizeof(SimGrid) * nsims, hipMemcpyHostToDevice, s) != hipSuccess)
         return bail(fail(ABM_E_HIP, "workspace initialisation failed"));
     std::vector<uint16_t> sim_of;
@@ -455,7 +483,7 @@ int query_impl(abm_ctx* c, int32_t field, void* dst, int64_t dst_bytes, int32_t 
         case ABM_FIELD_STORAGE_IDS: need = 4 * n; break;
         case ABM_FIELD_CELL_START: {
             // box starts are not kept by the step (it counts super-boxes);
-            // they are rebuilt here from the boxes of the last grid's slots
+            // they are counted here from the boxes of the last grid's agents
             if (!c->have_grid) return fail(ABM_E_STATE, "no grid has been built yet (run a step)");
             if (c->nsims != 1) return fail(ABM_E_UNSUPPORTED, "box starts are kept for a single simulation only");
             HIP_TRY(hipStreamSynchronize(c->stream));
@@ -466,25 +494,19 @@ int query_impl(abm_ctx* c, int32_t field, void* dst, int64_t dst_bytes, int32_t 
             need = 4 * (nbox + 1);
             if (dst_bytes < need) return fail(ABM_E_INVAL, "destination too small: need " + std::to_string(need));
             uint32_t* ranks = reinterpret_cast<uint32_t*>(c->ws + c->L.stage);
-            launch_box_ranks<T>(b, c->grid_ids, ranks, false, c->stream);
+            launch_box_ranks<T>(b, c->grid_ids, ranks, c->stream);
             HIP_TRY(hipGetLastError());
-            if (dst_is_device) {
-                launch_cell_start(ranks, uint32_t(n), 0u, uint32_t(nbox), static_cast<uint32_t*>(dst), c->stream);
-                HIP_TRY(hipGetLastError());
-            } else {
-                // through the rest of the staging area, in chunks
-                uint32_t* part = ranks + n;
-                const int64_t chunk = (24 * n - 4 * n) / 4;
-                for (int64_t r0 = 0; r0 <= nbox; r0 += chunk) {
-                    const int64_t m = std::min<int64_t>(chunk, nbox + 1 - r0);
-                    launch_cell_start(ranks, uint32_t(n), uint32_t(r0), uint32_t(m - 1), part, c->stream);
-                    HIP_TRY(hipGetLastError());
-                    HIP_TRY(hipMemcpyAsync(static_cast<uint32_t*>(dst) + r0, part, 4 * m, hipMemcpyDeviceToHost,
-                                           c->stream));
-                }
+            if (const int rc = read_error(c, false)) return rc;
+            std::vector<uint32_t> r(n);
+            HIP_TRY(hipMemcpy(r.data(), ranks, 4 * n, hipMemcpyDeviceToHost));
+            std::vector<uint32_t> start(nbox + 1, 0u);
+            for (int64_t k = 0; k < n; ++k) {
+                if (r[k] >= uint64_t(nbox)) return fail(ABM_E_HIP, "internal index check failed");
+                ++start[r[k] + 1];
             }
-            HIP_TRY(hipStreamSynchronize(c->stream));
-            return read_error(c, false);
+            for (int64_t k = 0; k < nbox; ++k) start[k + 1] += start[k];
+            HIP_TRY(hipMemcpy(dst, start.data(), need, dst_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+            return ABM_OK;
         }
         case ABM_FIELD_NEIGHBOR_COUNT:
         case ABM_FIELD_NEIGHBORS: {
@@ -541,7 +563,9 @@ int query_impl(abm_ctx* c, int32_t field, void* dst, int64_t dst_bytes, int32_t 
     if (field == ABM_FIELD_POSITIONS)
         launch_unpack_positions<T>(b, c->pos_cur, ids_buf, static_cast<T*>(target), c->stream);
     else if (field == ABM_FIELD_KEY)
-        launch_box_ranks<T>(b, ids_buf, static_cast<uint32_t*>(target), true, c->stream);
+        launch_box_ranks<T>(b, ids_buf, static_cast<uint32_t*>(target), c->stream);
+    else if (field == ABM_FIELD_PERM)
+        launch_canonical_ids<T>(b, ids_buf, last_grid_starts<T>(c), static_cast<uint32_t*>(target), c->stream);
     else
         launch_unpack_field<T>(b, c->pos_cur, ids_buf, field, target, c->stream);
     HIP_TRY(hipGetLastError());
@@ -665,9 +689,11 @@ void load_and_grid(abm_ctx* c, const T* pos_by_id) {
     c->inc_ready = false;   // positions replaced outside the step
     launch_bbox<T>(b, c->pos_cur, 0, c->stream);
     guard_stamps<T>(c, 1);
+    set_grid_pos<T>(c, c->pos_cur);
     launch_setup<T>(b, 0, false, c->stream);
     launch_grid<T>(b, c->pos_cur, c->ids_cur, false, c->stream);
     swap_cell_start<T>(c);
+    c->grid_ids = c->ids_cur;
     c->inc_ready = false;
     c->stamp_count += 1;
 }
@@ -747,6 +773,7 @@ int graph_capture_impl(abm_ctx* c, int32_t nsteps) {
     const int saved_pos = c->pos_cur, saved_ids = c->ids_cur;
     const uint32_t saved_stamp = c->stamp_count;
     const bool saved_inc = c->inc_ready;
+    const int saved_grid_pos = c->grid_pos;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     launch_clear_cellinfo<T>(c->buf<T>(), c->stream);
     c->stamp_count = 0;
@@ -761,6 +788,7 @@ int graph_capture_impl(abm_ctx* c, int32_t nsteps) {
     c->ids_cur = saved_ids;
     c->stamp_count = saved_stamp;
     c->inc_ready = saved_inc;   // the captured steps did not run (cell_start parity is back: even steps)
+    set_grid_pos<T>(c, saved_grid_pos);
     if (e != hipSuccess) return fail(ABM_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
     c->graph = g;
     HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
@@ -768,6 +796,7 @@ int graph_capture_impl(abm_ctx* c, int32_t nsteps) {
     return ABM_OK;
 }
 
+template <class T>
 int graph_launch_impl(abm_ctx* c) {
     if (!c->graph_exec) return fail(ABM_E_STATE, "no graph captured");
     HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
@@ -778,6 +807,9 @@ int graph_launch_impl(abm_ctx* c) {
     c->grid_ids = c->graph_grid_ids;
     c->inc_ready = c->graph_inc_after;
     c->have_grid = true;
+    // the last captured step built its grid in the copy the state left
+    // (an even number of steps returns the state to where it started)
+    set_grid_pos<T>(c, c->pos_cur ^ 1);
     return ABM_OK;
 }
 
@@ -964,7 +996,7 @@ int abm_graph_capture(abm_ctx* c, int32_t nsteps) {
 int abm_graph_launch(abm_ctx* c) {
     if (int rc = check_ctx(c)) return rc;
     c->recorded = false;
-    return graph_launch_impl(c);
+    return c->precision == ABM_F64 ? graph_launch_impl<double>(c) : graph_launch_impl<float>(c);
 }
 
 int abm_record_bytes(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, int64_t* bytes) {

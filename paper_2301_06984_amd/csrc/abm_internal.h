@@ -6,32 +6,47 @@
 // are one contiguous slot range, sorted by octant (x bit lowest) and then id.
 // The grid build therefore counts and scans super-boxes, not boxes.
 //
+// The grid holds the agents in "loose" slots u in [0, 2n): the walk reads a
+// super-box's agents at [x, x + count) of the loose position array, x taken
+// from its table entry.  A full build writes every agent to n + its canonical
+// slot.  An update build (after a step that re-laid the agents out, with the
+// same box extent) leaves the agents of every super-box that neither gained
+// nor lost agents where the last step wrote them, at storage slots [0, n),
+// and writes the agents of the other super-boxes, in canonical order per
+// super-box, to an append region [n, n + napp).  Storage slots of those
+// super-boxes are marked dead (kDeadKey).
+//
 // Layout in HBM (one workspace, carved by abm_api.hip):
-//   per agent, two copies (ping-pong between steps):
-//     pos4   {x, y, z, d} in the element type T (16 B for float, 32 B for double)
+//   per agent, two copies (ping-pong between steps), over the loose slots:
+//     pos4   {x, y, z, d} in the element type T (16 B for float, 32 B for
+//            double); the sign of d is the moved flag of the agent (written
+//            so by the step; a full build sets it from the flags)
+//     flags  bit 0 moved, bit 1 static (last step), bit 2 left its box, bits 8.. non-zero pair terms
+//     skey   key of the grid the slot's agent was ranked in: (global
+//            super-box rank << 3) | octant
+//   per agent, two copies over the storage slots [0, n):
 //     ids    persistent agent id held by each storage slot
-//     flags  bit 0 moved, bit 1 static (last step), bits 8.. non-zero pair terms
 //     force  3 doubles (only with keep_forces)
 //   per agent, one copy (rebuilt every step):
-//     key    (global super-box index << 3) | octant of the agent's box
+//     key    new key of an agent (full build: all; update: agents that left their box)
 //     sub    arrival index of the agent in its super-box (histogram atomics)
-//     rec    agents in super-box order, arrival order inside a super-box:
-//            {storage index, id, super-box start, count << 4 | octant << 1 | moved}
-//     perm   agents in canonical (box rank, id) order
-//     sflags flags of the agents in canonical order
-//     skey   keys of the agents in canonical order
-//     spos   {x, y, z, d} of the agents in canonical order (sign of d = moved)
+//     rec    agents of the rebuilt super-boxes in arrival order per super-box, at
+//            canonical slots: {storage index, id, super-box start, count << 4 | octant << 1 | moved}
+//     perm   storage index of loose slot n + j
+//     movers storage slots of the agents that left their box (update
+//            build), listed per block of 256 agents, + a count per block
 //   per super-box (capacity = sum of the per-simulation box capacities):
 //     count       histogram (or count changes); every scan leaves it zeroed
 //     cell_start  exclusive prefix sum of the counts (+1 entry), two copies
 //                 (this grid and the last)
-//     dirty, darr, dirty_list, mmask   bookkeeping of the update build
+//     dirty, dirty_list, aoff   bookkeeping of the update build
+//     tabidx      table index of the super-box (written with its entry)
 //     tile_off    rank of the first super-box of every tile (2^tlev super-boxes per axis)
 //     cellinfo    row-major super-box table, 16 B per entry (SuperEntry); an
-//                 entry whose stamp is not the current step's is empty, so
-//                 the table is never cleared between steps (the timestamp
-//                 trick of Section 3.1)
-//   per scan tile: one 64-bit word (tile sums).
+//                 entry whose stamp is not the current one is empty, so the
+//                 table is never cleared between steps (the timestamp trick
+//                 of Section 3.1; update builds keep the stamp)
+//   per scan tile: three 32-bit sums.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,6 +58,7 @@ constexpr uint32_t kMovedBit = 1u;
 constexpr uint32_t kStaticBit = 2u;
 constexpr uint32_t kBoxChangedBit = 4u;   // the last step took the agent out of the box it was ranked in
 constexpr int kNnzShift = 8;
+constexpr uint32_t kDeadKey = 0xFFFFFFFFu;   // storage slot whose agent the update build moved to the append region
 constexpr uint32_t kMaxBoxesPerAxis = 1u << 21;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
@@ -94,17 +110,14 @@ struct SimGrid {
 struct Globals {
     uint32_t err;
     uint32_t total_super;    // super-boxes of all simulations in this step's grid
-    uint32_t stamp;          // of the current step's super-box table entries (1..32767)
-    uint32_t scan_epoch;     // tag of the current step's scan status words (never 0)
+    uint32_t stamp;          // of the current super-box table entries (1..32767)
     uint32_t tiles_dirty;    // some simulation's super grid changed: rebuild the tile table
     uint32_t inc;            // this step's grid is an update of the last one (see launch_grid)
     uint32_t epoch;          // counts grid builds (marks this step's changed super-boxes; never 0)
-    unsigned long long scan_ticket;
+    uint32_t ndirty;         // changed super-boxes of an update build (dirty_list, from the scan)
+    uint32_t napp;           // agents in the append region (an update: of the changed super-boxes; full: n)
     // per step parity and replica: agents skipped as static, agents moved
     unsigned long long stats[2][kReplicas][2];
-    // changed super-boxes listed in Buffers::dirty_list this step; on a cache
-    // line of its own, away from the fields every thread reads
-    alignas(256) uint32_t ndirty;
 };
 
 // Pointers into the workspace, passed by value to kernels.
@@ -117,29 +130,34 @@ struct Buffers {
     uint32_t n;
     uint32_t box_capacity;    // sum of per-simulation capacities
     uint32_t scan_tiles;
-    // per agent
+    // per loose slot [0, 2n) (+ kSposPad positions)
     void* pos4[2];
-    uint32_t* ids[2];
     uint32_t* flags[2];
+    uint32_t* skey[2];
+    // per storage slot
+    uint32_t* ids[2];
     double* force[2];         // null without keep_forces
     uint32_t* key;
     uint32_t* sub;
-    uint4* rec;               // per arrival slot: {storage index, id, super-box start, count << 4 | octant << 1 | moved}
-    uint32_t* perm;
-    uint32_t* sflags;         // flags of the agents in canonical order (grid build)
-    uint32_t* skey;           // key of the agents in canonical order (grid build)
-    void* spos;               // V4<T> per slot of the canonical order; sign of d = moved
+    uint4* rec;               // per canonical slot of a rebuilt super-box: {storage index, id, super-box start, count << 4 | octant << 1 | moved}
+    uint32_t* perm;           // storage index of loose slot n + j
+    uint32_t* movers;         // agents that left their box (update build): block b of the keys kernel lists its own at [256 b, ...)
+    uint32_t* mcount;         // ... and their number, per block of the keys kernel
+    // loose slots of the last grid (set by the host with the grid build):
+    // positions and keys of the grid's pos4/skey copy
+    void* gpos;
+    const uint32_t* gkey;
     // per super-box
     uint32_t* count;          // histogram (full build) or change of the counts (update)
     uint32_t* cell_start;     // first slot of every super-box, this grid
     uint32_t* cell_start_old; // ... of the last grid
     uint32_t* dirty;          // epoch of the last build in which the super-box gained or lost agents
-    uint32_t* darr;           // arrivals so far in a changed super-box
-    uint32_t* dirty_list;     // the changed super-boxes of this build
-    uint32_t* mmask;          // bit o: an agent of octant o moved (update builds; cleared when used)
+    uint32_t* dirty_list;     // the changed super-boxes of this build, in rank order
+    uint32_t* aoff;           // first append slot (minus n) of a changed super-box
+    uint32_t* tabidx;         // table index of the super-box, written with its entry
     uint4* cellinfo;
     uint32_t* tile_off;       // per tile (at the simulation's super-box base): rank of its first super-box
-    unsigned long long* scan_status;
+    uint32_t* tile_sums;      // per scan tile: agents, changed super-boxes, agents of changed super-boxes
     double* partials;         // per-block partial sums (adjoint)
     uint32_t partial_cap;
     // box extent accumulators [2 slots][kReplicas][nsims][6]: one slot is
@@ -150,13 +168,15 @@ struct Buffers {
 // Host-side description of which kernels to run for one step.
 struct StepArgs {
     int parity;             // which bbox accumulator describes the current positions
-    int pos_cur;            // which pos4/flags/force buffer holds the state
+    int pos_cur;            // which pos4/flags/skey/force buffer holds the state
     int ids_cur;            // which ids buffer holds the state
     bool relayout;          // write the new state in canonical slot order
     bool detect_static;
     bool keep_forces;
+    bool full_only;         // the grid is a full build (no agent in storage slots)
     int block_size;
     int walk_chunk;         // 2 or 4 candidate slots tested together by the neighbour walk
+    const uint32_t* cs;     // this grid's super-box starts
 };
 
 constexpr uint32_t kStampPeriod = 32767;   // 15-bit stamps in the super-box table
@@ -177,12 +197,12 @@ void launch_set_params(SimGrid* sims, int nsims, double k, double gamma, double 
 void launch_permute3(const uint32_t* ids, uint32_t n, const double* in, double* out, bool to_id, hipStream_t s);
 template <class T> void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s);
 template <class T> void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s);
-template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, hipStream_t s,
+template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool moved_bits, hipStream_t s,
                                     hipEvent_t* const* marks = nullptr);
 template <class T> void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s);
-template <class T> void launch_box_ranks(const Buffers<T>& b, int ids_cur, uint32_t* out, bool by_id, hipStream_t s);
-void launch_cell_start(const uint32_t* slot_rank, uint32_t n, uint32_t first_box, uint32_t nbox, uint32_t* out,
-                       hipStream_t s);
+template <class T> void launch_box_ranks(const Buffers<T>& b, int ids_cur, uint32_t* out, hipStream_t s);
+template <class T> void launch_canonical_ids(const Buffers<T>& b, int ids_cur, const uint32_t* cs, uint32_t* out,
+                                             hipStream_t s);
 template <class T> void launch_reset_bbox(const Buffers<T>& b, int parity, hipStream_t s);
 
 // ---- launchers (force_kernels.hip)

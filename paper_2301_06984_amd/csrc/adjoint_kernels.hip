@@ -8,6 +8,9 @@
 // when clamped, or 0 below the threshold), then
 //   lambda_m <- lambda_m + sum_{j in contact with m} A_mj (w_m - w_j),
 //   dL/dk += sum_i w_i . sum_j delta_ij u_ij,  dL/dgamma -= sum_i w_i . sum_j sqrt(rho delta) u_ij.
+//
+// The grids of the reverse steps are full builds: the agent of canonical slot
+// t sits in loose slot n + t, with storage index perm[t].
 #include "force_loop.h"
 
 namespace abm {
@@ -29,7 +32,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, co
     if (t < b.n && i >= b.n) raise_error(b.g, kErrInternal);
     if (i < b.n) {
         const SimGrid& G = b.sims[sim_index(b, t)];
-        const V4<T> p = spos_ptr(b)[t];
+        const V4<T> p = gpos_ptr(b)[b.n + t];
         uint32_t q[3];
         double wi[3] = {0.0, 0.0, 0.0};
         if (G.valid && box_of<T>(G, p, q)) {
@@ -86,8 +89,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
         raise_error(b.g, kErrInternal);
         return;
     }
-    const V4<T> p = spos_ptr(b)[t];
-    const V4<T>* __restrict__ sp = spos_ptr(b);
+    const V4<T>* __restrict__ sp = gpos_ptr(b);
+    const V4<T> p = sp[b.n + t];
     uint32_t q[3];
     double acc[3] = {lam[3 * size_t(m)], lam[3 * size_t(m) + 1], lam[3 * size_t(m) + 2]};
     if (G.valid && box_of<T>(G, p, q)) {
@@ -96,8 +99,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
         const double rm = 0.5 * fabs(double(p.w));
         const double wm[3] = {w[3 * size_t(m)], w[3 * size_t(m) + 1], w[3 * size_t(m) + 2]};
         stream_pieces(L, P, [&](uint32_t u) {
-            if (u == t || u >= b.n) return true;
-            const uint32_t j = b.perm[u];
+            if (u == b.n + t || u < b.n) return true;
+            const uint32_t j = b.perm[u - b.n];
             if (j >= b.n) return true;
             const V4<T> pj = sp[u];
             const double ev3[3] = {xm - double(pj.x), ym - double(pj.y), zm - double(pj.z)};

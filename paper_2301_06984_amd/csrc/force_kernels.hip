@@ -10,35 +10,45 @@ namespace abm {
 // the global accumulators).
 constexpr int kMaxBlockSims = 4;
 
-// One thread per slot of the canonical (box rank, id) order, so a wave works
-// on agents that are close in space and shares their neighbour boxes in
-// cache.  The grid build left the agent's position (spos) and flags (sflags)
-// at its slot t; the agent's storage index is i = perm[t].  The new state
-// goes to storage index i, or to slot t when this step re-lays agents out in
-// Morton order (Section 4.2, step G; the grid build then already wrote the
-// ids in slot order).  The static test (Section 5) runs first: an agent that
-// did not move, had at most one non-zero pair term, and has no moved
-// neighbour within R keeps its force and does not move.  The new positions'
-// box extent is reduced here for the next step's grid: each wave folds into
-// the block's LDS copy, and the block's last wave to finish adds it to the
-// global accumulators, so no wave waits for the others.
+// One thread per loose slot of the grid (Section 4.2, step G): the agents of
+// a super-box sit in consecutive slots in canonical order, so a wave works on
+// agents that are close in space and shares their neighbour boxes in cache.
+// Chunks of blockDim slots: the first nb = ceil(n / blockDim) cover the
+// storage slots [0, n) (agents there only in an update build, and not in
+// slots marked dead), the next nb the append region [n, n + napp); a block
+// whose chunk holds no agent returns at once, and a launch for a full build
+// starts at the append chunks.  The agent's storage index is i = u below n,
+// else perm[u - n].  The new state goes to storage index i, or, when this
+// step re-lays agents out in Morton order, to the agent's canonical slot: its
+// super-box's start plus its offset in the super-box's loose range; the step
+// then also writes the ids and grid keys in that order, which lets the next
+// grid be built as an update.  The static test (Section 5) runs first: an
+// agent that did not move, had at most one non-zero pair term, and has no
+// moved neighbour within R keeps its force and does not move.  The new
+// positions' box extent is reduced here for the next step's grid: each wave
+// folds into the block's LDS copy, and the block's last wave to finish adds
+// it to the global accumulators, so no wave waits for the others.
 #ifndef ABM_FORCE_WAVES_PER_EU
 #define ABM_FORCE_WAVES_PER_EU 1
 #endif
 template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT, int CH>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_WAVES_PER_EU))) void k_force(
-    Buffers<T> b, StepArgs a, uint32_t run) {
+    Buffers<T> b, StepArgs a, uint32_t run, uint32_t first_chunk) {
     extern __shared__ __align__(16) unsigned char s_walk[];
     __shared__ int32_t s_box[kMaxBlockSims][6];
     __shared__ int s_sims[kMaxBlockSims];
     __shared__ uint32_t s_cnt[3];   // static, moved, waves done
+    const uint32_t n = b.n, nb = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t chunk = first_chunk + xcd_block(run);
+    const bool append = chunk >= nb;
+    const uint32_t c0 = append ? n + (chunk - nb) * blockDim.x : chunk * blockDim.x;
+    const uint32_t napp = b.g->napp;
+    if (append ? c0 - n >= napp : !b.g->inc) return;   // no agent in the chunk
     const WalkLds L = walk_lds(s_walk);
-    const uint32_t blk = xcd_block(run);
-    const uint32_t t = blk * blockDim.x + threadIdx.x;
-    // the block's slots belong to at most kMaxBlockSims simulations (the
-    // first and last slot bound them); their LDS accumulators start empty
-    const uint32_t t0 = blk * blockDim.x;
-    const int sim0 = BATCHED && t0 < b.n ? sim_index(b, t0) : 0;
+    // the block's agents mostly belong to at most kMaxBlockSims simulations
+    // from that of its chunk's first slot on (others fold straight into the
+    // global accumulators); their LDS accumulators start empty
+    const int sim0 = BATCHED ? sim_index(b, min(append ? c0 - n : c0, n - 1u)) : 0;
     if (threadIdx.x < kMaxBlockSims * 6) {
         const int k = int(threadIdx.x) % 6;
         s_box[threadIdx.x / 6][k] = k < 3 ? INT32_MAX : INT32_MIN;
@@ -46,49 +56,72 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
     if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0u;
     if (threadIdx.x < kMaxBlockSims) s_sims[threadIdx.x] = -1;
     __syncthreads();
-    bool active = t < b.n;
+    const int cur = a.pos_cur, nxt = cur ^ 1;
+    const bool KEEP_F = a.keep_forces;
+    const uint32_t u = c0 + threadIdx.x;
+    uint32_t key = kDeadKey, i = u;
+    bool active = false;
+    if (!append) {
+        if (u < n) {
+            key = b.skey[cur][u];
+            active = key != kDeadKey;
+        }
+    } else if (u - n < napp) {
+        key = b.skey[cur][u];
+        i = b.perm[u - n];
+        active = i < n;
+        if (!active) raise_error(b.g, kErrInternal);
+    }
     bool ok = false, is_static = false, moved = false;
     int sim = 0;
     int32_t cnew[3] = {0, 0, 0};
-    const bool KEEP_F = a.keep_forces;
     if (active) {
         // one simulation: its parameters are the same for every lane
-        sim = BATCHED ? sim_index(b, t) : 0;
+        sim = BATCHED ? sim_index(b, i) : 0;
         const SimGrid& G = b.sims[sim];
-        const int cur = a.pos_cur, nxt = cur ^ 1;
         V4<T>* __restrict__ pout = pos4_ptr(b, nxt);
+        const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
         if (!G.valid) {
-            // grid overflow (reported at sync): keep this slot's state unchanged
-            const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
-            pout[t] = pin[t];
-            b.flags[nxt][t] = b.flags[cur][t] | kBoxChangedBit;
-            if (RELAYOUT) b.ids[a.ids_cur ^ 1][t] = b.ids[a.ids_cur][t];
+            // grid overflow (reported at sync): the agent keeps its state (a
+            // full build copied it to loose slot n + i)
+            const V4<T> p = pin[u];
+            pout[i] = p;
+            b.flags[nxt][i] = b.flags[cur][u] | kBoxChangedBit;
+            if (RELAYOUT) {
+                b.ids[a.ids_cur ^ 1][i] = b.ids[a.ids_cur][i];
+                b.skey[nxt][i] = kDeadKey;
+            }
             if (KEEP_F)
-                for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(t) + c] = b.force[cur][3 * size_t(t) + c];
-            const V4<T> p = pin[t];
+                for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(i) + c] = b.force[cur][3 * size_t(i) + c];
             ok = box_coord(double(p.x), G.inv_h, &cnew[0]) && box_coord(double(p.y), G.inv_h, &cnew[1]) &&
                  box_coord(double(p.z), G.inv_h, &cnew[2]);
         } else {
-            V4<T> p = spos_ptr(b)[t];   // own state, from the slot-ordered copy
-            const uint32_t f = b.sflags[t];
-            uint32_t i = t;
-            if (!RELAYOUT || KEEP_F) {
-                i = b.perm[t];
-                if (i >= b.n) {
-                    raise_error(b.g, kErrInternal);
-                    i = t;
-                }
-            }
-            const uint32_t out = RELAYOUT ? t : i;
+            V4<T> p = pin[u];   // own state, sign of d = moved
+            const uint32_t f = b.flags[cur][u];
             uint32_t q[3];
             if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
             const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
+            uint32_t out = i;
+            if (RELAYOUT) {
+                const uint32_t sk = key >> 3;
+                out = sk < b.g->total_super ? a.cs[sk] + (u - P.xown) : n;
+                if (u < P.xown || out >= n) {
+                    raise_error(b.g, kErrInternal);
+                    out = i;
+                }
+                // what does not depend on the forces is written before the
+                // walk, so that i and the key need not live through it
+                b.ids[a.ids_cur ^ 1][out] = b.ids[a.ids_cur][i];
+                b.skey[nxt][out] = key;
+            }
             // Static test (Section 5): the agent did not move, had at most one
             // non-zero pair term, and no agent within R moved.  At step 0
             // every agent carries the moved bit, so none is static.  With no
             // moved agent in the 27 boxes it holds at once; otherwise the
             // force walk itself reports a moved agent within R.
             const bool cand = STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u;
+            if (KEEP_F && cand)   // a static agent keeps its force (replaced below if it is not static)
+                for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
             is_static = cand && !P.moved;
             p.w = T(fabs(double(p.w)));
             V4<T> np = p;
@@ -100,8 +133,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
             }
             if (is_static) {
                 nf = kStaticBit | (f & ~(kMovedBit | kStaticBit | kBoxChangedBit));
-                if (KEEP_F)
-                    for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
             } else {
                 const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
                 np.x = T(double(p.x) + m.ux);
@@ -110,6 +141,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
                 moved = m.ux != 0.0 || m.uy != 0.0 || m.uz != 0.0;
                 const uint32_t nz = acc.nnz < 0xFFFFFFu ? acc.nnz : 0xFFFFFFu;
                 nf = (moved ? kMovedBit : 0u) | (nz << kNnzShift);
+                if (moved) np.w = -np.w;
                 if (KEEP_F) {
                     b.force[nxt][3 * size_t(out)] = acc.fx;
                     b.force[nxt][3 * size_t(out) + 1] = acc.fy;
@@ -119,15 +151,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
             pout[out] = np;
             ok = box_coord(double(np.x), G.inv_h, &cnew[0]) && box_coord(double(np.y), G.inv_h, &cnew[1]) &&
                  box_coord(double(np.z), G.inv_h, &cnew[2]);
-            // left the box it was ranked in (the next grid build re-ranks it)
-            bool left = !ok;
-            for (int c = 0; c < 3; ++c) left = left || int64_t(cnew[c]) - int64_t(G.cmin[c]) != int64_t(q[c]);
+            // left the box it was ranked in (the next grid build re-ranks it);
+            // that box is recomputed from p, so q need not live through the walk
+            int32_t cold[3];
+            bool left = !ok || !(box_coord(double(p.x), G.inv_h, &cold[0]) && box_coord(double(p.y), G.inv_h, &cold[1]) &&
+                                 box_coord(double(p.z), G.inv_h, &cold[2]));
+            for (int c = 0; c < 3; ++c) left = left || cnew[c] != cold[c];
             b.flags[nxt][out] = nf | (left ? kBoxChangedBit : 0u);
         }
         if (!ok) raise_error(b.g, kErrNonfinite);
     }
-    // ---- box extent and statistics: wave, then block (LDS atomics), then
-    // the last wave of the block adds the block's result to the replicas
+    // ---- box extent and statistics: wave, then block (LDS atomics)
     const bool contrib = active && ok;
     const unsigned long long any = __ballot(contrib);
     const uint32_t ns = uint32_t(__popcll(__ballot(active && is_static)));
@@ -160,6 +194,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
     if (lane_id() == 0) {
         if (ns) atomicAdd(&s_cnt[0], ns);
         if (nm) atomicAdd(&s_cnt[1], nm);
+    }
+    // ---- the last wave of the block to finish adds the block's result to the replicas
+    if (lane_id() == 0) {
         __threadfence_block();
         const uint32_t nwaves = (blockDim.x + 63u) >> 6;
         if (atomicAdd(&s_cnt[2], 1u) == nwaves - 1) {
@@ -185,10 +222,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
 template <class T, bool S, bool K, bool R, int CH>
 static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
     const int bs = a.block_size;
-    const uint32_t blocks = (b.n + bs - 1) / bs;
+    const uint32_t nb = (b.n + bs - 1) / bs;
+    // storage chunks hold agents only in an update build
+    const uint32_t first = a.full_only ? nb : 0u;
+    const uint32_t blocks = 2u * nb - first;
     const uint32_t run = xcd_run(blocks);
     hipLaunchKernelGGL((k_force<T, S, K, R, CH>), dim3(xcd_grid(blocks, run)), dim3(bs), walk_lds_bytes(bs), s, b, a,
-                       run);
+                       run, first);
 }
 
 template <class T, int CH>
@@ -219,23 +259,30 @@ void launch_force(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
 // the step): the walk of the step, the exact test |e|^2 < R^2 in double.
 // rows == nullptr: counts[id] = |N(i)|.  Otherwise row id of `rows` (width
 // K) gets the neighbour ids in ascending order (insertion), and *worst the
-// largest count.
+// largest count.  One thread per loose slot of the grid.
+template <class T>
+__device__ __forceinline__ uint32_t loose_storage(const Buffers<T>& b, uint32_t u) {
+    return u < b.n ? u : b.perm[u - b.n];
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_neighbors(Buffers<T> b, int ids_cur, uint32_t* __restrict__ counts,
                                                    uint32_t* __restrict__ rows, uint32_t K, uint32_t* worst) {
     extern __shared__ __align__(16) unsigned char s_walk[];
     const WalkLds L = walk_lds(s_walk);
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= b.n) return;
-    const SimGrid& G = b.sims[sim_index(b, t)];
+    if (t >= 2u * b.n) return;
+    const bool live = t < b.n ? (b.g->inc && b.gkey[t] != kDeadKey) : t - b.n < b.g->napp;
+    if (!live) return;
     const uint32_t* ids = b.ids[ids_cur];
-    const uint32_t i = b.perm[t];
+    const uint32_t i = loose_storage(b, t);
     const uint32_t id = i < b.n ? ids[i] : 0xFFFFFFFFu;
     if (id >= b.n) {
         raise_error(b.g, kErrInternal);
         return;
     }
-    const V4<T> p = spos_ptr(b)[t];
+    const SimGrid& G = b.sims[sim_index(b, i)];
+    const V4<T> p = gpos_ptr(b)[t];
     uint32_t q[3];
     if (!G.valid || !box_of<T>(G, p, q)) {
         raise_error(b.g, kErrInternal);
@@ -247,11 +294,11 @@ __global__ __launch_bounds__(256) void k_neighbors(Buffers<T> b, int ids_cur, ui
     uint32_t* row = rows ? rows + size_t(id) * K : nullptr;
     stream_pieces(L, P, [&](uint32_t u) {
         if (u == t) return true;
-        const V4<T> pj = spos_ptr(b)[u];
+        const V4<T> pj = gpos_ptr(b)[u];
         const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
         if (!(((ex * ex + ey * ey) + ez * ez) < G.r2)) return true;
         if (row && cnt < K) {
-            const uint32_t j = b.perm[u];
+            const uint32_t j = loose_storage(b, u);
             const uint32_t jd = j < b.n ? ids[j] : 0xFFFFFFFFu;
             uint32_t x = cnt;
             while (x > 0 && row[x - 1] > jd) {
@@ -273,8 +320,8 @@ __global__ __launch_bounds__(256) void k_neighbors(Buffers<T> b, int ids_cur, ui
 template <class T>
 void launch_neighbors(const Buffers<T>& b, int ids_cur, uint32_t* counts, uint32_t* rows, uint32_t K,
                       uint32_t* worst, hipStream_t s) {
-    hipLaunchKernelGGL(k_neighbors<T>, dim3((b.n + 255) / 256), dim3(256), walk_lds_bytes(256), s, b, ids_cur, counts,
-                       rows, K, worst);
+    hipLaunchKernelGGL(k_neighbors<T>, dim3((2u * b.n + 255) / 256), dim3(256), walk_lds_bytes(256), s, b, ids_cur,
+                       counts, rows, K, worst);
 }
 
 // ------------------------------------------------------------------ copies
@@ -298,17 +345,12 @@ void launch_unpack_positions(const Buffers<T>& b, int pos_cur, int ids_cur, T* o
     hipLaunchKernelGGL(k_unpack_positions<T>, dim3((b.n + 255) / 256), dim3(256), 0, s, b, pos_cur, ids_cur, out);
 }
 
-// field: 1 forces, 2 moved, 3 static, 4 nnz, 6 perm, 9 storage ids
+// field: 1 forces, 2 moved, 3 static, 4 nnz, 9 storage ids
 template <class T>
 __global__ void k_unpack_field(Buffers<T> b, int cur, int ids_cur, int field, void* out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.n) return;
     const uint32_t* ids = b.ids[ids_cur];
-    if (field == 6) {   // canonical order of the last grid: slot -> id
-        const uint32_t j = b.perm[i];
-        static_cast<uint32_t*>(out)[i] = j < b.n ? ids[j] : 0xFFFFFFFFu;
-        return;
-    }
     if (field == 9) {
         static_cast<uint32_t*>(out)[i] = ids[i];
         return;

@@ -1,9 +1,9 @@
 // force_loop.h -- the neighbour walk and the pair force, shared by the step
 // kernel and the reverse-mode kernels.
 //
-// Agents sit in slots of the canonical (box rank, id) order; the grid build
-// writes the slot-ordered copy `spos` ({x, y, z, d}, sign of d = moved in the
-// last step).  The walk covers the 3x3x3 boxes of Section 3.1 through
+// The walk reads the agents of a super-box from the grid's loose position
+// array ({x, y, z, d}, sign of d = moved in the last step) at the slot range
+// its table entry gives.  The walk covers the 3x3x3 boxes of Section 3.1 through
 // super-boxes, the aligned 2x2x2 blocks S = q >> 1 of boxes: a super-box is 8
 // consecutive Morton codes, so its agents are one contiguous slot range,
 // sorted by octant.  Along each axis the boxes q-1..q+1 lie in two
@@ -23,7 +23,8 @@
 // block's lower coordinate on that axis.  So the block's Morton order is a
 // 3-bit count whose digits are the axes ranked by 3 t_a + a.  Pieces within a
 // super-box are in octant order, hence the walk yields every neighbour in
-// ascending slot order, the canonical order of the sums.
+// canonical (box rank, id) order, the order of the sums, wherever the grid
+// put each super-box's slot range.
 #pragma once
 
 #include "abm_device.h"
@@ -31,12 +32,12 @@
 namespace abm {
 
 template <class T>
-__device__ __forceinline__ const V4<T>* spos_ptr(const Buffers<T>& b) {
-    return reinterpret_cast<const V4<T>*>(b.spos);
+__device__ __forceinline__ const V4<T>* gpos_ptr(const Buffers<T>& b) {
+    return reinterpret_cast<const V4<T>*>(b.gpos);
 }
 
 // Super-box table entry (16 B):
-//   x  first slot of the super-box
+//   x  first loose slot of the super-box
 //   y  number of its agents (bits 0..23); bit 24 + o: an agent of octant o
 //      moved in the last step
 //   z  agents in octants < 2 (bits 0..15) and in octants < 4 (bits 16..31)
@@ -104,6 +105,7 @@ __device__ __forceinline__ WalkLds walk_lds(void* base) {
 struct Pieces {
     uint32_t mask = 0;    // bit j: piece j (Morton position j of its super-box) is not empty
     uint32_t total = 0;   // slots in all pieces
+    uint32_t xown = 0;    // first loose slot of the super-box of box q
     bool moved = false;   // an agent of one of the 27 boxes moved in the last step
 };
 
@@ -141,12 +143,14 @@ __device__ __forceinline__ Pieces load_pieces(const Buffers<T>& b, const SimGrid
     const uint32_t zm[2] = {bq[2] ? 0xFFu : 0xF0u, bq[2] ? 0x0Fu : 0xFFu};
     uint32_t moved = 0;
     Pieces P;
+    const int own = int(bq[0] ^ 1u) | int((bq[1] ^ 1u) << 1) | int((bq[2] ^ 1u) << 2);   // S = q >> 1
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const uint32_t dx = uint32_t(c) & 1u, dy = (uint32_t(c) >> 1) & 1u, dz = uint32_t(c) >> 2;
         uint4 e = make_uint4(0u, 0u, 0u, 0u);
         if (inx[dx] && iny[dy] && inz[dz]) e = b.cellinfo[base + dz * plane + dy * sd0 + dx];
         if (super_stamp(e) != st15) e = make_uint4(0u, 0u, 0u, 0u);
+        P.xown = c == own ? e.x : P.xown;
         moved |= (e.y >> 24) & xm[dx] & ym[dy] & zm[dz];
         const uint32_t c8 = e.y & kMaxSuperCount, c2 = e.z & 0xFFFFu, c4 = e.z >> 16, c6 = e.w & 0xFFFFu;
         // the y (z) half of this super-box is cut when it lies on the far side
@@ -203,14 +207,14 @@ __device__ __forceinline__ bool stream_pieces(const WalkLds& L, const Pieces& P,
 // requested before the current one is tested (two register buffers, A and B,
 // take turns).  A chunk is [u, u + CH) of a piece [.., e); the next
 // non-empty piece is already read from LDS.  Slots past the piece end are
-// read (the slot-ordered array is padded) but must not be used:
+// read (the loose position array is padded) but must not be used:
 // test(pc, u, left) sees the chunk's positions, its first slot and the
 // number of its slots inside the piece, and returns false to stop the walk.
 template <int CH, class T, class Test>
 __device__ __forceinline__ void walk_chunks(const Buffers<T>& b, const Pieces& P, const WalkLds& L, Test&& test) {
     static_assert(CH >= 1 && CH <= kSposPad && kQueueCap > CH, "walk chunk");
     if (!P.mask) return;
-    const V4<T>* __restrict__ sp = spos_ptr(b);
+    const V4<T>* __restrict__ sp = gpos_ptr(b);
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
     uint32_t M = P.mask;
     const uint32_t k0 = uint32_t(__ffs(M)) - 1u;
@@ -288,13 +292,12 @@ struct ForceSum {
 // survivors (the agent itself among them: the exact test drops d = 0);
 // a nearly full queue (and the end) is drained by pass 2, which keeps the
 // candidates in contact (exact test, in place) and then adds their terms.
-// Queue order is stream order, so the terms are summed in ascending slot
-// order.
+// Queue order is stream order, so the terms are summed in canonical order.
 template <int CH, class T, bool PARAM_GRADS>
 __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, const Pieces& P,
                                          const WalkLds& L, ForceSum& acc) {
-    const V4<T>* __restrict__ sp = spos_ptr(b);
-    const uint32_t tid = threadIdx.x, bs = blockDim.x, last = b.n - 1;
+    const V4<T>* __restrict__ sp = gpos_ptr(b);
+    const uint32_t tid = threadIdx.x, bs = blockDim.x, last = 2u * b.n - 1u;
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
     const double ri = 0.5 * fabs(double(p.w));
     const double r2 = G.r2, k = G.k, gamma = G.gamma;

@@ -4,12 +4,15 @@
 // order):
 //   bbox     box extent of the agents (per simulation)
 //   setup    dims, box and super-box counts and bases of every simulation
-//   keys     super-box key and octant of every agent + histogram (atomics)
+//   keys     super-box key and octant of every agent + histogram (atomics);
+//            an update build: only the agents that left their box
 //   scan     exclusive scan of the super-box counts (tile sums, their scan,
 //            rescan)
-//   scatter  agents into super-box order (arrival order inside a super-box)
-//   fixup    canonical (box, id) order inside each super-box + the row-major
-//            super-box table
+//   scatter  records of the agents of the (re)built super-boxes, in arrival
+//            order inside a super-box
+//   fixup    canonical (box, id) order inside each (re)built super-box, its
+//            agents written to loose slots + the row-major super-box table
+//   clean    update build: table entries of the super-boxes kept in place
 #include "force_loop.h"
 
 namespace abm {
@@ -53,7 +56,7 @@ __global__ void k_radius(Buffers<T> b, int cur) {
     unsigned long long v = 0;
     if (active) {
         sim = sim_index(b, i);
-        const double d = double(pos4_ptr(b, cur)[i].w);
+        const double d = fabs(double(pos4_ptr(b, cur)[i].w));   // the sign of d is the moved flag
         active = d > 0.0 && isfinite(d);
         v = (unsigned long long)__double_as_longlong(d);
     }
@@ -222,7 +225,8 @@ constexpr int kTileLevels = 3;    // tiles of 8 x 8 x 8 super-boxes
 constexpr int kTileBlocks = 256;  // grid of the tile-table kernel (it loops)
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int32_t* rep, int nsims,
-                                                           int parity, uint32_t box_capacity, int allow_inc) {
+                                                           int parity, uint32_t box_capacity, int allow_inc,
+                                                           uint32_t n) {
     __shared__ unsigned long long s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
     __shared__ uint32_t s_dirty, s_same;
@@ -337,11 +341,11 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
         g->inc = (allow_inc && s_same && total > 0) ? 1u : 0u;
         g->epoch = g->epoch + 1u ? g->epoch + 1u : 1u;
         g->ndirty = 0u;
-        // a fresh stamp marks this step's box table entries (the host clears
-        // the table before the 15-bit stamp wraps); a fresh epoch tags this
-        // step's scan status words
-        g->stamp = g->stamp + 1;
-        g->scan_epoch = (g->scan_epoch % 0x3FFFFFFFu) + 1;
+        g->napp = n;   // a full build fills the whole append region (an update: set by its scan)
+        // a full build marks its box table entries with a fresh stamp (the
+        // host clears the table before the 15-bit stamp wraps); an update
+        // keeps the entries of the super-boxes it does not rebuild
+        if (!g->inc) g->stamp = g->stamp + 1;
     }
 }
 
@@ -378,7 +382,7 @@ __global__ __launch_bounds__(256) void k_tiles(const Globals* g, const SimGrid* 
 template <class T>
 void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, b.g, b.sims, b.bbox_rep, b.nsims, parity,
-                       b.box_capacity, allow_inc ? 1 : 0);
+                       b.box_capacity, allow_inc ? 1 : 0, b.n);
     hipLaunchKernelGGL(k_tiles, dim3(kTileBlocks), dim3(256), 0, s, b.g, b.sims, b.nsims, b.tile_off);
 }
 
@@ -406,7 +410,7 @@ __device__ __forceinline__ bool super_key(const Buffers<T>& b, const SimGrid& G,
 // Lanes of a wave that hold equal values of k come in runs (agents of one
 // super-box are neighbours in storage).  wave_run_add adds each run's length
 // to arr[k] with one atomic and returns every lane's index in arr[k]'s
-// count; wave_run_or ORs each run's bits into arr[k] with one atomic.
+// count.
 __device__ __forceinline__ uint32_t wave_run_add(uint32_t* arr, bool act, uint32_t k) {
     const int lane = lane_id();
     const uint32_t pk = __shfl_up(k, 1, 64);
@@ -424,93 +428,65 @@ __device__ __forceinline__ uint32_t wave_run_add(uint32_t* arr, bool act, uint32
     return old + uint32_t(lane - leader);
 }
 
-__device__ __forceinline__ void wave_run_or(uint32_t* arr, bool act, uint32_t k, uint32_t bits) {
-    const int lane = lane_id();
-    const uint32_t pk = __shfl_up(k, 1, 64);
-    const int pact = __shfl_up(act ? 1 : 0, 1, 64);
-    const bool head = act && (lane == 0 || !pact || pk != k);
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0..lane
-    // the run of a lane is named by its first lane (inactive lanes: a name of their own)
-    const int run = act ? 63 - __clzll((long long)(heads & upto)) : 64 + lane;
-    // segmented OR towards the run's first lane: after the step with distance
-    // d, a lane holds the OR over [lane, lane + 2d) within its run
-    uint32_t v = act ? bits : 0u;
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_down(v, d, 64);
-        const int orun = __shfl_down(run, d, 64);
-        if (lane + d < 64 && orun == run) v |= o;
-    }
-    if (head && v) atomicOr(&arr[k], v);
-}
-
-// Claim super-box sk as changed in this build: true for the one caller that
-// marks it first (it resets the super-box's arrival counter and lists it).
-__device__ __forceinline__ bool claim_changed(Globals* g, uint32_t* dirty, uint32_t* darr, uint32_t sk) {
-    const uint32_t ep = g->epoch;
-    if (atomicExch(&dirty[sk], ep) == ep) return false;
-    darr[sk] = 0u;
-    return true;
-}
-
-// Append the claimed super-boxes of a wave to the list with one atomic.
-__device__ __forceinline__ void list_claimed(Globals* g, uint32_t* list, bool c0, uint32_t k0, bool c1, uint32_t k1) {
-    const unsigned long long b0 = __ballot(c0), b1 = __ballot(c1);
-    if (!(b0 | b1)) return;
-    const int lane = lane_id();
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const uint32_t n0 = uint32_t(__popcll(b0)), total = n0 + uint32_t(__popcll(b1));
-    const int leader = __ffsll((long long)(b0 | b1)) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&g->ndirty, total);
-    base = __shfl(base, leader, 64);
-    if (c0) list[base + uint32_t(__popcll(b0 & below))] = k0;
-    if (c1) list[base + n0 + uint32_t(__popcll(b1 & below))] = k1;
-}
-
 // Full build: key of every agent and its arrival index in its super-box
 // (histogram atomics).  Update build (the last grid's extent, agents stored in
-// its canonical order): agents that stayed in their box keep their key; the
-// others get a new key, move one count from the old to the new super-box and
-// mark both as changed.  Both: the moved bits per octant of every super-box.
+// its canonical order): only agents that left their box get a new key; each
+// moves one count from its old to its new super-box, marks both as changed
+// (the epoch of this build) and is listed as a mover in its block's segment.
+constexpr int kKeysThreads = 256;
 template <class T>
-__global__ void k_keys(Buffers<T> b, int cur) {
+__global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur) {
+    __shared__ uint32_t s_movers;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool inc = b.g->inc != 0u;
-    bool act = false, c0 = false, c1 = false;
-    uint32_t key = 0, f = 0, old = 0;
+    bool act = false, mv = false;
+    uint32_t key = 0;
+    if (inc && threadIdx.x == 0) s_movers = 0u;
     if (i < b.n) {
         const SimGrid& G = b.sims[sim_index(b, i)];
-        if (G.valid) {
-            f = b.flags[cur][i];
-            if (inc && !(f & kBoxChangedBit)) {
-                key = b.skey[i];
+        if (G.valid && !inc) {
+            if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
                 act = true;
-            } else if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
-                act = true;
-                if (inc) {
-                    old = b.skey[i];
-                    if (key != old) {   // left its box: one count moves, both super-boxes change
-                        atomicAdd(&b.count[old >> 3], 0xFFFFFFFFu);
-                        atomicAdd(&b.count[key >> 3], 1u);
-                        c0 = claim_changed(b.g, b.dirty, b.darr, old >> 3);
-                        c1 = claim_changed(b.g, b.dirty, b.darr, key >> 3);
-                    }
-                }
             } else {   // the extent is computed from these very positions
                 raise_error(b.g, kErrInternal);
                 key = 0xFFFFFFFFu;
             }
             b.key[i] = key;
+        } else if (G.valid && (b.flags[cur][i] & kBoxChangedBit)) {
+            const uint32_t old = b.skey[cur][i];
+            if ((old >> 3) >= b.g->total_super) {
+                raise_error(b.g, kErrInternal);
+            } else if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
+                b.key[i] = key;   // read by the scatter for every agent that left its box
+                if (key != old) {
+                    mv = true;
+                    const uint32_t ep = b.g->epoch;
+                    atomicAdd(&b.count[old >> 3], 0xFFFFFFFFu);
+                    atomicAdd(&b.count[key >> 3], 1u);
+                    b.dirty[old >> 3] = ep;
+                    b.dirty[key >> 3] = ep;
+                }
+            } else {
+                raise_error(b.g, kErrInternal);
+                b.key[i] = old;
+            }
         }
     }
     if (!inc) {
         const uint32_t sub = wave_run_add(b.count, act, key >> 3);
         if (act) b.sub[i] = sub;
-    } else {
-        list_claimed(b.g, b.dirty_list, c0, old >> 3, c1, key >> 3);
-        wave_run_or(b.mmask, act && (f & kMovedBit), key >> 3, 1u << (key & 7u));
+        return;
     }
+    // the block's movers, at its own segment of the list (LDS atomics only)
+    __syncthreads();
+    const unsigned long long m = __ballot(mv);
+    const int lane = lane_id();
+    uint32_t base = 0;
+    if (m && lane == 0) base = atomicAdd(&s_movers, uint32_t(__popcll(m)));
+    base = __shfl(base, 0, 64);
+    if (mv) b.movers[blockIdx.x * kKeysThreads + base + uint32_t(__popcll(m & ((1ull << lane) - 1ull)))] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) b.mcount[blockIdx.x] = s_movers;
 }
 
 // ------------------------------------------------------------------ scan
@@ -523,19 +499,24 @@ __device__ __forceinline__ uint32_t wave_inclusive(uint32_t x) {
     return x;
 }
 
-// Exclusive scan of count[0, total) into cell_start[0, total], zeroing count,
-// in three passes over tiles of kScanTile boxes: per-tile sums, a one-block
-// scan of the tile sums, and a per-tile rescan that adds the tile's prefix.
-// Global loads and stores are striped across the block and transposed
-// through LDS, so every wave touches whole cache lines.
+// Exclusive scan of the super-box counts into cell_start[0, total], zeroing
+// count, in three passes over tiles of kScanTile super-boxes: per-tile sums,
+// a one-block scan of the tile sums, and a per-tile rescan that adds the
+// tile's prefix.  Global loads and stores of the counts are striped across
+// the block and transposed through LDS, so every wave touches whole cache
+// lines.  An update build scans two more quantities along: the changed
+// super-boxes (marked with this build's epoch) and their agents; the rescan
+// lists the changed super-boxes in rank order, each with its first slot in
+// the append region.
 __device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
 
 // Load tile `tile` of the counts into LDS (striped), return this thread's
 // blocked 16 values.  In an update build the counts are the last grid's
-// (differences of its starts) plus the changes in `count`.
+// (differences of its starts) plus the changes in `count`, and bit k of *dm
+// says that value k's super-box changed.
 __device__ __forceinline__ void load_tile(const uint32_t* __restrict__ count, const uint32_t* __restrict__ cs_old,
-                                          bool inc, uint32_t base, uint32_t total, uint32_t* s_data,
-                                          uint32_t v[kScanItems]) {
+                                          const uint32_t* __restrict__ dirty, uint32_t ep, bool inc, uint32_t base,
+                                          uint32_t total, uint32_t* s_data, uint32_t v[kScanItems], uint32_t* dm) {
     for (int k = 0; k < kScanItems / 4; ++k) {
         const uint32_t e4 = uint32_t(k) * kScanThreads + threadIdx.x;
         const uint32_t g0 = base + 4 * e4;
@@ -550,6 +531,7 @@ __device__ __forceinline__ void load_tile(const uint32_t* __restrict__ count, co
     }
     __syncthreads();
     for (int k = 0; k < kScanItems; ++k) v[k] = s_data[lds_pad(threadIdx.x * kScanItems + k)];
+    *dm = 0u;
     if (inc) {
         const uint32_t g0 = base + threadIdx.x * kScanItems;
         if (g0 < total) {
@@ -559,36 +541,54 @@ __device__ __forceinline__ void load_tile(const uint32_t* __restrict__ count, co
                 const uint32_t nxt = cs_old[g0 + k + 1];
                 v[k] += nxt - prev;
                 prev = nxt;
+                *dm |= (dirty[g0 + k] == ep ? 1u : 0u) << k;
             }
         }
     }
 }
 
+// This thread's sums: agents, changed super-boxes, agents of changed super-boxes.
+__device__ __forceinline__ void thread_sums(const uint32_t v[kScanItems], uint32_t dm, uint32_t x[3]) {
+    x[0] = 0u;
+    x[2] = 0u;
+    for (int k = 0; k < kScanItems; ++k) {
+        x[0] += v[k];
+        x[2] += ((dm >> k) & 1u) ? v[k] : 0u;
+    }
+    x[1] = uint32_t(__popc(dm));
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Globals* g, const uint32_t* __restrict__ count,
                                                                const uint32_t* __restrict__ cs_old,
-                                                               uint32_t* __restrict__ tile_sum, uint32_t ntiles) {
+                                                               const uint32_t* __restrict__ dirty,
+                                                               uint32_t* __restrict__ sums, uint32_t ntiles) {
     __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
-    __shared__ uint32_t s_wave[kScanThreads / 64];
+    __shared__ uint32_t s_wave[3][kScanThreads / 64];
     const uint32_t total = g->total_super;
     const uint32_t tile = blockIdx.x;
     if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
-    uint32_t v[kScanItems];
-    load_tile(count, cs_old, g->inc != 0u, tile * kScanTile, total, s_data, v);
-    uint32_t sum = 0;
-    for (int k = 0; k < kScanItems; ++k) sum += v[k];
-    for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
-    if (lane_id() == 0) s_wave[threadIdx.x >> 6] = sum;
+    const bool inc = g->inc != 0u;
+    uint32_t v[kScanItems], dm;
+    load_tile(count, cs_old, dirty, g->epoch, inc, tile * kScanTile, total, s_data, v, &dm);
+    uint32_t x[3];
+    thread_sums(v, dm, x);
+    for (int c = 0; c < 3; ++c) {
+        for (int d = 32; d >= 1; d >>= 1) x[c] += __shfl_xor(x[c], d, 64);
+        if (lane_id() == 0) s_wave[c][threadIdx.x >> 6] = x[c];
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 3) {
         uint32_t t = 0;
-        for (int w = 0; w < kScanThreads / 64; ++w) t += s_wave[w];
-        tile_sum[tile] = t;
+        for (int w = 0; w < kScanThreads / 64; ++w) t += s_wave[threadIdx.x][w];
+        sums[threadIdx.x * ntiles + tile] = t;
     }
 }
 
-// One block: exclusive scan of the tile sums in place; cell_start[total] = sum.
+// One block: exclusive scan of the tile sums in place; cell_start[total] =
+// agents, and in an update build the number of changed super-boxes and of
+// their agents.
 constexpr int kTileScanThreads = 1024;
-__global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uint32_t* __restrict__ tile_sum,
+__global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uint32_t* __restrict__ sums,
                                                                   uint32_t* __restrict__ cell_start,
                                                                   uint32_t ntiles) {
     __shared__ uint32_t s_wave[kTileScanThreads / 64];
@@ -599,153 +599,194 @@ __global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uin
         if (threadIdx.x == 0) raise_error(g, kErrInternal);
         return;
     }
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (uint32_t base = 0; base < needed; base += kTileScanThreads) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t x = i < needed ? tile_sum[i] : 0u;
-        const uint32_t incl = wave_inclusive(x);
-        const int wave = int(threadIdx.x >> 6);
-        if (lane_id() == 63) s_wave[wave] = incl;
+    const int ncomp = g->inc ? 3 : 1;
+    for (int c = 0; c < ncomp; ++c) {
+        uint32_t* ts = sums + size_t(c) * ntiles;
+        if (threadIdx.x == 0) s_carry = 0;
         __syncthreads();
-        uint32_t off = s_carry;
-        for (int w = 0; w < wave; ++w) off += s_wave[w];
-        if (i < needed) tile_sum[i] = off + incl - x;
-        __syncthreads();
-        if (threadIdx.x == kTileScanThreads - 1) s_carry = off + incl;
+        for (uint32_t base = 0; base < needed; base += kTileScanThreads) {
+            const uint32_t i = base + threadIdx.x;
+            const uint32_t x = i < needed ? ts[i] : 0u;
+            const uint32_t incl = wave_inclusive(x);
+            const int wave = int(threadIdx.x >> 6);
+            if (lane_id() == 63) s_wave[wave] = incl;
+            __syncthreads();
+            uint32_t off = s_carry;
+            for (int w = 0; w < wave; ++w) off += s_wave[w];
+            if (i < needed) ts[i] = off + incl - x;
+            __syncthreads();
+            if (threadIdx.x == kTileScanThreads - 1) s_carry = off + incl;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (c == 0 && total > 0) cell_start[total] = s_carry;
+            if (c == 1) g->ndirty = s_carry;
+            if (c == 2) g->napp = s_carry;
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0 && total > 0) cell_start[total] = s_carry;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, uint32_t* __restrict__ count,
                                                              const uint32_t* __restrict__ cs_old,
+                                                             const uint32_t* __restrict__ dirty,
                                                              uint32_t* __restrict__ cell_start,
-                                                             const uint32_t* __restrict__ tile_prefix,
-                                                             uint32_t ntiles) {
+                                                             const uint32_t* __restrict__ sums,
+                                                             uint32_t* __restrict__ dirty_list,
+                                                             uint32_t* __restrict__ aoff, uint32_t ntiles) {
     __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
-    __shared__ uint32_t s_wave[kScanThreads / 64];
+    __shared__ uint32_t s_wave[3][kScanThreads / 64];
     const uint32_t total = g->total_super;
     const uint32_t tile = blockIdx.x;
     if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
+    const bool inc = g->inc != 0u;
     const uint32_t base = tile * kScanTile;
-    uint32_t v[kScanItems];
-    load_tile(count, cs_old, g->inc != 0u, base, total, s_data, v);
-    uint32_t sum = 0;
-    for (int k = 0; k < kScanItems; ++k) sum += v[k];
-    const uint32_t incl = wave_inclusive(sum);
+    uint32_t v[kScanItems], dm;
+    load_tile(count, cs_old, dirty, g->epoch, inc, base, total, s_data, v, &dm);
+    uint32_t x[3], run[3];
+    thread_sums(v, dm, x);
     const int wave = int(threadIdx.x >> 6);
-    if (lane_id() == 63) s_wave[wave] = incl;
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t incl = wave_inclusive(x[c]);
+        if (lane_id() == 63) s_wave[c][wave] = incl;
+        run[c] = incl - x[c];
+    }
     __syncthreads();
-    uint32_t run = tile_prefix[tile] + incl - sum;
-    for (int w = 0; w < wave; ++w) run += s_wave[w];
+    for (int c = 0; c < (inc ? 3 : 1); ++c) {
+        run[c] += sums[c * ntiles + tile];
+        for (int w = 0; w < wave; ++w) run[c] += s_wave[c][w];
+    }
+    const uint32_t g0 = base + threadIdx.x * kScanItems;
     for (int k = 0; k < kScanItems; ++k) {
-        s_data[lds_pad(threadIdx.x * kScanItems + k)] = run;
-        run += v[k];
+        s_data[lds_pad(threadIdx.x * kScanItems + k)] = run[0];
+        if ((dm >> k) & 1u) {   // a changed super-box (update build only)
+            dirty_list[run[1]] = g0 + k;
+            aoff[g0 + k] = run[2];
+            run[1] += 1u;
+            run[2] += v[k];
+        }
+        run[0] += v[k];
     }
     __syncthreads();
     for (int k = 0; k < kScanItems / 4; ++k) {
         const uint32_t e4 = uint32_t(k) * kScanThreads + threadIdx.x;
-        const uint32_t g0 = base + 4 * e4;
+        const uint32_t q0 = base + 4 * e4;
         uint32_t o[4];
         for (int c = 0; c < 4; ++c) o[c] = s_data[lds_pad(4 * e4 + c)];
-        if (g0 + 4 <= total) {
-            reinterpret_cast<uint4*>(cell_start)[g0 >> 2] = make_uint4(o[0], o[1], o[2], o[3]);
-            reinterpret_cast<uint4*>(count)[g0 >> 2] = make_uint4(0u, 0u, 0u, 0u);
+        if (q0 + 4 <= total) {
+            reinterpret_cast<uint4*>(cell_start)[q0 >> 2] = make_uint4(o[0], o[1], o[2], o[3]);
+            reinterpret_cast<uint4*>(count)[q0 >> 2] = make_uint4(0u, 0u, 0u, 0u);
         } else {
             for (int c = 0; c < 4; ++c)
-                if (g0 + c < total) {
-                    cell_start[g0 + c] = o[c];
-                    count[g0 + c] = 0u;
+                if (q0 + c < total) {
+                    cell_start[q0 + c] = o[c];
+                    count[q0 + c] = 0u;
                 }
         }
     }
 }
 
 // ------------------------------------------------------------------ scatter / fixup
-// Full build: the scatter writes, per arrival slot, a record {storage index,
-// agent id, first slot of the super-box, agent count << 4 | octant << 1 |
-// moved}, so that the fixup finds everything it needs in the records of its
-// super-box.
-//
-// Update build (agents stored in the last grid's canonical order, same
-// extent): an agent of a super-box that neither gained nor lost agents keeps
-// its place among them, so its slot moves by the change of the super-box's
-// start; the first of them also rewrites the super-box's table entry (same
-// octant counts, new start, moved bits and stamp).  Agents of a changed
-// super-box leave a record for the fixup instead.
-
-// The agent at storage index i goes to slot t of the canonical order.
+// The scatter writes, per agent of a (re)built super-box, a record {storage
+// index, agent id, first canonical slot of the super-box, agent count << 4 |
+// octant << 1 | moved} at a canonical slot of that super-box, so that the
+// fixup finds everything it needs in the records of its super-box.  A full
+// build rebuilds every super-box.  An update build rebuilds the changed ones
+// (the list made by k_keys): their agents that stayed, found in their old
+// storage ranges (which the update leaves dead), and the movers.
 template <class T>
-__device__ __forceinline__ void place_agent(const Buffers<T>& b, int cur, int ids_cur, int ids_next, uint32_t i,
-                                            uint32_t t, uint32_t key, uint32_t fl, V4<T> p) {
-    b.perm[t] = i;
-    b.sflags[t] = fl;
-    b.skey[t] = key;
-    if (ids_next >= 0) b.ids[ids_next][t] = b.ids[ids_cur][i];   // the step re-lays agents out in this order
-    if (fl & kMovedBit) p.w = -p.w;
-    reinterpret_cast<V4<T>*>(b.spos)[t] = p;
-}
-
-template <class T>
-__global__ void k_scatter(Buffers<T> b, int cur, int ids_cur, int ids_next) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= b.n) return;
-    const SimGrid& G = b.sims[sim_index(b, i)];
-    if (!G.valid) return;
-    const uint32_t key = b.key[i];
-    const uint32_t sk = key >> 3;
-    if (sk >= b.g->total_super) {
-        raise_error(b.g, kErrInternal);
-        return;
-    }
-    const uint32_t st = b.cell_start[sk], en = b.cell_start[sk + 1];
-    const uint32_t fl = b.flags[cur][i];
-    if (b.g->inc && b.dirty[sk] != b.g->epoch) {
-        const uint32_t t = i + st - b.cell_start_old[sk];
-        if (t >= b.n) {
-            raise_error(b.g, kErrInternal);
-            return;
-        }
-        const V4<T> p = pos4_ptr(b, cur)[i];
-        place_agent<T>(b, cur, ids_cur, ids_next, i, t, key, fl, p);
-        if (i == b.cell_start_old[sk]) {
-            uint32_t q[3];
-            if (!box_of<T>(G, p, q)) {
+__global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    const uint32_t* __restrict__ cs = b.cell_start;
+    if (!b.g->inc) {
+        const uint32_t total = b.g->total_super;
+        for (uint32_t i = tid; i < b.n; i += stride) {
+            const SimGrid& G = b.sims[sim_index(b, i)];
+            if (!G.valid) continue;
+            const uint32_t key = b.key[i];
+            const uint32_t sk = key >> 3;
+            if (sk >= total) {
                 raise_error(b.g, kErrInternal);
-                return;
+                continue;
             }
-            uint4* entry = &b.cellinfo[super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1)];
-            const uint4 e = *entry;
-            const uint32_t mm = b.mmask[sk];
-            b.mmask[sk] = 0u;
-            *entry = make_uint4(st, (e.y & kMaxSuperCount) | (mm << 24), e.z,
-                                (e.w & 0xFFFFu) | ((b.g->stamp & 0x7FFFu) << 17));
+            const uint32_t st = cs[sk], en = cs[sk + 1];
+            const uint32_t slot = st + b.sub[i];
+            if (slot >= en || en > b.n) {
+                raise_error(b.g, kErrInternal);
+                continue;
+            }
+            b.rec[slot] = make_uint4(i, b.ids[ids_cur][i], st,
+                                     ((en - st) << 4) | ((key & 7u) << 1) | (b.flags[cur][i] & kMovedBit));
         }
         return;
     }
-    const uint32_t slot = st + (b.g->inc ? atomicAdd(&b.darr[sk], 1u) : b.sub[i]);
-    if (slot >= en || en > b.n) {
-        raise_error(b.g, kErrInternal);
-        return;
+    // changed super-boxes, kFixupLanes threads each: the agents that stayed
+    // (arrival counter: the super-box's count, which the scan left at zero)
+    const uint32_t nd = b.g->ndirty;
+    const uint32_t groups = stride / kFixupLanes, x0 = tid % kFixupLanes;
+    for (uint32_t d = tid / kFixupLanes; d < nd; d += groups) {
+        const uint32_t sk = b.dirty_list[d];
+        const uint32_t o0 = b.cell_start_old[sk], o1 = b.cell_start_old[sk + 1];
+        const uint32_t st = cs[sk], cnt = cs[sk + 1] - st;
+        if (o1 > b.n || st + cnt > b.n) {
+            raise_error(b.g, kErrInternal);
+            continue;
+        }
+        for (uint32_t u = o0 + x0; u < o1; u += kFixupLanes) {
+            const uint32_t kold = b.skey[cur][u], fl = b.flags[cur][u];
+            if (!(fl & kBoxChangedBit) || b.key[u] == kold) {
+                const uint32_t r = atomicAdd(&b.count[sk], 1u);
+                if (r < cnt)
+                    b.rec[st + r] = make_uint4(u, b.ids[ids_cur][u], st,
+                                               (cnt << 4) | ((kold & 7u) << 1) | (fl & kMovedBit));
+                else
+                    raise_error(b.g, kErrInternal);
+            }
+            b.skey[cur][u] = kDeadKey;   // the agent's loose slot is in the append region now
+        }
     }
-    b.rec[slot] = make_uint4(i, b.ids[ids_cur][i], st, ((en - st) << 4) | ((key & 7u) << 1) | (fl & kMovedBit));
+    // ... and the movers, from the segments of the keys kernel's blocks
+    const uint32_t kblocks = (b.n + kKeysThreads - 1) / kKeysThreads;
+    for (uint32_t kb = blockIdx.x; kb < kblocks; kb += gridDim.x) {
+        const uint32_t mc = b.mcount[kb];
+        for (uint32_t m = threadIdx.x; m < mc; m += blockDim.x) {
+            const uint32_t i = b.movers[kb * kKeysThreads + m];
+            if (i >= b.n) {
+                raise_error(b.g, kErrInternal);
+                continue;
+            }
+            const uint32_t key = b.key[i], sk = key >> 3;
+            if (sk >= b.g->total_super) {
+                raise_error(b.g, kErrInternal);
+                continue;
+            }
+            const uint32_t st = cs[sk], cnt = cs[sk + 1] - st;
+            const uint32_t r = atomicAdd(&b.count[sk], 1u);
+            if (r >= cnt || st + cnt > b.n) {
+                raise_error(b.g, kErrInternal);
+                continue;
+            }
+            b.rec[st + r] =
+                make_uint4(i, b.ids[ids_cur][i], st, (cnt << 4) | ((key & 7u) << 1) | (b.flags[cur][i] & kMovedBit));
+        }
+    }
 }
 
-// Rank of the agent of record slot t inside its super-box (records [st, st +
-// cnt)) by (octant, id); the agent goes to slot st + rank.  The first agent in
-// that order writes the super-box's table entry.
+// Rank of the agent of record slot t inside its super-box sk (records [st,
+// st + cnt)) by (octant, id); the agent goes to loose slot x + rank, x the
+// super-box's first loose slot.  The first agent in that order writes the
+// super-box's table entry.
 template <class T>
-__device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G, int cur, int ids_cur, int ids_next,
-                                           uint32_t t, bool inc) {
+__device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G, int cur, uint32_t t, uint32_t sk,
+                                           uint32_t x) {
     const uint4 me = b.rec[t];
     const uint32_t i = me.x, st = me.z, cnt = me.w >> 4;
-    if (i >= b.n || st + cnt > b.n || t < st || t >= st + cnt) {
+    if (i >= b.n || st + cnt > b.n || t < st || t >= st + cnt || x < b.n || x - b.n + cnt > b.n) {
         raise_error(b.g, kErrInternal);
         return;
     }
     // the agent's own state, requested before the walk over its super-box
-    const V4<T> p = pos4_ptr(b, cur)[i];
+    V4<T> p = pos4_ptr(b, cur)[i];
     const uint32_t fl = b.flags[cur][i];
     const unsigned long long mine = ((unsigned long long)((me.w >> 1) & 7u) << 32) | me.y;
     uint32_t r = 0, c2 = 0, c4 = 0, c6 = 0, moved = 0;
@@ -766,8 +807,13 @@ __device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G
             moved |= (in & o.w) << oc;   // bit oc: an agent of octant oc moved
         }
     }
-    const uint32_t sk = b.key[i] >> 3;
-    place_agent<T>(b, cur, ids_cur, ids_next, i, st + r, (sk << 3) | ((me.w >> 1) & 7u), fl, p);
+    const uint32_t u = x + r;
+    p.w = T(fabs(double(p.w)));
+    if (fl & kMovedBit) p.w = -p.w;   // the walk reads the moved flag from the sign of d
+    pos4_ptr(b, cur)[u] = p;
+    b.flags[cur][u] = fl;
+    b.skey[cur][u] = (sk << 3) | ((me.w >> 1) & 7u);
+    b.perm[u - b.n] = i;
     if (r == 0) {
         uint32_t q[3];
         if (!box_of<T>(G, p, q)) {
@@ -775,34 +821,95 @@ __device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G
             return;
         }
         if (cnt > kMaxSuperCount) raise_error(b.g, kErrGrid);
-        if (inc) b.mmask[sk] = 0u;   // the moved bits just recomputed from the records
-        b.cellinfo[super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1)] =
-            pack_super(st, cnt, c2, c4, c6, moved, b.g->stamp);
+        const uint32_t idx = super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1);
+        b.cellinfo[idx] = pack_super(x, cnt, c2, c4, c6, moved, b.g->stamp);
+        b.tabidx[sk] = idx;
     }
 }
 
-// Full build: one thread per record slot.  Update build: one thread per
-// record slot of the changed super-boxes (the list made by k_keys).
+// Full build: every canonical slot t, its agent to loose slot n + t (agents
+// of a simulation whose grid overflowed keep their storage slot, state
+// unchanged).  Update build: the changed super-boxes (the list made by
+// k_keys), kFixupLanes threads each, at append slots handed out per wave.
 template <class T>
-__global__ void k_fixup(Buffers<T> b, int cur, int ids_cur, int ids_next) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_fixup(Buffers<T> b, int cur) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    const uint32_t* __restrict__ cs = b.cell_start;
     if (!b.g->inc) {
-        if (t >= b.n) return;
-        const SimGrid& G = b.sims[sim_index(b, t)];   // a simulation's slots are its agents' range
-        if (!G.valid) return;
-        fixup_slot<T>(b, G, cur, ids_cur, ids_next, t, false);
+        for (uint32_t t = tid; t < b.n; t += stride) {
+            const SimGrid& G = b.sims[sim_index(b, t)];   // a simulation's slots are its agents' range
+            if (G.valid) {
+                const uint32_t i = b.rec[t].x;
+                if (i >= b.n) {
+                    raise_error(b.g, kErrInternal);
+                    continue;
+                }
+                const uint32_t sk = b.key[i] >> 3;
+                fixup_slot<T>(b, G, cur, t, sk, b.n + cs[sk]);
+            } else {
+                pos4_ptr(b, cur)[b.n + t] = pos4_ptr(b, cur)[t];
+                b.flags[cur][b.n + t] = b.flags[cur][t];
+                b.skey[cur][b.n + t] = kDeadKey;
+                b.perm[t] = t;
+            }
+        }
         return;
     }
-    // changed super-boxes of the list, kFixupLanes threads each (more
-    // agents, and more super-boxes than threads, loop)
+    // changed super-boxes, kFixupLanes threads each, at their append slots;
+    // the super-box's count (the scatter's arrival counter) returns to zero
     const uint32_t nd = b.g->ndirty;
-    const uint32_t groups = (gridDim.x * blockDim.x) / kFixupLanes, x0 = t % kFixupLanes;
-    for (uint32_t d = t / kFixupLanes; d < nd; d += groups) {
+    const uint32_t groups = stride / kFixupLanes, x0 = tid % kFixupLanes;
+    for (uint32_t d = tid / kFixupLanes; d < nd; d += groups) {
         const uint32_t sk = b.dirty_list[d];
-        const uint32_t st = b.cell_start[sk], en = b.cell_start[sk + 1];
-        for (uint32_t u = st + x0; u < en; u += kFixupLanes) {
-            const SimGrid& G = b.sims[sim_index(b, u)];
-            fixup_slot<T>(b, G, cur, ids_cur, ids_next, u, true);
+        const uint32_t st = cs[sk], cnt = cs[sk + 1] - st;
+        const uint32_t a0 = b.aoff[sk];
+        if (st + cnt > b.n || a0 + cnt > b.n) {
+            raise_error(b.g, kErrInternal);
+            continue;
+        }
+        if (x0 == 0) b.count[sk] = 0u;
+        if (cnt == 0) {   // emptied (so not empty in the last grid, which wrote its table index)
+            if (x0 == 0) {
+                const uint32_t idx = b.tabidx[sk];
+                if (idx < b.g->total_super)
+                    b.cellinfo[idx] = pack_super(0u, 0u, 0u, 0u, 0u, 0u, b.g->stamp);
+                else
+                    raise_error(b.g, kErrInternal);
+            }
+            continue;
+        }
+        for (uint32_t t = st + x0; t < st + cnt; t += kFixupLanes) {
+            const SimGrid& G = b.sims[sim_index(b, t)];
+            fixup_slot<T>(b, G, cur, t, sk, b.n + a0);
+        }
+    }
+}
+
+// Update build: the table entries of the super-boxes kept in place get their
+// storage range as first loose slot and, with moved_bits, the octants whose
+// agents moved in the last step (from the agents' flags and keys).
+template <class T>
+__global__ void k_clean(Buffers<T> b, int cur, int moved_bits) {
+    if (!b.g->inc) return;
+    const uint32_t total = b.g->total_super, ep = b.g->epoch;
+    const uint32_t* __restrict__ fl = b.flags[cur];
+    const uint32_t* __restrict__ kk = b.skey[cur];
+    for (uint32_t sk = blockIdx.x * blockDim.x + threadIdx.x; sk < total; sk += gridDim.x * blockDim.x) {
+        const uint32_t o0 = b.cell_start_old[sk], o1 = b.cell_start_old[sk + 1];
+        if (o1 == o0 || b.dirty[sk] == ep) continue;
+        const uint32_t idx = b.tabidx[sk];
+        if (o1 > b.n || idx >= total) {
+            raise_error(b.g, kErrInternal);
+            continue;
+        }
+        uint2* e = reinterpret_cast<uint2*>(&b.cellinfo[idx]);
+        if (moved_bits) {
+            uint32_t m = 0;
+            for (uint32_t u = o0; u < o1; ++u) m |= (fl[u] & kMovedBit) << (kk[u] & 7u);
+            const uint32_t y = (*e).y;
+            *e = make_uint2(o0, (y & kMaxSuperCount) | (m << 24));
+        } else {
+            reinterpret_cast<uint32_t*>(e)[0] = o0;
         }
     }
 }
@@ -820,86 +927,104 @@ void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s) {
     const uint64_t n = 2ull * b.box_capacity;   // 16-byte entries
     hipLaunchKernelGGL(k_clear_u64, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, s,
                        reinterpret_cast<unsigned long long*>(b.cellinfo), n);
-    const uint64_t nt = b.scan_tiles;
-    hipLaunchKernelGGL(k_clear_u64, dim3(uint32_t((nt + 255) / 256)), dim3(256), 0, s, b.scan_status, nt);
 }
 
 // ------------------------------------------------------------------ rank queries
-// Gap-free Morton rank (plus the simulation's box base) of the box of every
-// slot of the last grid, from the slot-ordered positions that grid was built
-// from; written per slot, or per agent id.
+// The agent in loose slot u of the last grid, if any: its storage index.
 template <class T>
-__global__ void k_box_ranks(Buffers<T> b, int ids_cur, uint32_t* __restrict__ out, int by_id) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= b.n) return;
-    const SimGrid& G = b.sims[sim_index(b, t)];
-    uint32_t rank = 0xFFFFFFFFu;
-    uint32_t q[3];
-    if (G.valid && box_of<T>(G, spos_ptr(b)[t], q))
-        rank = G.box_base + gapfree_rank(q[0], q[1], q[2], G.dims[0], G.dims[1], G.dims[2], G.levels);
-    if (!by_id) {
-        out[t] = rank;
-        return;
+__device__ __forceinline__ bool loose_agent(const Buffers<T>& b, uint32_t u, uint32_t* i) {
+    if (u < b.n) {
+        *i = u;
+        return b.g->inc && b.gkey[u] != kDeadKey;
     }
-    const uint32_t i = b.perm[t];
+    if (u - b.n >= b.g->napp) return false;
+    *i = b.perm[u - b.n];
+    return true;
+}
+
+// Gap-free Morton rank (plus the simulation's box base) of the box of every
+// agent of the last grid, from the positions that grid was built from, by id.
+template <class T>
+__global__ void k_box_ranks(Buffers<T> b, int ids_cur, uint32_t* __restrict__ out) {
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t i = 0;
+    if (u >= 2u * b.n || !loose_agent(b, u, &i)) return;
     const uint32_t id = i < b.n ? b.ids[ids_cur][i] : 0xFFFFFFFFu;
     if (id >= b.n) {
         raise_error(b.g, kErrInternal);
         return;
     }
+    const SimGrid& G = b.sims[sim_index(b, i)];
+    uint32_t rank = 0xFFFFFFFFu;
+    uint32_t q[3];
+    if (G.valid && box_of<T>(G, gpos_ptr(b)[u], q))
+        rank = G.box_base + gapfree_rank(q[0], q[1], q[2], G.dims[0], G.dims[1], G.dims[2], G.levels);
     out[id] = rank;
 }
 
 template <class T>
-void launch_box_ranks(const Buffers<T>& b, int ids_cur, uint32_t* out, bool by_id, hipStream_t s) {
-    hipLaunchKernelGGL(k_box_ranks<T>, dim3((b.n + 255) / 256), dim3(256), 0, s, b, ids_cur, out, by_id ? 1 : 0);
+void launch_box_ranks(const Buffers<T>& b, int ids_cur, uint32_t* out, hipStream_t s) {
+    const uint32_t m = 2u * b.n;
+    hipLaunchKernelGGL(k_box_ranks<T>, dim3((m + 255) / 256), dim3(256), 0, s, b, ids_cur, out);
 }
 
-// out[r] = number of slots whose rank is below first_box + r, r = 0..nbox
-// (slot ranks ascend, so a binary search per box).
-__global__ void k_cell_start(const uint32_t* __restrict__ slot_rank, uint32_t n, uint32_t first_box, uint32_t nbox,
-                             uint32_t* __restrict__ out) {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r > nbox) return;
-    const uint32_t target = first_box + r;
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (slot_rank[mid] < target)
-            lo = mid + 1;
-        else
-            hi = mid;
+// Canonical order of the last grid: out[slot] = id.  The slot of an agent is
+// its super-box's start cs[sk] plus its offset in the super-box's loose range.
+template <class T>
+__global__ void k_canonical_ids(Buffers<T> b, int ids_cur, const uint32_t* __restrict__ cs, uint32_t* __restrict__ out) {
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t i = 0;
+    if (u >= 2u * b.n || !loose_agent(b, u, &i)) return;
+    const uint32_t id = i < b.n ? b.ids[ids_cur][i] : 0xFFFFFFFFu;
+    const SimGrid& G = b.sims[sim_index(b, i < b.n ? i : 0u)];
+    uint32_t q[3];
+    if (id >= b.n || !G.valid || !box_of<T>(G, gpos_ptr(b)[u], q)) {
+        raise_error(b.g, kErrInternal);
+        return;
     }
-    out[r] = lo;
-}
-
-void launch_cell_start(const uint32_t* slot_rank, uint32_t n, uint32_t first_box, uint32_t nbox, uint32_t* out,
-                       hipStream_t s) {
-    const uint32_t m = nbox + 1;
-    hipLaunchKernelGGL(k_cell_start, dim3((m + 255) / 256), dim3(256), 0, s, slot_rank, n, first_box, nbox, out);
+    const uint32_t x = b.cellinfo[super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1)].x;
+    const uint32_t sk = b.gkey[u] >> 3;
+    const uint32_t t = sk < b.g->total_super ? cs[sk] + (u - x) : b.n;
+    if (u < x || t >= b.n) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    out[t] = id;
 }
 
 template <class T>
-void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, hipStream_t s,
+void launch_canonical_ids(const Buffers<T>& b, int ids_cur, const uint32_t* cs, uint32_t* out, hipStream_t s) {
+    const uint32_t m = 2u * b.n;
+    hipLaunchKernelGGL(k_canonical_ids<T>, dim3((m + 255) / 256), dim3(256), 0, s, b, ids_cur, cs, out);
+}
+
+// Grid of the kernels that loop over agents or changed super-boxes.
+constexpr uint32_t kLoopBlocks = 8192;
+
+template <class T>
+void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool moved_bits, hipStream_t s,
                  hipEvent_t* const* marks) {
     const uint32_t blocks = (b.n + 255) / 256;
-    const int ids_next = relayout ? ids_cur ^ 1 : -1;
+    const uint32_t loop_blocks = blocks < kLoopBlocks ? blocks : kLoopBlocks;
     auto mark = [&](int k) {
         if (marks) (void)hipEventRecord(*marks[k], s);
     };
-    hipLaunchKernelGGL(k_keys<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur);
+    hipLaunchKernelGGL(k_keys<T>, dim3((b.n + kKeysThreads - 1) / kKeysThreads), dim3(kKeysThreads), 0, s, b,
+                       pos_cur);
     mark(0);
-    uint32_t* tile_sum = reinterpret_cast<uint32_t*>(b.scan_status);
     hipLaunchKernelGGL(k_scan_reduce, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start_old,
-                       tile_sum, b.scan_tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kTileScanThreads), 0, s, b.g, tile_sum, b.cell_start,
+                       b.dirty, b.tile_sums, b.scan_tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kTileScanThreads), 0, s, b.g, b.tile_sums, b.cell_start,
                        b.scan_tiles);
     hipLaunchKernelGGL(k_scan_down, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start_old,
-                       b.cell_start, tile_sum, b.scan_tiles);
+                       b.dirty, b.cell_start, b.tile_sums, b.dirty_list, b.aoff, b.scan_tiles);
     mark(1);
-    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, ids_cur, ids_next);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(loop_blocks), dim3(256), 0, s, b, pos_cur, ids_cur);
     mark(2);
-    hipLaunchKernelGGL(k_fixup<T>, dim3(blocks), dim3(256), 0, s, b, pos_cur, ids_cur, ids_next);
+    hipLaunchKernelGGL(k_fixup<T>, dim3(loop_blocks), dim3(256), 0, s, b, pos_cur);
+    const uint32_t sb = (b.box_capacity + 255) / 256;
+    hipLaunchKernelGGL(k_clean<T>, dim3(sb < kLoopBlocks ? (sb ? sb : 1u) : kLoopBlocks), dim3(256), 0, s, b,
+                       pos_cur, moved_bits ? 1 : 0);
     mark(3);
 }
 
@@ -914,7 +1039,8 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, h
     template void launch_setup<T>(const Buffers<T>&, int, bool, hipStream_t);                            \
     template void launch_grid<T>(const Buffers<T>&, int, int, bool, hipStream_t, hipEvent_t* const*);   \
     template void launch_clear_cellinfo<T>(const Buffers<T>&, hipStream_t);                              \
-    template void launch_box_ranks<T>(const Buffers<T>&, int, uint32_t*, bool, hipStream_t);
+    template void launch_box_ranks<T>(const Buffers<T>&, int, uint32_t*, hipStream_t);                   \
+    template void launch_canonical_ids<T>(const Buffers<T>&, int, const uint32_t*, uint32_t*, hipStream_t);
 
 ABM_INSTANTIATE(float)
 ABM_INSTANTIATE(double)

@@ -289,7 +289,7 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, bool timed = false) {
     set_grid_pos<T>(c, c->pos_cur);
     launch_setup<T>(b, parity, c->inc_ready, c->stream);
     if (ev) (void)hipEventRecord((*ev)[1], c->stream);
-    launch_grid<T>(b, c->pos_cur, c->ids_cur, a.detect_static, c->stream, ev ? marks : nullptr);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, a.relayout, a.detect_static, c->stream, ev ? marks : nullptr);
     swap_cell_start<T>(c);
     a.cs = last_grid_starts<T>(c);
     launch_force<T>(b, a, c->stream);
@@ -691,7 +691,7 @@ void load_and_grid(abm_ctx* c, const T* pos_by_id) {
     guard_stamps<T>(c, 1);
     set_grid_pos<T>(c, c->pos_cur);
     launch_setup<T>(b, 0, false, c->stream);
-    launch_grid<T>(b, c->pos_cur, c->ids_cur, false, c->stream);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, false, false, c->stream);
     swap_cell_start<T>(c);
     c->grid_ids = c->ids_cur;
     c->inc_ready = false;

@@ -197,8 +197,8 @@ void launch_set_params(SimGrid* sims, int nsims, double k, double gamma, double 
 void launch_permute3(const uint32_t* ids, uint32_t n, const double* in, double* out, bool to_id, hipStream_t s);
 template <class T> void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s);
 template <class T> void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s);
-template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool moved_bits, hipStream_t s,
-                                    hipEvent_t* const* marks = nullptr);
+template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, bool moved_bits,
+                                    hipStream_t s, hipEvent_t* const* marks = nullptr);
 template <class T> void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s);
 template <class T> void launch_box_ranks(const Buffers<T>& b, int ids_cur, uint32_t* out, hipStream_t s);
 template <class T> void launch_canonical_ids(const Buffers<T>& b, int ids_cur, const uint32_t* cs, uint32_t* out,

@@ -13,11 +13,14 @@ constexpr int kMaxBlockSims = 4;
 // One thread per loose slot of the grid (Section 4.2, step G): the agents of
 // a super-box sit in consecutive slots in canonical order, so a wave works on
 // agents that are close in space and shares their neighbour boxes in cache.
-// Chunks of blockDim slots: the first nb = ceil(n / blockDim) cover the
+// Chunks of blockDim slots: nb = ceil(n / blockDim) chunks cover the
 // storage slots [0, n) (agents there only in an update build, and not in
-// slots marked dead), the next nb the append region [n, n + napp); a block
-// whose chunk holds no agent returns at once, and a launch for a full build
-// starts at the append chunks.  The agent's storage index is i = u below n,
+// slots marked dead), nb more the append region [n, n + napp).  With the
+// 2-wide walk, block k takes append chunk k and storage chunk k, those that
+// hold agents (nb blocks, two copies of the agent code); with the 4-wide walk
+// (more registers), each block takes one chunk, append chunks after storage
+// chunks, and a launch for a full build starts at the append chunks; a block
+// whose chunks hold no agent returns at once.  The agent's storage index is i = u below n,
 // else perm[u - n].  The new state goes to storage index i, or, when this
 // step re-lays agents out in Morton order, to the agent's canonical slot: its
 // super-box's start plus its offset in the super-box's loose range; the step
@@ -28,9 +31,14 @@ constexpr int kMaxBlockSims = 4;
 // positions' box extent is reduced here for the next step's grid: each wave
 // folds into the block's LDS copy, and the block's last wave to finish adds
 // it to the global accumulators, so no wave waits for the others.
+// At 96 VGPRs or fewer a SIMD holds 5 waves of this kernel (4 above); the
+// hint asks the compiler for that.
 #ifndef ABM_FORCE_WAVES_PER_EU
-#define ABM_FORCE_WAVES_PER_EU 1
+#define ABM_FORCE_WAVES_PER_EU 5
 #endif
+template <int CH>
+constexpr bool two_chunks() { return CH == 2; }
+
 template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT, int CH>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_WAVES_PER_EU))) void k_force(
     Buffers<T> b, StepArgs a, uint32_t run, uint32_t first_chunk) {
@@ -38,17 +46,29 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
     __shared__ int32_t s_box[kMaxBlockSims][6];
     __shared__ int s_sims[kMaxBlockSims];
     __shared__ uint32_t s_cnt[3];   // static, moved, waves done
-    const uint32_t n = b.n, nb = (n + blockDim.x - 1) / blockDim.x;
-    const uint32_t chunk = first_chunk + xcd_block(run);
-    const bool append = chunk >= nb;
-    const uint32_t c0 = append ? n + (chunk - nb) * blockDim.x : chunk * blockDim.x;
-    const uint32_t napp = b.g->napp;
-    if (append ? c0 - n >= napp : !b.g->inc) return;   // no agent in the chunk
+    const uint32_t n = b.n, bs = blockDim.x, nb = (n + bs - 1) / bs;
+    const uint32_t napp = min(b.g->napp, n);
+    const bool inc = b.g->inc != 0u;
+    // the block's chunks: append chunk ka and storage chunk ks, where they hold agents
+    uint32_t ka = 0, ks = 0;
+    bool has_a = false, has_s = false;
+    if constexpr (two_chunks<CH>()) {
+        ka = ks = xcd_block(run);
+        has_a = ka * bs < napp;
+        has_s = inc && ks < nb;
+    } else {
+        const uint32_t chunk = first_chunk + xcd_block(run);
+        ka = chunk - nb;
+        ks = chunk;
+        has_a = chunk >= nb && ka * bs < napp;
+        has_s = chunk < nb && inc;
+    }
+    if (!has_a && !has_s) return;   // no agent in the block's chunks
     const WalkLds L = walk_lds(s_walk);
     // the block's agents mostly belong to at most kMaxBlockSims simulations
     // from that of its chunk's first slot on (others fold straight into the
     // global accumulators); their LDS accumulators start empty
-    const int sim0 = BATCHED ? sim_index(b, min(append ? c0 - n : c0, n - 1u)) : 0;
+    const int sim0 = BATCHED ? sim_index(b, min((has_a ? ka : ks) * bs, n - 1u)) : 0;
     if (threadIdx.x < kMaxBlockSims * 6) {
         const int k = int(threadIdx.x) % 6;
         s_box[threadIdx.x / 6][k] = k < 3 ? INT32_MAX : INT32_MIN;
@@ -58,142 +78,164 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
     __syncthreads();
     const int cur = a.pos_cur, nxt = cur ^ 1;
     const bool KEEP_F = a.keep_forces;
-    const uint32_t u = c0 + threadIdx.x;
-    uint32_t key = kDeadKey, i = u;
-    bool active = false;
-    if (!append) {
-        if (u < n) {
-            key = b.skey[cur][u];
-            active = key != kDeadKey;
+    // the agents of one chunk (c0 its first slot)
+    auto chunk_agents = [&](const uint32_t c0, const bool append) {
+        const uint32_t u = c0 + threadIdx.x;
+        // key: for the canonical slot of an agent of an update build; i: the
+        // storage index (a full build's append slot n + t is canonical slot t,
+        // in the same simulation's range as its storage index)
+        uint32_t key = kDeadKey, i = u;
+        bool active = false;
+        if (!append) {
+            if (u < n) {
+                key = b.skey[cur][u];
+                active = key != kDeadKey;
+            }
+        } else if (u - n < napp) {
+            i = u - n;
+            active = true;
+            if (inc) key = b.skey[cur][u];
+            if (inc || !RELAYOUT || KEEP_F) {
+                i = b.perm[u - n];
+                active = i < n;
+                if (!active) raise_error(b.g, kErrInternal);
+            }
         }
-    } else if (u - n < napp) {
-        key = b.skey[cur][u];
-        i = b.perm[u - n];
-        active = i < n;
-        if (!active) raise_error(b.g, kErrInternal);
-    }
-    bool ok = false, is_static = false, moved = false;
-    int sim = 0;
-    int32_t cnew[3] = {0, 0, 0};
-    if (active) {
-        // one simulation: its parameters are the same for every lane
-        sim = BATCHED ? sim_index(b, i) : 0;
-        const SimGrid& G = b.sims[sim];
-        V4<T>* __restrict__ pout = pos4_ptr(b, nxt);
-        const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
-        if (!G.valid) {
-            // grid overflow (reported at sync): the agent keeps its state (a
-            // full build copied it to loose slot n + i)
-            const V4<T> p = pin[u];
-            pout[i] = p;
-            b.flags[nxt][i] = b.flags[cur][u] | kBoxChangedBit;
-            if (RELAYOUT) {
-                b.ids[a.ids_cur ^ 1][i] = b.ids[a.ids_cur][i];
-                b.skey[nxt][i] = kDeadKey;
-            }
-            if (KEEP_F)
-                for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(i) + c] = b.force[cur][3 * size_t(i) + c];
-            ok = box_coord(double(p.x), G.inv_h, &cnew[0]) && box_coord(double(p.y), G.inv_h, &cnew[1]) &&
-                 box_coord(double(p.z), G.inv_h, &cnew[2]);
-        } else {
-            V4<T> p = pin[u];   // own state, sign of d = moved
-            const uint32_t f = b.flags[cur][u];
-            uint32_t q[3];
-            if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
-            const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
-            uint32_t out = i;
-            if (RELAYOUT) {
-                const uint32_t sk = key >> 3;
-                out = sk < b.g->total_super ? a.cs[sk] + (u - P.xown) : n;
-                if (u < P.xown || out >= n) {
-                    raise_error(b.g, kErrInternal);
-                    out = i;
-                }
-                // what does not depend on the forces is written before the
-                // walk, so that i and the key need not live through it
-                b.ids[a.ids_cur ^ 1][out] = b.ids[a.ids_cur][i];
-                b.skey[nxt][out] = key;
-            }
-            // Static test (Section 5): the agent did not move, had at most one
-            // non-zero pair term, and no agent within R moved.  At step 0
-            // every agent carries the moved bit, so none is static.  With no
-            // moved agent in the 27 boxes it holds at once; otherwise the
-            // force walk itself reports a moved agent within R.
-            const bool cand = STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u;
-            if (KEEP_F && cand)   // a static agent keeps its force (replaced below if it is not static)
-                for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
-            is_static = cand && !P.moved;
-            p.w = T(fabs(double(p.w)));
-            V4<T> np = p;
-            uint32_t nf = 0;
-            ForceSum acc;
-            if (!is_static) {
-                force_of<CH, T, false>(b, G, p, P, L, acc);
-                is_static = cand && !acc.moved_near;
-            }
-            if (is_static) {
-                nf = kStaticBit | (f & ~(kMovedBit | kStaticBit | kBoxChangedBit));
+        bool ok = false, is_static = false, moved = false;
+        int sim = 0;
+        int32_t cnew[3] = {0, 0, 0};
+        if (active) {
+            // one simulation: its parameters are the same for every lane
+            sim = BATCHED ? sim_index(b, i) : 0;
+            const SimGrid& G = b.sims[sim];
+            V4<T>* __restrict__ pout = pos4_ptr(b, nxt);
+            const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
+            if (!G.valid) {
+                // grid overflow (reported at sync): the agent keeps its state (a
+                // full build copied it to loose slot n + i, and its id and key
+                // to the next state)
+                const V4<T> p = pin[u];
+                pout[i] = p;
+                b.flags[nxt][i] = b.flags[cur][u] | kBoxChangedBit;
+                if (KEEP_F)
+                    for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(i) + c] = b.force[cur][3 * size_t(i) + c];
+                ok = box_coord(double(p.x), G.inv_h, &cnew[0]) && box_coord(double(p.y), G.inv_h, &cnew[1]) &&
+                     box_coord(double(p.z), G.inv_h, &cnew[2]);
             } else {
-                const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
-                np.x = T(double(p.x) + m.ux);
-                np.y = T(double(p.y) + m.uy);
-                np.z = T(double(p.z) + m.uz);
-                moved = m.ux != 0.0 || m.uy != 0.0 || m.uz != 0.0;
-                const uint32_t nz = acc.nnz < 0xFFFFFFu ? acc.nnz : 0xFFFFFFu;
-                nf = (moved ? kMovedBit : 0u) | (nz << kNnzShift);
-                if (moved) np.w = -np.w;
-                if (KEEP_F) {
-                    b.force[nxt][3 * size_t(out)] = acc.fx;
-                    b.force[nxt][3 * size_t(out) + 1] = acc.fy;
-                    b.force[nxt][3 * size_t(out) + 2] = acc.fz;
+                V4<T> p = pin[u];   // own state, sign of d = moved
+                const uint32_t f = b.flags[cur][u];
+                uint32_t q[3];
+                if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
+                const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
+                uint32_t out = i;
+                if (RELAYOUT && !inc) {
+                    out = u - n;
+                } else if (RELAYOUT) {
+                    const uint32_t sk = key >> 3;
+                    out = sk < b.g->total_super ? a.cs[sk] + (u - P.xown) : n;
+                    if (u < P.xown || out >= n) {
+                        raise_error(b.g, kErrInternal);
+                        out = i;
+                    }
+                    // an agent kept in place carries its id and key to the next
+                    // state (the grid build wrote those of the append region);
+                    // written before the walk, so that they need not live
+                    // through it
+                    if (!append) {
+                        b.ids[a.ids_cur ^ 1][out] = b.ids[a.ids_cur][i];
+                        b.skey[nxt][out] = key;
+                    }
+                }
+                // Static test (Section 5): the agent did not move, had at most one
+                // non-zero pair term, and no agent within R moved.  At step 0
+                // every agent carries the moved bit, so none is static.  With no
+                // moved agent in the 27 boxes it holds at once; otherwise the
+                // force walk itself reports a moved agent within R.
+                const bool cand = STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u;
+                if (KEEP_F && cand)   // a static agent keeps its force (replaced below if it is not static)
+                    for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
+                is_static = cand && !P.moved;
+                p.w = T(fabs(double(p.w)));
+                V4<T> np = p;
+                uint32_t nf = 0;
+                ForceSum acc;
+                if (!is_static) {
+                    force_of<CH, T, false>(b, G, p, P, L, acc);
+                    is_static = cand && !acc.moved_near;
+                }
+                if (is_static) {
+                    nf = kStaticBit | (f & ~(kMovedBit | kStaticBit | kBoxChangedBit));
+                } else {
+                    const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
+                    np.x = T(double(p.x) + m.ux);
+                    np.y = T(double(p.y) + m.uy);
+                    np.z = T(double(p.z) + m.uz);
+                    moved = m.ux != 0.0 || m.uy != 0.0 || m.uz != 0.0;
+                    const uint32_t nz = acc.nnz < 0xFFFFFFu ? acc.nnz : 0xFFFFFFu;
+                    nf = (moved ? kMovedBit : 0u) | (nz << kNnzShift);
+                    if (moved) np.w = -np.w;
+                    if (KEEP_F) {
+                        b.force[nxt][3 * size_t(out)] = acc.fx;
+                        b.force[nxt][3 * size_t(out) + 1] = acc.fy;
+                        b.force[nxt][3 * size_t(out) + 2] = acc.fz;
+                    }
+                }
+                pout[out] = np;
+                ok = box_coord(double(np.x), G.inv_h, &cnew[0]) && box_coord(double(np.y), G.inv_h, &cnew[1]) &&
+                     box_coord(double(np.z), G.inv_h, &cnew[2]);
+                // left the box it was ranked in (the next grid build re-ranks it);
+                // that box is recomputed from p, so q need not live through the walk
+                int32_t cold[3];
+                bool left = !ok || !(box_coord(double(p.x), G.inv_h, &cold[0]) && box_coord(double(p.y), G.inv_h, &cold[1]) &&
+                                     box_coord(double(p.z), G.inv_h, &cold[2]));
+                for (int c = 0; c < 3; ++c) left = left || cnew[c] != cold[c];
+                b.flags[nxt][out] = nf | (left ? kBoxChangedBit : 0u);
+            }
+            if (!ok) raise_error(b.g, kErrNonfinite);
+        }
+        // ---- box extent and statistics: wave, then block (LDS atomics)
+        const bool contrib = active && ok;
+        const unsigned long long any = __ballot(contrib);
+        const uint32_t ns = uint32_t(__popcll(__ballot(active && is_static)));
+        const uint32_t nm = uint32_t(__popcll(__ballot(active && moved)));
+        const int lead = any ? __ffsll((long long)any) - 1 : 0;
+        const int wsim = __shfl(sim, lead, 64);
+        const bool uniform = __ballot(contrib && sim != wsim) == 0;
+        if (uniform) {
+            int32_t lo[3], hi[3];
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = wave_min(contrib ? cnew[c] : INT32_MAX);
+                hi[c] = wave_max(contrib ? cnew[c] : INT32_MIN);
+            }
+            const int slot = wsim - sim0;
+            if (lane_id() == 0 && any) {
+                if (slot >= 0 && slot < kMaxBlockSims) {
+                    s_sims[slot] = wsim;
+                    for (int c = 0; c < 3; ++c) {
+                        atomicMin(&s_box[slot][c], lo[c]);
+                        atomicMax(&s_box[slot][3 + c], hi[c]);
+                    }
+                } else {
+                    bbox_atomic(bbox_replica(b, a.parity ^ 1, wsim), lo, hi);
                 }
             }
-            pout[out] = np;
-            ok = box_coord(double(np.x), G.inv_h, &cnew[0]) && box_coord(double(np.y), G.inv_h, &cnew[1]) &&
-                 box_coord(double(np.z), G.inv_h, &cnew[2]);
-            // left the box it was ranked in (the next grid build re-ranks it);
-            // that box is recomputed from p, so q need not live through the walk
-            int32_t cold[3];
-            bool left = !ok || !(box_coord(double(p.x), G.inv_h, &cold[0]) && box_coord(double(p.y), G.inv_h, &cold[1]) &&
-                                 box_coord(double(p.z), G.inv_h, &cold[2]));
-            for (int c = 0; c < 3; ++c) left = left || cnew[c] != cold[c];
-            b.flags[nxt][out] = nf | (left ? kBoxChangedBit : 0u);
+        } else if (contrib) {
+            // several simulations in one wave (batched, small simulations)
+            bbox_atomic(bbox_replica(b, a.parity ^ 1, sim), cnew, cnew);
         }
-        if (!ok) raise_error(b.g, kErrNonfinite);
-    }
-    // ---- box extent and statistics: wave, then block (LDS atomics)
-    const bool contrib = active && ok;
-    const unsigned long long any = __ballot(contrib);
-    const uint32_t ns = uint32_t(__popcll(__ballot(active && is_static)));
-    const uint32_t nm = uint32_t(__popcll(__ballot(active && moved)));
-    const int lead = any ? __ffsll((long long)any) - 1 : 0;
-    const int wsim = __shfl(sim, lead, 64);
-    const bool uniform = __ballot(contrib && sim != wsim) == 0;
-    if (uniform) {
-        int32_t lo[3], hi[3];
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = wave_min(contrib ? cnew[c] : INT32_MAX);
-            hi[c] = wave_max(contrib ? cnew[c] : INT32_MIN);
+        if (lane_id() == 0) {
+            if (ns) atomicAdd(&s_cnt[0], ns);
+            if (nm) atomicAdd(&s_cnt[1], nm);
         }
-        const int slot = wsim - sim0;
-        if (lane_id() == 0 && any) {
-            if (slot >= 0 && slot < kMaxBlockSims) {
-                s_sims[slot] = wsim;
-                for (int c = 0; c < 3; ++c) {
-                    atomicMin(&s_box[slot][c], lo[c]);
-                    atomicMax(&s_box[slot][3 + c], hi[c]);
-                }
-            } else {
-                bbox_atomic(bbox_replica(b, a.parity ^ 1, wsim), lo, hi);
-            }
+    };
+    if constexpr (two_chunks<CH>()) {
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 0 && has_a) chunk_agents(n + ka * bs, true);
+            if (pass == 1 && has_s) chunk_agents(ks * bs, false);
         }
-    } else if (contrib) {
-        // several simulations in one wave (batched, small simulations)
-        bbox_atomic(bbox_replica(b, a.parity ^ 1, sim), cnew, cnew);
-    }
-    if (lane_id() == 0) {
-        if (ns) atomicAdd(&s_cnt[0], ns);
-        if (nm) atomicAdd(&s_cnt[1], nm);
+    } else {
+        chunk_agents(has_a ? n + ka * bs : ks * bs, has_a);
     }
     // ---- the last wave of the block to finish adds the block's result to the replicas
     if (lane_id() == 0) {
@@ -223,9 +265,10 @@ template <class T, bool S, bool K, bool R, int CH>
 static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
     const int bs = a.block_size;
     const uint32_t nb = (b.n + bs - 1) / bs;
-    // storage chunks hold agents only in an update build
-    const uint32_t first = a.full_only ? nb : 0u;
-    const uint32_t blocks = 2u * nb - first;
+    // two chunks per block; or one, and storage chunks hold agents only in
+    // an update build
+    const uint32_t first = two_chunks<CH>() || !a.full_only ? 0u : nb;
+    const uint32_t blocks = two_chunks<CH>() ? nb : 2u * nb - first;
     const uint32_t run = xcd_run(blocks);
     hipLaunchKernelGGL((k_force<T, S, K, R, CH>), dim3(xcd_grid(blocks, run)), dim3(bs), walk_lds_bytes(bs), s, b, a,
                        run, first);
@@ -272,7 +315,7 @@ __global__ __launch_bounds__(256) void k_neighbors(Buffers<T> b, int ids_cur, ui
     const WalkLds L = walk_lds(s_walk);
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2u * b.n) return;
-    const bool live = t < b.n ? (b.g->inc && b.gkey[t] != kDeadKey) : t - b.n < b.g->napp;
+    const bool live = t < b.n ? (b.g->inc && b.gkey[t] != kDeadKey) : t - b.n < min(b.g->napp, b.n);
     if (!live) return;
     const uint32_t* ids = b.ids[ids_cur];
     const uint32_t i = loose_storage(b, t);

@@ -7,12 +7,14 @@
 //   keys     super-box key and octant of every agent + histogram (atomics);
 //            an update build: only the agents that left their box
 //   scan     exclusive scan of the super-box counts (tile sums, their scan,
-//            rescan)
+//            rescan); an update build also lists the changed super-boxes
+//            and refreshes the table entries of the others
 //   scatter  records of the agents of the (re)built super-boxes, in arrival
 //            order inside a super-box
 //   fixup    canonical (box, id) order inside each (re)built super-box, its
 //            agents written to loose slots + the row-major super-box table
-//   clean    update build: table entries of the super-boxes kept in place
+//   clean    update build with the static test: moved octants of the
+//            super-boxes kept in place
 #include "force_loop.h"
 
 namespace abm {
@@ -433,58 +435,70 @@ __device__ __forceinline__ uint32_t wave_run_add(uint32_t* arr, bool act, uint32
 // its canonical order): only agents that left their box get a new key; each
 // moves one count from its old to its new super-box, marks both as changed
 // (the epoch of this build) and is listed as a mover in its block's segment.
+// A block covers kKeysPer runs of kKeysThreads consecutive agents; in an
+// update build a thread requests the flags of its kKeysPer agents together.
 constexpr int kKeysThreads = 256;
+constexpr int kKeysPer = 4;
+constexpr uint32_t kKeysSpan = kKeysThreads * kKeysPer;
 template <class T>
 __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur) {
     __shared__ uint32_t s_movers;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool inc = b.g->inc != 0u;
-    bool act = false, mv = false;
-    uint32_t key = 0;
-    if (inc && threadIdx.x == 0) s_movers = 0u;
-    if (i < b.n) {
-        const SimGrid& G = b.sims[sim_index(b, i)];
-        if (G.valid && !inc) {
-            if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
-                act = true;
-            } else {   // the extent is computed from these very positions
-                raise_error(b.g, kErrInternal);
-                key = 0xFFFFFFFFu;
-            }
-            b.key[i] = key;
-        } else if (G.valid && (b.flags[cur][i] & kBoxChangedBit)) {
-            const uint32_t old = b.skey[cur][i];
-            if ((old >> 3) >= b.g->total_super) {
-                raise_error(b.g, kErrInternal);
-            } else if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
-                b.key[i] = key;   // read by the scatter for every agent that left its box
-                if (key != old) {
-                    mv = true;
-                    const uint32_t ep = b.g->epoch;
-                    atomicAdd(&b.count[old >> 3], 0xFFFFFFFFu);
-                    atomicAdd(&b.count[key >> 3], 1u);
-                    b.dirty[old >> 3] = ep;
-                    b.dirty[key >> 3] = ep;
+    const uint32_t i0 = blockIdx.x * kKeysSpan + threadIdx.x;
+    if (!b.g->inc) {
+#pragma unroll
+        for (int k = 0; k < kKeysPer; ++k) {
+            const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
+            bool act = false;
+            uint32_t key = 0;
+            if (i < b.n) {
+                const SimGrid& G = b.sims[sim_index(b, i)];
+                if (G.valid) {
+                    if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
+                        act = true;
+                    } else {   // the extent is computed from these very positions
+                        raise_error(b.g, kErrInternal);
+                        key = 0xFFFFFFFFu;
+                    }
+                    b.key[i] = key;
                 }
-            } else {
-                raise_error(b.g, kErrInternal);
-                b.key[i] = old;
             }
+            const uint32_t sub = wave_run_add(b.count, act, key >> 3);
+            if (act) b.sub[i] = sub;
         }
-    }
-    if (!inc) {
-        const uint32_t sub = wave_run_add(b.count, act, key >> 3);
-        if (act) b.sub[i] = sub;
         return;
     }
-    // the block's movers, at its own segment of the list (LDS atomics only)
+    uint32_t f[kKeysPer];
+#pragma unroll
+    for (int k = 0; k < kKeysPer; ++k) {
+        const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
+        f[k] = i < b.n ? b.flags[cur][i] : 0u;
+    }
+    if (threadIdx.x == 0) s_movers = 0u;
     __syncthreads();
-    const unsigned long long m = __ballot(mv);
-    const int lane = lane_id();
-    uint32_t base = 0;
-    if (m && lane == 0) base = atomicAdd(&s_movers, uint32_t(__popcll(m)));
-    base = __shfl(base, 0, 64);
-    if (mv) b.movers[blockIdx.x * kKeysThreads + base + uint32_t(__popcll(m & ((1ull << lane) - 1ull)))] = i;
+    for (int k = 0; k < kKeysPer; ++k) {
+        if (!(f[k] & kBoxChangedBit)) continue;
+        const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
+        const SimGrid& G = b.sims[sim_index(b, i)];
+        if (!G.valid) continue;
+        const uint32_t old = b.skey[cur][i];
+        uint32_t key = 0;
+        if ((old >> 3) >= b.g->total_super) {
+            raise_error(b.g, kErrInternal);
+        } else if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
+            b.key[i] = key;   // read by the scatter for every agent that left its box
+            if (key != old) {
+                const uint32_t ep = b.g->epoch;
+                atomicAdd(&b.count[old >> 3], 0xFFFFFFFFu);
+                atomicAdd(&b.count[key >> 3], 1u);
+                b.dirty[old >> 3] = ep;
+                b.dirty[key >> 3] = ep;
+                b.movers[blockIdx.x * kKeysSpan + atomicAdd(&s_movers, 1u)] = i;   // LDS atomic
+            }
+        } else {
+            raise_error(b.g, kErrInternal);
+            b.key[i] = old;
+        }
+    }
     __syncthreads();
     if (threadIdx.x == 0) b.mcount[blockIdx.x] = s_movers;
 }
@@ -510,40 +524,76 @@ __device__ __forceinline__ uint32_t wave_inclusive(uint32_t x) {
 // the append region.
 __device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
 
-// Load tile `tile` of the counts into LDS (striped), return this thread's
-// blocked 16 values.  In an update build the counts are the last grid's
-// (differences of its starts) plus the changes in `count`, and bit k of *dm
-// says that value k's super-box changed.
-__device__ __forceinline__ void load_tile(const uint32_t* __restrict__ count, const uint32_t* __restrict__ cs_old,
-                                          const uint32_t* __restrict__ dirty, uint32_t ep, bool inc, uint32_t base,
+// Load tile `tile` of the counts into LDS (striped: thread x takes 4
+// consecutive super-boxes per round, with 16-byte loads), return this
+// thread's blocked 16 values.  In an update build the counts are the last
+// grid's (differences of its starts) plus the changes in `count`, and bit k of
+// *dm says that value k's super-box changed; with `refresh` the table entry
+// of every other non-empty super-box gets its new first loose slot, its start
+// in the storage order (the last grid's start).
+struct ScanIn {
+    const uint32_t* count;
+    const uint32_t* cs_old;
+    const uint32_t* dirty;
+    const uint32_t* tabidx;
+    uint4* cellinfo;
+};
+constexpr uint32_t kDirtyFlag = 0x80000000u;   // counts stay below 2^31
+__device__ __forceinline__ void load_tile(const ScanIn& in, uint32_t ep, bool inc, bool refresh, uint32_t base,
                                           uint32_t total, uint32_t* s_data, uint32_t v[kScanItems], uint32_t* dm) {
     for (int k = 0; k < kScanItems / 4; ++k) {
         const uint32_t e4 = uint32_t(k) * kScanThreads + threadIdx.x;
         const uint32_t g0 = base + 4 * e4;
-        uint32_t c4[4];
-        if (g0 + 4 <= total) {
-            const uint4 u = reinterpret_cast<const uint4*>(count)[g0 >> 2];
+        uint32_t c4[4] = {0u, 0u, 0u, 0u};
+        const bool whole = g0 + 4 <= total;
+        if (whole) {
+            const uint4 u = reinterpret_cast<const uint4*>(in.count)[g0 >> 2];
             c4[0] = u.x; c4[1] = u.y; c4[2] = u.z; c4[3] = u.w;
         } else {
-            for (int c = 0; c < 4; ++c) c4[c] = g0 + c < total ? count[g0 + c] : 0u;
+            for (int c = 0; c < 4; ++c) c4[c] = g0 + c < total ? in.count[g0 + c] : 0u;
+        }
+        if (inc && g0 < total) {
+            uint32_t o[5], d[4], ti[4];
+            if (whole) {
+                const uint4 uo = reinterpret_cast<const uint4*>(in.cs_old)[g0 >> 2];
+                const uint4 ud = reinterpret_cast<const uint4*>(in.dirty)[g0 >> 2];
+                o[0] = uo.x; o[1] = uo.y; o[2] = uo.z; o[3] = uo.w;
+                d[0] = ud.x; d[1] = ud.y; d[2] = ud.z; d[3] = ud.w;
+                o[4] = in.cs_old[g0 + 4];
+                if (refresh) {
+                    const uint4 ut = reinterpret_cast<const uint4*>(in.tabidx)[g0 >> 2];
+                    ti[0] = ut.x; ti[1] = ut.y; ti[2] = ut.z; ti[3] = ut.w;
+                }
+            } else {
+                for (int c = 0; c < 4; ++c) {
+                    const bool ok = g0 + c < total;
+                    o[c] = ok ? in.cs_old[g0 + c] : 0u;
+                    d[c] = ok ? in.dirty[g0 + c] : 0u;
+                    ti[c] = ok && refresh ? in.tabidx[g0 + c] : 0u;
+                }
+                o[4] = 0u;
+                for (int c = 0; c < 4; ++c)
+                    if (g0 + c < total) o[c + 1] = in.cs_old[g0 + c + 1];
+            }
+            for (int c = 0; c < 4; ++c) {
+                if (g0 + c >= total) break;
+                const bool changed = d[c] == ep;
+                c4[c] += o[c + 1] - o[c];
+                if (changed) c4[c] |= kDirtyFlag;
+                if (refresh && !changed && o[c + 1] != o[c]) {
+                    if (ti[c] < total)
+                        reinterpret_cast<uint32_t*>(&in.cellinfo[ti[c]])[0] = o[c];
+                }
+            }
         }
         for (int c = 0; c < 4; ++c) s_data[lds_pad(4 * e4 + c)] = c4[c];
     }
     __syncthreads();
-    for (int k = 0; k < kScanItems; ++k) v[k] = s_data[lds_pad(threadIdx.x * kScanItems + k)];
     *dm = 0u;
-    if (inc) {
-        const uint32_t g0 = base + threadIdx.x * kScanItems;
-        if (g0 < total) {
-            uint32_t prev = cs_old[g0];
-            for (int k = 0; k < kScanItems; ++k) {
-                if (g0 + k >= total) break;
-                const uint32_t nxt = cs_old[g0 + k + 1];
-                v[k] += nxt - prev;
-                prev = nxt;
-                *dm |= (dirty[g0 + k] == ep ? 1u : 0u) << k;
-            }
-        }
+    for (int k = 0; k < kScanItems; ++k) {
+        const uint32_t x = s_data[lds_pad(threadIdx.x * kScanItems + k)];
+        v[k] = x & ~kDirtyFlag;
+        *dm |= (x >> 31) << k;
     }
 }
 
@@ -558,10 +608,8 @@ __device__ __forceinline__ void thread_sums(const uint32_t v[kScanItems], uint32
     x[1] = uint32_t(__popc(dm));
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Globals* g, const uint32_t* __restrict__ count,
-                                                               const uint32_t* __restrict__ cs_old,
-                                                               const uint32_t* __restrict__ dirty,
-                                                               uint32_t* __restrict__ sums, uint32_t ntiles) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Globals* g, ScanIn in, uint32_t* __restrict__ sums,
+                                                               uint32_t ntiles) {
     __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
     __shared__ uint32_t s_wave[3][kScanThreads / 64];
     const uint32_t total = g->total_super;
@@ -569,7 +617,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Globals* g, 
     if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
     const bool inc = g->inc != 0u;
     uint32_t v[kScanItems], dm;
-    load_tile(count, cs_old, dirty, g->epoch, inc, tile * kScanTile, total, s_data, v, &dm);
+    load_tile(in, g->epoch, inc, true, tile * kScanTile, total, s_data, v, &dm);
     uint32_t x[3];
     thread_sums(v, dm, x);
     for (int c = 0; c < 3; ++c) {
@@ -627,9 +675,7 @@ __global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uin
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, uint32_t* __restrict__ count,
-                                                             const uint32_t* __restrict__ cs_old,
-                                                             const uint32_t* __restrict__ dirty,
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, ScanIn in, uint32_t* __restrict__ count,
                                                              uint32_t* __restrict__ cell_start,
                                                              const uint32_t* __restrict__ sums,
                                                              uint32_t* __restrict__ dirty_list,
@@ -642,7 +688,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, ui
     const bool inc = g->inc != 0u;
     const uint32_t base = tile * kScanTile;
     uint32_t v[kScanItems], dm;
-    load_tile(count, cs_old, dirty, g->epoch, inc, base, total, s_data, v, &dm);
+    load_tile(in, g->epoch, inc, false, base, total, s_data, v, &dm);
     uint32_t x[3], run[3];
     thread_sums(v, dm, x);
     const int wave = int(threadIdx.x >> 6);
@@ -687,6 +733,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, ui
 }
 
 // ------------------------------------------------------------------ scatter / fixup
+// [st, en) is a slot range inside [0, n) (checked without wrap-around, so a
+// corrupted start array cannot lead to accesses out of bounds).
+__device__ __forceinline__ bool slot_range(uint32_t st, uint32_t en, uint32_t n) { return st <= en && en <= n; }
+
 // The scatter writes, per agent of a (re)built super-box, a record {storage
 // index, agent id, first canonical slot of the super-box, agent count << 4 |
 // octant << 1 | moved} at a canonical slot of that super-box, so that the
@@ -709,12 +759,12 @@ __global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
                 raise_error(b.g, kErrInternal);
                 continue;
             }
-            const uint32_t st = cs[sk], en = cs[sk + 1];
-            const uint32_t slot = st + b.sub[i];
-            if (slot >= en || en > b.n) {
+            const uint32_t st = cs[sk], en = cs[sk + 1], sub = b.sub[i];
+            if (!slot_range(st, en, b.n) || sub >= en - st) {
                 raise_error(b.g, kErrInternal);
                 continue;
             }
+            const uint32_t slot = st + sub;
             b.rec[slot] = make_uint4(i, b.ids[ids_cur][i], st,
                                      ((en - st) << 4) | ((key & 7u) << 1) | (b.flags[cur][i] & kMovedBit));
         }
@@ -727,11 +777,12 @@ __global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
     for (uint32_t d = tid / kFixupLanes; d < nd; d += groups) {
         const uint32_t sk = b.dirty_list[d];
         const uint32_t o0 = b.cell_start_old[sk], o1 = b.cell_start_old[sk + 1];
-        const uint32_t st = cs[sk], cnt = cs[sk + 1] - st;
-        if (o1 > b.n || st + cnt > b.n) {
+        const uint32_t st = cs[sk], en = cs[sk + 1];
+        if (!slot_range(o0, o1, b.n) || !slot_range(st, en, b.n)) {
             raise_error(b.g, kErrInternal);
             continue;
         }
+        const uint32_t cnt = en - st;
         for (uint32_t u = o0 + x0; u < o1; u += kFixupLanes) {
             const uint32_t kold = b.skey[cur][u], fl = b.flags[cur][u];
             if (!(fl & kBoxChangedBit) || b.key[u] == kold) {
@@ -746,11 +797,11 @@ __global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
         }
     }
     // ... and the movers, from the segments of the keys kernel's blocks
-    const uint32_t kblocks = (b.n + kKeysThreads - 1) / kKeysThreads;
+    const uint32_t kblocks = (b.n + kKeysSpan - 1) / kKeysSpan;
     for (uint32_t kb = blockIdx.x; kb < kblocks; kb += gridDim.x) {
         const uint32_t mc = b.mcount[kb];
         for (uint32_t m = threadIdx.x; m < mc; m += blockDim.x) {
-            const uint32_t i = b.movers[kb * kKeysThreads + m];
+            const uint32_t i = b.movers[kb * kKeysSpan + m];
             if (i >= b.n) {
                 raise_error(b.g, kErrInternal);
                 continue;
@@ -760,9 +811,13 @@ __global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
                 raise_error(b.g, kErrInternal);
                 continue;
             }
-            const uint32_t st = cs[sk], cnt = cs[sk + 1] - st;
+            const uint32_t st = cs[sk], en = cs[sk + 1], cnt = en - st;
+            if (!slot_range(st, en, b.n)) {
+                raise_error(b.g, kErrInternal);
+                continue;
+            }
             const uint32_t r = atomicAdd(&b.count[sk], 1u);
-            if (r >= cnt || st + cnt > b.n) {
+            if (r >= cnt) {
                 raise_error(b.g, kErrInternal);
                 continue;
             }
@@ -774,14 +829,15 @@ __global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
 
 // Rank of the agent of record slot t inside its super-box sk (records [st,
 // st + cnt)) by (octant, id); the agent goes to loose slot x + rank, x the
-// super-box's first loose slot.  The first agent in that order writes the
-// super-box's table entry.
+// super-box's first loose slot.  When the step re-lays agents out (ids_next
+// >= 0), its id and key also go to its canonical slot st + rank of the next
+// state.  The first agent in that order writes the super-box's table entry.
 template <class T>
-__device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G, int cur, uint32_t t, uint32_t sk,
-                                           uint32_t x) {
+__device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G, int cur, int ids_next, uint32_t t,
+                                           uint32_t sk, uint32_t x) {
     const uint4 me = b.rec[t];
     const uint32_t i = me.x, st = me.z, cnt = me.w >> 4;
-    if (i >= b.n || st + cnt > b.n || t < st || t >= st + cnt || x < b.n || x - b.n + cnt > b.n) {
+    if (i >= b.n || st > b.n || cnt > b.n - st || t < st || t - st >= cnt || x < b.n || x - b.n > b.n - cnt) {
         raise_error(b.g, kErrInternal);
         return;
     }
@@ -808,12 +864,17 @@ __device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G
         }
     }
     const uint32_t u = x + r;
+    const uint32_t key = (sk << 3) | ((me.w >> 1) & 7u);
     p.w = T(fabs(double(p.w)));
     if (fl & kMovedBit) p.w = -p.w;   // the walk reads the moved flag from the sign of d
     pos4_ptr(b, cur)[u] = p;
     b.flags[cur][u] = fl;
-    b.skey[cur][u] = (sk << 3) | ((me.w >> 1) & 7u);
+    b.skey[cur][u] = key;
     b.perm[u - b.n] = i;
+    if (ids_next >= 0) {
+        b.ids[ids_next][st + r] = me.y;
+        b.skey[cur ^ 1][st + r] = key;
+    }
     if (r == 0) {
         uint32_t q[3];
         if (!box_of<T>(G, p, q)) {
@@ -829,10 +890,10 @@ __device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G
 
 // Full build: every canonical slot t, its agent to loose slot n + t (agents
 // of a simulation whose grid overflowed keep their storage slot, state
-// unchanged).  Update build: the changed super-boxes (the list made by
-// k_keys), kFixupLanes threads each, at append slots handed out per wave.
+// unchanged).  Update build: the changed super-boxes (the list made by the
+// scan), kFixupLanes threads each, at their append slots.
 template <class T>
-__global__ void k_fixup(Buffers<T> b, int cur) {
+__global__ void k_fixup(Buffers<T> b, int cur, int ids_next) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     const uint32_t* __restrict__ cs = b.cell_start;
     if (!b.g->inc) {
@@ -845,12 +906,20 @@ __global__ void k_fixup(Buffers<T> b, int cur) {
                     continue;
                 }
                 const uint32_t sk = b.key[i] >> 3;
-                fixup_slot<T>(b, G, cur, t, sk, b.n + cs[sk]);
+                if (sk >= b.g->total_super) {
+                    raise_error(b.g, kErrInternal);
+                    continue;
+                }
+                fixup_slot<T>(b, G, cur, ids_next, t, sk, b.n + cs[sk]);
             } else {
                 pos4_ptr(b, cur)[b.n + t] = pos4_ptr(b, cur)[t];
                 b.flags[cur][b.n + t] = b.flags[cur][t];
                 b.skey[cur][b.n + t] = kDeadKey;
                 b.perm[t] = t;
+                if (ids_next >= 0) {
+                    b.ids[ids_next][t] = b.ids[ids_next ^ 1][t];
+                    b.skey[cur ^ 1][t] = kDeadKey;
+                }
             }
         }
         return;
@@ -861,9 +930,9 @@ __global__ void k_fixup(Buffers<T> b, int cur) {
     const uint32_t groups = stride / kFixupLanes, x0 = tid % kFixupLanes;
     for (uint32_t d = tid / kFixupLanes; d < nd; d += groups) {
         const uint32_t sk = b.dirty_list[d];
-        const uint32_t st = cs[sk], cnt = cs[sk + 1] - st;
+        const uint32_t st = cs[sk], en = cs[sk + 1], cnt = en - st;
         const uint32_t a0 = b.aoff[sk];
-        if (st + cnt > b.n || a0 + cnt > b.n) {
+        if (!slot_range(st, en, b.n) || a0 > b.n - cnt) {
             raise_error(b.g, kErrInternal);
             continue;
         }
@@ -880,16 +949,16 @@ __global__ void k_fixup(Buffers<T> b, int cur) {
         }
         for (uint32_t t = st + x0; t < st + cnt; t += kFixupLanes) {
             const SimGrid& G = b.sims[sim_index(b, t)];
-            fixup_slot<T>(b, G, cur, t, sk, b.n + a0);
+            fixup_slot<T>(b, G, cur, ids_next, t, sk, b.n + a0);
         }
     }
 }
 
-// Update build: the table entries of the super-boxes kept in place get their
-// storage range as first loose slot and, with moved_bits, the octants whose
-// agents moved in the last step (from the agents' flags and keys).
+// Update build with the static test: the table entries of the super-boxes
+// kept in place get the octants whose agents moved in the last step (from the
+// agents' flags and keys); the scan already gave them their first loose slot.
 template <class T>
-__global__ void k_clean(Buffers<T> b, int cur, int moved_bits) {
+__global__ void k_clean(Buffers<T> b, int cur) {
     if (!b.g->inc) return;
     const uint32_t total = b.g->total_super, ep = b.g->epoch;
     const uint32_t* __restrict__ fl = b.flags[cur];
@@ -898,19 +967,14 @@ __global__ void k_clean(Buffers<T> b, int cur, int moved_bits) {
         const uint32_t o0 = b.cell_start_old[sk], o1 = b.cell_start_old[sk + 1];
         if (o1 == o0 || b.dirty[sk] == ep) continue;
         const uint32_t idx = b.tabidx[sk];
-        if (o1 > b.n || idx >= total) {
+        if (!slot_range(o0, o1, b.n) || idx >= total) {
             raise_error(b.g, kErrInternal);
             continue;
         }
-        uint2* e = reinterpret_cast<uint2*>(&b.cellinfo[idx]);
-        if (moved_bits) {
-            uint32_t m = 0;
-            for (uint32_t u = o0; u < o1; ++u) m |= (fl[u] & kMovedBit) << (kk[u] & 7u);
-            const uint32_t y = (*e).y;
-            *e = make_uint2(o0, (y & kMaxSuperCount) | (m << 24));
-        } else {
-            reinterpret_cast<uint32_t*>(e)[0] = o0;
-        }
+        uint32_t m = 0;
+        for (uint32_t u = o0; u < o1; ++u) m |= (fl[u] & kMovedBit) << (kk[u] & 7u);
+        uint32_t* e = reinterpret_cast<uint32_t*>(&b.cellinfo[idx]);
+        e[1] = (e[1] & kMaxSuperCount) | (m << 24);
     }
 }
 
@@ -937,7 +1001,7 @@ __device__ __forceinline__ bool loose_agent(const Buffers<T>& b, uint32_t u, uin
         *i = u;
         return b.g->inc && b.gkey[u] != kDeadKey;
     }
-    if (u - b.n >= b.g->napp) return false;
+    if (u - b.n >= min(b.g->napp, b.n)) return false;
     *i = b.perm[u - b.n];
     return true;
 }
@@ -1002,29 +1066,32 @@ void launch_canonical_ids(const Buffers<T>& b, int ids_cur, const uint32_t* cs, 
 constexpr uint32_t kLoopBlocks = 8192;
 
 template <class T>
-void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool moved_bits, hipStream_t s,
+void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, bool moved_bits, hipStream_t s,
                  hipEvent_t* const* marks) {
     const uint32_t blocks = (b.n + 255) / 256;
     const uint32_t loop_blocks = blocks < kLoopBlocks ? blocks : kLoopBlocks;
     auto mark = [&](int k) {
         if (marks) (void)hipEventRecord(*marks[k], s);
     };
-    hipLaunchKernelGGL(k_keys<T>, dim3((b.n + kKeysThreads - 1) / kKeysThreads), dim3(kKeysThreads), 0, s, b,
+    hipLaunchKernelGGL(k_keys<T>, dim3((b.n + kKeysSpan - 1) / kKeysSpan), dim3(kKeysThreads), 0, s, b,
                        pos_cur);
     mark(0);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start_old,
-                       b.dirty, b.tile_sums, b.scan_tiles);
+    const ScanIn in{b.count, b.cell_start_old, b.dirty, b.tabidx, b.cellinfo};
+    hipLaunchKernelGGL(k_scan_reduce, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, in, b.tile_sums,
+                       b.scan_tiles);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kTileScanThreads), 0, s, b.g, b.tile_sums, b.cell_start,
                        b.scan_tiles);
-    hipLaunchKernelGGL(k_scan_down, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, b.count, b.cell_start_old,
-                       b.dirty, b.cell_start, b.tile_sums, b.dirty_list, b.aoff, b.scan_tiles);
+    hipLaunchKernelGGL(k_scan_down, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, in, b.count, b.cell_start,
+                       b.tile_sums, b.dirty_list, b.aoff, b.scan_tiles);
     mark(1);
     hipLaunchKernelGGL(k_scatter<T>, dim3(loop_blocks), dim3(256), 0, s, b, pos_cur, ids_cur);
     mark(2);
-    hipLaunchKernelGGL(k_fixup<T>, dim3(loop_blocks), dim3(256), 0, s, b, pos_cur);
-    const uint32_t sb = (b.box_capacity + 255) / 256;
-    hipLaunchKernelGGL(k_clean<T>, dim3(sb < kLoopBlocks ? (sb ? sb : 1u) : kLoopBlocks), dim3(256), 0, s, b,
-                       pos_cur, moved_bits ? 1 : 0);
+    hipLaunchKernelGGL(k_fixup<T>, dim3(loop_blocks), dim3(256), 0, s, b, pos_cur, relayout ? ids_cur ^ 1 : -1);
+    if (moved_bits) {
+        const uint32_t sb = (b.box_capacity + 255) / 256;
+        hipLaunchKernelGGL(k_clean<T>, dim3(sb < kLoopBlocks ? (sb ? sb : 1u) : kLoopBlocks), dim3(256), 0, s, b,
+                           pos_cur);
+    }
     mark(3);
 }
 
@@ -1037,7 +1104,7 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool moved_bits,
     template void launch_bbox<T>(const Buffers<T>&, int, int, hipStream_t);                              \
     template void launch_reset_bbox<T>(const Buffers<T>&, int, hipStream_t);                             \
     template void launch_setup<T>(const Buffers<T>&, int, bool, hipStream_t);                            \
-    template void launch_grid<T>(const Buffers<T>&, int, int, bool, hipStream_t, hipEvent_t* const*);   \
+    template void launch_grid<T>(const Buffers<T>&, int, int, bool, bool, hipStream_t, hipEvent_t* const*); \
     template void launch_clear_cellinfo<T>(const Buffers<T>&, hipStream_t);                              \
     template void launch_box_ranks<T>(const Buffers<T>&, int, uint32_t*, hipStream_t);                   \
     template void launch_canonical_ids<T>(const Buffers<T>&, int, const uint32_t*, uint32_t*, hipStream_t);

@@ -99,6 +99,44 @@ def cpu_baseline(w, budget_s: float):
                        f"{el:.1f} s)")
 
 
+DEFAULT_SWEEP = "1e3,1e4,1e5,1e6,1e7,1e8,3e8,1e9"
+
+
+def scale_sweep(sizes, block_size):
+    """Plain step (skip off, re-layout every step) on n spheres uniform in a
+    cube at c2's density (about 12 candidates per agent), d ~ U[8, 12],
+    FP32 state, seed (6, n): agent-steps/s per n, HIP-event phase times, and
+    the workspace size."""
+    import numpy as np
+    import torch
+    from paper_2301_06984_amd import abm, workloads
+    for n in sizes:
+        side = (n / workloads.C2_DENSITY) ** (1.0 / 3.0)
+        log(f"sweep n={n}: generating (side {side:.1f})")
+        p, d = workloads.uniform_cube(n, side, (6, n), dtype=np.float32)
+        pos = torch.from_numpy(p).cuda()
+        diam = torch.from_numpy(d).cuda()
+        del p, d
+        # the grid grows by a box or two per axis as the agents relax: a
+        # tight box capacity keeps the largest runs inside the GPU's memory
+        sim = abm.Sim(pos, diam, detect_static=False, sort_every=1, block_size=block_size,
+                      box_slack=1.5 if n < 100_000_000 else 1.05)
+        steps = int(min(200, max(5, 2e8 // n)))
+        sim.step(3)
+        sim.sync()
+        el, tm = timed_steps(sim, steps, timing=True)
+        value = n * steps / el
+        rec = dict(sweep="uniform cube at c2 density, d~U[8,12], FP32 state, seed (6, n)", n=int(n), steps=steps,
+                   value=value, unit="agent-steps/s", ms_per_step=1e3 * el / steps,
+                   step_frac=round(value * STEP_BYTES["f32"] / (HBM_PEAK_GBS * 1e9), 4),
+                   workspace_gb=round(sim.ws.numel() / 1e9, 2),
+                   phase_ms={k: round(tm[k] / tm["steps"], 4) for k in abm.TIMED_PHASES})
+        print(json.dumps(rec), flush=True)
+        sim.close()
+        del sim, pos, diam
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +149,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--sweep", nargs="?", const=DEFAULT_SWEEP, default=None,
+                    help="instead of the headline: agent-steps/s of the plain step on a uniform cube at c2's "
+                         "density for each N of a comma-separated list (one JSON line per N)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scales rocprof byte counters)")
     args = ap.parse_args()
@@ -139,6 +180,9 @@ def main():
         hip_build.build()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sweep:
+        scale_sweep([int(float(x)) for x in args.sweep.split(",")], args.block_size)
+        return
 
     # ---------------------------------------------------------------- headline
     log(f"generating headline workload n={args.n}")

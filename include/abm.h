@@ -150,8 +150,10 @@ int abm_extent_of(int64_t n, const void* pos, const void* diam, const abm_params
 
 /*
  * Bytes of device workspace for nsims simulations with the given agent
- * offsets (host, nsims + 1, offsets[0] = 0) and box capacities (host, nsims:
- * boxes each simulation's grid may span; see abm_extent.nboxes).
+ * offsets (host, nsims + 1, offsets[0] = 0; at most 2^31 - 2^20 agents in
+ * all) and box capacities (host, nsims: boxes each simulation's grid may
+ * span; see abm_extent.nboxes).  The per-box tables are held per super-box,
+ * ceil((capacity + 1) / 2) entries per simulation.
  */
 int abm_workspace_bytes(int32_t nsims, const int64_t* offsets, const int64_t* box_capacity,
                         const abm_params* p, int64_t* bytes);

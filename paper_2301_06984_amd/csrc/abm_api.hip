@@ -43,6 +43,11 @@ struct Layout {
     uint32_t scan_tiles, partial_cap;
 };
 
+// Super-boxes of a grid of at most cap boxes: prod ceil(d_a / 2) with d_x d_y
+// d_z <= cap is largest for dims (1, 1, cap), so at most ceil((cap + 1) / 2).
+int64_t super_capacity(int64_t cap) { return (cap + 2) / 2; }
+
+// boxes: capacity in super-boxes (sum of super_capacity over the simulations)
 Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, int64_t elem) {
     Layout L{};
     int64_t off = 0;
@@ -330,7 +335,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     // loose slots [0, 2n) and the padded step grid stay below 2^32
     if (n > (int64_t(1) << 31) - (int64_t(1) << 20)) return fail(ABM_E_INVAL, "at most 2^31 - 2^20 agents");
     std::vector<SimGrid> sims(nsims);
-    uint64_t boxes = 0;
+    uint64_t boxes = 0, supers = 0;
     for (int s = 0; s < nsims; ++s) {
         std::string why;
         if (!valid_params(&per_sim[s], &why)) return fail(ABM_E_INVAL, "simulation " + std::to_string(s) + ": " + why);
@@ -338,6 +343,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
         if (box_capacity[s] < 1 || box_capacity[s] > 0xFFFFFFFFll)
             return fail(ABM_E_INVAL, "box capacity must be in [1, 2^32)");
         boxes += uint64_t(box_capacity[s]);
+        supers += uint64_t(super_capacity(box_capacity[s]));
         SimGrid& G = sims[s];
         std::memset(&G, 0, sizeof(G));
         G.radius = per_sim[s].interaction_radius;
@@ -353,7 +359,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     }
     if (boxes >= 0xFFFFFFFFull) return fail(ABM_E_GRID, "total box capacity must be below 2^32");
     const abm_params& p0 = per_sim[0];
-    const Layout L = make_layout(n, nsims, int64_t(boxes), p0.keep_forces != 0, sizeof(T));
+    const Layout L = make_layout(n, nsims, int64_t(supers), p0.keep_forces != 0, sizeof(T));
     if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(ABM_E_INVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < L.total)
         return fail(ABM_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
@@ -368,7 +374,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     c->params = p0;
     fill_buffers<T>(c);
     Buffers<T>& b = c->buf<T>();
-    b.box_capacity = uint32_t(boxes);
+    b.super_capacity = uint32_t(supers);
     hipStream_t s = c->stream;
     auto bail = [&](int code) {
         delete c;
@@ -378,10 +384,10 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     // marks, table indices; and the positions with their padding (read,
     // never used, by the walk)
     if (hipMemsetAsync(c->ws + L.globals, 0, sizeof(Globals), s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.count, 0, 4 * boxes, s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.cellinfo, 0, 16 * boxes, s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.dirty, 0, 4 * boxes, s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.tabidx, 0, 4 * boxes, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.count, 0, 4 * supers, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.cellinfo, 0, 16 * supers, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.dirty, 0, 4 * supers, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.tabidx, 0, 4 * supers, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.pos4[0], 0, 4 * c->elem() * (2 * n + kSposPad), s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.pos4[1], 0, 4 * c->elem() * (2 * n + kSposPad), s) != hipSuccess ||
         hipMemcpyAsync(b.sims, sims.data(), sizeof(SimGrid) * nsims, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -860,15 +866,17 @@ int abm_workspace_bytes(int32_t nsims, const int64_t* offsets, const int64_t* bo
     if (!valid_params(p, &why)) return fail(ABM_E_INVAL, why);
     if (nsims < 1 || nsims > 65535 || !offsets || !box_capacity || !bytes) return fail(ABM_E_INVAL, "bad arguments");
     const int64_t n = offsets[nsims];
-    if (offsets[0] != 0 || n <= 0 || n > 0xFFFFFFFEll) return fail(ABM_E_INVAL, "offsets must start at 0, n in [1, 2^32-1)");
-    int64_t boxes = 0;
+    if (offsets[0] != 0 || n <= 0 || n > (int64_t(1) << 31) - (int64_t(1) << 20))
+        return fail(ABM_E_INVAL, "offsets must start at 0, n in [1, 2^31 - 2^20]");
+    int64_t boxes = 0, supers = 0;
     for (int s = 0; s < nsims; ++s) {
         if (offsets[s + 1] < offsets[s]) return fail(ABM_E_INVAL, "offsets must be non-decreasing");
         if (box_capacity[s] < 1) return fail(ABM_E_INVAL, "box capacity must be >= 1");
         boxes += box_capacity[s];
+        supers += super_capacity(box_capacity[s]);
     }
     if (boxes >= 0xFFFFFFFFll) return fail(ABM_E_GRID, "total box capacity must be below 2^32");
-    *bytes = make_layout(n, nsims, boxes, p->keep_forces != 0, p->precision == ABM_F64 ? 8 : 4).total;
+    *bytes = make_layout(n, nsims, supers, p->keep_forces != 0, p->precision == ABM_F64 ? 8 : 4).total;
     return ABM_OK;
 }
 

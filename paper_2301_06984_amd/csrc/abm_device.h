@@ -95,13 +95,13 @@ __device__ __forceinline__ void bbox_atomic(int32_t* t, const int32_t lo[3], con
     }
 }
 
-// Fold the box coordinates c of the active threads of a block into the
+// Fold the box ranges [clo, chi] of the active threads of a block into the
 // accumulator target(sim) (6 ints: min x,y,z then max x,y,z).  Waves reduce
 // in registers, the block combines its waves in LDS, and one set of atomics
 // per simulation present in the block goes out, so that same-address
 // atomics stay few.  Every thread of the block must call this once.
 template <class Target>
-__device__ void bbox_fold_block(int sim, bool active, const int32_t c[3], Target target) {
+__device__ void bbox_fold_block(int sim, bool active, const int32_t clo[3], const int32_t chi[3], Target target) {
     __shared__ int32_t s_box[16][6];
     __shared__ int s_sim[16];
     const int wave = int(threadIdx.x >> 6);
@@ -117,8 +117,8 @@ __device__ void bbox_fold_block(int sim, bool active, const int32_t c[3], Target
     if (act && uniform) {
         int32_t lo[3], hi[3];
         for (int a = 0; a < 3; ++a) {
-            lo[a] = wave_min(active ? c[a] : INT32_MAX);
-            hi[a] = wave_max(active ? c[a] : INT32_MIN);
+            lo[a] = wave_min(active ? clo[a] : INT32_MAX);
+            hi[a] = wave_max(active ? chi[a] : INT32_MIN);
         }
         if (lane_id() == 0) {
             s_sim[wave] = s0;
@@ -128,7 +128,7 @@ __device__ void bbox_fold_block(int sim, bool active, const int32_t c[3], Target
             }
         }
     } else {
-        if (active) bbox_atomic(target(sim), c, c);
+        if (active) bbox_atomic(target(sim), clo, chi);
         if (lane_id() == 0) s_sim[wave] = -1;
     }
     __syncthreads();
@@ -154,6 +154,11 @@ __device__ void bbox_fold_block(int sim, bool active, const int32_t c[3], Target
         }
         if (cur >= 0) bbox_atomic(target(cur), lo, hi);
     }
+}
+
+template <class Target>
+__device__ void bbox_fold_block(int sim, bool active, const int32_t c[3], Target target) {
+    bbox_fold_block(sim, active, c, c, target);
 }
 
 // Replica of the bbox accumulator that this block folds into.

@@ -128,7 +128,7 @@ struct Buffers {
     const uint16_t* sim_of;   // null for a single simulation
     int32_t nsims;
     uint32_t n;
-    uint32_t box_capacity;    // sum of per-simulation capacities
+    uint32_t super_capacity;  // super-boxes the per-super-box arrays hold (a bound from the box capacities)
     uint32_t scan_tiles;
     // per loose slot [0, 2n) (+ kSposPad positions)
     void* pos4[2];

@@ -17,6 +17,8 @@
 //            super-boxes kept in place
 #include "force_loop.h"
 
+#include <algorithm>
+
 namespace abm {
 
 // ------------------------------------------------------------------ init
@@ -90,19 +92,23 @@ void launch_finish_radius(const Buffers<T>& b, hipStream_t s) {
 }
 
 // Extent of caller-layout positions (n x 3 + diameters) for sizing a grid:
-// largest diameter, then box coordinates into SimGrid::bbox[0].
+// largest diameter, then box coordinates into SimGrid::bbox[0].  Threads loop
+// over the agents (a grid of at most kExtentBlocks blocks), so that one
+// accumulator takes few same-address atomics.
+constexpr uint32_t kExtentBlocks = 1024;
 template <class T>
 __global__ void k_extent_radius(const T* __restrict__ diam, uint32_t n, Globals* g, SimGrid* sim) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool active = i < n;
+    bool active = false;
     unsigned long long v = 0;
-    if (active) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const double d = double(diam[i]);
         if (!(d > 0.0) || !isfinite(d)) {
             raise_error(g, kErrNonfinite);
-            active = false;
+            continue;
         }
-        v = (unsigned long long)__double_as_longlong(d);
+        const unsigned long long x = (unsigned long long)__double_as_longlong(d);
+        v = active && v > x ? v : x;
+        active = true;
     }
     max_fold_block(0, active, v, [&](int) { return &sim->radius_bits; });
 }
@@ -116,25 +122,30 @@ __global__ void k_extent_reset(SimGrid* sim) {
 
 template <class T>
 __global__ void k_extent_bbox(const T* __restrict__ pos, uint32_t n, Globals* g, SimGrid* sim) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool active = i < n;
-    int32_t c[3] = {0, 0, 0};
-    if (active) {
-        const double ih = sim->inv_h;
+    bool active = false;
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    const double ih = sim->inv_h;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int32_t c[3];
         const bool ok = box_coord(double(pos[3 * size_t(i)]), ih, &c[0]) &&
                         box_coord(double(pos[3 * size_t(i) + 1]), ih, &c[1]) &&
                         box_coord(double(pos[3 * size_t(i) + 2]), ih, &c[2]);
         if (!ok) {
             raise_error(g, kErrNonfinite);
-            active = false;
+            continue;
         }
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = min(lo[a], c[a]);
+            hi[a] = max(hi[a], c[a]);
+        }
+        active = true;
     }
-    bbox_fold_block(0, active, c, [&](int) { return sim->bbox[0]; });
+    bbox_fold_block(0, active, lo, hi, [&](int) { return sim->bbox[0]; });
 }
 
 template <class T>
 void launch_extent(const T* pos, const T* diam, uint32_t n, Globals* g, SimGrid* sim, hipStream_t s) {
-    const uint32_t blocks = (n + 255) / 256;
+    const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, kExtentBlocks);
     hipLaunchKernelGGL(k_extent_radius<T>, dim3(blocks), dim3(256), 0, s, diam, n, g, sim);
     hipLaunchKernelGGL(k_finish_radius, dim3(1), dim3(64), 0, s, sim, 1);
     hipLaunchKernelGGL(k_extent_reset, dim3(1), dim3(1), 0, s, sim);
@@ -227,7 +238,7 @@ constexpr int kTileLevels = 3;    // tiles of 8 x 8 x 8 super-boxes
 constexpr int kTileBlocks = 256;  // grid of the tile-table kernel (it loops)
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int32_t* rep, int nsims,
-                                                           int parity, uint32_t box_capacity, int allow_inc,
+                                                           int parity, uint32_t super_capacity, int allow_inc,
                                                            uint32_t n) {
     __shared__ unsigned long long s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
@@ -331,7 +342,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
     }
     if (threadIdx.x == 0) {
         unsigned long long total = s_carry >> 32;
-        if (total > box_capacity || total >= kMaxSuperBoxes) {
+        if (total > super_capacity || total >= kMaxSuperBoxes) {
             raise_error(g, kErrGrid);
             total = 0;
             for (int s = 0; s < nsims; ++s) sims[s].valid = 0;
@@ -384,7 +395,7 @@ __global__ __launch_bounds__(256) void k_tiles(const Globals* g, const SimGrid* 
 template <class T>
 void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, b.g, b.sims, b.bbox_rep, b.nsims, parity,
-                       b.box_capacity, allow_inc ? 1 : 0, b.n);
+                       b.super_capacity, allow_inc ? 1 : 0, b.n);
     hipLaunchKernelGGL(k_tiles, dim3(kTileBlocks), dim3(256), 0, s, b.g, b.sims, b.nsims, b.tile_off);
 }
 
@@ -988,7 +999,7 @@ __global__ void k_reset_stamp(Globals* g) { g->stamp = 0; }
 template <class T>
 void launch_clear_cellinfo(const Buffers<T>& b, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_stamp, dim3(1), dim3(1), 0, s, b.g);
-    const uint64_t n = 2ull * b.box_capacity;   // 16-byte entries
+    const uint64_t n = 2ull * b.super_capacity;   // 16-byte entries
     hipLaunchKernelGGL(k_clear_u64, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, s,
                        reinterpret_cast<unsigned long long*>(b.cellinfo), n);
 }
@@ -1088,7 +1099,7 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, b
     mark(2);
     hipLaunchKernelGGL(k_fixup<T>, dim3(loop_blocks), dim3(256), 0, s, b, pos_cur, relayout ? ids_cur ^ 1 : -1);
     if (moved_bits) {
-        const uint32_t sb = (b.box_capacity + 255) / 256;
+        const uint32_t sb = (b.super_capacity + 255) / 256;
         hipLaunchKernelGGL(k_clean<T>, dim3(sb < kLoopBlocks ? (sb ? sb : 1u) : kLoopBlocks), dim3(256), 0, s, b,
                            pos_cur);
     }

@@ -42,6 +42,13 @@ def test_headline_1e7_first_step():
     sim.sync()
     x = sim.query("positions").cpu().numpy()
     assert np.isfinite(x).all()
+    # a later step: its grid is an update of the last one (agents re-laid out
+    # every step, extent unchanged); grid and sampled agents against the oracle
+    note("headline step 22 (update build) grid + samples")
+    sim.step(1)
+    sim.sync()
+    assert_grid_equal(sim, x, w.diam, oracle.Params())
+    check_samples(x, w.diam, sim.query("positions").cpu().numpy(), 96, 2)
 
 
 def test_c2_full_parity_and_skip():

@@ -194,6 +194,45 @@ class State:
                      self.force.copy(), self.t)
 
 
+# ---------------------------------------------------------------- Section 3.2
+def remove_agents(state: State, ids) -> State:
+    """Remove the agents ``ids`` (distinct indices below n) the way Section
+    3.2 keeps the agent vector dense: it shrinks to new_size = n - m, and an
+    agent to be removed left of new_size leaves a hole, filled by an agent
+    right of new_size that stays.  Reading of the pairing (the paper's figure
+    is not in its text): the k-th hole in ascending index takes the k-th such
+    agent in ascending index.  Every other agent keeps its index, which is its
+    id.  Returns the new state."""
+    n = state.pos.shape[0]
+    ids = np.asarray(ids, dtype=np.int64).reshape(-1)
+    m = ids.size
+    if m and (ids.min() < 0 or ids.max() >= n or np.unique(ids).size != m):
+        raise ValueError("ids must be distinct and below n")
+    new_size = n - m
+    removed = np.zeros(n, bool)
+    removed[ids] = True
+    holes = np.nonzero(removed[:new_size])[0]                 # left of new_size, ascending
+    fillers = new_size + np.nonzero(~removed[new_size:])[0]   # right of new_size and kept, ascending
+    assert holes.size == fillers.size
+    src = np.arange(new_size)
+    src[holes] = fillers                                      # new index j holds old agent src[j]
+    return State(state.pos[src].copy(), state.diam[src].copy(), state.moved[src].copy(), state.nnz[src].copy(),
+                 state.force[src].copy(), state.t)
+
+
+def add_agents(state: State, pos, diam) -> State:
+    """Append new agents (Section 3.2: additions grow the vectors), ids n, n+1,
+    ...  A new agent has no history: it counts as moved, so no agent within
+    R of it is static in the next step (condition (iii) of Section 5), and it
+    has no non-zero pair term and no force yet."""
+    pos = np.asarray(pos, dtype=state.pos.dtype).reshape(-1, 3)
+    diam = np.asarray(diam, dtype=state.diam.dtype).reshape(-1)
+    m = pos.shape[0]
+    return State(np.concatenate([state.pos, pos]), np.concatenate([state.diam, diam]),
+                 np.concatenate([state.moved, np.ones(m, np.uint8)]), np.concatenate([state.nnz, np.zeros(m, np.int32)]),
+                 np.concatenate([state.force, np.zeros((m, 3), np.float64)]), state.t)
+
+
 def step(state: State, params: Params, want_static: bool = False, want_disp: bool = False):
     """Advance ``state`` by one step in place; returns (static, disp) if asked."""
     n = state.pos.shape[0]

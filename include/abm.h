@@ -184,6 +184,46 @@ int abm_init_batched(abm_ctx** ctx, int32_t nsims, const int64_t* offsets, const
                      void* stream);
 
 /*
+ * Dynamic population (Section 3.2: agents are added and removed between
+ * iterations).  abm_workspace_bytes_capacity gives the workspace of a
+ * single-simulation context that holds up to `capacity` agents (1 <= capacity
+ * <= 2^31 - 2^20); abm_init_capacity creates one with n <= capacity agents,
+ * otherwise as abm_init.  The interaction radius stays the one fixed at init
+ * (the largest initial diameter unless p->interaction_radius > 0).
+ */
+int abm_workspace_bytes_capacity(int64_t capacity, int64_t box_capacity, const abm_params* p, int64_t* bytes);
+int abm_init_capacity(abm_ctx** ctx, int64_t n, int64_t capacity, const void* pos, const void* diam,
+                      const abm_params* p, int64_t box_capacity, void* ws, int64_t ws_bytes, void* stream);
+
+/*
+ * Append m agents between steps (Section 3.2): pos (m x 3) and diam (m) on
+ * the device, element type of the context, read before the call returns.
+ * They get ids n, n+1, ..., n+m-1, count as moved in the last step (no
+ * history; so no agent within R of one is static in the next step, condition
+ * (iii) of Section 5), with no pair terms and no force.  The call
+ * synchronizes the context's stream.  Errors: ABM_E_INVAL (n + m above the
+ * capacity, or a diameter above the interaction radius: the population is
+ * then unchanged), ABM_E_NONFINITE, ABM_E_UNSUPPORTED (batched context).
+ */
+int abm_add_agents(abm_ctx* ctx, int64_t m, const void* pos, const void* diam);
+
+/*
+ * Remove the m agents with the given ids (device, m distinct int64 ids below
+ * n) between steps, keeping the ids dense as Section 3.2 keeps the agent
+ * vector dense: with new_size = n - m, each removed id below new_size is a
+ * hole that a kept id at or above new_size takes over, the k-th hole in
+ * ascending order the k-th such id in ascending order; every other agent
+ * keeps its id.  Agents near a removed one keep their static state
+ * (condition (iv) of Section 5).  The call synchronizes the context's stream.
+ * Errors: ABM_E_INVAL (an id out of range or given twice, or m = n: nothing
+ * is removed then), ABM_E_UNSUPPORTED (batched context).
+ */
+int abm_remove_agents(abm_ctx* ctx, int64_t m, const int64_t* ids);
+
+/* Agents now and the context's capacity (host outputs; either may be null). */
+int abm_population(abm_ctx* ctx, int64_t* n, int64_t* capacity);
+
+/*
  * Change the force-law, mobility, threshold or clamp parameters (all
  * simulations of a batched context take the same values).  Every agent counts
  * as moved at the next step, so none is static there (Section 5: a changed

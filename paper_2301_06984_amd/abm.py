@@ -28,7 +28,8 @@ EXPORTS = ["abm_abi_version", "abm_default_params", "abm_last_error", "abm_exten
            "abm_init", "abm_init_batched", "abm_set_params", "abm_step", "abm_sync", "abm_query",
            "abm_get_stats", "abm_state_bytes", "abm_export_state", "abm_import_state", "abm_graph_capture",
            "abm_graph_launch", "abm_record_bytes", "abm_forward_record", "abm_backward", "abm_set_timing",
-           "abm_get_timing", "abm_destroy"]
+           "abm_get_timing", "abm_destroy", "abm_workspace_bytes_capacity", "abm_init_capacity", "abm_add_agents",
+           "abm_remove_agents", "abm_population"]
 TIMED_PHASES = ["setup", "keys", "scan", "scatter", "fixup", "force"]
 
 
@@ -94,6 +95,11 @@ def lib():
             "abm_set_timing": (C.c_int, [P, i32]),
             "abm_get_timing": (C.c_int, [P, C.POINTER(abm_timing)]),
             "abm_destroy": (None, [P]),
+            "abm_workspace_bytes_capacity": (C.c_int, [i64, i64, C.POINTER(abm_params), C.POINTER(i64)]),
+            "abm_init_capacity": (C.c_int, [C.POINTER(P), i64, i64, P, P, C.POINTER(abm_params), i64, P, i64, P]),
+            "abm_add_agents": (C.c_int, [P, i64, P, P]),
+            "abm_remove_agents": (C.c_int, [P, i64, P]),
+            "abm_population": (C.c_int, [P, C.POINTER(i64), C.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -151,7 +157,8 @@ class Sim:
     (n x 3 and n, float32 or float64 per ``precision``)."""
 
     def __init__(self, pos: torch.Tensor, diam: torch.Tensor, *, box_slack: float = 1.5,
-                 box_capacity: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None, **params):
+                 box_capacity: Optional[int] = None, capacity: Optional[int] = None,
+                 stream: Optional[torch.cuda.Stream] = None, **params):
         if "precision" not in params:
             params["precision"] = "f64" if pos.dtype == torch.float64 else "f32"
         self.params = default_params(**params)
@@ -165,15 +172,49 @@ class Sim:
         ext = extent_of(self.pos_in, self.diam_in, self.params, self.stream)
         self.extent0 = ext
         self.box_capacity = int(box_capacity) if box_capacity else box_capacity_for(ext.nboxes, box_slack)
-        offs = (C.c_int64 * 2)(0, self.n)
-        caps = (C.c_int64 * 1)(self.box_capacity)
         nbytes = C.c_int64()
-        _check(lib().abm_workspace_bytes(1, offs, caps, C.byref(self.params), C.byref(nbytes)), "abm_workspace_bytes")
-        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=pos.device)
         self.ctx = C.c_void_p()
-        _check(lib().abm_init(C.byref(self.ctx), self.n, _ptr(self.pos_in), _ptr(self.diam_in), C.byref(self.params),
-                              self.box_capacity, _ptr(self.ws), self.ws.numel(), int(self.stream.cuda_stream)),
-               "abm_init")
+        if capacity is None:
+            offs = (C.c_int64 * 2)(0, self.n)
+            caps = (C.c_int64 * 1)(self.box_capacity)
+            _check(lib().abm_workspace_bytes(1, offs, caps, C.byref(self.params), C.byref(nbytes)),
+                   "abm_workspace_bytes")
+            self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=pos.device)
+            _check(lib().abm_init(C.byref(self.ctx), self.n, _ptr(self.pos_in), _ptr(self.diam_in),
+                                  C.byref(self.params), self.box_capacity, _ptr(self.ws), self.ws.numel(),
+                                  int(self.stream.cuda_stream)), "abm_init")
+        else:
+            _check(lib().abm_workspace_bytes_capacity(int(capacity), self.box_capacity, C.byref(self.params),
+                                                      C.byref(nbytes)), "abm_workspace_bytes_capacity")
+            self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=pos.device)
+            _check(lib().abm_init_capacity(C.byref(self.ctx), self.n, int(capacity), _ptr(self.pos_in),
+                                           _ptr(self.diam_in), C.byref(self.params), self.box_capacity,
+                                           _ptr(self.ws), self.ws.numel(), int(self.stream.cuda_stream)),
+                   "abm_init_capacity")
+
+    # ---------------------------------------------------------------- population
+    def add_agents(self, pos: torch.Tensor, diam: torch.Tensor):
+        """Append agents (ids n, n+1, ...); needs a context made with ``capacity``."""
+        dt = _dtype_of(self.params)
+        pos = pos.to(dtype=dt).contiguous()
+        diam = diam.to(dtype=dt).contiguous()
+        if not pos.is_cuda or not diam.is_cuda or pos.shape[0] != diam.shape[0]:
+            raise TypeError("pos (m x 3) and diam (m) must be CUDA tensors")
+        _check(lib().abm_add_agents(self.ctx, int(pos.shape[0]), _ptr(pos), _ptr(diam)), "abm_add_agents")
+        self.n = self.population()[0]
+
+    def remove_agents(self, ids: torch.Tensor):
+        """Remove agents by id; ids stay dense (see abm_remove_agents)."""
+        ids = ids.to(dtype=torch.int64).contiguous()
+        if not ids.is_cuda:
+            raise TypeError("ids must be a CUDA tensor")
+        _check(lib().abm_remove_agents(self.ctx, int(ids.numel()), _ptr(ids)), "abm_remove_agents")
+        self.n = self.population()[0]
+
+    def population(self):
+        n, cap = C.c_int64(), C.c_int64()
+        _check(lib().abm_population(self.ctx, C.byref(n), C.byref(cap)), "abm_population")
+        return int(n.value), int(cap.value)
 
     # ---------------------------------------------------------------- stepping
     def step(self, nsteps: int = 1):

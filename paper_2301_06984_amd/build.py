@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libabm.so")
-SOURCES = ["grid_kernels.hip", "force_kernels.hip", "adjoint_kernels.hip", "abm_api.hip"]
+SOURCES = ["grid_kernels.hip", "force_kernels.hip", "adjoint_kernels.hip", "population_kernels.hip", "abm_api.hip"]
 HEADERS = ["abm_internal.h", "abm_device.h", "force_loop.h"]
 ARCH = os.environ.get("ABM_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

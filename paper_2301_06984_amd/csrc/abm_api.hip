@@ -43,6 +43,9 @@ struct Layout {
     uint32_t scan_tiles, partial_cap;
 };
 
+// Agents per context: loose slots [0, 2n) and the padded step grid stay below 2^32.
+constexpr int64_t kMaxAgents = (int64_t(1) << 31) - (int64_t(1) << 20);
+
 // Super-boxes of a grid of at most cap boxes: prod ceil(d_a / 2) with d_x d_y
 // d_z <= cap is largest for dims (1, 1, cap), so at most ceil((cap + 1) / 2).
 int64_t super_capacity(int64_t cap) { return (cap + 2) / 2; }
@@ -95,7 +98,8 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
 struct abm_ctx {
     int precision = ABM_F32;
     int32_t nsims = 1;
-    int64_t n = 0;
+    int64_t n = 0;           // agents now
+    int64_t cap = 0;         // agents the workspace holds (additions up to it)
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     Layout L{};
@@ -230,6 +234,9 @@ int block_size_of(const abm_params& p) { return p.block_size ? p.block_size : 25
 int error_code(uint32_t err) {
     if (err & kErrNonfinite) return fail(ABM_E_NONFINITE, "non-finite position or diameter");
     if (err & kErrGrid) return fail(ABM_E_GRID, "grid exceeds its box capacity or 2^21 boxes per axis");
+    if (err & kErrRange)
+        return fail(ABM_E_INVAL, "value out of range (an added diameter above the interaction radius, or an id "
+                                 "out of range or given twice)");
     if (err & kErrInternal) return fail(ABM_E_HIP, "internal index check failed");
     return ABM_OK;
 }
@@ -330,10 +337,12 @@ int check_ctx(abm_ctx* c) {
 
 template <class T>
 int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* pos, const void* diam,
-              const abm_params* per_sim, const int64_t* box_capacity, void* ws, int64_t ws_bytes, void* stream) {
+              const abm_params* per_sim, const int64_t* box_capacity, void* ws, int64_t ws_bytes, void* stream,
+              int64_t capacity) {
     const int64_t n = offsets[nsims];
+    const int64_t cap = std::max(capacity, n);
     // loose slots [0, 2n) and the padded step grid stay below 2^32
-    if (n > (int64_t(1) << 31) - (int64_t(1) << 20)) return fail(ABM_E_INVAL, "at most 2^31 - 2^20 agents");
+    if (cap > kMaxAgents) return fail(ABM_E_INVAL, "at most 2^31 - 2^20 agents");
     std::vector<SimGrid> sims(nsims);
     uint64_t boxes = 0, supers = 0;
     for (int s = 0; s < nsims; ++s) {
@@ -359,7 +368,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     }
     if (boxes >= 0xFFFFFFFFull) return fail(ABM_E_GRID, "total box capacity must be below 2^32");
     const abm_params& p0 = per_sim[0];
-    const Layout L = make_layout(n, nsims, int64_t(supers), p0.keep_forces != 0, sizeof(T));
+    const Layout L = make_layout(cap, nsims, int64_t(supers), p0.keep_forces != 0, sizeof(T));
     if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(ABM_E_INVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < L.total)
         return fail(ABM_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
@@ -367,6 +376,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     c->precision = p0.precision;
     c->nsims = nsims;
     c->n = n;
+    c->cap = cap;
     c->stream = static_cast<hipStream_t>(stream);
     c->ws = static_cast<char*>(ws);
     c->L = L;
@@ -388,8 +398,8 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
         hipMemsetAsync(c->ws + L.cellinfo, 0, 16 * supers, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.dirty, 0, 4 * supers, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.tabidx, 0, 4 * supers, s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.pos4[0], 0, 4 * c->elem() * (2 * n + kSposPad), s) != hipSuccess ||
-        hipMemsetAsync(c->ws + L.pos4[1], 0, 4 * c->elem() * (2 * n + kSposPad), s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.pos4[0], 0, 4 * c->elem() * (2 * cap + kSposPad), s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.pos4[1], 0, 4 * c->elem() * (2 * cap + kSposPad), s) != hipSuccess ||
         hipMemcpyAsync(b.sims, sims.data(), sizeof(SimGrid) * nsims, hipMemcpyHostToDevice, s) != hipSuccess)
         return bail(fail(ABM_E_HIP, "workspace initialisation failed"));
     std::vector<uint16_t> sim_of;
@@ -822,6 +832,73 @@ int graph_launch_impl(abm_ctx* c) {
 template <class T>
 int dispatch_steps(abm_ctx* c, int32_t nsteps) { return do_steps<T>(c, nsteps, true); }
 
+// ---------------------------------------------------------------- population
+// After agents were added or removed: the new population's extent for the
+// next step, whose grid is a full build; the last grid, a captured graph and
+// a recorded forward run no longer apply.
+template <class T>
+int population_changed(abm_ctx* c, int64_t n) {
+    c->n = n;
+    c->offsets.back() = n;
+    Buffers<T>& b = c->buf<T>();
+    b.n = uint32_t(n);
+    launch_set_population(b.sims, uint32_t(n), c->stream);
+    c->inc_ready = false;
+    c->have_grid = false;
+    c->recorded = false;
+    if (c->graph_exec) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    enqueue_extent<T>(c);
+    HIP_TRY(hipGetLastError());
+    return read_error(c, true);
+}
+
+template <class T>
+int add_impl(abm_ctx* c, int64_t m, const void* pos, const void* diam) {
+    if (c->nsims != 1) return fail(ABM_E_UNSUPPORTED, "agents are added to single-simulation contexts only");
+    if (m < 0 || (m > 0 && (!pos || !diam))) return fail(ABM_E_INVAL, "bad arguments");
+    if (c->n + m > c->cap)
+        return fail(ABM_E_INVAL, "capacity exceeded: " + std::to_string(c->n + m) + " > " + std::to_string(c->cap));
+    if (m == 0) return ABM_OK;
+    if (const int rc = read_error(c, true)) return rc;
+    Buffers<T>& b = c->buf<T>();
+    launch_add<T>(b, c->pos_cur, c->ids_cur, uint32_t(c->n), uint32_t(m), static_cast<const T*>(pos),
+                  static_cast<const T*>(diam), c->stream);
+    HIP_TRY(hipGetLastError());
+    // the new agents went to slots past the population, where the last
+    // grid's append region lies: that grid cannot be queried any more.  A
+    // rejected agent leaves the population as it was.
+    c->have_grid = false;
+    if (const int rc = read_error(c, true)) return rc;
+    return population_changed<T>(c, c->n + m);
+}
+
+template <class T>
+int remove_impl(abm_ctx* c, int64_t m, const int64_t* ids) {
+    if (c->nsims != 1) return fail(ABM_E_UNSUPPORTED, "agents are removed from single-simulation contexts only");
+    if (m < 0 || m > c->n || (m > 0 && !ids)) return fail(ABM_E_INVAL, "bad arguments");
+    if (m == 0) return ABM_OK;
+    if (m == c->n) return fail(ABM_E_INVAL, "a context keeps at least one agent");
+    if (const int rc = read_error(c, true)) return rc;
+    Buffers<T>& b = c->buf<T>();
+    uint32_t* work = reinterpret_cast<uint32_t*>(c->ws + c->L.stage);
+    launch_remove<T>(b, c->pos_cur, c->ids_cur, uint32_t(m), ids, work, uint32_t(c->cap), c->stream, 0);
+    HIP_TRY(hipGetLastError());
+    // bad or repeated ids are reported before anything moves
+    if (const int rc = read_error(c, true)) return rc;
+    launch_remove<T>(b, c->pos_cur, c->ids_cur, uint32_t(m), ids, work, uint32_t(c->cap), c->stream, 1);
+    HIP_TRY(hipGetLastError());
+    c->pos_cur ^= 1;
+    c->ids_cur ^= 1;
+    return population_changed<T>(c, c->n - m);
+}
+
 }  // namespace
 
 // ======================================================================= C ABI
@@ -866,7 +943,7 @@ int abm_workspace_bytes(int32_t nsims, const int64_t* offsets, const int64_t* bo
     if (!valid_params(p, &why)) return fail(ABM_E_INVAL, why);
     if (nsims < 1 || nsims > 65535 || !offsets || !box_capacity || !bytes) return fail(ABM_E_INVAL, "bad arguments");
     const int64_t n = offsets[nsims];
-    if (offsets[0] != 0 || n <= 0 || n > (int64_t(1) << 31) - (int64_t(1) << 20))
+    if (offsets[0] != 0 || n <= 0 || n > kMaxAgents)
         return fail(ABM_E_INVAL, "offsets must start at 0, n in [1, 2^31 - 2^20]");
     int64_t boxes = 0, supers = 0;
     for (int s = 0; s < nsims; ++s) {
@@ -885,8 +962,44 @@ int abm_init(abm_ctx** ctx, int64_t n, const void* pos, const void* diam, const 
     if (!ctx || !pos || !diam || !p || n <= 0 || n > 0xFFFFFFFEll) return fail(ABM_E_INVAL, "bad arguments");
     const int64_t offsets[2] = {0, n};
     return p->precision == ABM_F64
-               ? init_impl<double>(ctx, 1, offsets, pos, diam, p, &box_capacity, ws, ws_bytes, stream)
-               : init_impl<float>(ctx, 1, offsets, pos, diam, p, &box_capacity, ws, ws_bytes, stream);
+               ? init_impl<double>(ctx, 1, offsets, pos, diam, p, &box_capacity, ws, ws_bytes, stream, 0)
+               : init_impl<float>(ctx, 1, offsets, pos, diam, p, &box_capacity, ws, ws_bytes, stream, 0);
+}
+
+int abm_workspace_bytes_capacity(int64_t capacity, int64_t box_capacity, const abm_params* p, int64_t* bytes) {
+    std::string why;
+    if (!p || !valid_params(p, &why)) return fail(ABM_E_INVAL, p ? why : "params is null");
+    if (!bytes || capacity < 1 || capacity > kMaxAgents) return fail(ABM_E_INVAL, "capacity must be in [1, 2^31 - 2^20]");
+    if (box_capacity < 1 || box_capacity >= 0xFFFFFFFFll) return fail(ABM_E_INVAL, "box capacity must be in [1, 2^32 - 1)");
+    *bytes = make_layout(capacity, 1, super_capacity(box_capacity), p->keep_forces != 0,
+                         p->precision == ABM_F64 ? 8 : 4).total;
+    return ABM_OK;
+}
+
+int abm_init_capacity(abm_ctx** ctx, int64_t n, int64_t capacity, const void* pos, const void* diam,
+                      const abm_params* p, int64_t box_capacity, void* ws, int64_t ws_bytes, void* stream) {
+    if (!ctx || !pos || !diam || !p || n <= 0 || capacity < n) return fail(ABM_E_INVAL, "bad arguments");
+    const int64_t offsets[2] = {0, n};
+    return p->precision == ABM_F64
+               ? init_impl<double>(ctx, 1, offsets, pos, diam, p, &box_capacity, ws, ws_bytes, stream, capacity)
+               : init_impl<float>(ctx, 1, offsets, pos, diam, p, &box_capacity, ws, ws_bytes, stream, capacity);
+}
+
+int abm_add_agents(abm_ctx* c, int64_t m, const void* pos, const void* diam) {
+    if (int rc = check_ctx(c)) return rc;
+    return c->precision == ABM_F64 ? add_impl<double>(c, m, pos, diam) : add_impl<float>(c, m, pos, diam);
+}
+
+int abm_remove_agents(abm_ctx* c, int64_t m, const int64_t* ids) {
+    if (int rc = check_ctx(c)) return rc;
+    return c->precision == ABM_F64 ? remove_impl<double>(c, m, ids) : remove_impl<float>(c, m, ids);
+}
+
+int abm_population(abm_ctx* c, int64_t* n, int64_t* capacity) {
+    if (int rc = check_ctx(c)) return rc;
+    if (n) *n = c->n;
+    if (capacity) *capacity = c->cap;
+    return ABM_OK;
 }
 
 int abm_init_batched(abm_ctx** ctx, int32_t nsims, const int64_t* offsets, const void* pos, const void* diam,
@@ -898,8 +1011,8 @@ int abm_init_batched(abm_ctx** ctx, int32_t nsims, const int64_t* offsets, const
     for (int s = 0; s < nsims; ++s)
         if (per_sim[s].precision != per_sim[0].precision) return fail(ABM_E_INVAL, "all simulations need one precision");
     return per_sim[0].precision == ABM_F64
-               ? init_impl<double>(ctx, nsims, offsets, pos, diam, per_sim, box_capacity, ws, ws_bytes, stream)
-               : init_impl<float>(ctx, nsims, offsets, pos, diam, per_sim, box_capacity, ws, ws_bytes, stream);
+               ? init_impl<double>(ctx, nsims, offsets, pos, diam, per_sim, box_capacity, ws, ws_bytes, stream, 0)
+               : init_impl<float>(ctx, nsims, offsets, pos, diam, per_sim, box_capacity, ws, ws_bytes, stream, 0);
 }
 
 int abm_set_params(abm_ctx* c, const abm_params* p) {

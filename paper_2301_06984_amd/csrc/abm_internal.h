@@ -73,6 +73,7 @@ enum : uint32_t {
     kErrNonfinite = 1u,     // a position or diameter is not finite
     kErrGrid = 2u,          // grid larger than its capacity or 2^21 boxes per axis
     kErrInternal = 8u,      // an index left its range (should never fire)
+    kErrRange = 16u,        // a caller's value out of range (added diameter above R, bad or repeated id)
 };
 
 struct SimGrid {
@@ -216,6 +217,17 @@ template <class T> void launch_load_positions(const Buffers<T>& b, int pos_cur, 
                                               hipStream_t s);
 template <class T> void launch_set_flags(const Buffers<T>& b, int pos_cur, int ids_cur, const uint8_t* moved,
                                          const int32_t* nnz, hipStream_t s);
+
+// ---- launchers (population_kernels.hip)
+void launch_scan_u32(uint32_t* a, uint32_t n, uint32_t* tsum, hipStream_t s);
+uint32_t gscan_tiles(uint32_t n);
+template <class T> void launch_add(const Buffers<T>& b, int pos_cur, int ids_cur, uint32_t n0, uint32_t m, const T* pos,
+                                   const T* diam, hipStream_t s);
+// phase 0 marks the ids (rm = work[0, cap)); phase 1 renumbers and compacts
+// into the other pos/flags/force and ids copies.  work: 4 cap + gscan_tiles(cap) words.
+template <class T> void launch_remove(const Buffers<T>& b, int pos_cur, int ids_cur, uint32_t m, const int64_t* ids,
+                                      uint32_t* work, uint32_t cap, hipStream_t s, int phase);
+void launch_set_population(SimGrid* sims, uint32_t n, hipStream_t s);
 
 // ---- launchers (adjoint_kernels.hip)
 template <class T> void launch_adj_w(const Buffers<T>& b, int pos_cur, const double* lam, double* w, hipStream_t s);

@@ -225,6 +225,35 @@ def main():
                                  static_fraction_last_step=round(st["n_static"] / w.n, 4))
         log(f"skip on {extras['skip_on']}")
         del s2
+        # dynamic population (Section 3.2): 1% of the agents removed and as
+        # many added between two steps; the next grid is a full build
+        sd = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size,
+                     capacity=w.n + w.n // 50)
+        sd.step(args.warmup)
+        sd.sync()
+        gd = np.random.default_rng(8)
+        m = w.n // 100
+        rm = torch.from_numpy(gd.choice(w.n, m, replace=False)).to(dev)
+        R = float(w.diam.max())
+        side = float(w.meta["side"])
+        newp = torch.from_numpy(gd.uniform(0.0, side, size=(m, 3)).astype(w.pos.dtype)).to(dev)
+        newd = torch.from_numpy(gd.uniform(8.0, R, size=m).astype(w.diam.dtype)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sd.remove_agents(rm)
+        t1 = time.perf_counter()
+        sd.add_agents(newp, newd)
+        t2 = time.perf_counter()
+        el_full, _ = timed_steps(sd, 1)
+        el_upd, _ = timed_steps(sd, 1)
+        extras["dynamic"] = dict(removed=m, added=m, remove_ms=round(1e3 * (t1 - t0), 3),
+                                 add_ms=round(1e3 * (t2 - t1), 3),
+                                 removed_per_s=m / (t1 - t0), added_per_s=m / (t2 - t1),
+                                 next_step_ms=round(1e3 * el_full, 3), following_step_ms=round(1e3 * el_upd, 3),
+                                 note="calls include their stream synchronisations; the next step's grid is a "
+                                      "full build, the following one an update")
+        log(f"dynamic {extras['dynamic']}")
+        del sd, rm, newp, newd
         del pos, diam
         torch.cuda.empty_cache()
         # batched: 512 simulations, 50 steps in one graph launch, with the

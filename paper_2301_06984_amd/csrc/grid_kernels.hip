@@ -444,8 +444,9 @@ __device__ __forceinline__ uint32_t wave_run_add(uint32_t* arr, bool act, uint32
 // Full build: key of every agent and its arrival index in its super-box
 // (histogram atomics).  Update build (the last grid's extent, agents stored in
 // its canonical order): only agents that left their box get a new key; each
-// moves one count from its old to its new super-box, marks both as changed
-// (the epoch of this build) and is listed as a mover in its block's segment.
+// that enters another super-box moves one count from its old to its new
+// super-box and marks both as changed (the epoch of this build).  All are
+// listed in their block's segment, sub[i] noting the ones that moved on.
 // A block covers kKeysPer runs of kKeysThreads consecutive agents; in an
 // update build a thread requests the flags of its kKeysPer agents together.
 constexpr int kKeysThreads = 256;
@@ -454,6 +455,7 @@ constexpr uint32_t kKeysSpan = kKeysThreads * kKeysPer;
 template <class T>
 __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur) {
     __shared__ uint32_t s_movers;
+    __shared__ uint32_t s_list[kKeysSpan];
     const uint32_t i0 = blockIdx.x * kKeysSpan + threadIdx.x;
     if (!b.g->inc) {
 #pragma unroll
@@ -484,34 +486,34 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur) {
         const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
         f[k] = i < b.n ? b.flags[cur][i] : 0u;
     }
+    // the block's agents that left their box, gathered in LDS, then taken
+    // one per thread, so that their dependent loads overlap
     if (threadIdx.x == 0) s_movers = 0u;
     __syncthreads();
-    for (int k = 0; k < kKeysPer; ++k) {
-        if (!(f[k] & kBoxChangedBit)) continue;
-        const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
-        const SimGrid& G = b.sims[sim_index(b, i)];
-        if (!G.valid) continue;
-        const uint32_t old = b.skey[cur][i];
-        uint32_t key = 0;
-        if ((old >> 3) >= b.g->total_super) {
-            raise_error(b.g, kErrInternal);
-        } else if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
-            b.key[i] = key;   // read by the scatter for every agent that left its box
-            if (key != old) {
-                const uint32_t ep = b.g->epoch;
-                atomicAdd(&b.count[old >> 3], 0xFFFFFFFFu);
-                atomicAdd(&b.count[key >> 3], 1u);
-                b.dirty[old >> 3] = ep;
-                b.dirty[key >> 3] = ep;
-                b.movers[blockIdx.x * kKeysSpan + atomicAdd(&s_movers, 1u)] = i;   // LDS atomic
-            }
-        } else {
-            raise_error(b.g, kErrInternal);
-            b.key[i] = old;
-        }
-    }
+    for (int k = 0; k < kKeysPer; ++k)
+        if (f[k] & kBoxChangedBit) s_list[atomicAdd(&s_movers, 1u)] = i0 + uint32_t(k) * kKeysThreads;
     __syncthreads();
-    if (threadIdx.x == 0) b.mcount[blockIdx.x] = s_movers;
+    const uint32_t nl = s_movers, ep = b.g->epoch, total = b.g->total_super;
+    for (uint32_t j = threadIdx.x; j < nl; j += kKeysThreads) {
+        const uint32_t i = s_list[j];
+        const SimGrid& G = b.sims[sim_index(b, i)];
+        const uint32_t old = b.skey[cur][i];
+        uint32_t key = old, real = 0;
+        if (!G.valid || (old >> 3) >= total || !super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
+            raise_error(b.g, kErrInternal);
+            key = old;
+        } else if (key != old) {
+            real = 1;
+            atomicAdd(&b.count[old >> 3], 0xFFFFFFFFu);
+            atomicAdd(&b.count[key >> 3], 1u);
+            b.dirty[old >> 3] = ep;
+            b.dirty[key >> 3] = ep;
+        }
+        b.key[i] = key;   // read by the scatter for every agent that left its box
+        b.sub[i] = real;  // ... and whether it entered another super-box
+        b.movers[blockIdx.x * kKeysSpan + j] = i;
+    }
+    if (threadIdx.x == 0) b.mcount[blockIdx.x] = nl;
 }
 
 // ------------------------------------------------------------------ scan
@@ -807,16 +809,19 @@ __global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
             b.skey[cur][u] = kDeadKey;   // the agent's loose slot is in the append region now
         }
     }
-    // ... and the movers, from the segments of the keys kernel's blocks
+    // ... and the agents that entered another super-box, from the segments
+    // of the keys kernel's blocks, one wave per segment
     const uint32_t kblocks = (b.n + kKeysSpan - 1) / kKeysSpan;
-    for (uint32_t kb = blockIdx.x; kb < kblocks; kb += gridDim.x) {
-        const uint32_t mc = b.mcount[kb];
-        for (uint32_t m = threadIdx.x; m < mc; m += blockDim.x) {
+    const uint32_t waves = stride >> 6;
+    for (uint32_t kb = tid >> 6; kb < kblocks; kb += waves) {
+        const uint32_t mc = min(b.mcount[kb], kKeysSpan);
+        for (uint32_t m = uint32_t(lane_id()); m < mc; m += 64u) {
             const uint32_t i = b.movers[kb * kKeysSpan + m];
             if (i >= b.n) {
                 raise_error(b.g, kErrInternal);
                 continue;
             }
+            if (!b.sub[i]) continue;
             const uint32_t key = b.key[i], sk = key >> 3;
             if (sk >= b.g->total_super) {
                 raise_error(b.g, kErrInternal);

@@ -112,7 +112,6 @@ struct Globals {
     uint32_t err;
     uint32_t total_super;    // super-boxes of all simulations in this step's grid
     uint32_t stamp;          // of the current super-box table entries (1..32767)
-    uint32_t tiles_dirty;    // some simulation's super grid changed: rebuild the tile table
     uint32_t inc;            // this step's grid is an update of the last one (see launch_grid)
     uint32_t epoch;          // counts grid builds (marks this step's changed super-boxes; never 0)
     uint32_t ndirty;         // changed super-boxes of an update build (dirty_list, from the scan)

@@ -235,11 +235,10 @@ void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s) {
 constexpr int kSetupThreads = 1024;
 constexpr uint32_t kFixupLanes = 8;   // threads per changed super-box in an update build
 constexpr int kTileLevels = 3;    // tiles of 8 x 8 x 8 super-boxes
-constexpr int kTileBlocks = 256;  // grid of the tile-table kernel (it loops)
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int32_t* rep, int nsims,
                                                            int parity, uint32_t super_capacity, int allow_inc,
-                                                           uint32_t n) {
+                                                           uint32_t n, uint32_t* __restrict__ tile_off) {
     __shared__ unsigned long long s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
     __shared__ uint32_t s_dirty, s_same;
@@ -348,7 +347,6 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
             for (int s = 0; s < nsims; ++s) sims[s].valid = 0;
         }
         g->total_super = uint32_t(total);
-        g->tiles_dirty = s_dirty;
         // an update of the last grid needs the same boxes (extent) and agents
         // stored in that grid's canonical order (the caller's allow_inc)
         g->inc = (allow_inc && s_same && total > 0) ? 1u : 0u;
@@ -360,43 +358,27 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
         // keeps the entries of the super-boxes it does not rebuild
         if (!g->inc) g->stamp = g->stamp + 1;
     }
-}
-
-// Rank of the first super-box of every tile, rebuilt when a super grid
-// changed.  Tile t of a simulation (row-major over its tile grid) is stored
-// at the simulation's super-box base + t (tiles are never more than
-// super-boxes).
-__global__ __launch_bounds__(256) void k_tiles(const Globals* g, const SimGrid* __restrict__ sims, int nsims,
-                                               uint32_t* __restrict__ tile_off) {
-    if (!g->tiles_dirty) return;
-    const uint32_t total = g->total_super;
-    for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += gridDim.x * blockDim.x) {
-        // the simulation owning global super-box index gi: the last one whose
-        // base is not above gi (simulations without super-boxes share the
-        // next one's base)
-        int lo = 0, hi = nsims - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sims[mid].sbase <= gi)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const SimGrid& G = sims[lo];
+    // Rank of the first super-box of every tile, rebuilt when a super grid
+    // changed.  Tile t of a simulation (row-major over its tile grid) is
+    // stored at the simulation's super-box base + t (tiles are never more
+    // than super-boxes).
+    __syncthreads();
+    if (!s_dirty) return;
+    for (int s = 0; s < nsims; ++s) {
+        const SimGrid& G = sims[s];
         if (!G.valid) continue;
-        const uint32_t t = gi - G.sbase;
-        if (t >= G.ntiles) continue;
-        const uint32_t tx = t % G.tdims[0], ty = (t / G.tdims[0]) % G.tdims[1], tz = t / (G.tdims[0] * G.tdims[1]);
-        tile_off[gi] = gapfree_rank(tx << G.tlev, ty << G.tlev, tz << G.tlev, G.sdims[0], G.sdims[1], G.sdims[2],
-                                    G.slevels);
+        for (uint32_t t = threadIdx.x; t < G.ntiles; t += kSetupThreads) {
+            const uint32_t tx = t % G.tdims[0], ty = (t / G.tdims[0]) % G.tdims[1], tz = t / (G.tdims[0] * G.tdims[1]);
+            tile_off[G.sbase + t] = gapfree_rank(tx << G.tlev, ty << G.tlev, tz << G.tlev, G.sdims[0], G.sdims[1],
+                                                 G.sdims[2], G.slevels);
+        }
     }
 }
 
 template <class T>
 void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, b.g, b.sims, b.bbox_rep, b.nsims, parity,
-                       b.super_capacity, allow_inc ? 1 : 0, b.n);
-    hipLaunchKernelGGL(k_tiles, dim3(kTileBlocks), dim3(256), 0, s, b.g, b.sims, b.nsims, b.tile_off);
+                       b.super_capacity, allow_inc ? 1 : 0, b.n, b.tile_off);
 }
 
 // ------------------------------------------------------------------ keys

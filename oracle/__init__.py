@@ -233,6 +233,37 @@ def add_agents(state: State, pos, diam) -> State:
                  np.concatenate([state.force, np.zeros((m, 3), np.float64)]), state.t)
 
 
+def set_diameters(state: State, ids, diam, radius: float = None) -> State:
+    """Give the agents ``ids`` (distinct indices below n) the diameters
+    ``diam`` between steps: growth, shrinking, or the mother's half of a
+    division.  Condition (ii) of Section 5 forbids a static agent whose own
+    or a neighbour's attributes changed in a way that could raise a pair
+    force.  Under f = k*delta - gamma*sqrt(rho*delta) a smaller diameter can
+    raise it too (a smaller overlap deepens the attraction), so every agent
+    whose diameter changed counts as moved in the last step, which unsets
+    it and each agent within R of it.  With ``radius`` given, a diameter
+    above it is refused (it would let contacts escape the neighbour
+    search).  Returns the new state."""
+    ids = np.asarray(ids, dtype=np.int64).reshape(-1)
+    n = state.pos.shape[0]
+    m = ids.size
+    new = np.asarray(diam, dtype=state.diam.dtype).reshape(-1)
+    if new.size != m:
+        raise ValueError("one diameter per id")
+    if m and (ids.min() < 0 or ids.max() >= n or np.unique(ids).size != m):
+        raise ValueError("ids must be distinct and below n")
+    if m and not (np.all(np.isfinite(new)) and np.all(new > 0)):
+        raise ValueError("diameters must be finite and positive")
+    if m and radius is not None and np.any(new.astype(np.float64) > radius):
+        raise ValueError("diameter above the interaction radius")
+    d = state.diam.copy()
+    moved = state.moved.copy()
+    changed = d[ids] != new
+    d[ids] = new
+    moved[ids[changed]] = 1
+    return State(state.pos.copy(), d, moved, state.nnz.copy(), state.force.copy(), state.t)
+
+
 def step(state: State, params: Params, want_static: bool = False, want_disp: bool = False):
     """Advance ``state`` by one step in place; returns (static, disp) if asked."""
     n = state.pos.shape[0]

@@ -125,8 +125,9 @@ enum abm_field {
     ABM_FIELD_STORAGE_IDS = 9, /* n uint32: agent id held by each storage slot */
     ABM_FIELD_NEIGHBOR_COUNT = 10, /* n uint32, by agent id: |N(i)| = #{j != i : |x_i - x_j|^2 < R^2} on the
                                       positions of the last grid (Section 3.1's neighbourhood) */
-    ABM_FIELD_NEIGHBORS = 11   /* n x K uint32, by agent id, K = dst_bytes / (4 n): the ids of N(i) in
+    ABM_FIELD_NEIGHBORS = 11,  /* n x K uint32, by agent id, K = dst_bytes / (4 n): the ids of N(i) in
                                   ascending order, padded with 0xFFFFFFFF; ABM_E_INVAL if some |N(i)| > K */
+    ABM_FIELD_DIAMETERS = 12   /* n element type, by agent id */
 };
 
 /* Version of this ABI (ABM_ABI_VERSION). */
@@ -219,6 +220,24 @@ int abm_add_agents(abm_ctx* ctx, int64_t m, const void* pos, const void* diam);
  * is removed then), ABM_E_UNSUPPORTED (batched context).
  */
 int abm_remove_agents(abm_ctx* ctx, int64_t m, const int64_t* ids);
+
+/*
+ * Give the m agents with the given ids (device, m distinct int64 ids below n)
+ * the diameters diam (device, m values of the context's element type) between
+ * steps: growth, shrinking, or the mother's half of a division (whose
+ * daughter abm_add_agents appends).  Condition (ii) of Section 5: an agent
+ * whose diameter changed counts as moved in the last step, so neither it nor
+ * an agent within R of it is static in the next step; under this force law a
+ * smaller diameter can raise a pair force as well as a larger one.  An
+ * unchanged value changes nothing.  Positions and boxes stay, so the last
+ * grid and a captured graph remain valid; a recorded forward run does not.
+ * Works for batched contexts (ids are global agent indices).  The call reads
+ * its inputs and synchronizes the context's stream before it returns.
+ * Errors (nothing changes then): ABM_E_INVAL (an id out of range or given
+ * twice, or a diameter above the interaction radius of its simulation),
+ * ABM_E_NONFINITE (a diameter not finite and > 0).
+ */
+int abm_set_diameters(abm_ctx* ctx, int64_t m, const int64_t* ids, const void* diam);
 
 /* Agents now and the context's capacity (host outputs; either may be null). */
 int abm_population(abm_ctx* ctx, int64_t* n, int64_t* capacity);

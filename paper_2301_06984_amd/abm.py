@@ -20,7 +20,7 @@ ABM_OK, ABM_E_INVAL, ABM_E_NONFINITE, ABM_E_GRID, ABM_E_WORKSPACE, ABM_E_HIP, AB
     0, -1, -2, -3, -4, -5, -6, -7
 ABM_F32, ABM_F64 = 0, 1
 FIELD = dict(positions=0, forces=1, moved=2, static=3, nnz=4, key=5, perm=6, cell_start=7, extent=8,
-             storage_ids=9, neighbor_count=10, neighbors=11)
+             storage_ids=9, neighbor_count=10, neighbors=11, diameters=12)
 EXTENT_SCRATCH_BYTES = 1024
 
 # every symbol include/abm.h declares
@@ -29,7 +29,7 @@ EXPORTS = ["abm_abi_version", "abm_default_params", "abm_last_error", "abm_exten
            "abm_get_stats", "abm_state_bytes", "abm_export_state", "abm_import_state", "abm_graph_capture",
            "abm_graph_launch", "abm_record_bytes", "abm_forward_record", "abm_backward", "abm_set_timing",
            "abm_get_timing", "abm_destroy", "abm_workspace_bytes_capacity", "abm_init_capacity", "abm_add_agents",
-           "abm_remove_agents", "abm_population"]
+           "abm_remove_agents", "abm_set_diameters", "abm_population"]
 TIMED_PHASES = ["setup", "keys", "scan", "scatter", "fixup", "force"]
 
 
@@ -99,6 +99,7 @@ def lib():
             "abm_init_capacity": (C.c_int, [C.POINTER(P), i64, i64, P, P, C.POINTER(abm_params), i64, P, i64, P]),
             "abm_add_agents": (C.c_int, [P, i64, P, P]),
             "abm_remove_agents": (C.c_int, [P, i64, P]),
+            "abm_set_diameters": (C.c_int, [P, i64, P, P]),
             "abm_population": (C.c_int, [P, C.POINTER(i64), C.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
@@ -211,6 +212,14 @@ class Sim:
         _check(lib().abm_remove_agents(self.ctx, int(ids.numel()), _ptr(ids)), "abm_remove_agents")
         self.n = self.population()[0]
 
+    def set_diameters(self, ids: torch.Tensor, diam: torch.Tensor):
+        """New diameters for agents by id; a changed agent counts as moved (see abm_set_diameters)."""
+        ids = ids.to(dtype=torch.int64).contiguous()
+        diam = diam.to(dtype=_dtype_of(self.params)).contiguous()
+        if not ids.is_cuda or not diam.is_cuda or ids.numel() != diam.numel():
+            raise TypeError("ids and diam must be CUDA tensors of one value per id")
+        _check(lib().abm_set_diameters(self.ctx, int(ids.numel()), _ptr(ids), _ptr(diam)), "abm_set_diameters")
+
     def population(self):
         n, cap = C.c_int64(), C.c_int64()
         _check(lib().abm_population(self.ctx, C.byref(n), C.byref(cap)), "abm_population")
@@ -253,6 +262,8 @@ class Sim:
         n = self.n
         if field == "positions":
             out = torch.empty((n, 3), dtype=_dtype_of(self.params), device=dev)
+        elif field == "diameters":
+            out = torch.empty(n, dtype=_dtype_of(self.params), device=dev)
         elif field == "forces":
             out = torch.empty((n, 3), dtype=torch.float64, device=dev)
         elif field in ("moved", "static"):

@@ -483,6 +483,7 @@ int query_impl(abm_ctx* c, int32_t field, void* dst, int64_t dst_bytes, int32_t 
     int ids_buf = c->ids_cur;
     switch (field) {
         case ABM_FIELD_POSITIONS: need = 3 * n * int64_t(sizeof(T)); break;
+        case ABM_FIELD_DIAMETERS: need = n * int64_t(sizeof(T)); break;
         case ABM_FIELD_FORCES:
             if (!c->params.keep_forces) return fail(ABM_E_UNSUPPORTED, "forces are kept only with keep_forces");
             need = 24 * n;
@@ -899,6 +900,27 @@ int remove_impl(abm_ctx* c, int64_t m, const int64_t* ids) {
     return population_changed<T>(c, c->n - m);
 }
 
+template <class T>
+int diameters_impl(abm_ctx* c, int64_t m, const int64_t* ids, const void* diam) {
+    if (m < 0 || m > c->n || (m > 0 && (!ids || !diam))) return fail(ABM_E_INVAL, "bad arguments");
+    if (m == 0) return ABM_OK;
+    if (const int rc = read_error(c, true)) return rc;
+    Buffers<T>& b = c->buf<T>();
+    uint32_t* mk = reinterpret_cast<uint32_t*>(c->ws + c->L.stage);
+    const T* d = static_cast<const T*>(diam);
+    launch_set_diameters<T>(b, c->pos_cur, c->ids_cur, uint32_t(m), ids, d, mk, c->stream, 0);
+    HIP_TRY(hipGetLastError());
+    // bad ids or diameters are reported before anything changes
+    if (const int rc = read_error(c, true)) return rc;
+    launch_set_diameters<T>(b, c->pos_cur, c->ids_cur, uint32_t(m), ids, d, mk, c->stream, 1);
+    HIP_TRY(hipGetLastError());
+    // positions, boxes and the population are as they were, so the last grid,
+    // the next step's update build and a captured graph still apply; a
+    // recorded forward run used the old diameters
+    c->recorded = false;
+    return read_error(c, true);
+}
+
 }  // namespace
 
 // ======================================================================= C ABI
@@ -993,6 +1015,11 @@ int abm_add_agents(abm_ctx* c, int64_t m, const void* pos, const void* diam) {
 int abm_remove_agents(abm_ctx* c, int64_t m, const int64_t* ids) {
     if (int rc = check_ctx(c)) return rc;
     return c->precision == ABM_F64 ? remove_impl<double>(c, m, ids) : remove_impl<float>(c, m, ids);
+}
+
+int abm_set_diameters(abm_ctx* c, int64_t m, const int64_t* ids, const void* diam) {
+    if (int rc = check_ctx(c)) return rc;
+    return c->precision == ABM_F64 ? diameters_impl<double>(c, m, ids, diam) : diameters_impl<float>(c, m, ids, diam);
 }
 
 int abm_population(abm_ctx* c, int64_t* n, int64_t* capacity) {

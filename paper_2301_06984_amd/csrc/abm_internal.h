@@ -227,6 +227,10 @@ template <class T> void launch_add(const Buffers<T>& b, int pos_cur, int ids_cur
 template <class T> void launch_remove(const Buffers<T>& b, int pos_cur, int ids_cur, uint32_t m, const int64_t* ids,
                                       uint32_t* work, uint32_t cap, hipStream_t s, int phase);
 void launch_set_population(SimGrid* sims, uint32_t n, hipStream_t s);
+// phase 0 marks the ids (mk = n words) and checks ids and diameters; phase 1
+// writes the diameters that changed and marks their agents as moved.
+template <class T> void launch_set_diameters(const Buffers<T>& b, int pos_cur, int ids_cur, uint32_t m,
+                                             const int64_t* ids, const T* diam, uint32_t* mk, hipStream_t s, int phase);
 
 // ---- launchers (adjoint_kernels.hip)
 template <class T> void launch_adj_w(const Buffers<T>& b, int pos_cur, const double* lam, double* w, hipStream_t s);

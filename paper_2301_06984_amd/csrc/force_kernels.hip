@@ -411,6 +411,7 @@ __global__ void k_unpack_field(Buffers<T> b, int cur, int ids_cur, int field, vo
         case 2: static_cast<uint8_t*>(out)[id] = uint8_t(f & kMovedBit); break;
         case 3: static_cast<uint8_t*>(out)[id] = uint8_t((f & kStaticBit) ? 1 : 0); break;
         case 4: static_cast<int32_t*>(out)[id] = int32_t(f >> kNnzShift); break;
+        case 12: static_cast<T*>(out)[id] = T(fabs(double(pos4_ptr(b, cur)[i].w))); break;
         default: break;
     }
 }

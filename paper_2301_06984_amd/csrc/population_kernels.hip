@@ -1,6 +1,6 @@
 // population_kernels.hip -- adding and removing agents between steps
-// (Section 3.2), and a device-wide exclusive scan of 32-bit counts that the
-// removal uses.
+// (Section 3.2), changing their diameters, and a device-wide exclusive scan
+// of 32-bit counts that the removal uses.
 //
 // Agent ids are the agents' indices in the population, 0..n-1.  Addition
 // appends: the new agents take ids n, n+1, ... and the storage slots after
@@ -233,6 +233,78 @@ void launch_remove(const Buffers<T>& b, int pos_cur, int ids_cur, uint32_t m, co
     hipLaunchKernelGGL(k_compact<T>, g, bl, 0, s, b, pos_cur, ids_cur, new_size, rm, pf, holes, kp);
 }
 
+// ------------------------------------------------------------------ diameters
+// New diameters between steps (growth, shrinking, the mother's half of a
+// division).  The grid stays valid: boxes depend on positions only, and a
+// diameter may not exceed the interaction radius, which is also the box edge.
+
+// mk[id] = j + 1 for the j-th (id, diameter) pair; an id out of range or
+// given twice is a range error, a diameter that is not finite and positive a
+// non-finite one.
+template <class T>
+__global__ void k_mark_diameters(const int64_t* __restrict__ ids, const T* __restrict__ diam, uint32_t m, uint32_t n,
+                                 uint32_t* __restrict__ mk, Globals* g) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const double d = double(diam[j]);
+    if (!(d > 0.0) || !isfinite(d)) raise_error(g, kErrNonfinite);
+    const int64_t id = ids[j];
+    if (id < 0 || id >= int64_t(n)) {
+        raise_error(g, kErrRange);
+        return;
+    }
+    if (atomicExch(&mk[id], j + 1u) != 0u) raise_error(g, kErrRange);
+}
+
+// One thread per storage slot; the agent there, if listed, takes its new
+// diameter.  Without apply the diameter is only checked against the
+// interaction radius of the agent's simulation.  With apply it is written,
+// and an agent whose diameter changed counts as moved in the last step, in
+// its flags and in the sign of its stored diameter: then neither it nor an
+// agent within R of it is static in the next step (condition (ii) of
+// Section 5; a smaller diameter can raise a pair force too, by deepening the
+// attraction).
+template <class T>
+__global__ void k_set_diameters(Buffers<T> b, int cur, int ids_cur, const T* __restrict__ diam,
+                                const uint32_t* __restrict__ mk, uint32_t m, int apply) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= b.n) return;
+    const uint32_t id = b.ids[ids_cur][s];
+    if (id >= b.n) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    const uint32_t j = mk[id];
+    if (j == 0u) return;
+    if (j > m) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    const T d = diam[j - 1u];
+    if (!apply) {
+        if (double(d) > b.sims[sim_index(b, s)].radius) raise_error(b.g, kErrRange);
+        return;
+    }
+    V4<T>* __restrict__ p = pos4_ptr(b, cur);
+    if (d == T(fabs(double(p[s].w)))) return;
+    p[s].w = -d;
+    b.flags[cur][s] |= kMovedBit;
+}
+
+template <class T>
+void launch_set_diameters(const Buffers<T>& b, int pos_cur, int ids_cur, uint32_t m, const int64_t* ids,
+                          const T* diam, uint32_t* mk, hipStream_t s, int phase) {
+    const uint32_t n = b.n;
+    const dim3 g((n + 255) / 256), bl(256);
+    if (phase == 0) {   // mark and check (the caller reads the errors before anything changes)
+        hipLaunchKernelGGL(k_fill_u32, g, bl, 0, s, mk, n, 0u);
+        hipLaunchKernelGGL(k_mark_diameters<T>, dim3((m + 255) / 256), bl, 0, s, ids, diam, m, n, mk, b.g);
+        hipLaunchKernelGGL(k_set_diameters<T>, g, bl, 0, s, b, pos_cur, ids_cur, diam, mk, m, 0);
+        return;
+    }
+    hipLaunchKernelGGL(k_set_diameters<T>, g, bl, 0, s, b, pos_cur, ids_cur, diam, mk, m, 1);
+}
+
 void launch_set_population(SimGrid* sims, uint32_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_set_population, dim3(1), dim3(1), 0, s, sims, n);
 }
@@ -241,7 +313,9 @@ void launch_set_population(SimGrid* sims, uint32_t n, hipStream_t s) {
     template void launch_add<T>(const Buffers<T>&, int, int, uint32_t, uint32_t, const T*, const T*,     \
                                 hipStream_t);                                                            \
     template void launch_remove<T>(const Buffers<T>&, int, int, uint32_t, const int64_t*, uint32_t*,       \
-                                   uint32_t, hipStream_t, int);
+                                   uint32_t, hipStream_t, int);                                         \
+    template void launch_set_diameters<T>(const Buffers<T>&, int, int, uint32_t, const int64_t*, const T*, \
+                                          uint32_t*, hipStream_t, int);
 
 ABM_INSTANTIATE(float)
 ABM_INSTANTIATE(double)

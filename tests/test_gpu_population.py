@@ -145,3 +145,114 @@ def test_population_invalidates_graph_and_batched_is_unsupported():
     with pytest.raises(abm.ABMError) as e:
         b.remove_agents(torch.tensor([0], device="cuda"))
     assert e.value.code == abm.ABM_E_UNSUPPORTED
+
+
+def pick_diameters(g, diam, ids, R):
+    """Half grow (up to R), half shrink, a few keep their value."""
+    d = diam[ids].astype(np.float64)
+    new = np.where(np.arange(ids.size) % 2 == 0, np.minimum(R, d + g.uniform(0.2, 2.0, ids.size)),
+                   d - g.uniform(0.3, 2.0, ids.size))
+    new[::17] = d[::17]
+    return new.astype(diam.dtype)
+
+
+@pytest.mark.parametrize("precision,detect_static", [("f64", False), ("f32", True), ("f32", False)])
+def test_set_diameters_match_oracle(precision, detect_static):
+    w = workloads.c2(n=6000, seed=99) if precision == "f32" else workloads.c1(n=4000, seed=98)
+    pos, diam = w.pos, w.diam.copy()
+    R = float(diam.max())
+    note(f"diameters {precision} static={detect_static} n={pos.shape[0]}")
+    sim = make_sim(pos, diam, detect_static=detect_static, interaction_radius=R)
+    p = oracle.Params(detect_static=detect_static, interaction_radius=R)
+    g = np.random.default_rng(11)
+    for _ in range(3):
+        step_and_compare(sim, diam, p, detect_static)
+    n = pos.shape[0]
+    ids = g.choice(n, 500, replace=False)
+    if detect_static:   # half of them among the agents the last step skipped
+        stat = np.nonzero(sim.query("static").cpu().numpy())[0]
+        assert stat.size > 250
+        ids = np.unique(np.concatenate([g.choice(stat, 250, replace=False), ids]))[:500]
+        g.shuffle(ids)
+    new = pick_diameters(g, diam, ids, R)
+    before = ref_state(gpu_state(sim), diam)
+    note("set 500 diameters")
+    sim.set_diameters(torch.from_numpy(ids).cuda(), to_dev(new))
+    exp = oracle.set_diameters(before, ids, new, radius=R)
+    assert_same(gpu_state(sim), exp)
+    np.testing.assert_array_equal(sim.query("diameters").cpu().numpy(), exp.diam)
+    diam = exp.diam
+    # the next grid is an update build over unchanged positions: the oracle's grid
+    before_step = step_and_compare(sim, diam, p, detect_static)
+    assert_grid_equal(sim, before_step, diam, p)
+    for _ in range(3):
+        step_and_compare(sim, diam, p, detect_static)
+
+
+def test_set_diameters_errors_leave_state():
+    w = workloads.c1(n=1000, seed=96)
+    R = float(w.diam.max())
+    sim = make_sim(w.pos, w.diam, interaction_radius=R)
+    sim.step(2)
+    sim.sync()
+    base = gpu_state(sim)
+    base_d = sim.query("diameters").cpu().numpy()
+    note("diameter errors")
+    ids = lambda v: torch.tensor(v, device="cuda")
+    cases = [
+        ("above R", ids([3, 4]), [9.0, R * 1.01], abm.ABM_E_INVAL),
+        ("repeated id", ids([3, 5, 3]), [9.0, 9.0, 9.0], abm.ABM_E_INVAL),
+        ("id range", ids([1000]), [9.0], abm.ABM_E_INVAL),
+        ("negative id", ids([-1]), [9.0], abm.ABM_E_INVAL),
+        ("zero", ids([2]), [0.0], abm.ABM_E_NONFINITE),
+        ("nan", ids([2, 6]), [9.0, float("nan")], abm.ABM_E_NONFINITE),
+    ]
+    for name, i, d, code in cases:
+        with pytest.raises(abm.ABMError) as e:
+            sim.set_diameters(i, to_dev(np.array(d, dtype=w.diam.dtype)))
+        assert e.value.code == code, name
+        after = gpu_state(sim)
+        for k in base:
+            np.testing.assert_array_equal(after[k], base[k], err_msg=name)
+        np.testing.assert_array_equal(sim.query("diameters").cpu().numpy(), base_d, err_msg=name)
+    # still steps as before the failed calls
+    ref = make_sim(w.pos, w.diam, interaction_radius=R)
+    ref.step(3)
+    sim.step(1)
+    np.testing.assert_array_equal(gpu_state(sim)["pos"], gpu_state(ref)["pos"])
+
+
+def test_set_diameters_batched_and_graph():
+    # every simulation of a batch takes the change exactly as it does alone,
+    # and a graph captured before the change replays the steps after it
+    wb = workloads.c4(nsims=5, nmin=300, nmax=1500, seed=12, steps=6)
+    off = wb.offsets
+    g = np.random.default_rng(13)
+    note(f"batched diameters {len(off) - 1} sims")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = abm.BatchedSim(to_dev(wb.pos), to_dev(wb.diam), off, common=dict(detect_static=True), stream=s)
+        b.step(2)
+        b.graph_capture(2)
+        ids, new = [], []
+        for k in range(len(off) - 1):
+            a, e = off[k], off[k + 1]
+            loc = g.choice(e - a, 40, replace=False)
+            ids.append(a + loc)
+            new.append(pick_diameters(g, wb.diam[a:e], loc, float(wb.diam[a:e].max())))
+        ids, new = np.concatenate(ids), np.concatenate(new)
+        b.set_diameters(torch.from_numpy(ids).cuda(), to_dev(new))
+        b.graph_launch()
+        b.step(1)
+        b.sync()
+    got = b.query("positions").cpu().numpy()
+    got_d = b.query("diameters").cpu().numpy()
+    for k in range(len(off) - 1):
+        a, e = off[k], off[k + 1]
+        sel = (ids >= a) & (ids < e)
+        sim = make_sim(wb.pos[a:e], wb.diam[a:e], detect_static=True)
+        sim.step(2)
+        sim.set_diameters(torch.from_numpy(ids[sel] - a).cuda(), to_dev(new[sel]))
+        sim.step(3)
+        np.testing.assert_array_equal(got[a:e], sim.query("positions").cpu().numpy(), err_msg=f"sim {k}")
+        np.testing.assert_array_equal(got_d[a:e], sim.query("diameters").cpu().numpy(), err_msg=f"sim {k}")

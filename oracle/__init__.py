@@ -22,7 +22,8 @@ _lib = None
 class _Params(C.Structure):
     _fields_ = [("k", C.c_double), ("gamma", C.c_double), ("mu", C.c_double), ("f_adh", C.c_double),
                 ("delta_max", C.c_double), ("interaction_radius", C.c_double),
-                ("cell_factor", C.c_double), ("detect_static", C.c_int32), ("nthreads", C.c_int32)]
+                ("cell_factor", C.c_double), ("detect_static", C.c_int32), ("nthreads", C.c_int32),
+                ("order", C.c_int32)]
 
 
 @dataclasses.dataclass
@@ -36,10 +37,11 @@ class Params:
     cell_factor: float = 1.0
     detect_static: bool = False
     nthreads: int = 0
+    order: int = 0           # 0: Morton order of the boxes; 1: Hilbert order of the 2x2x2 super-boxes
 
     def c(self) -> _Params:
         return _Params(self.k, self.gamma, self.mu, self.f_adh, self.delta_max, self.interaction_radius,
-                       self.cell_factor, int(bool(self.detect_static)), int(self.nthreads))
+                       self.cell_factor, int(bool(self.detect_static)), int(self.nthreads), int(self.order))
 
 
 def lib():
@@ -55,10 +57,12 @@ def lib():
         L.orc_ranks.argtypes = [C.c_int32, P, i64, P, P, i64, P, P]
         L.orc_morton.restype = C.c_uint64
         L.orc_morton.argtypes = [C.c_int32, P, C.c_int32]
+        L.orc_hilbert.restype = i64
+        L.orc_hilbert.argtypes = [i64, P, C.c_int32, P]
         for suf in ("f64", "f32"):
             g = getattr(L, f"orc_grid_{suf}")
             g.restype = i64
-            g.argtypes = [i64, P, C.c_double, P, P, P, P, P, i64]
+            g.argtypes = [i64, P, C.c_double, P, P, P, P, P, i64, C.c_int32]
             nb = getattr(L, f"orc_neighbors_{suf}")
             nb.restype = i64
             nb.argtypes = [i64, P, C.c_double, C.c_double, P, P, i64]
@@ -138,8 +142,19 @@ def inv_cell(diam, params: Params) -> float:
     return 1.0 / (R * max(params.cell_factor, 1.0))
 
 
-def grid(pos, inv_h: float):
-    """Box keys, canonical order and box starts of the uniform grid."""
+def hilbert(q, b: int):
+    """Hilbert index (Skilling's transform) of points q (n x 3) below 2^b."""
+    qq = np.ascontiguousarray(q, dtype=np.int64).reshape(-1, 3)
+    out = np.zeros(qq.shape[0], np.uint64)
+    if lib().orc_hilbert(qq.shape[0], _ptr(qq), int(b), _ptr(out)) != 0:
+        raise ValueError("orc_hilbert failed")
+    return out
+
+
+def grid(pos, inv_h: float, order: int = 0):
+    """Box keys, canonical order and box starts of the uniform grid (order 0:
+    Morton order of the boxes; 1: Hilbert order of the 2x2x2 super-boxes,
+    Morton order inside each)."""
     pos = np.ascontiguousarray(pos)
     n = pos.shape[0]
     cmin = np.zeros(3, np.int64)
@@ -147,11 +162,11 @@ def grid(pos, inv_h: float):
     key = np.zeros(n, np.uint32)
     perm = np.zeros(n, np.uint32)
     fn = getattr(lib(), f"orc_grid_{_suffix(pos)}")
-    nb = fn(n, _ptr(pos), float(inv_h), _ptr(cmin), _ptr(dims), _ptr(key), _ptr(perm), None, 0)
+    nb = fn(n, _ptr(pos), float(inv_h), _ptr(cmin), _ptr(dims), _ptr(key), _ptr(perm), None, 0, int(order))
     if nb < 0:
         raise ValueError(f"orc_grid failed ({nb})")
     cs = np.zeros(nb + 1, np.uint32)
-    nb2 = fn(n, _ptr(pos), float(inv_h), _ptr(cmin), _ptr(dims), None, None, _ptr(cs), nb + 1)
+    nb2 = fn(n, _ptr(pos), float(inv_h), _ptr(cmin), _ptr(dims), None, None, _ptr(cs), nb + 1, int(order))
     assert nb2 == nb
     return dict(cmin=cmin, dims=dims, key=key, perm=perm, cell_start=cs, nboxes=int(nb))
 

@@ -14,6 +14,9 @@
 //    depth-first walk of the implicit 2^D-ary tree over the power-of-two cube
 //    produces a sorted table of (box counter, offset) entries; Morton code =
 //    rank + offset of the entry that covers the rank.
+//  * A variant order (Section 4.2 compares Morton order with the Hilbert
+//    curve): the 2x2x2 blocks of boxes follow a Hilbert curve (Skilling's
+//    transform), the boxes inside a block Morton order; ranks by brute force.
 //  * Static agents (Section 5): the force of an agent is skipped when it and
 //    none of its neighbours moved in the last iteration and at most one
 //    neighbour force was non-zero.
@@ -62,6 +65,7 @@ struct orc_params {
     double cell_factor;         // box edge = cell_factor * interaction radius (>= 1)
     int32_t detect_static;      // skip the force of static agents
     int32_t nthreads;           // OpenMP threads, 0 = runtime default
+    int32_t order;              // 0: Morton order of the boxes; 1: Hilbert order of the 2x2x2 blocks
 };
 
 }  // extern "C"
@@ -169,6 +173,75 @@ uint64_t code_of_rank(const GapTable& t, int64_t r) {
     return uint64_t(r + t.offset[lo]);
 }
 
+// ---- Section 4.2 names the Hilbert curve as the other space-filling curve
+// it compared with Morton order.  The variant here orders the aligned 2x2x2
+// blocks of boxes ("super-boxes") along a Hilbert curve and keeps Morton
+// order among the 8 boxes of a block.
+//
+// Hilbert index of a lattice point with coordinates below 2^b, by Skilling's
+// transform (J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc.
+// 707, 2004): from the top bit level down, the lower bits of the first
+// coordinate are inverted or exchanged with those of each coordinate in turn
+// (undoing the rotations of the recursive construction), then the
+// coordinates are Gray-encoded into the "transposed" index.  The index reads
+// its bits level by level from the top, the first coordinate's bit first.
+uint64_t hilbert_index(const int64_t* q, int b) {
+    if (b <= 0) return 0;
+    uint64_t X[3] = {uint64_t(q[0]), uint64_t(q[1]), uint64_t(q[2])};
+    const uint64_t M = uint64_t(1) << (b - 1);
+    for (uint64_t Q = M; Q > 1; Q >>= 1) {
+        const uint64_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint64_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint64_t t = 0;
+    for (uint64_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    uint64_t h = 0;
+    for (int lev = b - 1; lev >= 0; --lev)
+        for (int i = 0; i < 3; ++i) h = (h << 1) | ((X[i] >> lev) & 1);
+    return h;
+}
+
+// Rank of every box (indexed x fastest) in the Hilbert variant, by brute
+// force: the super-boxes that meet the space sorted by Hilbert index over the
+// smallest power-of-two cube that holds them, then the boxes inside the
+// space of each super-box in Morton order (x lowest), counted consecutively.
+std::vector<uint32_t> hilbert_box_ranks(const int64_t* dims) {
+    int64_t sd[3];
+    for (int a = 0; a < 3; ++a) sd[a] = (dims[a] + 1) / 2;
+    const int L = levels_for(sd, 3);
+    std::vector<std::pair<uint64_t, int64_t>> order;
+    order.reserve(size_t(sd[0] * sd[1] * sd[2]));
+    for (int64_t z = 0; z < sd[2]; ++z)
+        for (int64_t y = 0; y < sd[1]; ++y)
+            for (int64_t x = 0; x < sd[0]; ++x) {
+                const int64_t S[3] = {x, y, z};
+                order.push_back({hilbert_index(S, L), (z * sd[1] + y) * sd[0] + x});
+            }
+    std::sort(order.begin(), order.end());
+    std::vector<uint32_t> rank(size_t(dims[0] * dims[1] * dims[2]), 0xFFFFFFFFu);
+    uint32_t r = 0;
+    for (const auto& e : order) {
+        const int64_t S[3] = {e.second % sd[0], (e.second / sd[0]) % sd[1], e.second / (sd[0] * sd[1])};
+        for (int c = 0; c < 8; ++c) {
+            const int64_t q[3] = {2 * S[0] + (c & 1), 2 * S[1] + ((c >> 1) & 1), 2 * S[2] + ((c >> 2) & 1)};
+            if (q[0] < dims[0] && q[1] < dims[1] && q[2] < dims[2]) rank[size_t((q[2] * dims[1] + q[1]) * dims[0] + q[0])] = r++;
+        }
+    }
+    return rank;
+}
+
 // ---- Section 3.1: the uniform grid.
 template <class T>
 struct Grid {
@@ -177,16 +250,21 @@ struct Grid {
     int64_t cmin[3] = {0, 0, 0}, dims[3] = {1, 1, 1};
     int64_t nboxes = 0;
     GapTable table;
+    int order = 0;                      // 0: Morton; 1: Hilbert order of the super-boxes
+    std::vector<uint32_t> hrank;        // order 1: rank of every box (x fastest)
     std::vector<int64_t> cell;          // per agent: 3 box coordinates relative to cmin
-    std::vector<uint32_t> key;          // per agent: gap-free Morton rank of its box
+    std::vector<uint32_t> key;          // per agent: gap-free rank of its box in the grid's order
     std::vector<uint32_t> perm;         // slot -> agent id, ordered by (key, id)
     std::vector<uint32_t> cell_start;   // nboxes + 1 (exclusive prefix sum of counts)
 
-    int64_t box_rank(const int64_t* q) const { return rank_of_code(table, morton(q, 3, table.L)); }
+    int64_t box_rank(const int64_t* q) const {
+        if (order == 1) return hrank[size_t((q[2] * dims[1] + q[1]) * dims[0] + q[0])];
+        return rank_of_code(table, morton(q, 3, table.L));
+    }
 };
 
 template <class T>
-int build_grid(Grid<T>& g, int64_t n, const T* pos, double inv_h) {
+int build_grid(Grid<T>& g, int64_t n, const T* pos, double inv_h, int order = 0) {
     g.n = n;
     g.inv_h = inv_h;
     std::vector<int64_t> c(3 * n);
@@ -208,7 +286,11 @@ int build_grid(Grid<T>& g, int64_t n, const T* pos, double inv_h) {
         g.nboxes *= g.dims[a];
     }
     if (g.nboxes > (int64_t(1) << 32) - 1) return -3;
-    g.table = build_gap_table(g.dims, 3);
+    g.order = order;
+    if (order == 1)
+        g.hrank = hilbert_box_ranks(g.dims);
+    else
+        g.table = build_gap_table(g.dims, 3);
     g.cell.resize(3 * n);
     g.key.resize(n);
     for (int64_t i = 0; i < n; ++i) {
@@ -312,7 +394,7 @@ int step_impl(int64_t n, T* pos, const T* diam, uint8_t* moved, int32_t* nnz, do
     const double inv_h = 1.0 / h;
     const double R2 = R * R;
     Grid<T> g;
-    const int rc = build_grid(g, n, pos, inv_h);
+    const int rc = build_grid(g, n, pos, inv_h, p->order);
     if (rc != 0) return rc;
 
     // Section 5: static agents, decided from the last iteration's state.
@@ -389,9 +471,9 @@ int step_impl(int64_t n, T* pos, const T* diam, uint8_t* moved, int32_t* nnz, do
 
 template <class T>
 int64_t grid_impl(int64_t n, const T* pos, double inv_h, int64_t* cmin, int64_t* dims, uint32_t* key,
-                  uint32_t* perm, uint32_t* cell_start, int64_t cell_cap) {
+                  uint32_t* perm, uint32_t* cell_start, int64_t cell_cap, int order) {
     Grid<T> g;
-    const int rc = build_grid(g, n, pos, inv_h);
+    const int rc = build_grid(g, n, pos, inv_h, order);
     if (rc != 0) return rc;
     for (int a = 0; a < 3; ++a) {
         cmin[a] = g.cmin[a];
@@ -534,7 +616,7 @@ int adjoint_impl(int64_t n, const T* pos0, const T* diam, int32_t nsteps, const 
     for (int32_t s = nsteps - 1; s >= 0; --s) {
         const T* x = xs[s].data();
         Grid<T> g;
-        const int rc = build_grid(g, n, x, inv_h);
+        const int rc = build_grid(g, n, x, inv_h, p->order);
         if (rc != 0) return rc;
         const double R2 = R * R;
         // w_i = (dDelta_i/dF_i)^T lambda_i, plus sum_j dF_i/dk, dF_i/dgamma
@@ -645,12 +727,19 @@ int64_t orc_ranks(int32_t D, const int64_t* dims, int64_t n, const int64_t* q, i
 uint64_t orc_morton(int32_t D, const int64_t* q, int32_t levels) { return morton(q, D, levels); }
 
 int64_t orc_grid_f64(int64_t n, const double* pos, double inv_h, int64_t* cmin, int64_t* dims, uint32_t* key,
-                     uint32_t* perm, uint32_t* cell_start, int64_t cell_cap) {
-    return grid_impl(n, pos, inv_h, cmin, dims, key, perm, cell_start, cell_cap);
+                     uint32_t* perm, uint32_t* cell_start, int64_t cell_cap, int32_t order) {
+    return grid_impl(n, pos, inv_h, cmin, dims, key, perm, cell_start, cell_cap, order);
 }
 int64_t orc_grid_f32(int64_t n, const float* pos, double inv_h, int64_t* cmin, int64_t* dims, uint32_t* key,
-                     uint32_t* perm, uint32_t* cell_start, int64_t cell_cap) {
-    return grid_impl(n, pos, inv_h, cmin, dims, key, perm, cell_start, cell_cap);
+                     uint32_t* perm, uint32_t* cell_start, int64_t cell_cap, int32_t order) {
+    return grid_impl(n, pos, inv_h, cmin, dims, key, perm, cell_start, cell_cap, order);
+}
+
+// Hilbert index of n points (n x 3 coordinates below 2^b).
+int64_t orc_hilbert(int64_t n, const int64_t* q, int32_t b, uint64_t* out) {
+    if (b < 0 || b > 21) return -1;
+    for (int64_t i = 0; i < n; ++i) out[i] = hilbert_index(&q[3 * i], b);
+    return 0;
 }
 
 int64_t orc_neighbors_f64(int64_t n, const double* pos, double R, double inv_h, int64_t* start, uint32_t* nbr,

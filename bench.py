@@ -215,6 +215,21 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        # Hilbert order of the super-boxes (the other curve Section 4.2
+        # compares): the same steps, only the order of the boxes changed
+        sh = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size,
+                     order="hilbert")
+        sh.step(args.warmup)
+        sh.sync()
+        elh, tmh = timed_steps(sh, args.steps, timing=True)
+        extras["hilbert"] = dict(value=w.n * args.steps / elh, unit="agent-steps/s",
+                                 ms_per_step=round(1e3 * elh / args.steps, 4),
+                                 speedup_vs_morton=round(el / elh, 3),
+                                 phase_ms={k: round(tmh[k] / tmh["steps"], 4) for k in abm.TIMED_PHASES},
+                                 note="2x2x2 super-boxes along a Hilbert curve, Morton order inside each; "
+                                      "phase_ms of the Morton run are under roofline")
+        log(f"hilbert {extras['hilbert']}")
+        del sh
         # static skip on (same workload): the shell is force-free and static
         s2 = abm.Sim(pos, diam, detect_static=True, sort_every=args.sort_every, block_size=args.block_size)
         s2.step(args.warmup)
@@ -273,14 +288,38 @@ def main():
             b.graph_launch()
             b.sync()
             elb = time.perf_counter() - t0
+            del b
+            # the same simulations without batching: one plain context each,
+            # default knobs, each replaying a graph of its own 10 steps
+            kp = 10
+            plain_sims = []
+            for k in range(len(wb.offsets) - 1):
+                a, e = int(wb.offsets[k]), int(wb.offsets[k + 1])
+                sp = abm.Sim(pb[a:e].contiguous(), db[a:e].contiguous(), stream=s)
+                sp.step(2)
+                sp.graph_capture(kp)
+                sp.graph_launch()     # warm-up replay
+                plain_sims.append(sp)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for sp in plain_sims:
+                sp.graph_launch()
+            torch.cuda.synchronize()
+            elc = (time.perf_counter() - t0) / kp
+            del plain_sims, sp
         extras["batched"] = dict(value=wb.n * wb.steps / elb, unit="agent-steps/s", nsims=len(wb.offsets) - 1,
                                  agents=int(wb.n), steps=wb.steps, launch="one hipGraph replay of 50 steps",
+                                 ms_per_step=round(1e3 * elb / wb.steps, 4),
+                                 plain_contexts_ms_per_step=round(1e3 * elc, 4),
+                                 speedup_vs_plain_contexts=round(elc / (elb / wb.steps), 3),
+                                 plain_contexts="the same simulations, one plain context each, each replaying a "
+                                                "graph of 10 steps, one after another on one stream",
                                  ratio_vs_plain=round((wb.n * wb.steps / elb) / value, 3),
                                  autotuned=tuned.params, tune_trials=len(tuned.trials),
                                  untuned_ms_per_step=round(tuned.trials[0][1], 4),
                                  tuned_ms_per_step=round(tuned.ms_per_step, 4))
         log(f"batched {extras['batched']}")
-        del b, pb, db
+        del pb, db
         torch.cuda.empty_cache()
         # adjoint: 1e5 spheres, 50 steps, checkpoint every 10, forward + backward
         wa = workloads.c5()

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define ABM_ABI_VERSION 1
+#define ABM_ABI_VERSION 2
 #define ABM_EXTENT_SCRATCH_BYTES 1024
 
 enum abm_status {
@@ -64,6 +64,13 @@ enum abm_status {
 
 enum abm_precision { ABM_F32 = 0, ABM_F64 = 1 };
 
+/* Order of the boxes in memory (Section 4.2 compares the two space-filling curves). */
+enum abm_order {
+    ABM_ORDER_MORTON = 0,   /* gap-free Morton order of the boxes */
+    ABM_ORDER_HILBERT = 1   /* the 2x2x2 blocks of boxes along a Hilbert curve (Skilling's transform, x first),
+                               over the smallest power-of-two cube holding them; Morton order inside a block */
+};
+
 typedef struct abm_params {
     double k;                  /* repulsion coefficient (default 2) */
     double gamma;              /* adhesion coefficient (default 1) */
@@ -79,6 +86,9 @@ typedef struct abm_params {
     int32_t keep_forces;       /* store F_i each step so ABM_FIELD_FORCES can be queried */
     int32_t walk_chunk;        /* candidates the neighbour walk tests together: 2 or 4; 0 = chosen at init
                                   from the agents per box (4 at one or more, else 2) */
+    int32_t order;             /* ABM_ORDER_MORTON (default) or ABM_ORDER_HILBERT; fixed at init, the same for
+                                  every simulation of a batch.  It sets the canonical order, and with it the
+                                  order in which each agent's pair terms are summed */
 } abm_params;
 
 /* Grid extent of a set of positions (Section 3.1), as abm_extent reports it. */
@@ -117,7 +127,8 @@ enum abm_field {
     ABM_FIELD_MOVED = 2,       /* n uint8, by agent id: displacement of the last step was non-zero */
     ABM_FIELD_STATIC = 3,      /* n uint8, by agent id: the force was skipped in the last step */
     ABM_FIELD_NNZ = 4,         /* n int32, by agent id: non-zero pair terms in the last force evaluation */
-    ABM_FIELD_KEY = 5,         /* n uint32, by agent id: gap-free Morton rank of the agent's box (last grid) */
+    ABM_FIELD_KEY = 5,         /* n uint32, by agent id: gap-free rank of the agent's box in the context's order
+                                  (last grid) */
     ABM_FIELD_PERM = 6,        /* n uint32: agent ids in (box rank, id) order of the last grid */
     ABM_FIELD_CELL_START = 7,  /* nboxes + 1 uint32: first slot of each box, last grid (single simulation;
                                   ABM_E_UNSUPPORTED for a batched context) */

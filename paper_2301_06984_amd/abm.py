@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libabm.so")
 ABM_OK, ABM_E_INVAL, ABM_E_NONFINITE, ABM_E_GRID, ABM_E_WORKSPACE, ABM_E_HIP, ABM_E_STATE, ABM_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
 ABM_F32, ABM_F64 = 0, 1
+ABM_ORDER_MORTON, ABM_ORDER_HILBERT = 0, 1
+ABI_VERSION = 2   # the layout of the structs below
 FIELD = dict(positions=0, forces=1, moved=2, static=3, nnz=4, key=5, perm=6, cell_start=7, extent=8,
              storage_ids=9, neighbor_count=10, neighbors=11, diameters=12)
 EXTENT_SCRATCH_BYTES = 1024
@@ -37,7 +39,8 @@ class abm_params(C.Structure):
     _fields_ = [("k", C.c_double), ("gamma", C.c_double), ("mu", C.c_double), ("f_adh", C.c_double),
                 ("delta_max", C.c_double), ("interaction_radius", C.c_double), ("cell_factor", C.c_double),
                 ("precision", C.c_int32), ("detect_static", C.c_int32), ("sort_every", C.c_int32),
-                ("block_size", C.c_int32), ("keep_forces", C.c_int32), ("walk_chunk", C.c_int32)]
+                ("block_size", C.c_int32), ("keep_forces", C.c_int32), ("walk_chunk", C.c_int32),
+                ("order", C.c_int32)]
 
 
 class abm_extent(C.Structure):
@@ -106,6 +109,8 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        if L.abm_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI {L.abm_abi_version()}, this binding {ABI_VERSION}: rebuild it")
         _lib = L
     return _lib
 
@@ -121,6 +126,8 @@ def default_params(**kw) -> abm_params:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = ABM_F64 if v in ("f64", "float64", "double") else ABM_F32
+        if k == "order" and isinstance(v, str):
+            v = {"morton": ABM_ORDER_MORTON, "hilbert": ABM_ORDER_HILBERT}[v]
         if isinstance(v, bool):
             v = int(v)
         setattr(p, k, v)

@@ -18,8 +18,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libabm.so")
-SOURCES = ["grid_kernels.hip", "force_kernels.hip", "adjoint_kernels.hip", "population_kernels.hip", "abm_api.hip"]
-HEADERS = ["abm_internal.h", "abm_device.h", "force_loop.h"]
+SOURCES = ["grid_kernels.hip", "force_kernels.hip", "adjoint_kernels.hip", "population_kernels.hip", "hilbert_order.hip",
+           "abm_api.hip"]
+HEADERS = ["abm_internal.h", "abm_device.h", "force_loop.h", "hilbert_order.h"]
 ARCH = os.environ.get("ABM_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

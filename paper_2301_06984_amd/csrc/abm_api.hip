@@ -38,8 +38,8 @@ constexpr int kTimedPhases = 6;
 
 struct Layout {
     int64_t globals, sims, sim_of, bbox_rep, pos4[2], flags[2], skey[2], ids[2], force[2], key, sub, rec, perm, movers,
-        mcount, count, cell_start[2], dirty, dirty_list, aoff, tabidx, cellinfo, tile_off, tile_sums, partials, stage,
-        total;
+        mcount, count, cell_start[2], dirty, dirty_list, aoff, tabidx, cellinfo, tile_off, hil, tile_sums, partials,
+        stage, total;
     uint32_t scan_tiles, partial_cap;
 };
 
@@ -83,6 +83,7 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.tabidx = take(4 * boxes);
     L.cellinfo = take(16 * boxes);
     L.tile_off = take(4 * boxes);
+    L.hil = take(sizeof(HilbertTables));
     L.scan_tiles = uint32_t((boxes + kScanTile - 1) / kScanTile);
     if (L.scan_tiles == 0) L.scan_tiles = 1;
     L.tile_sums = take(12 * int64_t(L.scan_tiles));
@@ -180,6 +181,7 @@ void fill_buffers(abm_ctx* c) {
     b.tabidx = reinterpret_cast<uint32_t*>(w + L.tabidx);
     b.cellinfo = reinterpret_cast<uint4*>(w + L.cellinfo);
     b.tile_off = reinterpret_cast<uint32_t*>(w + L.tile_off);
+    b.hil = c->params.order == ABM_ORDER_HILBERT ? reinterpret_cast<const HilbertTables*>(w + L.hil) : nullptr;
     b.tile_sums = reinterpret_cast<uint32_t*>(w + L.tile_sums);
     b.scan_tiles = L.scan_tiles;
     b.partials = reinterpret_cast<double*>(w + L.partials);
@@ -211,6 +213,14 @@ const uint32_t* last_grid_starts(abm_ctx* c) {
     return reinterpret_cast<const uint32_t*>(c->ws + c->L.cell_start[c->cs_cur ^ 1]);
 }
 
+// The Hilbert order's tables, built on first use and kept for the process
+// (the same for every context; null if they cannot be built).
+const HilbertTables* hilbert_tables() {
+    static HilbertTables t;
+    static const bool ok = build_hilbert_tables(&t);
+    return ok ? &t : nullptr;
+}
+
 bool valid_params(const abm_params* p, std::string* why) {
     if (!p) return *why = "params is null", false;
     if (p->precision != ABM_F32 && p->precision != ABM_F64) return *why = "precision must be ABM_F32 or ABM_F64", false;
@@ -225,6 +235,8 @@ bool valid_params(const abm_params* p, std::string* why) {
         return *why = "block_size must be 0 or a multiple of 64 in [64, 1024]", false;
     if (p->walk_chunk != 0 && p->walk_chunk != 2 && p->walk_chunk != 4)
         return *why = "walk_chunk must be 0, 2 or 4", false;
+    if (p->order != ABM_ORDER_MORTON && p->order != ABM_ORDER_HILBERT)
+        return *why = "order must be ABM_ORDER_MORTON or ABM_ORDER_HILBERT", false;
     return true;
 }
 
@@ -349,6 +361,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
         std::string why;
         if (!valid_params(&per_sim[s], &why)) return fail(ABM_E_INVAL, "simulation " + std::to_string(s) + ": " + why);
         if (offsets[s + 1] <= offsets[s]) return fail(ABM_E_INVAL, "every simulation needs at least one agent");
+        if (per_sim[s].order != per_sim[0].order) return fail(ABM_E_INVAL, "all simulations need the same order");
         if (box_capacity[s] < 1 || box_capacity[s] > 0xFFFFFFFFll)
             return fail(ABM_E_INVAL, "box capacity must be in [1, 2^32)");
         boxes += uint64_t(box_capacity[s]);
@@ -402,6 +415,12 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
         hipMemsetAsync(c->ws + L.pos4[1], 0, 4 * c->elem() * (2 * cap + kSposPad), s) != hipSuccess ||
         hipMemcpyAsync(b.sims, sims.data(), sizeof(SimGrid) * nsims, hipMemcpyHostToDevice, s) != hipSuccess)
         return bail(fail(ABM_E_HIP, "workspace initialisation failed"));
+    if (b.hil) {
+        const HilbertTables* t = hilbert_tables();
+        if (!t) return bail(fail(ABM_E_HIP, "the Hilbert curve's tables could not be built"));
+        if (hipMemcpyAsync(c->ws + L.hil, t, sizeof(HilbertTables), hipMemcpyHostToDevice, s) != hipSuccess)
+            return bail(fail(ABM_E_HIP, "Hilbert table upload failed"));
+    }
     std::vector<uint16_t> sim_of;
     if (nsims > 1) {
         sim_of.resize(n);
@@ -1048,7 +1067,8 @@ int abm_set_params(abm_ctx* c, const abm_params* p) {
     if (!valid_params(p, &why)) return fail(ABM_E_INVAL, why);
     if (p->precision != c->precision) return fail(ABM_E_INVAL, "precision cannot change");
     if (p->keep_forces && c->L.force[0] < 0) return fail(ABM_E_UNSUPPORTED, "workspace has no force buffers");
-    if (p->cell_factor != c->params.cell_factor || p->interaction_radius != c->params.interaction_radius)
+    if (p->cell_factor != c->params.cell_factor || p->interaction_radius != c->params.interaction_radius ||
+        p->order != c->params.order)
         return fail(ABM_E_UNSUPPORTED, "the grid geometry is fixed at init");
     const bool force_law_changed = p->k != c->params.k || p->gamma != c->params.gamma || p->mu != c->params.mu ||
                                    p->f_adh != c->params.f_adh || p->delta_max != c->params.delta_max;

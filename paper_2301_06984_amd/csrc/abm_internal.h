@@ -52,6 +52,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hilbert_order.h"
+
 namespace abm {
 
 constexpr uint32_t kMovedBit = 1u;
@@ -157,6 +159,7 @@ struct Buffers {
     uint32_t* tabidx;         // table index of the super-box, written with its entry
     uint4* cellinfo;
     uint32_t* tile_off;       // per tile (at the simulation's super-box base): rank of its first super-box
+    const HilbertTables* hil; // the Hilbert order's tables; null: Morton order
     uint32_t* tile_sums;      // per scan tile: agents, changed super-boxes, agents of changed super-boxes
     double* partials;         // per-block partial sums (adjoint)
     uint32_t partial_cap;

@@ -383,21 +383,30 @@ void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s
 
 // ------------------------------------------------------------------ keys
 // Key of a position: (global super-box rank << 3) | octant of its box (x bit
-// lowest).  The super-box rank, in gap-free Morton order of the super grid,
+// lowest).  In Morton order the super-box rank, gap-free over the super grid,
 // is the rank of its tile's first super-box (tile table) plus the rank inside
-// the tile.  false if the position lies outside the grid.
+// the tile; in Hilbert order it comes from the walk down the curve's octree
+// (hil: the curve's tables, an LDS copy).  false if the position lies
+// outside the grid.
 template <class T>
-__device__ __forceinline__ bool super_key(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, uint32_t* key) {
+__device__ __forceinline__ bool super_key(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, uint32_t* key,
+                                          const HilbertTables* hil) {
     uint32_t q[3];
     if (!box_of<T>(G, p, q)) return false;
-    const uint32_t tl = uint32_t(G.tlev), tm = (1u << tl) - 1u;
-    uint32_t S[3], w[3];
-    for (int a = 0; a < 3; ++a) {
-        S[a] = q[a] >> 1;
-        w[a] = min(tm + 1u, G.sdims[a] - (S[a] & ~tm));
+    uint32_t rank;
+    if (hil) {
+        rank = hilbert_rank(q[0] >> 1, q[1] >> 1, q[2] >> 1, G.sdims[0], G.sdims[1], G.sdims[2], G.slevels, 1u,
+                            hil->before, hil->next);
+    } else {
+        const uint32_t tl = uint32_t(G.tlev), tm = (1u << tl) - 1u;
+        uint32_t S[3], w[3];
+        for (int a = 0; a < 3; ++a) {
+            S[a] = q[a] >> 1;
+            w[a] = min(tm + 1u, G.sdims[a] - (S[a] & ~tm));
+        }
+        const uint32_t tile = G.sbase + ((S[2] >> tl) * G.tdims[1] + (S[1] >> tl)) * G.tdims[0] + (S[0] >> tl);
+        rank = b.tile_off[tile] + gapfree_rank(S[0] & tm, S[1] & tm, S[2] & tm, w[0], w[1], w[2], int(tl));
     }
-    const uint32_t tile = G.sbase + ((S[2] >> tl) * G.tdims[1] + (S[1] >> tl)) * G.tdims[0] + (S[0] >> tl);
-    const uint32_t rank = b.tile_off[tile] + gapfree_rank(S[0] & tm, S[1] & tm, S[2] & tm, w[0], w[1], w[2], int(tl));
     *key = ((G.sbase + rank) << 3) | (q[0] & 1u) | ((q[1] & 1u) << 1) | ((q[2] & 1u) << 2);
     return true;
 }
@@ -438,7 +447,16 @@ template <class T>
 __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur) {
     __shared__ uint32_t s_movers;
     __shared__ uint32_t s_list[kKeysSpan];
+    __shared__ __align__(16) HilbertTables s_hil;
     const uint32_t i0 = blockIdx.x * kKeysSpan + threadIdx.x;
+    const HilbertTables* hil = nullptr;
+    if (b.hil) {   // the same for the whole block
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(b.hil);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&s_hil);
+        for (uint32_t w = threadIdx.x; w < uint32_t(sizeof(HilbertTables) / 4); w += kKeysThreads) dst[w] = src[w];
+        __syncthreads();
+        hil = &s_hil;
+    }
     if (!b.g->inc) {
 #pragma unroll
         for (int k = 0; k < kKeysPer; ++k) {
@@ -448,7 +466,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur) {
             if (i < b.n) {
                 const SimGrid& G = b.sims[sim_index(b, i)];
                 if (G.valid) {
-                    if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
+                    if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key, hil)) {
                         act = true;
                     } else {   // the extent is computed from these very positions
                         raise_error(b.g, kErrInternal);
@@ -481,7 +499,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur) {
         const SimGrid& G = b.sims[sim_index(b, i)];
         const uint32_t old = b.skey[cur][i];
         uint32_t key = old, real = 0;
-        if (!G.valid || (old >> 3) >= total || !super_key<T>(b, G, pos4_ptr(b, cur)[i], &key)) {
+        if (!G.valid || (old >> 3) >= total || !super_key<T>(b, G, pos4_ptr(b, cur)[i], &key, hil)) {
             raise_error(b.g, kErrInternal);
             key = old;
         } else if (key != old) {
@@ -1004,8 +1022,10 @@ __device__ __forceinline__ bool loose_agent(const Buffers<T>& b, uint32_t u, uin
     return true;
 }
 
-// Gap-free Morton rank (plus the simulation's box base) of the box of every
-// agent of the last grid, from the positions that grid was built from, by id.
+// Gap-free rank (plus the simulation's box base) of the box of every agent of
+// the last grid, from the positions that grid was built from, by id.  In
+// Hilbert order: the boxes of the super-boxes the curve visits first, plus
+// the box's Morton rank among the in-space boxes of its own super-box.
 template <class T>
 __global__ void k_box_ranks(Buffers<T> b, int ids_cur, uint32_t* __restrict__ out) {
     const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1019,8 +1039,18 @@ __global__ void k_box_ranks(Buffers<T> b, int ids_cur, uint32_t* __restrict__ ou
     const SimGrid& G = b.sims[sim_index(b, i)];
     uint32_t rank = 0xFFFFFFFFu;
     uint32_t q[3];
-    if (G.valid && box_of<T>(G, gpos_ptr(b)[u], q))
-        rank = G.box_base + gapfree_rank(q[0], q[1], q[2], G.dims[0], G.dims[1], G.dims[2], G.levels);
+    if (G.valid && box_of<T>(G, gpos_ptr(b)[u], q)) {
+        if (b.hil) {
+            const uint32_t S[3] = {q[0] >> 1, q[1] >> 1, q[2] >> 1};
+            rank = G.box_base +
+                   hilbert_rank(S[0], S[1], S[2], G.dims[0], G.dims[1], G.dims[2], G.slevels, 2u, b.hil->before,
+                                b.hil->next) +
+                   gapfree_rank(q[0] & 1u, q[1] & 1u, q[2] & 1u, min(2u, G.dims[0] - 2u * S[0]),
+                                min(2u, G.dims[1] - 2u * S[1]), min(2u, G.dims[2] - 2u * S[2]), 1);
+        } else {
+            rank = G.box_base + gapfree_rank(q[0], q[1], q[2], G.dims[0], G.dims[1], G.dims[2], G.levels);
+        }
+    }
     out[id] = rank;
 }
 

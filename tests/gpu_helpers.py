@@ -36,7 +36,7 @@ def gpu_state(sim: abm.Sim):
 
 def assert_grid_equal(sim: abm.Sim, pos_before: np.ndarray, diam: np.ndarray, params: oracle.Params):
     """Keys, canonical order and box starts of the last GPU grid == oracle."""
-    g = oracle.grid(pos_before, oracle.inv_cell(diam, params))
+    g = oracle.grid(pos_before, oracle.inv_cell(diam, params), order=params.order)
     ext = sim.query("extent").numpy()[0]
     np.testing.assert_array_equal(ext[:3], g["cmin"])
     np.testing.assert_array_equal(ext[3:6], g["dims"])

@@ -131,3 +131,35 @@ def test_c5_adjoint_full():
     np.testing.assert_array_equal(xT.cpu().numpy(), ref["posT"].astype(np.float64))
     np.testing.assert_allclose(gp.cpu().numpy(), [ref["dL_dk"], ref["dL_dgamma"]], rtol=1e-8)
     assert np.abs(gx0.cpu().numpy() - ref["dL_dx0"]).max() <= 1e-8 * np.abs(ref["dL_dx0"]).max()
+
+
+def test_headline_1e7_hilbert_order():
+    # the headline workload in the Hilbert order: the grid of a full build and
+    # of an update build against the oracle's, sampled agents against the
+    # all-pairs definition, and the same integer outcome as the Morton order
+    # (the order changes only the summation order of the pair terms)
+    w = workloads.headline()
+    note(f"headline hilbert n={w.n}")
+    p = oracle.Params(order=1)
+    sim = make_sim(w.pos, w.diam, order="hilbert", **BENCH)
+    ref = make_sim(w.pos, w.diam, **BENCH)
+    sim.step(1)
+    ref.step(1)
+    sim.sync()
+    note("headline hilbert grid parity")
+    assert_grid_equal(sim, w.pos, w.diam, p)
+    got = sim.query("positions").cpu().numpy()
+    check_samples(w.pos, w.diam, got, 96, 3)
+    np.testing.assert_array_equal(sim.query("nnz").cpu().numpy(), ref.query("nnz").cpu().numpy())
+    np.testing.assert_array_equal(sim.query("moved").cpu().numpy(), ref.query("moved").cpu().numpy())
+    d = np.abs(got.astype(np.float64) - ref.query("positions").cpu().numpy().astype(np.float64))
+    assert np.all(d <= np.spacing(np.abs(got)).astype(np.float64))
+    del ref
+    note("headline hilbert 10 more steps, then an update build")
+    sim.step(10)
+    sim.sync()
+    x = sim.query("positions").cpu().numpy()
+    sim.step(1)
+    sim.sync()
+    assert_grid_equal(sim, x, w.diam, p)
+    check_samples(x, w.diam, sim.query("positions").cpu().numpy(), 96, 4)

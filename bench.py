@@ -37,11 +37,12 @@ FORCE_BYTES = {"f32": 4 * 4 + 4 + 3 * 4, "f64": 4 * 8 + 4 + 3 * 8}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_headline_traffic.json")
 
 
-def measured_traffic(n, prec, block_size):
+def measured_traffic(n, prec, block_size, order="morton"):
     """HBM bytes per force launch from the committed FETCH_SIZE/WRITE_SIZE
     counter runs (scaled by a plain copy's reading), or None when the kernel
     sources changed since the counters were taken or the configuration
-    differs from the profiled one (1e7 agents, FP32 state, 256 threads)."""
+    differs from the profiled one (1e7 agents, FP32 state, 256 threads,
+    Morton order)."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
@@ -52,7 +53,8 @@ def measured_traffic(n, prec, block_size):
                 h.update(f.read())
     except (OSError, KeyError, ValueError):
         return None
-    if h.hexdigest() != rec["source_sha256"] or n != 10_000_000 or prec != "f32" or block_size != 256:
+    if (h.hexdigest() != rec["source_sha256"] or n != 10_000_000 or prec != "f32" or block_size != 256
+            or order != "morton"):
         return None
     return float(rec["traffic_bytes"])
 
@@ -144,6 +146,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--block-size", type=int, default=256)
+    ap.add_argument("--order", choices=["morton", "hilbert"], default="morton",
+                    help="order of the boxes for the headline run (the legs keep their own)")
     ap.add_argument("--sort-every", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true", help="skip the skip-on, batched and adjoint legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -189,7 +193,8 @@ def main():
     w = workloads.headline(n=args.n)
     pos = torch.from_numpy(w.pos).to(dev)
     diam = torch.from_numpy(w.diam).to(dev)
-    sim = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size)
+    sim = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size,
+                  order=args.order)
     sim.step(args.warmup)
     sim.sync()
     log("timed region")
@@ -201,7 +206,7 @@ def main():
     prec = w.precision
     force_bytes = FORCE_BYTES[prec] * w.n
     ach = force_bytes / (phases["force"] * 1e-3) / 1e9
-    traffic = measured_traffic(w.n, prec, args.block_size)
+    traffic = measured_traffic(w.n, prec, args.block_size, args.order)
     roof = dict(bound="hbm", kernel="k_force (static flags + force + move)", achieved=round(ach, 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic), traffic_unit="bytes per launch",
@@ -359,7 +364,7 @@ def main():
            "config": {"workload": "headline: 1e7 spheres, c2 construction (uniform inner cube + jittered "
                                   "force-free lattice shell), side 3387.7, d~U[8,12], seed 2",
                       "n": w.n, "state": prec, "arithmetic": "f64", "detect_static": False,
-                      "sort_every": args.sort_every, "block_size": args.block_size},
+                      "sort_every": args.sort_every, "block_size": args.block_size, "order": args.order},
            "roofline": roof, "cpu_baseline": cpu, **extras}
     line = json.dumps(out)
     print(line, flush=True)

@@ -38,7 +38,7 @@ constexpr int kTimedPhases = 6;
 
 struct Layout {
     int64_t globals, sims, sim_of, bbox_rep, pos4[2], flags[2], skey[2], ids[2], force[2], key, sub, rec, perm, movers,
-        mcount, count, cell_start[2], dirty, dirty_list, aoff, tabidx, cellinfo, tile_off, hil, tile_sums, partials,
+        mcount, count, cell_start[2], dirty, dirty_list, aoff, tabidx, cellinfo, hil, tile_sums, partials,
         stage, total;
     uint32_t scan_tiles, partial_cap;
 };
@@ -82,7 +82,6 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.aoff = take(4 * boxes);
     L.tabidx = take(4 * boxes);
     L.cellinfo = take(16 * boxes);
-    L.tile_off = take(4 * boxes);
     L.hil = take(sizeof(HilbertTables));
     L.scan_tiles = uint32_t((boxes + kScanTile - 1) / kScanTile);
     if (L.scan_tiles == 0) L.scan_tiles = 1;
@@ -180,7 +179,6 @@ void fill_buffers(abm_ctx* c) {
     b.aoff = reinterpret_cast<uint32_t*>(w + L.aoff);
     b.tabidx = reinterpret_cast<uint32_t*>(w + L.tabidx);
     b.cellinfo = reinterpret_cast<uint4*>(w + L.cellinfo);
-    b.tile_off = reinterpret_cast<uint32_t*>(w + L.tile_off);
     b.hil = c->params.order == ABM_ORDER_HILBERT ? reinterpret_cast<const HilbertTables*>(w + L.hil) : nullptr;
     b.tile_sums = reinterpret_cast<uint32_t*>(w + L.tile_sums);
     b.scan_tiles = L.scan_tiles;

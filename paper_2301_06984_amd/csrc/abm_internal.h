@@ -41,12 +41,12 @@
 //                 (this grid and the last)
 //     dirty, dirty_list, aoff   bookkeeping of the update build
 //     tabidx      table index of the super-box (written with its entry)
-//     tile_off    rank of the first super-box of every tile (2^tlev super-boxes per axis)
 //     cellinfo    row-major super-box table, 16 B per entry (SuperEntry); an
 //                 entry whose stamp is not the current one is empty, so the
 //                 table is never cleared between steps (the timestamp trick
 //                 of Section 3.1; update builds keep the stamp)
 //   per scan tile: three 32-bit sums.
+//   the Hilbert order's tables (HilbertTables, 768 B).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -99,11 +99,6 @@ struct SimGrid {
     uint32_t nsuper;        // sdims[0] * sdims[1] * sdims[2]
     uint32_t sbase;         // first global super-box index of this simulation
     int32_t slevels;        // smallest L with 2^L >= max(sdims)
-    // super-boxes are ranked through tiles of 2^tlev super-boxes per axis: the
-    // rank of a tile's first super-box (a table) plus the rank inside the tile
-    int32_t tlev;
-    uint32_t tdims[3];
-    uint32_t ntiles;
     // min x,y,z then max x,y,z of the box coordinates (extent queries only;
     // the step keeps its accumulators in Buffers::bbox_rep)
     int32_t bbox[2][6];
@@ -158,7 +153,6 @@ struct Buffers {
     uint32_t* aoff;           // first append slot (minus n) of a changed super-box
     uint32_t* tabidx;         // table index of the super-box, written with its entry
     uint4* cellinfo;
-    uint32_t* tile_off;       // per tile (at the simulation's super-box base): rank of its first super-box
     const HilbertTables* hil; // the Hilbert order's tables; null: Morton order
     uint32_t* tile_sums;      // per scan tile: agents, changed super-boxes, agents of changed super-boxes
     double* partials;         // per-block partial sums (adjoint)

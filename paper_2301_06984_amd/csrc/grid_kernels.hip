@@ -234,17 +234,15 @@ void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s) {
 // move kernel and the step statistics.
 constexpr int kSetupThreads = 1024;
 constexpr uint32_t kFixupLanes = 8;   // threads per changed super-box in an update build
-constexpr int kTileLevels = 3;    // tiles of 8 x 8 x 8 super-boxes
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int32_t* rep, int nsims,
                                                            int parity, uint32_t super_capacity, int allow_inc,
-                                                           uint32_t n, uint32_t* __restrict__ tile_off) {
+                                                           uint32_t n) {
     __shared__ unsigned long long s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
-    __shared__ uint32_t s_dirty, s_same;
+    __shared__ uint32_t s_same;
     if (threadIdx.x == 0) {
         s_carry = 0;
-        s_dirty = 0u;
         s_same = 1u;
     }
     // the other accumulator slot and this step's statistics start empty
@@ -261,7 +259,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
     for (int chunk = 0; chunk < nsims; chunk += kSetupThreads) {
         const int s = chunk + int(threadIdx.x);
         uint32_t nb = 0, nsup = 0;
-        bool changed = false, same = true;
+        bool same = true;
         if (s < nsims) {
             SimGrid& G = sims[s];
             same = G.valid != 0u;   // the last grid of this simulation was built
@@ -294,25 +292,16 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
             uint32_t ns = 1;
             for (int a = 0; a < 3; ++a) {
                 const uint32_t sd = ok ? super_dim(G.dims[a]) : 1u;
-                changed = changed || sd != G.sdims[a];
                 G.sdims[a] = sd;
                 ns *= sd;
             }
             G.slevels = levels > 0 ? levels - 1 : 0;
             G.nsuper = ok ? ns : 0u;
-            G.tlev = G.slevels < kTileLevels ? G.slevels : kTileLevels;
-            uint32_t nt = 1;
-            for (int a = 0; a < 3; ++a) {
-                G.tdims[a] = (G.sdims[a] + (1u << G.tlev) - 1u) >> G.tlev;
-                nt *= G.tdims[a];
-            }
-            G.ntiles = ok ? nt : 0u;
             nb = G.nboxes;
             nsup = G.nsuper;
             same = same && ok;
             if (!ok) raise_error(g, kErrGrid);
         }
-        if (__syncthreads_or(changed ? 1 : 0) && threadIdx.x == 0) s_dirty = 1u;
         if (!__syncthreads_and(same ? 1 : 0) && threadIdx.x == 0) s_same = 0u;
         // block exclusive scans of nb (box bases) and nsup (super-box bases)
         unsigned long long x = (unsigned long long)nb | ((unsigned long long)nsup << 32);
@@ -358,36 +347,20 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
         // keeps the entries of the super-boxes it does not rebuild
         if (!g->inc) g->stamp = g->stamp + 1;
     }
-    // Rank of the first super-box of every tile, rebuilt when a super grid
-    // changed.  Tile t of a simulation (row-major over its tile grid) is
-    // stored at the simulation's super-box base + t (tiles are never more
-    // than super-boxes).
-    __syncthreads();
-    if (!s_dirty) return;
-    for (int s = 0; s < nsims; ++s) {
-        const SimGrid& G = sims[s];
-        if (!G.valid) continue;
-        for (uint32_t t = threadIdx.x; t < G.ntiles; t += kSetupThreads) {
-            const uint32_t tx = t % G.tdims[0], ty = (t / G.tdims[0]) % G.tdims[1], tz = t / (G.tdims[0] * G.tdims[1]);
-            tile_off[G.sbase + t] = gapfree_rank(tx << G.tlev, ty << G.tlev, tz << G.tlev, G.sdims[0], G.sdims[1],
-                                                 G.sdims[2], G.slevels);
-        }
-    }
 }
 
 template <class T>
 void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, b.g, b.sims, b.bbox_rep, b.nsims, parity,
-                       b.super_capacity, allow_inc ? 1 : 0, b.n, b.tile_off);
+                       b.super_capacity, allow_inc ? 1 : 0, b.n);
 }
 
 // ------------------------------------------------------------------ keys
 // Key of a position: (global super-box rank << 3) | octant of its box (x bit
-// lowest).  In Morton order the super-box rank, gap-free over the super grid,
-// is the rank of its tile's first super-box (tile table) plus the rank inside
-// the tile; in Hilbert order it comes from the walk down the curve's octree
-// (hil: the curve's tables, an LDS copy).  false if the position lies
-// outside the grid.
+// lowest).  The super-box rank is gap-free over the super grid: in Morton
+// order from the closed-form walk of gapfree_rank, in Hilbert order from the
+// walk down the curve's octree (hil: the curve's tables, an LDS copy).
+// false if the position lies outside the grid.
 template <class T>
 __device__ __forceinline__ bool super_key(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, uint32_t* key,
                                           const HilbertTables* hil) {
@@ -398,14 +371,7 @@ __device__ __forceinline__ bool super_key(const Buffers<T>& b, const SimGrid& G,
         rank = hilbert_rank(q[0] >> 1, q[1] >> 1, q[2] >> 1, G.sdims[0], G.sdims[1], G.sdims[2], G.slevels, 1u,
                             hil->before, hil->next);
     } else {
-        const uint32_t tl = uint32_t(G.tlev), tm = (1u << tl) - 1u;
-        uint32_t S[3], w[3];
-        for (int a = 0; a < 3; ++a) {
-            S[a] = q[a] >> 1;
-            w[a] = min(tm + 1u, G.sdims[a] - (S[a] & ~tm));
-        }
-        const uint32_t tile = G.sbase + ((S[2] >> tl) * G.tdims[1] + (S[1] >> tl)) * G.tdims[0] + (S[0] >> tl);
-        rank = b.tile_off[tile] + gapfree_rank(S[0] & tm, S[1] & tm, S[2] & tm, w[0], w[1], w[2], int(tl));
+        rank = gapfree_rank(q[0] >> 1, q[1] >> 1, q[2] >> 1, G.sdims[0], G.sdims[1], G.sdims[2], G.slevels);
     }
     *key = ((G.sbase + rank) << 3) | (q[0] & 1u) | ((q[1] & 1u) << 1) | ((q[2] & 1u) << 2);
     return true;

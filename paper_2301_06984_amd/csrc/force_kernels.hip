@@ -104,30 +104,36 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
         bool ok = false, is_static = false, moved = false;
         int sim = 0;
         int32_t cnew[3] = {0, 0, 0};
+        // ---- before the walk, per agent
+        const SimGrid* Gp = b.sims;
+        V4<T> p{};
+        Pieces P;
+        uint32_t f = 0, out = i;
+        bool cand = false, walks = false;
+        V4<T>* __restrict__ pout = pos4_ptr(b, nxt);
         if (active) {
             // one simulation: its parameters are the same for every lane
             sim = BATCHED ? sim_index(b, i) : 0;
-            const SimGrid& G = b.sims[sim];
-            V4<T>* __restrict__ pout = pos4_ptr(b, nxt);
+            Gp = b.sims + sim;
+            const SimGrid& G = *Gp;
             const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
             if (!G.valid) {
                 // grid overflow (reported at sync): the agent keeps its state (a
                 // full build copied it to loose slot n + i, and its id and key
                 // to the next state)
-                const V4<T> p = pin[u];
-                pout[i] = p;
+                const V4<T> p0 = pin[u];
+                pout[i] = p0;
                 b.flags[nxt][i] = b.flags[cur][u] | kBoxChangedBit;
                 if (KEEP_F)
                     for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(i) + c] = b.force[cur][3 * size_t(i) + c];
-                ok = box_coord(double(p.x), G.inv_h, &cnew[0]) && box_coord(double(p.y), G.inv_h, &cnew[1]) &&
-                     box_coord(double(p.z), G.inv_h, &cnew[2]);
+                ok = box_coord(double(p0.x), G.inv_h, &cnew[0]) && box_coord(double(p0.y), G.inv_h, &cnew[1]) &&
+                     box_coord(double(p0.z), G.inv_h, &cnew[2]);
             } else {
-                V4<T> p = pin[u];   // own state, sign of d = moved
-                const uint32_t f = b.flags[cur][u];
+                p = pin[u];   // own state, sign of d = moved
+                f = b.flags[cur][u];
                 uint32_t q[3];
                 if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
-                const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
-                uint32_t out = i;
+                P = load_pieces(b, G, q, b.g->stamp, L);
                 if (RELAYOUT && !inc) {
                     out = u - n;
                 } else if (RELAYOUT) {
@@ -151,48 +157,55 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
                 // every agent carries the moved bit, so none is static.  With no
                 // moved agent in the 27 boxes it holds at once; otherwise the
                 // force walk itself reports a moved agent within R.
-                const bool cand = STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u;
+                cand = STATIC_ON && !(f & kMovedBit) && (f >> kNnzShift) <= 1u;
                 if (KEEP_F && cand)   // a static agent keeps its force (replaced below if it is not static)
                     for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(out) + c] = b.force[cur][3 * size_t(i) + c];
                 is_static = cand && !P.moved;
                 p.w = T(fabs(double(p.w)));
-                V4<T> np = p;
-                uint32_t nf = 0;
-                ForceSum acc;
-                if (!is_static) {
-                    force_of<CH, T, false>(b, G, p, P, L, acc);
-                    is_static = cand && !acc.moved_near;
-                }
-                if (is_static) {
-                    nf = kStaticBit | (f & ~(kMovedBit | kStaticBit | kBoxChangedBit));
-                } else {
-                    const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
-                    np.x = T(double(p.x) + m.ux);
-                    np.y = T(double(p.y) + m.uy);
-                    np.z = T(double(p.z) + m.uz);
-                    moved = m.ux != 0.0 || m.uy != 0.0 || m.uz != 0.0;
-                    const uint32_t nz = acc.nnz < 0xFFFFFFu ? acc.nnz : 0xFFFFFFu;
-                    nf = (moved ? kMovedBit : 0u) | (nz << kNnzShift);
-                    if (moved) np.w = -np.w;
-                    if (KEEP_F) {
-                        b.force[nxt][3 * size_t(out)] = acc.fx;
-                        b.force[nxt][3 * size_t(out) + 1] = acc.fy;
-                        b.force[nxt][3 * size_t(out) + 2] = acc.fz;
-                    }
-                }
-                pout[out] = np;
-                ok = box_coord(double(np.x), G.inv_h, &cnew[0]) && box_coord(double(np.y), G.inv_h, &cnew[1]) &&
-                     box_coord(double(np.z), G.inv_h, &cnew[2]);
-                // left the box it was ranked in (the next grid build re-ranks it);
-                // that box is recomputed from p, so q need not live through the walk
-                int32_t cold[3];
-                bool left = !ok || !(box_coord(double(p.x), G.inv_h, &cold[0]) && box_coord(double(p.y), G.inv_h, &cold[1]) &&
-                                     box_coord(double(p.z), G.inv_h, &cold[2]));
-                for (int c = 0; c < 3; ++c) left = left || cnew[c] != cold[c];
-                b.flags[nxt][out] = nf | (left ? kBoxChangedBit : 0u);
+                walks = !is_static;
             }
-            if (!ok) raise_error(b.g, kErrNonfinite);
         }
+        // ---- the walk and the pair terms, with every lane of the wave (a lane
+        // that does not walk has no pieces), so that the wave can share out
+        // its pair terms
+        if (!walks) P.mask = 0u;
+        ForceSum acc;
+        force_of<CH, T, false, true>(b, *Gp, p, P, L, acc);
+        // ---- after the walk, per agent
+        if (active && Gp->valid) {
+            const SimGrid& G = *Gp;
+            if (walks) is_static = cand && !acc.moved_near;
+            V4<T> np = p;
+            uint32_t nf = 0;
+            if (is_static) {
+                nf = kStaticBit | (f & ~(kMovedBit | kStaticBit | kBoxChangedBit));
+            } else {
+                const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
+                np.x = T(double(p.x) + m.ux);
+                np.y = T(double(p.y) + m.uy);
+                np.z = T(double(p.z) + m.uz);
+                moved = m.ux != 0.0 || m.uy != 0.0 || m.uz != 0.0;
+                const uint32_t nz = acc.nnz < 0xFFFFFFu ? acc.nnz : 0xFFFFFFu;
+                nf = (moved ? kMovedBit : 0u) | (nz << kNnzShift);
+                if (moved) np.w = -np.w;
+                if (KEEP_F) {
+                    b.force[nxt][3 * size_t(out)] = acc.fx;
+                    b.force[nxt][3 * size_t(out) + 1] = acc.fy;
+                    b.force[nxt][3 * size_t(out) + 2] = acc.fz;
+                }
+            }
+            pout[out] = np;
+            ok = box_coord(double(np.x), G.inv_h, &cnew[0]) && box_coord(double(np.y), G.inv_h, &cnew[1]) &&
+                 box_coord(double(np.z), G.inv_h, &cnew[2]);
+            // left the box it was ranked in (the next grid build re-ranks it);
+            // that box is recomputed from p, so q need not live through the walk
+            int32_t cold[3];
+            bool left = !ok || !(box_coord(double(p.x), G.inv_h, &cold[0]) && box_coord(double(p.y), G.inv_h, &cold[1]) &&
+                                 box_coord(double(p.z), G.inv_h, &cold[2]));
+            for (int c = 0; c < 3; ++c) left = left || cnew[c] != cold[c];
+            b.flags[nxt][out] = nf | (left ? kBoxChangedBit : 0u);
+        }
+        if (active && !ok) raise_error(b.g, kErrNonfinite);
         // ---- box extent and statistics: wave, then block (LDS atomics)
         const bool contrib = active && ok;
         const unsigned long long any = __ballot(contrib);

@@ -83,22 +83,26 @@ __device__ __forceinline__ bool box_of(const SimGrid& G, const V4<T>& p, uint32_
 // Per-thread scratch in LDS for the neighbour walk: the pieces (start slot in
 // the low, end slot in the high 32 bits) and a queue of candidate slots.  Laid
 // out [entry][thread] so that the threads of a wave hit distinct banks.
-// LDS per thread of the walk: kPieces * 8 + kQueueCap * 4 bytes, which
-// bounds the waves per CU.  The walk tests CH = 2 or 4 candidate slots of a
+// LDS per thread of the walk: kPieces * 8 + kQueueCap * 4 bytes, plus 12
+// bytes per thread for the pair terms a wave shares out (32 per wave, three
+// doubles each), which bounds the waves per CU.  The walk tests CH = 2 or 4 candidate slots of a
 // piece together (4 pays off where boxes hold one or more agents).
 constexpr int kPieces = 8;   // one per super-box of the 2x2x2 block, in Morton order
 constexpr int kQueueCap = 10;
 static_assert(4 <= kSposPad, "the walk reads up to 3 slots past a piece");
+constexpr int kShare = 32;   // pair terms a wave passes through LDS at a time
 struct WalkLds {
     unsigned long long* rng;   // [kPieces][blockDim]
     uint32_t* queue;           // [kQueueCap][blockDim]
+    double* res;               // [blockDim / 64][3][kShare]
 };
-inline size_t walk_lds_bytes(int block) { return size_t(block) * (kPieces * 8 + kQueueCap * 4); }
+inline size_t walk_lds_bytes(int block) { return size_t(block) * (kPieces * 8 + kQueueCap * 4 + 3 * kShare * 8 / 64); }
 
 __device__ __forceinline__ WalkLds walk_lds(void* base) {
     WalkLds w;
     w.rng = static_cast<unsigned long long*>(base);
     w.queue = reinterpret_cast<uint32_t*>(w.rng + kPieces * blockDim.x);
+    w.res = reinterpret_cast<double*>(w.queue + kQueueCap * blockDim.x);
     return w;
 }
 
@@ -282,32 +286,73 @@ struct ForceSum {
     bool moved_near = false;               // an agent within R (not i) moved in the last step
 };
 
-// F_i over the neighbours j (|e|^2 < R^2) in contact (0 < |e| < r_i + r_j):
-// f = k delta - gamma sqrt(rho delta) along e / |e| (the force-law reading of
-// Section 5).  Evaluated in double, without fused multiply-adds (the library
-// is built with contraction off), in ascending slot order.
+// One pair term: f = k delta - gamma sqrt(rho delta) along e / |e| (the
+// force-law reading of Section 5), for agent i at (xi, yi, zi) with radius ri
+// and a neighbour pj in contact.  Evaluated in double, without fused
+// multiply-adds (the library is built with contraction off).
+struct PairTerm {
+    double fx, fy, fz;      // the term's force on i
+    double delta, sr, dist; // overlap, sqrt(rho delta), |e|
+    double ex, ey, ez;
+    bool nonzero;
+};
+template <class T>
+__device__ __forceinline__ PairTerm pair_term(double xi, double yi, double zi, double ri, const V4<T>& pj, double k,
+                                              double gamma) {
+    PairTerm t;
+    t.ex = xi - double(pj.x);
+    t.ey = yi - double(pj.y);
+    t.ez = zi - double(pj.z);
+    const double s2 = (t.ex * t.ex + t.ey * t.ey) + t.ez * t.ez;
+    const double rj = 0.5 * fabs(double(pj.w));
+    const double S = ri + rj;
+    t.dist = sqrt(s2);
+    t.delta = S - t.dist;
+    const double rho = (ri * rj) / S;
+    t.sr = sqrt(rho * t.delta);
+    const double f = k * t.delta - gamma * t.sr;
+    const double sc = f / t.dist;
+    t.fx = sc * t.ex;
+    t.fy = sc * t.ey;
+    t.fz = sc * t.ez;
+    t.nonzero = f != 0.0;
+    return t;
+}
+
+// F_i over the neighbours j (|e|^2 < R^2) in contact (0 < |e| < r_i + r_j),
+// summed in ascending slot order.
 //
 // Pass 1 takes the candidates CH slots of one piece at a time (their
 // positions requested together) through the cheap pre-test and queues the
-// survivors (the agent itself among them: the exact test drops d = 0);
-// a nearly full queue (and the end) is drained by pass 2, which keeps the
-// candidates in contact (exact test, in place) and then adds their terms.
-// Queue order is stream order, so the terms are summed in canonical order.
-template <int CH, class T, bool PARAM_GRADS>
+// survivors (the agent itself among them: the exact test drops d = 0).  A
+// nearly full queue is compacted by the exact test (neighbour and contact,
+// in place), which keeps the contacts in slot order at its head.
+//
+// The pair terms: without SHARE, each lane adds its own contacts' terms when
+// its queue fills and at the end.  With SHARE, force_of is entered by every
+// lane of the wave; a lane adds its contacts itself only if they fill its
+// queue, and at the end the wave shares out all its lanes' remaining
+// contacts, one per lane, kShare at a time through LDS back to their agent's
+// lane, which adds them in slot order: the same sums, bit for bit, with the
+// lanes of a wave busy however unevenly the contacts fall.
+template <int CH, class T, bool PARAM_GRADS, bool SHARE = false>
 __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, const Pieces& P,
                                          const WalkLds& L, ForceSum& acc) {
+    static_assert(!(SHARE && PARAM_GRADS), "shared pair terms carry the force only");
     const V4<T>* __restrict__ sp = gpos_ptr(b);
     const uint32_t tid = threadIdx.x, bs = blockDim.x, last = 2u * b.n - 1u;
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
     const double ri = 0.5 * fabs(double(p.w));
     const double r2 = G.r2, k = G.k, gamma = G.gamma;
     const float r2pad = padded_r2(r2);
-    uint32_t n = 0;
-    auto drain = [&]() {
-        // exact neighbour + contact test, keeping the survivors in place; the
-        // positions of a group of four are requested before any is tested
-        uint32_t m = 0;
-        for (uint32_t x0 = 0; x0 < n; x0 += 4) {
+    uint32_t n = 0;      // queue rows in use
+    uint32_t kept = 0;   // rows [0, kept): contacts whose terms are not added yet
+    // exact neighbour + contact test of rows [kept, n), keeping the contacts
+    // in place after row kept; the positions of a group of four are
+    // requested before any is tested
+    auto exact = [&]() {
+        uint32_t m = kept;
+        for (uint32_t x0 = kept; x0 < n; x0 += 4) {
             V4<T> pj[4];
             uint32_t uq[4];
 #pragma unroll
@@ -329,39 +374,35 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
                 m += keep ? 1u : 0u;
             }
         }
-        for (uint32_t x0 = 0; x0 < m; x0 += 4) {   // pair terms, in slot order, four positions requested together
+        kept = m;
+        n = m;
+    };
+    // this lane's contacts, rows [0, kept), in order; four positions requested together
+    auto own_terms = [&]() {
+        for (uint32_t x0 = 0; x0 < kept; x0 += 4) {
             V4<T> pj4[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) pj4[c] = sp[min(L.queue[min(x0 + c, m - 1) * bs + tid], last)];
+            for (int c = 0; c < 4; ++c) pj4[c] = sp[min(L.queue[min(x0 + c, kept - 1) * bs + tid], last)];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                if (x0 + c >= m) break;
-                const V4<T>& pj = pj4[c];
-                const double ex = xi - double(pj.x), ey = yi - double(pj.y), ez = zi - double(pj.z);
-                const double s2 = (ex * ex + ey * ey) + ez * ez;
-                const double rj = 0.5 * fabs(double(pj.w));
-                const double S = ri + rj;
-                const double dist = sqrt(s2);
-                const double delta = S - dist;
-                const double rho = (ri * rj) / S;
-                const double sr = sqrt(rho * delta);
-                const double f = k * delta - gamma * sr;
-                const double sc = f / dist;
-                acc.fx += sc * ex;
-                acc.fy += sc * ey;
-                acc.fz += sc * ez;
-                acc.nnz += f != 0.0 ? 1u : 0u;
+                if (x0 + c >= kept) break;
+                const PairTerm t = pair_term<T>(xi, yi, zi, ri, pj4[c], k, gamma);
+                acc.fx += t.fx;
+                acc.fy += t.fy;
+                acc.fz += t.fz;
+                acc.nnz += t.nonzero ? 1u : 0u;
                 if (PARAM_GRADS) {
-                    const double ux = ex / dist, uy = ey / dist, uz = ez / dist;
-                    acc.kx += delta * ux;
-                    acc.ky += delta * uy;
-                    acc.kz += delta * uz;
-                    acc.gx -= sr * ux;
-                    acc.gy -= sr * uy;
-                    acc.gz -= sr * uz;
+                    const double ux = t.ex / t.dist, uy = t.ey / t.dist, uz = t.ez / t.dist;
+                    acc.kx += t.delta * ux;
+                    acc.ky += t.delta * uy;
+                    acc.kz += t.delta * uz;
+                    acc.gx -= t.sr * ux;
+                    acc.gy -= t.sr * uy;
+                    acc.gz -= t.sr * uz;
                 }
             }
         }
+        kept = 0;
         n = 0;
     };
     // pass 1: the pre-test over the walk, survivors queued in slot order
@@ -376,12 +417,78 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
             qo += pass ? bs : 0u;
         }
         if (n > uint32_t(kQueueCap - CH)) {
-            drain();
-            qo = tid;
+            exact();
+            if (!SHARE || n > uint32_t(kQueueCap - CH)) own_terms();
+            qo = n * bs + tid;
         }
         return true;
     });
-    drain();
+    exact();
+    if constexpr (!SHARE) {
+        own_terms();
+    } else {
+        // the wave's contacts: lane l's rows [0, kept) are pairs [off, off +
+        // kept) of the wave, pair x evaluated by lane x mod 64 in round x / 64
+        const uint32_t lane = uint32_t(lane_id()), wbase = tid - lane;
+        double* const rx = L.res + size_t(tid >> 6) * (3 * kShare);
+        double* const ry = rx + kShare;
+        double* const rz = ry + kShare;
+        uint32_t incl = kept;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, 64);
+            if (lane >= uint32_t(d)) incl += y;
+        }
+        const uint32_t off = incl - kept, total = __shfl(incl, 63, 64);
+        for (uint32_t base = 0; base < total; base += 64) {
+            const uint32_t x = base + lane;
+            // the pair's agent: the last lane whose pairs start at or before x
+            uint32_t o = 0;
+            for (uint32_t step = 32; step >= 1; step >>= 1) {
+                const uint32_t v = __shfl(off, int(o + step), 64);
+                o = v <= x ? o + step : o;
+            }
+            const uint32_t row = x - __shfl(off, int(o), 64);
+            const double oxi = __shfl(xi, int(o), 64), oyi = __shfl(yi, int(o), 64), ozi = __shfl(zi, int(o), 64);
+            const double ori = __shfl(ri, int(o), 64), ok_ = __shfl(k, int(o), 64), og = __shfl(gamma, int(o), 64);
+            PairTerm t{};
+            t.fx = t.fy = t.fz = 0.0;
+            t.nonzero = false;
+            if (x < total) {
+                const uint32_t uj = L.queue[min(row, uint32_t(kQueueCap - 1)) * bs + wbase + o];
+                t = pair_term<T>(oxi, oyi, ozi, ori, sp[min(uj, last)], ok_, og);
+            }
+            const unsigned long long nzm = __ballot(x < total && t.nonzero);
+            // this lane's pairs in the round: [lo, hi) of the wave's numbering
+            const uint32_t lo = max(off, base), hi = min(off + kept, base + 64u);
+            if (hi > lo) {
+                const uint32_t a0 = lo - base, a1 = hi - base;
+                const unsigned long long bits = (a1 >= 64u ? ~0ull : ((1ull << a1) - 1ull)) & ~((1ull << a0) - 1ull);
+                acc.nnz += uint32_t(__popcll(nzm & bits));
+            }
+            // the terms go to their agent's lane in two halves of kShare
+#pragma unroll
+            for (uint32_t h = 0; h < 64u / kShare; ++h) {
+                const uint32_t h0 = base + h * kShare;
+                if (lane / kShare == h) {
+                    rx[lane % kShare] = t.fx;
+                    ry[lane % kShare] = t.fy;
+                    rz[lane % kShare] = t.fz;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const uint32_t j0 = max(off, h0), j1 = min(off + kept, h0 + kShare);
+                for (uint32_t jj = j0; jj < j1; ++jj) {
+                    acc.fx += rx[jj - h0];
+                    acc.fy += ry[jj - h0];
+                    acc.fz += rz[jj - h0];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+    }
 }
 
 // Displacement rule: Delta = mu F if |F| > f_adh, clamped to delta_max.

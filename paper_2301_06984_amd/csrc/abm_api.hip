@@ -38,7 +38,7 @@ constexpr int kTimedPhases = 6;
 
 struct Layout {
     int64_t globals, sims, sim_of, bbox_rep, pos4[2], flags[2], skey[2], ids[2], force[2], key, sub, rec, perm, movers,
-        mcount, count, cell_start[2], dirty, dirty_list, aoff, tabidx, cellinfo, hil, tile_sums, partials,
+        mcount, count, cell_start[2], dirty, dirty_list, aoff, tabidx, mmask, cellinfo, hil, tile_sums, partials,
         stage, total;
     uint32_t scan_tiles, partial_cap;
 };
@@ -81,6 +81,7 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.dirty_list = take(4 * boxes);
     L.aoff = take(4 * boxes);
     L.tabidx = take(4 * boxes);
+    L.mmask = take(4 * boxes);
     L.cellinfo = take(16 * boxes);
     L.hil = take(sizeof(HilbertTables));
     L.scan_tiles = uint32_t((boxes + kScanTile - 1) / kScanTile);
@@ -178,6 +179,7 @@ void fill_buffers(abm_ctx* c) {
     b.dirty_list = reinterpret_cast<uint32_t*>(w + L.dirty_list);
     b.aoff = reinterpret_cast<uint32_t*>(w + L.aoff);
     b.tabidx = reinterpret_cast<uint32_t*>(w + L.tabidx);
+    b.mmask = reinterpret_cast<uint32_t*>(w + L.mmask);
     b.cellinfo = reinterpret_cast<uint4*>(w + L.cellinfo);
     b.hil = c->params.order == ABM_ORDER_HILBERT ? reinterpret_cast<const HilbertTables*>(w + L.hil) : nullptr;
     b.tile_sums = reinterpret_cast<uint32_t*>(w + L.tile_sums);
@@ -402,13 +404,14 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
         return code;
     };
     // zero what must start at zero: globals, histogram, box table, change
-    // marks, table indices; and the positions with their padding (read,
+    // marks, table indices, moved masks; and the positions with their padding (read,
     // never used, by the walk)
     if (hipMemsetAsync(c->ws + L.globals, 0, sizeof(Globals), s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.count, 0, 4 * supers, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.cellinfo, 0, 16 * supers, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.dirty, 0, 4 * supers, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.tabidx, 0, 4 * supers, s) != hipSuccess ||
+        hipMemsetAsync(c->ws + L.mmask, 0, 4 * supers, s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.pos4[0], 0, 4 * c->elem() * (2 * cap + kSposPad), s) != hipSuccess ||
         hipMemsetAsync(c->ws + L.pos4[1], 0, 4 * c->elem() * (2 * cap + kSposPad), s) != hipSuccess ||
         hipMemcpyAsync(b.sims, sims.data(), sizeof(SimGrid) * nsims, hipMemcpyHostToDevice, s) != hipSuccess)

@@ -41,6 +41,8 @@
 //                 (this grid and the last)
 //     dirty, dirty_list, aoff   bookkeeping of the update build
 //     tabidx      table index of the super-box (written with its entry)
+//     mmask       moved octants of a kept super-box, gathered by the keys
+//                 kernel and moved into its table entry by the scan
 //     cellinfo    row-major super-box table, 16 B per entry (SuperEntry); an
 //                 entry whose stamp is not the current one is empty, so the
 //                 table is never cleared between steps (the timestamp trick
@@ -152,6 +154,7 @@ struct Buffers {
     uint32_t* dirty_list;     // the changed super-boxes of this build, in rank order
     uint32_t* aoff;           // first append slot (minus n) of a changed super-box
     uint32_t* tabidx;         // table index of the super-box, written with its entry
+    uint32_t* mmask;          // octants that hold an agent that moved (update build; zero between builds)
     uint4* cellinfo;
     const HilbertTables* hil; // the Hilbert order's tables; null: Morton order
     uint32_t* tile_sums;      // per scan tile: agents, changed super-boxes, agents of changed super-boxes

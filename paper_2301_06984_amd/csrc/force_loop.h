@@ -83,26 +83,22 @@ __device__ __forceinline__ bool box_of(const SimGrid& G, const V4<T>& p, uint32_
 // Per-thread scratch in LDS for the neighbour walk: the pieces (start slot in
 // the low, end slot in the high 32 bits) and a queue of candidate slots.  Laid
 // out [entry][thread] so that the threads of a wave hit distinct banks.
-// LDS per thread of the walk: kPieces * 8 + kQueueCap * 4 bytes, plus 12
-// bytes per thread for the pair terms a wave shares out (32 per wave, three
-// doubles each), which bounds the waves per CU.  The walk tests CH = 2 or 4 candidate slots of a
+// LDS per thread of the walk: kPieces * 8 + kQueueCap * 4 bytes, which
+// bounds the waves per CU.  The walk tests CH = 2 or 4 candidate slots of a
 // piece together (4 pays off where boxes hold one or more agents).
 constexpr int kPieces = 8;   // one per super-box of the 2x2x2 block, in Morton order
 constexpr int kQueueCap = 10;
 static_assert(4 <= kSposPad, "the walk reads up to 3 slots past a piece");
-constexpr int kShare = 32;   // pair terms a wave passes through LDS at a time
 struct WalkLds {
     unsigned long long* rng;   // [kPieces][blockDim]
     uint32_t* queue;           // [kQueueCap][blockDim]
-    double* res;               // [blockDim / 64][3][kShare]
 };
-inline size_t walk_lds_bytes(int block) { return size_t(block) * (kPieces * 8 + kQueueCap * 4 + 3 * kShare * 8 / 64); }
+inline size_t walk_lds_bytes(int block) { return size_t(block) * (kPieces * 8 + kQueueCap * 4); }
 
 __device__ __forceinline__ WalkLds walk_lds(void* base) {
     WalkLds w;
     w.rng = static_cast<unsigned long long*>(base);
     w.queue = reinterpret_cast<uint32_t*>(w.rng + kPieces * blockDim.x);
-    w.res = reinterpret_cast<double*>(w.queue + kQueueCap * blockDim.x);
     return w;
 }
 
@@ -332,9 +328,10 @@ __device__ __forceinline__ PairTerm pair_term(double xi, double yi, double zi, d
 // its queue fills and at the end.  With SHARE, force_of is entered by every
 // lane of the wave; a lane adds its contacts itself only if they fill its
 // queue, and at the end the wave shares out all its lanes' remaining
-// contacts, one per lane, kShare at a time through LDS back to their agent's
-// lane, which adds them in slot order: the same sums, bit for bit, with the
-// lanes of a wave busy however unevenly the contacts fall.
+// contacts, one per lane, and each term goes back to its agent's lane by
+// register shuffles (the j-th term of every lane at once), which adds them in
+// slot order: the same sums, bit for bit, with the lanes of a wave busy
+// however unevenly the contacts fall.
 template <int CH, class T, bool PARAM_GRADS, bool SHARE = false>
 __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, const Pieces& P,
                                          const WalkLds& L, ForceSum& acc) {
@@ -430,9 +427,6 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
         // the wave's contacts: lane l's rows [0, kept) are pairs [off, off +
         // kept) of the wave, pair x evaluated by lane x mod 64 in round x / 64
         const uint32_t lane = uint32_t(lane_id()), wbase = tid - lane;
-        double* const rx = L.res + size_t(tid >> 6) * (3 * kShare);
-        double* const ry = rx + kShare;
-        double* const rz = ry + kShare;
         uint32_t incl = kept;
         for (int d = 1; d < 64; d <<= 1) {
             const uint32_t y = __shfl_up(incl, d, 64);
@@ -465,27 +459,19 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
                 const unsigned long long bits = (a1 >= 64u ? ~0ull : ((1ull << a1) - 1ull)) & ~((1ull << a0) - 1ull);
                 acc.nnz += uint32_t(__popcll(nzm & bits));
             }
-            // the terms go to their agent's lane in two halves of kShare
-#pragma unroll
-            for (uint32_t h = 0; h < 64u / kShare; ++h) {
-                const uint32_t h0 = base + h * kShare;
-                if (lane / kShare == h) {
-                    rx[lane % kShare] = t.fx;
-                    ry[lane % kShare] = t.fy;
-                    rz[lane % kShare] = t.fz;
+            // the terms go back to their agent's lane: the j-th of every lane at once
+            const uint32_t j0 = max(off, base), j1 = min(off + kept, base + 64u);
+            const uint32_t cnt = j1 > j0 ? j1 - j0 : 0u;
+            uint32_t most = cnt;
+            for (int d = 32; d >= 1; d >>= 1) most = max(most, uint32_t(__shfl_xor(int(most), d, 64)));
+            for (uint32_t j = 0; j < most; ++j) {
+                const int src = int(min(j0 + j - base, 63u));
+                const double vx = __shfl(t.fx, src, 64), vy = __shfl(t.fy, src, 64), vz = __shfl(t.fz, src, 64);
+                if (j < cnt) {
+                    acc.fx += vx;
+                    acc.fy += vy;
+                    acc.fz += vz;
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const uint32_t j0 = max(off, h0), j1 = min(off + kept, h0 + kShare);
-                for (uint32_t jj = j0; jj < j1; ++jj) {
-                    acc.fx += rx[jj - h0];
-                    acc.fy += ry[jj - h0];
-                    acc.fz += rz[jj - h0];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
     }

@@ -1,11 +1,12 @@
 // grid_kernels.hip -- uniform-grid build of one step (Section 3.1) with boxes
-// in gap-free Morton order (Section 4.2, steps D-F), counted per super-box
-// (the aligned 2x2x2 blocks of boxes, whose agents are contiguous in that
-// order):
+// in gap-free Morton order (Section 4.2, steps D-F; or the Hilbert order of
+// the super-boxes), counted per super-box (the aligned 2x2x2 blocks of
+// boxes, whose agents are contiguous in that order):
 //   bbox     box extent of the agents (per simulation)
 //   setup    dims, box and super-box counts and bases of every simulation
 //   keys     super-box key and octant of every agent + histogram (atomics);
-//            an update build: only the agents that left their box
+//            an update build: only the agents that left their box, and with
+//            the static test the moved octants of every super-box
 //   scan     exclusive scan of the super-box counts (tile sums, their scan,
 //            rescan); an update build also lists the changed super-boxes
 //            and refreshes the table entries of the others
@@ -13,8 +14,6 @@
 //            order inside a super-box
 //   fixup    canonical (box, id) order inside each (re)built super-box, its
 //            agents written to loose slots + the row-major super-box table
-//   clean    update build with the static test: moved octants of the
-//            super-boxes kept in place
 #include "force_loop.h"
 
 #include <algorithm>
@@ -398,19 +397,40 @@ __device__ __forceinline__ uint32_t wave_run_add(uint32_t* arr, bool act, uint32
     return old + uint32_t(lane - leader);
 }
 
+// The same runs for a bit mask: each run's OR goes to arr[k] with one
+// atomicOr (a lane with act false is in no run).
+__device__ __forceinline__ void wave_run_or(uint32_t* arr, bool act, uint32_t k, uint32_t bits) {
+    const int lane = lane_id();
+    const uint32_t kk = act ? k : 0xFFFFFFFFu;
+    uint32_t acc = act ? bits : 0u;
+    // lane l gathers the run from l on: after the step of width d it holds
+    // lanes [l, l + 2d) of its run
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_down(acc, d, 64);
+        const uint32_t ok = __shfl_down(kk, d, 64);
+        if (lane + d < 64 && ok == kk) acc |= o;
+    }
+    const uint32_t pk = __shfl_up(kk, 1, 64);
+    if (act && (lane == 0 || pk != kk) && acc) atomicOr(&arr[k], acc);
+}
+
 // Full build: key of every agent and its arrival index in its super-box
 // (histogram atomics).  Update build (the last grid's extent, agents stored in
 // its canonical order): only agents that left their box get a new key; each
 // that enters another super-box moves one count from its old to its new
 // super-box and marks both as changed (the epoch of this build).  All are
 // listed in their block's segment, sub[i] noting the ones that moved on.
-// A block covers kKeysPer runs of kKeysThreads consecutive agents; in an
-// update build a thread requests the flags of its kKeysPer agents together.
+// With moved_bits, an update build also ORs every agent's moved bit into its
+// (last) super-box's mask at its octant; the scan moves the masks of the kept
+// super-boxes into their table entries (a rebuilt one gets its bits from the
+// fix-up).  A block covers kKeysPer runs of kKeysThreads consecutive agents;
+// in an update build a thread requests the flags of its kKeysPer agents
+// together.
 constexpr int kKeysThreads = 256;
 constexpr int kKeysPer = 4;
 constexpr uint32_t kKeysSpan = kKeysThreads * kKeysPer;
 template <class T>
-__global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur) {
+__global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur, int moved_bits) {
     __shared__ uint32_t s_movers;
     __shared__ uint32_t s_list[kKeysSpan];
     __shared__ __align__(16) HilbertTables s_hil;
@@ -451,6 +471,16 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur) {
     for (int k = 0; k < kKeysPer; ++k) {
         const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
         f[k] = i < b.n ? b.flags[cur][i] : 0u;
+    }
+    if (moved_bits) {   // agents in storage order: equal super-boxes in runs
+        const uint32_t total = b.g->total_super;
+#pragma unroll
+        for (int k = 0; k < kKeysPer; ++k) {
+            const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
+            const uint32_t key = i < b.n ? b.skey[cur][i] : kDeadKey;
+            const bool act = key != kDeadKey && (key >> 3) < total;
+            wave_run_or(b.mmask, act, key >> 3, (f[k] & kMovedBit) << (key & 7u));
+        }
     }
     // the block's agents that left their box, gathered in LDS, then taken
     // one per thread, so that their dependent loads overlap
@@ -515,6 +545,7 @@ struct ScanIn {
     const uint32_t* cs_old;
     const uint32_t* dirty;
     const uint32_t* tabidx;
+    uint32_t* mmask;
     uint4* cellinfo;
 };
 constexpr uint32_t kDirtyFlag = 0x80000000u;   // counts stay below 2^31
@@ -532,7 +563,7 @@ __device__ __forceinline__ void load_tile(const ScanIn& in, uint32_t ep, bool in
             for (int c = 0; c < 4; ++c) c4[c] = g0 + c < total ? in.count[g0 + c] : 0u;
         }
         if (inc && g0 < total) {
-            uint32_t o[5], d[4], ti[4];
+            uint32_t o[5], d[4], ti[4], mm[4] = {0u, 0u, 0u, 0u};
             if (whole) {
                 const uint4 uo = reinterpret_cast<const uint4*>(in.cs_old)[g0 >> 2];
                 const uint4 ud = reinterpret_cast<const uint4*>(in.dirty)[g0 >> 2];
@@ -542,6 +573,9 @@ __device__ __forceinline__ void load_tile(const ScanIn& in, uint32_t ep, bool in
                 if (refresh) {
                     const uint4 ut = reinterpret_cast<const uint4*>(in.tabidx)[g0 >> 2];
                     ti[0] = ut.x; ti[1] = ut.y; ti[2] = ut.z; ti[3] = ut.w;
+                    const uint4 um = reinterpret_cast<const uint4*>(in.mmask)[g0 >> 2];
+                    mm[0] = um.x; mm[1] = um.y; mm[2] = um.z; mm[3] = um.w;
+                    if (um.x | um.y | um.z | um.w) reinterpret_cast<uint4*>(in.mmask)[g0 >> 2] = make_uint4(0u, 0u, 0u, 0u);
                 }
             } else {
                 for (int c = 0; c < 4; ++c) {
@@ -549,6 +583,8 @@ __device__ __forceinline__ void load_tile(const ScanIn& in, uint32_t ep, bool in
                     o[c] = ok ? in.cs_old[g0 + c] : 0u;
                     d[c] = ok ? in.dirty[g0 + c] : 0u;
                     ti[c] = ok && refresh ? in.tabidx[g0 + c] : 0u;
+                    mm[c] = ok && refresh ? in.mmask[g0 + c] : 0u;
+                    if (mm[c]) in.mmask[g0 + c] = 0u;
                 }
                 o[4] = 0u;
                 for (int c = 0; c < 4; ++c)
@@ -559,9 +595,9 @@ __device__ __forceinline__ void load_tile(const ScanIn& in, uint32_t ep, bool in
                 const bool changed = d[c] == ep;
                 c4[c] += o[c + 1] - o[c];
                 if (changed) c4[c] |= kDirtyFlag;
-                if (refresh && !changed && o[c + 1] != o[c]) {
+                if (refresh && !changed && o[c + 1] != o[c]) {   // first slot, count and moved octants
                     if (ti[c] < total)
-                        reinterpret_cast<uint32_t*>(&in.cellinfo[ti[c]])[0] = o[c];
+                        *reinterpret_cast<uint2*>(&in.cellinfo[ti[c]]) = make_uint2(o[c], (o[c + 1] - o[c]) | (mm[c] << 24));
                 }
             }
         }
@@ -936,30 +972,6 @@ __global__ void k_fixup(Buffers<T> b, int cur, int ids_next) {
     }
 }
 
-// Update build with the static test: the table entries of the super-boxes
-// kept in place get the octants whose agents moved in the last step (from the
-// agents' flags and keys); the scan already gave them their first loose slot.
-template <class T>
-__global__ void k_clean(Buffers<T> b, int cur) {
-    if (!b.g->inc) return;
-    const uint32_t total = b.g->total_super, ep = b.g->epoch;
-    const uint32_t* __restrict__ fl = b.flags[cur];
-    const uint32_t* __restrict__ kk = b.skey[cur];
-    for (uint32_t sk = blockIdx.x * blockDim.x + threadIdx.x; sk < total; sk += gridDim.x * blockDim.x) {
-        const uint32_t o0 = b.cell_start_old[sk], o1 = b.cell_start_old[sk + 1];
-        if (o1 == o0 || b.dirty[sk] == ep) continue;
-        const uint32_t idx = b.tabidx[sk];
-        if (!slot_range(o0, o1, b.n) || idx >= total) {
-            raise_error(b.g, kErrInternal);
-            continue;
-        }
-        uint32_t m = 0;
-        for (uint32_t u = o0; u < o1; ++u) m |= (fl[u] & kMovedBit) << (kk[u] & 7u);
-        uint32_t* e = reinterpret_cast<uint32_t*>(&b.cellinfo[idx]);
-        e[1] = (e[1] & kMaxSuperCount) | (m << 24);
-    }
-}
-
 __global__ void k_clear_u64(unsigned long long* p, uint64_t n) {
     const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
@@ -1068,9 +1080,9 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, b
         if (marks) (void)hipEventRecord(*marks[k], s);
     };
     hipLaunchKernelGGL(k_keys<T>, dim3((b.n + kKeysSpan - 1) / kKeysSpan), dim3(kKeysThreads), 0, s, b,
-                       pos_cur);
+                       pos_cur, moved_bits ? 1 : 0);
     mark(0);
-    const ScanIn in{b.count, b.cell_start_old, b.dirty, b.tabidx, b.cellinfo};
+    const ScanIn in{b.count, b.cell_start_old, b.dirty, b.tabidx, b.mmask, b.cellinfo};
     hipLaunchKernelGGL(k_scan_reduce, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, in, b.tile_sums,
                        b.scan_tiles);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kTileScanThreads), 0, s, b.g, b.tile_sums, b.cell_start,
@@ -1081,11 +1093,6 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, b
     hipLaunchKernelGGL(k_scatter<T>, dim3(loop_blocks), dim3(256), 0, s, b, pos_cur, ids_cur);
     mark(2);
     hipLaunchKernelGGL(k_fixup<T>, dim3(loop_blocks), dim3(256), 0, s, b, pos_cur, relayout ? ids_cur ^ 1 : -1);
-    if (moved_bits) {
-        const uint32_t sb = (b.super_capacity + 255) / 256;
-        hipLaunchKernelGGL(k_clean<T>, dim3(sb < kLoopBlocks ? (sb ? sb : 1u) : kLoopBlocks), dim3(256), 0, s, b,
-                           pos_cur);
-    }
     mark(3);
 }
 

@@ -100,3 +100,29 @@ def test_autotuned_batch_matches_plain_runs():
         sim = make_sim(w.pos[a:e], w.diam[a:e], **res.params)
         sim.step(10)
         np.testing.assert_array_equal(got[a:e], sim.query("positions").cpu().numpy(), err_msg=f"sim {q}")
+
+
+@pytest.mark.parametrize("sort_every", [0, 1])
+def test_batched_dense_repeatable(sort_every):
+    # dense simulations (volume fraction up to 0.6): the waves share out
+    # their pair terms.  Contexts made again and again in one process (the
+    # allocator hands back memory the last one used, here filled with a
+    # pattern) give each simulation's plain run bit for bit every time
+    w = workloads.c4(nsims=10, nmin=500, nmax=4000, seed=14, steps=5)
+    off = w.offsets
+    note(f"batched dense repeat sort_every={sort_every} n={w.n}")
+    want = []
+    for s in range(len(off) - 1):
+        a, e = off[s], off[s + 1]
+        sim = make_sim(w.pos[a:e], w.diam[a:e], sort_every=sort_every)
+        sim.step(w.steps)
+        want.append(sim.query("positions").cpu().numpy())
+    for rep in range(4):
+        b = abm.BatchedSim(to_dev(w.pos), to_dev(w.diam), off, common=dict(sort_every=sort_every))
+        b.step(w.steps)
+        got = b.query("positions").cpu().numpy()
+        for s in range(len(off) - 1):
+            np.testing.assert_array_equal(got[off[s]:off[s + 1]], want[s], err_msg=f"rep {rep} sim {s}")
+        del b
+        junk = torch.full((64 << 20,), 0x7F, dtype=torch.uint8, device="cuda")
+        del junk

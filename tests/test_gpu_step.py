@@ -251,3 +251,23 @@ def test_dense_packing_matches_oracle_bitwise(walk_chunk):
         np.testing.assert_array_equal(g["pos"], st.pos, err_msg=f"step {t}")
         np.testing.assert_array_equal(g["nnz"], st.nnz, err_msg=f"step {t}")
     assert st.nnz.mean() > 3.0 and st.nnz.max() >= 8
+
+
+@pytest.mark.parametrize("sort_every", [0, 1])
+def test_repeated_contexts_match_oracle(sort_every):
+    # the adjoint workload's density (about 47 candidates per agent, the
+    # 4-wide walk): contexts made one after another in one process, on
+    # memory the last one used (filled with a pattern in between), each
+    # give the oracle's 10 steps bit for bit
+    w = workloads.c5()
+    note(f"repeated contexts sort_every={sort_every} n={w.n}")
+    ref = oracle.State.initial(w.pos, w.diam)
+    for _ in range(10):
+        oracle.step(ref, oracle.Params())
+    for rep in range(4):
+        sim = make_sim(w.pos, w.diam, sort_every=sort_every)
+        sim.step(10)
+        np.testing.assert_array_equal(sim.query("positions").cpu().numpy(), ref.pos, err_msg=f"rep {rep}")
+        sim.close()
+        junk = torch.full((64 << 20,), 0x7F, dtype=torch.uint8, device="cuda")
+        del junk

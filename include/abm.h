@@ -11,7 +11,10 @@
  *     causes, with a force threshold (Section 5; force law: see below);
  *   - the skip of the force computation for static agents (Section 5);
  *   - agents re-laid out along the Morton curve every sort_every steps
- *     (Section 4.2, step G);
+ *     (Section 4.2, step G), or, as an option, with the 2x2x2 blocks of
+ *     boxes along a Hilbert curve (the other curve Section 4.2 compares);
+ *   - agents added, removed and given new diameters between steps
+ *     (Section 3.2; conditions (ii) and (iii) of the static test, Section 5);
  *   - a batched form (many independent simulations per launch) and a
  *     reverse-mode (adjoint) form of the step.
  *

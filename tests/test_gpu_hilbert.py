@@ -90,3 +90,26 @@ def test_hilbert_order_arguments():
     assert e.value.code == abm.ABM_E_UNSUPPORTED
     sim.step(2)
     sim.sync()
+
+
+def test_hilbert_adjoint_matches_oracle():
+    # the reverse step in the Hilbert order against the oracle's reverse mode
+    # in that order: the pair terms are summed in another order than the
+    # oracle's (see the steps above), so positions agree to 1e-12 and the
+    # gradients to the adjoint's 1e-9
+    import torch
+    g = np.random.default_rng(46)
+    n = 3000
+    side = (n / workloads.C1_DENSITY) ** (1 / 3)
+    pos = g.uniform(0, side, size=(n, 3))
+    diam = g.uniform(8, 12, size=n)
+    target = pos + g.normal(0, 0.5, size=(n, 3))
+    note(f"hilbert adjoint n={n}")
+    sim = make_sim(pos, diam, order="hilbert")
+    sim.forward_record(12, 5)
+    xT = sim.query("positions").double()
+    gx0, gp = sim.backward(2.0 * (xT - torch.from_numpy(target).cuda()) / (3 * n))
+    ref = oracle.adjoint(pos, diam, 12, oracle.Params(order=1), target)
+    assert np.abs(xT.cpu().numpy() - ref["posT"]).max() <= 1e-12 * np.abs(ref["posT"]).max()
+    np.testing.assert_allclose(gp.cpu().numpy(), [ref["dL_dk"], ref["dL_dgamma"]], rtol=1e-9)
+    assert np.abs(gx0.cpu().numpy() - ref["dL_dx0"]).max() <= 1e-9 * np.abs(ref["dL_dx0"]).max()

@@ -361,8 +361,7 @@ void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s
 // walk down the curve's octree (hil: the curve's tables, an LDS copy).
 // false if the position lies outside the grid.
 template <class T>
-__device__ __forceinline__ bool super_key(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, uint32_t* key,
-                                          const HilbertTables* hil) {
+__device__ __forceinline__ bool super_key(const SimGrid& G, const V4<T>& p, uint32_t* key, const HilbertTables* hil) {
     uint32_t q[3];
     if (!box_of<T>(G, p, q)) return false;
     uint32_t rank;
@@ -452,7 +451,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur, in
             if (i < b.n) {
                 const SimGrid& G = b.sims[sim_index(b, i)];
                 if (G.valid) {
-                    if (super_key<T>(b, G, pos4_ptr(b, cur)[i], &key, hil)) {
+                    if (super_key<T>(G, pos4_ptr(b, cur)[i], &key, hil)) {
                         act = true;
                     } else {   // the extent is computed from these very positions
                         raise_error(b.g, kErrInternal);
@@ -495,7 +494,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur, in
         const SimGrid& G = b.sims[sim_index(b, i)];
         const uint32_t old = b.skey[cur][i];
         uint32_t key = old, real = 0;
-        if (!G.valid || (old >> 3) >= total || !super_key<T>(b, G, pos4_ptr(b, cur)[i], &key, hil)) {
+        if (!G.valid || (old >> 3) >= total || !super_key<T>(G, pos4_ptr(b, cur)[i], &key, hil)) {
             raise_error(b.g, kErrInternal);
             key = old;
         } else if (key != old) {

@@ -167,10 +167,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
         }
         // ---- the walk and the pair terms, with every lane of the wave (a lane
         // that does not walk has no pieces), so that the wave can share out
-        // its pair terms (batched: dense simulations, uneven contact counts)
+        // its pair terms where contacts are many and uneven: batched (dense
+        // simulations) and the 4-wide walk (one or more agents per box)
         if (!walks) P.mask = 0u;
         ForceSum acc;
-        force_of<CH, T, false, BATCHED>(b, *Gp, p, P, L, acc);
+        force_of<CH, T, false, BATCHED || CH == 4>(b, *Gp, p, P, L, acc);
         // ---- after the walk, per agent
         if (active && Gp->valid) {
             const SimGrid& G = *Gp;

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, co
         } else {
             raise_error(b.g, kErrInternal);
         }
-        for (int a = 0; a < 3; ++a) w[3 * size_t(i) + a] = wi[a];
+        for (int a = 0; a < 3; ++a) w[3 * size_t(t) + a] = wi[a];   // by canonical slot: the gather reads it there
     }
     // fixed-shape tree reduction: the result does not depend on timing
     s_k[threadIdx.x] = gk;
@@ -75,54 +75,120 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, co
     }
 }
 
+// One term of the update of lambda_m for its contact at loose slot u:
+// A_mj (w_m - w_j), zero for a slot that holds no agent.  w is indexed by
+// canonical slot (the agent at loose slot n + t has w[t]).
+template <class T>
+__device__ __forceinline__ void gather_term(const Buffers<T>& b, const SimGrid& G, double xm, double ym, double zm,
+                                            double rm, const double wm[3], const double* __restrict__ w,
+                                            const V4<T>& pj, uint32_t u, double out[3]) {
+    out[0] = out[1] = out[2] = 0.0;
+    if (u < b.n) return;
+    const uint32_t j = u - b.n;   // w is kept by canonical slot
+    if (j >= b.n) return;
+    const double ev3[3] = {xm - double(pj.x), ym - double(pj.y), zm - double(pj.z)};
+    const double s2 = (ev3[0] * ev3[0] + ev3[1] * ev3[1]) + ev3[2] * ev3[2];
+    const double rj = 0.5 * fabs(double(pj.w)), S = rm + rj;
+    const double dist = sqrt(s2);
+    const double delta = S - dist, rho = (rm * rj) / S;
+    const double f = G.k * delta - G.gamma * sqrt(rho * delta);
+    const double fp = G.k - G.gamma * rho / (2.0 * sqrt(rho * delta));
+    const double gd = f / dist;
+    const double gprime = -(fp * dist + f) / (dist * dist);
+    const double v[3] = {wm[0] - w[3 * size_t(j)], wm[1] - w[3 * size_t(j) + 1], wm[2] - w[3 * size_t(j) + 2]};
+    const double ev = ev3[0] * v[0] + ev3[1] * v[1] + ev3[2] * v[2];
+    for (int a = 0; a < 3; ++a) out[a] = gd * v[a] + gprime / dist * ev3[a] * ev;
+}
+
+// lambda_m <- lambda_m + sum_j A_mj (w_m - w_j) over the contacts of m, in
+// slot order.  Every lane of the wave takes part (none returns early): the
+// contacts, several per agent and uneven, are dealt out over the wave, one
+// per lane, and each term goes back to its agent's lane by register
+// shuffles; a lane whose queue fills with contacts mid-walk adds those
+// itself.  The sums are in slot order either way.
 template <class T>
 __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cur, const double* __restrict__ lam,
                                                              const double* __restrict__ w,
                                                              double* __restrict__ lam_out) {
     extern __shared__ __align__(16) unsigned char s_walk[];
     const WalkLds L = walk_lds(s_walk);
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= b.n) return;
-    const SimGrid& G = b.sims[sim_index(b, t)];
-    const uint32_t m = b.perm[t];
-    if (m >= b.n) {
-        raise_error(b.g, kErrInternal);
-        return;
-    }
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, tid = threadIdx.x, bs = blockDim.x;
+    const SimGrid& G = b.sims[0];   // the adjoint covers one simulation
     const V4<T>* __restrict__ sp = gpos_ptr(b);
-    const V4<T> p = sp[b.n + t];
-    uint32_t q[3];
-    double acc[3] = {lam[3 * size_t(m)], lam[3 * size_t(m) + 1], lam[3 * size_t(m) + 2]};
-    if (G.valid && box_of<T>(G, p, q)) {
-        const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
-        const double xm = double(p.x), ym = double(p.y), zm = double(p.z);
-        const double rm = 0.5 * fabs(double(p.w));
-        const double wm[3] = {w[3 * size_t(m)], w[3 * size_t(m) + 1], w[3 * size_t(m) + 2]};
-        stream_pieces(L, P, [&](uint32_t u) {
-            if (u == b.n + t || u < b.n) return true;
-            const uint32_t j = b.perm[u - b.n];
-            if (j >= b.n) return true;
-            const V4<T> pj = sp[u];
-            const double ev3[3] = {xm - double(pj.x), ym - double(pj.y), zm - double(pj.z)};
-            const double s2 = (ev3[0] * ev3[0] + ev3[1] * ev3[1]) + ev3[2] * ev3[2];
-            if (!(s2 < G.r2)) return true;
-            const double rj = 0.5 * fabs(double(pj.w)), S = rm + rj;
-            if (!(s2 > 0.0) || !(s2 < S * S)) return true;
-            const double dist = sqrt(s2);
-            const double delta = S - dist, rho = (rm * rj) / S;
-            const double f = G.k * delta - G.gamma * sqrt(rho * delta);
-            const double fp = G.k - G.gamma * rho / (2.0 * sqrt(rho * delta));
-            const double gd = f / dist;
-            const double gprime = -(fp * dist + f) / (dist * dist);
-            const double v[3] = {wm[0] - w[3 * size_t(j)], wm[1] - w[3 * size_t(j) + 1], wm[2] - w[3 * size_t(j) + 2]};
-            const double ev = ev3[0] * v[0] + ev3[1] * v[1] + ev3[2] * v[2];
-            for (int a = 0; a < 3; ++a) acc[a] += gd * v[a] + gprime / dist * ev3[a] * ev;
-            return true;
-        });
-    } else {
-        raise_error(b.g, kErrInternal);
+    const uint32_t last = 2u * b.n - 1u;
+    uint32_t m = 0xFFFFFFFFu;
+    if (t < b.n) {
+        m = b.perm[t];
+        if (m >= b.n) raise_error(b.g, kErrInternal);
     }
-    for (int a = 0; a < 3; ++a) lam_out[3 * size_t(m) + a] = acc[a];
+    const bool has = m < b.n;
+    V4<T> p{};
+    Pieces P;
+    double acc[3] = {0.0, 0.0, 0.0}, wm[3] = {0.0, 0.0, 0.0};
+    if (has) {
+        p = sp[b.n + t];
+        for (int a = 0; a < 3; ++a) {
+            acc[a] = lam[3 * size_t(m) + a];
+            wm[a] = w[3 * size_t(t) + a];
+        }
+        uint32_t q[3];
+        if (G.valid && box_of<T>(G, p, q))
+            P = load_pieces(b, G, q, b.g->stamp, L);
+        else
+            raise_error(b.g, kErrInternal);
+    }
+    const double xm = double(p.x), ym = double(p.y), zm = double(p.z);
+    const double rm = 0.5 * fabs(double(p.w));
+    const uint32_t kept = queue_contacts<kAdjChunk, T>(b, G, p, P, L, [&](uint32_t k) {
+        for (uint32_t r = 0; r < k; ++r) {
+            const uint32_t u = L.queue[r * bs + tid];
+            double o[3];
+            gather_term<T>(b, G, xm, ym, zm, rm, wm, w, sp[min(u, last)], u, o);
+            for (int a = 0; a < 3; ++a) acc[a] += o[a];
+        }
+    });
+    // the wave's remaining contacts: lane l's rows [0, kept) are pairs
+    // [off, off + kept) of the wave, pair x evaluated by lane x mod 64
+    const uint32_t lane = uint32_t(lane_id()), wbase = tid - lane;
+    uint32_t incl = kept;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 64);
+        if (lane >= uint32_t(d)) incl += y;
+    }
+    const uint32_t off = incl - kept, total = __shfl(incl, 63, 64);
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t x = base + lane;
+        uint32_t o = 0;   // the pair's agent: the last lane whose pairs start at or before x
+        for (uint32_t step = 32; step >= 1; step >>= 1) {
+            const uint32_t v = __shfl(off, int(o + step), 64);
+            o = v <= x ? o + step : o;
+        }
+        const uint32_t row = x - __shfl(off, int(o), 64);
+        const double oxm = __shfl(xm, int(o), 64), oym = __shfl(ym, int(o), 64), ozm = __shfl(zm, int(o), 64);
+        const double orm = __shfl(rm, int(o), 64);
+        const double owm[3] = {__shfl(wm[0], int(o), 64), __shfl(wm[1], int(o), 64), __shfl(wm[2], int(o), 64)};
+        double term[3] = {0.0, 0.0, 0.0};
+        if (x < total) {
+            const uint32_t u = L.queue[min(row, uint32_t(kQueueCap - 1)) * bs + wbase + o];
+            gather_term<T>(b, G, oxm, oym, ozm, orm, owm, w, sp[min(u, last)], u, term);
+        }
+        // the terms go back to their agent's lane: the j-th of every lane at once
+        const uint32_t j0 = max(off, base), j1 = min(off + kept, base + 64u);
+        const uint32_t cnt = j1 > j0 ? j1 - j0 : 0u;
+        uint32_t most = cnt;
+        for (int d = 32; d >= 1; d >>= 1) most = max(most, uint32_t(__shfl_xor(int(most), d, 64)));
+        for (uint32_t j = 0; j < most; ++j) {
+            const int src = int(min(j0 + j - base, 63u));
+            const double v0 = __shfl(term[0], src, 64), v1 = __shfl(term[1], src, 64), v2 = __shfl(term[2], src, 64);
+            if (j < cnt) {
+                acc[0] += v0;
+                acc[1] += v1;
+                acc[2] += v2;
+            }
+        }
+    }
+    if (has)
+        for (int a = 0; a < 3; ++a) lam_out[3 * size_t(m) + a] = acc[a];
 }
 
 // dparams[0..1] += the block partials, summed in block order by one block.

@@ -477,6 +477,67 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
     }
 }
 
+// The walk's pre-test and exact test for agent p, keeping its contacts
+// (neighbours within R, 0 < |e| < r_i + r_j) at the head of its LDS queue in
+// slot order; returns their number, rows [0, kept).  When contacts fill the
+// queue mid-walk, own(kept) consumes rows [0, kept) first.
+template <int CH, class T, class Own>
+__device__ __forceinline__ uint32_t queue_contacts(const Buffers<T>& b, const SimGrid& G, const V4<T>& p,
+                                                   const Pieces& P, const WalkLds& L, Own&& own) {
+    const V4<T>* __restrict__ sp = gpos_ptr(b);
+    const uint32_t tid = threadIdx.x, bs = blockDim.x, last = 2u * b.n - 1u;
+    const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
+    const double ri = 0.5 * fabs(double(p.w));
+    const double r2 = G.r2;
+    const float r2pad = padded_r2(r2);
+    uint32_t n = 0, kept = 0;
+    // exact test of rows [kept, n), the contacts kept in place after row kept
+    auto exact = [&]() {
+        uint32_t m = kept;
+        for (uint32_t x0 = kept; x0 < n; x0 += 4) {
+            V4<T> pj[4];
+            uint32_t uq[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                uq[c] = L.queue[min(x0 + c, n - 1) * bs + tid];
+                pj[c] = sp[min(uq[c], last)];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double ex = xi - double(pj[c].x), ey = yi - double(pj[c].y), ez = zi - double(pj[c].z);
+                const double s2 = (ex * ex + ey * ey) + ez * ez;
+                const double S = ri + 0.5 * fabs(double(pj[c].w));
+                const bool keep = x0 + c < n && s2 < r2 && s2 > 0.0 && s2 < S * S;
+                L.queue[m * bs + tid] = uq[c];
+                m += keep ? 1u : 0u;
+            }
+        }
+        kept = m;
+        n = m;
+    };
+    uint32_t qo = tid;
+    walk_chunks<CH>(b, P, L, [&](const V4<T>* pc, uint32_t u, uint32_t left) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const uint32_t pass = uint32_t(uint32_t(c) < left) & uint32_t(maybe_within<T>(p, pc[c], r2pad));
+            L.queue[qo] = u + c;   // n < kQueueCap here
+            n += pass;
+            qo += pass ? bs : 0u;
+        }
+        if (n > uint32_t(kQueueCap - CH)) {
+            exact();
+            if (kept > uint32_t(kQueueCap - CH)) {
+                own(kept);
+                kept = n = 0;
+            }
+            qo = n * bs + tid;
+        }
+        return true;
+    });
+    exact();
+    return kept;
+}
+
 // Displacement rule: Delta = mu F if |F| > f_adh, clamped to delta_max.
 struct Move {
     double ux = 0.0, uy = 0.0, uz = 0.0;

@@ -2,12 +2,12 @@
 """Benchmark of the agent step on one MI355X.
 
 Headline: agent-steps/s of the plain step (grid build + static flags + force
-+ move, every agent's force computed) on 1e7 spheres in FP32 state, the c2
-construction scaled to 1e7 agents (uniform inner cube + force-free jittered
++ move, the force of static agents skipped) on 1e7 spheres in FP32 state, the
+c2 construction scaled to 1e7 agents (uniform inner cube + force-free jittered
 lattice shell, cube side 3387.7, d ~ U[8, 12]).  Beside it, on the same GPU:
-the static skip switched on, the batched form (512 simulations, 50 steps in
-one graph launch) and the adjoint form (1e5 spheres, 50 steps forward +
-backward), each as agent-steps/s; the dominant kernel's roofline from HIP
+the same steps without the static skip and in the Hilbert order, the batched
+form (512 simulations, 50 steps in one graph launch) and the adjoint form (1e5
+spheres, 50 steps forward + backward), each as agent-steps/s; the dominant kernel's roofline from HIP
 events around it over the timed region; and the CPU oracle timed on a bounded
 sample of the same workload.
 
@@ -37,12 +37,12 @@ FORCE_BYTES = {"f32": 4 * 4 + 4 + 3 * 4, "f64": 4 * 8 + 4 + 3 * 8}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_headline_traffic.json")
 
 
-def measured_traffic(n, prec, block_size, order="morton"):
+def measured_traffic(n, prec, block_size, order="morton", skip=True):
     """HBM bytes per force launch from the committed FETCH_SIZE/WRITE_SIZE
     counter runs (scaled by a plain copy's reading), or None when the kernel
     sources changed since the counters were taken or the configuration
     differs from the profiled one (1e7 agents, FP32 state, 256 threads,
-    Morton order)."""
+    Morton order, static skip on)."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
@@ -54,7 +54,7 @@ def measured_traffic(n, prec, block_size, order="morton"):
     except (OSError, KeyError, ValueError):
         return None
     if (h.hexdigest() != rec["source_sha256"] or n != 10_000_000 or prec != "f32" or block_size != 256
-            or order != "morton"):
+            or order != "morton" or not skip):
         return None
     return float(rec["traffic_bytes"])
 
@@ -79,12 +79,12 @@ def timed_steps(sim, steps, timing=False):
     return t1 - t0, tm
 
 
-def cpu_baseline(w, budget_s: float):
+def cpu_baseline(w, budget_s: float, skip: bool):
     """The oracle (as it is) on the same workload, whole steps until the budget is used."""
     import numpy as np
     import oracle
     st = oracle.State.initial(w.pos, w.diam)
-    p = oracle.Params(detect_static=False)
+    p = oracle.Params(detect_static=skip)
     steps = 0
     t0 = time.perf_counter()
     while True:
@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--block-size", type=int, default=256)
+    ap.add_argument("--skip", action=argparse.BooleanOptionalAction, default=True,
+                    help="the static skip (Section 5) in the headline run (--no-skip: every force computed)")
     ap.add_argument("--order", choices=["morton", "hilbert"], default="morton",
                     help="order of the boxes for the headline run (the legs keep their own)")
     ap.add_argument("--sort-every", type=int, default=1)
@@ -193,7 +195,7 @@ def main():
     w = workloads.headline(n=args.n)
     pos = torch.from_numpy(w.pos).to(dev)
     diam = torch.from_numpy(w.diam).to(dev)
-    sim = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size,
+    sim = abm.Sim(pos, diam, detect_static=args.skip, sort_every=args.sort_every, block_size=args.block_size,
                   order=args.order)
     sim.step(args.warmup)
     sim.sync()
@@ -206,7 +208,7 @@ def main():
     prec = w.precision
     force_bytes = FORCE_BYTES[prec] * w.n
     ach = force_bytes / (phases["force"] * 1e-3) / 1e9
-    traffic = measured_traffic(w.n, prec, args.block_size, args.order)
+    traffic = measured_traffic(w.n, prec, args.block_size, args.order, args.skip)
     roof = dict(bound="hbm", kernel="k_force (static flags + force + move)", achieved=round(ach, 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic), traffic_unit="bytes per launch",
@@ -216,13 +218,14 @@ def main():
                 step_bytes_per_agent=STEP_BYTES[prec],
                 step_frac=round(value * STEP_BYTES[prec] / (HBM_PEAK_GBS * 1e9), 4))
     log(f"headline {value:.3e} agent-steps/s, {ms_step:.3f} ms/step, phases {phases}")
+    sim_stats = sim.stats()
     del sim
 
     extras = {}
     if not args.no_extras:
         # Hilbert order of the super-boxes (the other curve Section 4.2
         # compares): the same steps, only the order of the boxes changed
-        sh = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size,
+        sh = abm.Sim(pos, diam, detect_static=args.skip, sort_every=args.sort_every, block_size=args.block_size,
                      order="hilbert")
         sh.step(args.warmup)
         sh.sync()
@@ -235,15 +238,17 @@ def main():
                                       "phase_ms of the Morton run are under roofline")
         log(f"hilbert {extras['hilbert']}")
         del sh
-        # static skip on (same workload): the shell is force-free and static
-        s2 = abm.Sim(pos, diam, detect_static=True, sort_every=args.sort_every, block_size=args.block_size)
+        # the other setting of the static skip (same workload; the shell is
+        # force-free and static from its first step)
+        s2 = abm.Sim(pos, diam, detect_static=not args.skip, sort_every=args.sort_every, block_size=args.block_size)
         s2.step(args.warmup)
         el2, _ = timed_steps(s2, args.steps)
-        st = s2.stats()
-        extras["skip_on"] = dict(value=w.n * args.steps / el2, unit="agent-steps/s",
-                                 speedup_vs_skip_off=round(el / el2, 3),
-                                 static_fraction_last_step=round(st["n_static"] / w.n, 4))
-        log(f"skip on {extras['skip_on']}")
+        el_on, el_off = (el, el2) if args.skip else (el2, el)
+        son = (sim_stats if args.skip else s2.stats())
+        extras["static_skip"] = dict(skip_on=w.n * args.steps / el_on, skip_off=w.n * args.steps / el_off,
+                                     unit="agent-steps/s", speedup_on_vs_off=round(el_off / el_on, 3),
+                                     static_fraction_last_step=round(son["n_static"] / w.n, 4))
+        log(f"static skip {extras['static_skip']}")
         del s2
         # dynamic population (Section 3.2): 1% of the agents removed and as
         # many added between two steps; the next grid is a full build
@@ -356,14 +361,14 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
-        cpu = cpu_baseline(w, args.cpu_budget)
+        cpu = cpu_baseline(w, args.cpu_budget, args.skip)
 
     out = {"metric": METRIC, "value": value, "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "headline: 1e7 spheres, c2 construction (uniform inner cube + jittered "
                                   "force-free lattice shell), side 3387.7, d~U[8,12], seed 2",
-                      "n": w.n, "state": prec, "arithmetic": "f64", "detect_static": False,
+                      "n": w.n, "state": prec, "arithmetic": "f64", "detect_static": bool(args.skip),
                       "sort_every": args.sort_every, "block_size": args.block_size, "order": args.order},
            "roofline": roof, "cpu_baseline": cpu, **extras}
     line = json.dumps(out)

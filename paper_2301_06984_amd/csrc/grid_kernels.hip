@@ -465,18 +465,19 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur, in
         }
         return;
     }
-    uint32_t f[kKeysPer];
+    // flags and (for the moved octants) keys requested together
+    uint32_t f[kKeysPer], sk[kKeysPer];
 #pragma unroll
     for (int k = 0; k < kKeysPer; ++k) {
         const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
         f[k] = i < b.n ? b.flags[cur][i] : 0u;
+        sk[k] = moved_bits && i < b.n ? b.skey[cur][i] : kDeadKey;
     }
     if (moved_bits) {   // agents in storage order: equal super-boxes in runs
         const uint32_t total = b.g->total_super;
 #pragma unroll
         for (int k = 0; k < kKeysPer; ++k) {
-            const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
-            const uint32_t key = i < b.n ? b.skey[cur][i] : kDeadKey;
+            const uint32_t key = sk[k];
             const bool act = key != kDeadKey && (key >> 3) < total;
             wave_run_or(b.mmask, act, key >> 3, (f[k] & kMovedBit) << (key & 7u));
         }

@@ -12,7 +12,7 @@ from paper_2301_06984_amd import abm, workloads
 
 pytestmark = pytest.mark.gpu
 
-BENCH = dict(sort_every=1, block_size=256)
+BENCH = dict(sort_every=1, block_size=256, detect_static=True)   # the benchmark's launch configuration
 
 
 def check_samples(pos, diam, got_pos, nsamples, seed, params=oracle.Params()):
@@ -54,8 +54,8 @@ def test_headline_1e7_first_step():
 def test_c2_full_parity_and_skip():
     w = workloads.c2()
     note(f"c2 n={w.n}")
-    on = make_sim(w.pos, w.diam, detect_static=True, **BENCH)
-    off = make_sim(w.pos, w.diam, detect_static=False, **BENCH)
+    on = make_sim(w.pos, w.diam, **{**BENCH, "detect_static": True})
+    off = make_sim(w.pos, w.diam, **{**BENCH, "detect_static": False})
     on.step(1)
     st = oracle.State.initial(w.pos, w.diam)
     oracle.step(st, oracle.Params(detect_static=True))

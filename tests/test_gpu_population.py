@@ -189,6 +189,26 @@ def test_set_diameters_match_oracle(precision, detect_static):
         step_and_compare(sim, diam, p, detect_static)
 
 
+def test_static_switched_on_between_steps():
+    """The static test switched on between steps: the first step that runs it
+    already skips every agent the oracle calls static (the moved octants of
+    the super-boxes come from the agents, not from steps that did not run
+    the test), and it stays so over the update builds that follow."""
+    w = workloads.c2(n=6000, seed=101)
+    pos, diam = w.pos, w.diam.copy()
+    R = float(diam.max())
+    note(f"static switched on n={pos.shape[0]}")
+    sim = make_sim(pos, diam, detect_static=False, interaction_radius=R)
+    p = oracle.Params(detect_static=False, interaction_radius=R)
+    for _ in range(3):
+        step_and_compare(sim, diam, p, False)
+    sim.set_params(detect_static=True)
+    p = oracle.Params(detect_static=True, interaction_radius=R)
+    for _ in range(4):
+        step_and_compare(sim, diam, p, True)
+    assert sim.query("static").cpu().numpy().sum() > pos.shape[0] // 4
+
+
 def test_set_diameters_errors_leave_state():
     w = workloads.c1(n=1000, seed=96)
     R = float(w.diam.max())

@@ -242,7 +242,7 @@ def main():
         # force-free and static from its first step)
         s2 = abm.Sim(pos, diam, detect_static=not args.skip, sort_every=args.sort_every, block_size=args.block_size)
         s2.step(args.warmup)
-        el2, _ = timed_steps(s2, args.steps)
+        el2, _ = timed_steps(s2, args.steps, timing=True)   # timed as the headline (its phase events too)
         el_on, el_off = (el, el2) if args.skip else (el2, el)
         son = (sim_stats if args.skip else s2.stats())
         extras["static_skip"] = dict(skip_on=w.n * args.steps / el_on, skip_off=w.n * args.steps / el_off,

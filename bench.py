@@ -151,7 +151,7 @@ def main():
     ap.add_argument("--order", choices=["morton", "hilbert"], default="morton",
                     help="order of the boxes for the headline run (the legs keep their own)")
     ap.add_argument("--sort-every", type=int, default=1)
-    ap.add_argument("--no-extras", action="store_true", help="skip the skip-on, batched and adjoint legs")
+    ap.add_argument("--no-extras", action="store_true", help="leave out the Hilbert, static-skip, dynamic, batched and adjoint legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--json-out", default=None)

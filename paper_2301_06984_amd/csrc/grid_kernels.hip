@@ -232,6 +232,7 @@ void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s) {
 // the shared box arrays.  Also clears the other accumulator for this step's
 // move kernel and the step statistics.
 constexpr int kSetupThreads = 1024;
+constexpr int kSetupLdsSims = 512;   // simulations whose box ranges the block folds in LDS
 constexpr uint32_t kFixupLanes = 8;   // threads per changed super-box in an update build
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* sims, int32_t* rep, int nsims,
@@ -240,9 +241,27 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
     __shared__ unsigned long long s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
     __shared__ uint32_t s_same;
+    __shared__ int32_t s_bb[kSetupLdsSims][6];
     if (threadIdx.x == 0) {
         s_carry = 0;
         s_same = 1u;
+    }
+    // each simulation's box range from its replicas: one wave per simulation,
+    // one lane per replica (below kSetupLdsSims simulations; else per thread)
+    static_assert(kReplicas == 64, "one lane per replica");
+    const bool wave_fold = nsims <= kSetupLdsSims;
+    if (wave_fold) {
+        for (int s = int(threadIdx.x >> 6); s < nsims; s += kSetupThreads / 64) {
+            const int32_t* t = rep + ((size_t(parity) * kReplicas + size_t(lane_id())) * size_t(nsims) + s) * 6;
+            int32_t bb[6];
+            for (int a = 0; a < 6; ++a) bb[a] = t[a];
+            for (int a = 0; a < 3; ++a) {
+                bb[a] = wave_min(bb[a]);
+                bb[3 + a] = wave_max(bb[3 + a]);
+            }
+            if (lane_id() == 0)
+                for (int a = 0; a < 6; ++a) s_bb[s][a] = bb[a];
+        }
     }
     // the other accumulator slot and this step's statistics start empty
     const size_t per = size_t(kReplicas) * size_t(nsims);
@@ -263,11 +282,15 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
             SimGrid& G = sims[s];
             same = G.valid != 0u;   // the last grid of this simulation was built
             int32_t bb[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
-            for (int r = 0; r < kReplicas; ++r) {
-                const int32_t* t = rep + ((size_t(parity) * kReplicas + r) * size_t(nsims) + s) * 6;
-                for (int a = 0; a < 3; ++a) {
-                    bb[a] = min(bb[a], t[a]);
-                    bb[3 + a] = max(bb[3 + a], t[3 + a]);
+            if (wave_fold) {
+                for (int a = 0; a < 6; ++a) bb[a] = s_bb[s][a];
+            } else {
+                for (int r = 0; r < kReplicas; ++r) {
+                    const int32_t* t = rep + ((size_t(parity) * kReplicas + r) * size_t(nsims) + s) * 6;
+                    for (int a = 0; a < 3; ++a) {
+                        bb[a] = min(bb[a], t[a]);
+                        bb[3 + a] = max(bb[3 + a], t[3 + a]);
+                    }
                 }
             }
             bool ok = true;
@@ -525,7 +548,8 @@ __device__ __forceinline__ uint32_t wave_inclusive(uint32_t x) {
 // Exclusive scan of the super-box counts into cell_start[0, total], zeroing
 // count, in three passes over tiles of kScanTile super-boxes: per-tile sums,
 // a one-block scan of the tile sums, and a per-tile rescan that adds the
-// tile's prefix.  Global loads and stores of the counts are striped across
+// tile's prefix (with few tiles, the rescan adds up the sums before its tile
+// itself, and the one-block scan has nothing to do).  Global loads and stores of the counts are striped across
 // the block and transposed through LDS, so every wave touches whole cache
 // lines.  An update build scans two more quantities along: the changed
 // super-boxes (marked with this build's epoch) and their agents; the rescan
@@ -651,6 +675,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Globals* g, 
 // agents, and in an update build the number of changed super-boxes and of
 // their agents.
 constexpr int kTileScanThreads = 1024;
+// Up to this many tiles in use, the rescan adds up the tile sums before its
+// tile itself (at most 24 KB of reads per block) and the one-block scan
+// returns at once.
+constexpr uint32_t kFusedScanTiles = 2048;
 __global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uint32_t* __restrict__ sums,
                                                                   uint32_t* __restrict__ cell_start,
                                                                   uint32_t ntiles) {
@@ -658,6 +686,7 @@ __global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uin
     __shared__ uint32_t s_carry;
     const uint32_t total = g->total_super;
     const uint32_t needed = (total + kScanTile - 1) / kScanTile;
+    if (needed <= kFusedScanTiles) return;   // the rescan adds up the tile sums itself
     if (needed > ntiles) {
         if (threadIdx.x == 0) raise_error(g, kErrInternal);
         return;
@@ -690,31 +719,52 @@ __global__ __launch_bounds__(kTileScanThreads) void k_scan_tiles(Globals* g, uin
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, ScanIn in, uint32_t* __restrict__ count,
+// With few tiles (fused), the tile sums are as the first pass wrote them:
+// each block adds up those of the tiles before its own (so the one-block scan
+// is not launched), and the block of the last tile writes the totals.
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(Globals* g, ScanIn in, uint32_t* __restrict__ count,
                                                              uint32_t* __restrict__ cell_start,
                                                              const uint32_t* __restrict__ sums,
                                                              uint32_t* __restrict__ dirty_list,
                                                              uint32_t* __restrict__ aoff, uint32_t ntiles) {
     __shared__ uint32_t s_data[kScanTile + kScanTile / 32];
     __shared__ uint32_t s_wave[3][kScanThreads / 64];
+    __shared__ uint32_t s_pre[3][kScanThreads / 64];
     const uint32_t total = g->total_super;
     const uint32_t tile = blockIdx.x;
+    const uint32_t needed = (total + kScanTile - 1) / kScanTile;
+    const bool fused = needed <= kFusedScanTiles;
+    if (fused && tile == 0 && threadIdx.x == 0 && needed > ntiles) raise_error(g, kErrInternal);
     if (tile * uint32_t(kScanTile) >= total || tile >= ntiles) return;
     const bool inc = g->inc != 0u;
+    const int ncomp = inc ? 3 : 1;
     const uint32_t base = tile * kScanTile;
+    const int wave = int(threadIdx.x >> 6);
+    uint32_t pre[3] = {0u, 0u, 0u};
+    if (fused) {   // the sums of the tiles before this one
+        for (uint32_t t = threadIdx.x; t < tile; t += kScanThreads)
+            for (int c = 0; c < ncomp; ++c) pre[c] += sums[c * ntiles + t];
+        for (int c = 0; c < ncomp; ++c) {
+            for (int d = 32; d >= 1; d >>= 1) pre[c] += __shfl_xor(pre[c], d, 64);
+            if (lane_id() == 0) s_pre[c][wave] = pre[c];
+        }
+    }
     uint32_t v[kScanItems], dm;
     load_tile(in, g->epoch, inc, false, base, total, s_data, v, &dm);
     uint32_t x[3], run[3];
     thread_sums(v, dm, x);
-    const int wave = int(threadIdx.x >> 6);
     for (int c = 0; c < 3; ++c) {
         const uint32_t incl = wave_inclusive(x[c]);
         if (lane_id() == 63) s_wave[c][wave] = incl;
         run[c] = incl - x[c];
     }
     __syncthreads();
-    for (int c = 0; c < (inc ? 3 : 1); ++c) {
-        run[c] += sums[c * ntiles + tile];
+    for (int c = 0; c < ncomp; ++c) {
+        if (fused) {
+            for (int w = 0; w < kScanThreads / 64; ++w) run[c] += s_pre[c][w];
+        } else {
+            run[c] += sums[c * ntiles + tile];
+        }
         for (int w = 0; w < wave; ++w) run[c] += s_wave[c][w];
     }
     const uint32_t g0 = base + threadIdx.x * kScanItems;
@@ -727,6 +777,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const Globals* g, Sc
             run[2] += v[k];
         }
         run[0] += v[k];
+    }
+    // the last thread of the last tile ends with the totals
+    if (fused && tile + 1 == needed && threadIdx.x == kScanThreads - 1) {
+        cell_start[total] = run[0];
+        if (inc) {
+            g->ndirty = run[1];
+            g->napp = run[2];
+        }
     }
     __syncthreads();
     for (int k = 0; k < kScanItems / 4; ++k) {

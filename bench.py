@@ -174,8 +174,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the spatial decomposition over GPUs is a design, see DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the spatial decomposition over GPUs is designed, not built).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

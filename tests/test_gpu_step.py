@@ -182,6 +182,35 @@ def test_set_params_matches_oracle():
     np.testing.assert_array_equal(g["nnz"], st.nnz)
 
 
+def test_many_scan_tiles_update_builds():
+    """A thin plane of 1e8 boxes (about 3000 scan tiles of super-boxes in use,
+    more than the rescan adds up by itself): the one-block scan of the tile
+    sums runs in the full build and in the update builds after it (four fixed
+    corner agents keep the extent); the steps match the oracle."""
+    g = np.random.default_rng(23)
+    side = 60000.0
+    centers = np.concatenate([g.uniform(0.0, side, (30, 2)), np.zeros((30, 1))], 1)
+    pos = centers.repeat(100, 0) + g.uniform(-14.0, 14.0, (3000, 3))
+    corners = np.array([[0.0, 0.0, -25.0], [side, 0.0, 25.0], [0.0, side, 25.0], [side, side, -25.0]])
+    pos = np.concatenate([pos, corners])
+    diam = g.uniform(8.0, 12.0, pos.shape[0])
+    note(f"many scan tiles n={pos.shape[0]}")
+    sim = make_sim(pos, diam, detect_static=True)
+    q = np.floor(pos / diam.max())
+    supers = np.prod(np.ceil((q.max(0) - q.min(0) + 1) / 2))
+    assert supers > 2048 * 4096   # super-boxes in use: more than 2048 tiles of 4096
+    st = oracle.State.initial(pos, diam)
+    p = oracle.Params(detect_static=True)
+    for _ in range(4):
+        sim.step(1)
+        oracle.step(st, p)
+    got = gpu_state(sim)
+    assert np.abs(got["pos"] - st.pos).max() <= 1e-12 * side
+    np.testing.assert_array_equal(got["moved"], st.moved)
+    np.testing.assert_array_equal(got["nnz"], st.nnz)
+    assert sim.stats()["n_static"] >= 4
+
+
 def test_tiny_inputs():
     for n in (1, 2, 63, 64, 65):
         note(f"tiny n={n}")

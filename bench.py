@@ -63,10 +63,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def timed_steps(sim, steps, timing=False):
+def timed_steps(sim, steps, timing=0):
+    """Wall time of `steps` steps; timing 2: HIP events around the force
+    kernel of each step, 1: around every kernel (for the phase breakdown)."""
     import torch
     if timing:
-        sim.set_timing(True)
+        sim.set_timing(timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
@@ -200,21 +202,26 @@ def main():
     sim.step(args.warmup)
     sim.sync()
     log("timed region")
-    el, tm = timed_steps(sim, args.steps, timing=True)
+    el, tm = timed_steps(sim, args.steps, timing=2)
     value = w.n * args.steps / el
     ms_step = 1e3 * el / args.steps
-    phases = {k: tm[k] / tm["steps"] for k in abm.TIMED_PHASES}
+    force_ms = tm["force"] / tm["steps"]
+    # the phase breakdown: the next K steps, with events around every kernel
+    el_ph, tm_ph = timed_steps(sim, args.steps, timing=1)
+    phases = {k: tm_ph[k] / tm_ph["steps"] for k in abm.TIMED_PHASES}
     dominant = max(abm.TIMED_PHASES, key=lambda k: phases[k])
     prec = w.precision
     force_bytes = FORCE_BYTES[prec] * w.n
-    ach = force_bytes / (phases["force"] * 1e-3) / 1e9
+    ach = force_bytes / (force_ms * 1e-3) / 1e9
     traffic = measured_traffic(w.n, prec, args.block_size, args.order, args.skip)
     roof = dict(bound="hbm", kernel="k_force (static flags + force + move)", achieved=round(ach, 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic), traffic_unit="bytes per launch",
                 algorithmic_bytes=force_bytes,
-                bytes_per_agent=FORCE_BYTES[prec], avg_launch_ms=round(phases["force"], 4),
+                bytes_per_agent=FORCE_BYTES[prec], avg_launch_ms=round(force_ms, 4),
                 dominant_phase=dominant, phase_ms={k: round(v, 4) for k, v in phases.items()},
+                phase_ms_note="the K steps after the timed ones, with events around every kernel "
+                              f"({1e3 * el_ph / args.steps:.4f} ms per step there)",
                 step_bytes_per_agent=STEP_BYTES[prec],
                 step_frac=round(value * STEP_BYTES[prec] / (HBM_PEAK_GBS * 1e9), 4))
     log(f"headline {value:.3e} agent-steps/s, {ms_step:.3f} ms/step, phases {phases}")
@@ -229,20 +236,21 @@ def main():
                      order="hilbert")
         sh.step(args.warmup)
         sh.sync()
-        elh, tmh = timed_steps(sh, args.steps, timing=True)
+        elh, _ = timed_steps(sh, args.steps, timing=2)
+        _, tmh = timed_steps(sh, args.steps, timing=1)
         extras["hilbert"] = dict(value=w.n * args.steps / elh, unit="agent-steps/s",
                                  ms_per_step=round(1e3 * elh / args.steps, 4),
                                  speedup_vs_morton=round(el / elh, 3),
                                  phase_ms={k: round(tmh[k] / tmh["steps"], 4) for k in abm.TIMED_PHASES},
                                  note="2x2x2 super-boxes along a Hilbert curve, Morton order inside each; "
-                                      "phase_ms of the Morton run are under roofline")
+                                      "phase_ms from the K steps after the timed ones, as under roofline")
         log(f"hilbert {extras['hilbert']}")
         del sh
         # the other setting of the static skip (same workload; the shell is
         # force-free and static from its first step)
         s2 = abm.Sim(pos, diam, detect_static=not args.skip, sort_every=args.sort_every, block_size=args.block_size)
         s2.step(args.warmup)
-        el2, _ = timed_steps(s2, args.steps, timing=True)   # timed as the headline (its phase events too)
+        el2, _ = timed_steps(s2, args.steps, timing=2)   # timed as the headline
         el_on, el_off = (el, el2) if args.skip else (el2, el)
         son = (sim_stats if args.skip else s2.stats())
         extras["static_skip"] = dict(skip_on=w.n * args.steps / el_on, skip_off=w.n * args.steps / el_off,

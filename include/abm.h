@@ -321,10 +321,13 @@ int abm_forward_record(abm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, void* r
 int abm_backward(abm_ctx* ctx, const void* dL_dxT, void* dL_dx0, void* dL_dparams);
 
 /*
- * Timing mode: with enable != 0, every step enqueued by abm_step brackets
- * each of its kernels with HIP events on the context's stream (graph replays
- * are not timed).  abm_set_timing resets the accumulators; abm_get_timing
- * synchronises and adds the elapsed times of all timed steps so far.
+ * Timing mode: with enable = 1, every step enqueued by abm_step brackets
+ * each of its kernels with HIP events on the context's stream; with
+ * enable = 2, only the static flags + force + move kernel (ms[5]; the other
+ * entries stay 0), which adds fewer events to the steps; 0 turns timing off
+ * (graph replays are not timed).  abm_set_timing resets the accumulators;
+ * abm_get_timing synchronises and adds the elapsed times of all timed steps
+ * so far.
  */
 int abm_set_timing(abm_ctx* ctx, int32_t enable);
 int abm_get_timing(abm_ctx* ctx, abm_timing* out);

@@ -246,8 +246,11 @@ class Sim:
         _check(lib().abm_set_params(self.ctx, C.byref(p)), "abm_set_params")
         self.params = p
 
-    def set_timing(self, enable: bool = True):
-        _check(lib().abm_set_timing(self.ctx, int(bool(enable))), "abm_set_timing")
+    def set_timing(self, enable=True):
+        """True (or 1): events around every kernel of each step; 2: around
+        the force kernel only; False (0): off."""
+        mode = 2 if (not isinstance(enable, bool) and enable == 2) else int(bool(enable))
+        _check(lib().abm_set_timing(self.ctx, mode), "abm_set_timing")
 
     def timing(self) -> dict:
         """Accumulated per-kernel times (ms) of the timed steps."""

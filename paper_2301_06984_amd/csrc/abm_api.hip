@@ -125,8 +125,9 @@ struct abm_ctx {
     hipGraphExec_t graph_exec = nullptr;
     int32_t graph_steps = 0;
     int graph_grid_ids = 0;  // ids buffer of the last captured step's grid
-    // timing mode: one set of events per step around each kernel
-    bool timing = false;
+    // timing mode: 0 off; 1 one set of events per step around each kernel;
+    // 2 events around the step kernel only
+    int timing = 0;
     std::vector<std::array<hipEvent_t, kTimedPhases + 1>> ev_pending, ev_free;
     double ev_ms[kTimedPhases] = {};
     int64_t ev_steps = 0;
@@ -291,12 +292,13 @@ std::array<hipEvent_t, kTimedPhases + 1>* next_events(abm_ctx* c) {
 }
 
 template <class T>
-void enqueue_step(abm_ctx* c, bool allow_relayout, bool timed = false) {
+void enqueue_step(abm_ctx* c, bool allow_relayout, int timed = 0) {
     Buffers<T>& b = c->buf<T>();
     const int parity = int(c->step & 1);
     std::array<hipEvent_t, kTimedPhases + 1>* ev = timed ? next_events(c) : nullptr;
+    const bool all_phases = ev && timed == 1;
     hipEvent_t* marks[4] = {nullptr, nullptr, nullptr, nullptr};
-    if (ev) {
+    if (all_phases) {
         (void)hipEventRecord((*ev)[0], c->stream);
         for (int k = 0; k < 4; ++k) marks[k] = &(*ev)[2 + k];
     }
@@ -312,10 +314,11 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, bool timed = false) {
     a.full_only = !c->inc_ready;
     set_grid_pos<T>(c, c->pos_cur);
     launch_setup<T>(b, parity, c->inc_ready, c->stream);
-    if (ev) (void)hipEventRecord((*ev)[1], c->stream);
-    launch_grid<T>(b, c->pos_cur, c->ids_cur, a.relayout, a.detect_static, c->stream, ev ? marks : nullptr);
+    if (all_phases) (void)hipEventRecord((*ev)[1], c->stream);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, a.relayout, a.detect_static, c->stream, all_phases ? marks : nullptr);
     swap_cell_start<T>(c);
     a.cs = last_grid_starts<T>(c);
+    if (ev && !all_phases) (void)hipEventRecord((*ev)[kTimedPhases - 1], c->stream);
     launch_force<T>(b, a, c->stream);
     if (ev) (void)hipEventRecord((*ev)[kTimedPhases], c->stream);
     c->grid_ids = c->ids_cur;
@@ -1201,7 +1204,7 @@ int abm_set_timing(abm_ctx* c, int32_t enable) {
     c->ev_pending.clear();
     for (double& m : c->ev_ms) m = 0.0;
     c->ev_steps = 0;
-    c->timing = enable != 0;
+    c->timing = enable == 2 ? 2 : (enable != 0 ? 1 : 0);
     return ABM_OK;
 }
 
@@ -1210,7 +1213,9 @@ int abm_get_timing(abm_ctx* c, abm_timing* out) {
     if (!out) return fail(ABM_E_INVAL, "null output");
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (auto& e : c->ev_pending) {
-        for (int k = 0; k < kTimedPhases; ++k) {
+        // the pending steps all have the mode they were timed in (setting it
+        // drops them)
+        for (int k = c->timing == 2 ? kTimedPhases - 1 : 0; k < kTimedPhases; ++k) {
             float ms = 0.0f;
             HIP_TRY(hipEventElapsedTime(&ms, e[k], e[k + 1]));
             c->ev_ms[k] += ms;

@@ -211,6 +211,26 @@ def test_many_scan_tiles_update_builds():
     assert sim.stats()["n_static"] >= 4
 
 
+def test_timing_modes():
+    """Timing mode 2 times the force kernel alone; mode 1 every kernel; the
+    steps themselves are the same either way."""
+    p, d = workloads.uniform_cube(5000, 100.0, seed=5)
+    note("timing modes")
+    a, b = make_sim(p, d), make_sim(p, d)
+    a.set_timing(2)
+    a.step(3)
+    t = a.timing()
+    assert t["steps"] == 3 and t["force"] > 0.0
+    assert all(t[k] == 0.0 for k in abm.TIMED_PHASES if k != "force")
+    a.set_timing(True)
+    a.step(2)
+    t = a.timing()
+    assert t["steps"] == 2 and t["force"] > 0.0 and sum(t[k] for k in abm.TIMED_PHASES) > t["force"]
+    a.set_timing(False)
+    b.step(5)
+    np.testing.assert_array_equal(a.query("positions").cpu().numpy(), b.query("positions").cpu().numpy())
+
+
 def test_tiny_inputs():
     for n in (1, 2, 63, 64, 65):
         note(f"tiny n={n}")

@@ -41,7 +41,7 @@ def measured_traffic(n, prec, block_size, order="morton", skip=True):
     """HBM bytes per force launch from the committed FETCH_SIZE/WRITE_SIZE
     counter runs (scaled by a plain copy's reading), or None when the kernel
     sources changed since the counters were taken or the configuration
-    differs from the profiled one (1e7 agents, FP32 state, 256 threads,
+    differs from the profiled one (1e7 agents, FP32 state, the recorded threads per block,
     Morton order, static skip on)."""
     import hashlib
     try:
@@ -53,8 +53,8 @@ def measured_traffic(n, prec, block_size, order="morton", skip=True):
                 h.update(f.read())
     except (OSError, KeyError, ValueError):
         return None
-    if (h.hexdigest() != rec["source_sha256"] or n != 10_000_000 or prec != "f32" or block_size != 256
-            or order != "morton" or not skip):
+    if (h.hexdigest() != rec["source_sha256"] or n != 10_000_000 or prec != "f32"
+            or block_size != rec.get("block_size") or order != "morton" or not skip):
         return None
     return float(rec["traffic_bytes"])
 
@@ -149,7 +149,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=10_000_000)
-    ap.add_argument("--block-size", type=int, default=256)
+    ap.add_argument("--block-size", type=int, default=512)
     ap.add_argument("--skip", action=argparse.BooleanOptionalAction, default=True,
                     help="the static skip (Section 5) in the headline run (--no-skip: every force computed)")
     ap.add_argument("--order", choices=["morton", "hilbert"], default="morton",

@@ -47,6 +47,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <tuple>
 #include <utility>
 #include <vector>
 #ifdef _OPENMP
@@ -381,6 +382,21 @@ std::vector<double> promote(int64_t n, const T* v) {
     return out;
 }
 
+// Displacement from the summed force (Section 5): mu F when |F| exceeds the
+// threshold, clamped to delta_max; otherwise none.
+Vec3 displacement(double Fx, double Fy, double Fz, const orc_params* p) {
+    if (!(std::sqrt(sq3(Fx, Fy, Fz)) > p->f_adh)) return Vec3{0.0, 0.0, 0.0};
+    double ux = p->mu * Fx, uy = p->mu * Fy, uz = p->mu * Fz;
+    const double un = std::sqrt(sq3(ux, uy, uz));
+    if (un > p->delta_max) {
+        const double s = p->delta_max / un;
+        ux *= s;
+        uy *= s;
+        uz *= s;
+    }
+    return Vec3{ux, uy, uz};
+}
+
 template <class T>
 int step_impl(int64_t n, T* pos, const T* diam, uint8_t* moved, int32_t* nnz, double* force,
               int64_t t, const orc_params* p, uint8_t* is_static, double* disp) {
@@ -436,19 +452,7 @@ int step_impl(int64_t n, T* pos, const T* diam, uint8_t* moved, int32_t* nnz, do
         force[3 * i + 1] = Fy;
         force[3 * i + 2] = Fz;
         nnz[i] = cnt;
-        // Displacement: only above the threshold, clamped to delta_max.
-        const double Fn = std::sqrt(sq3(Fx, Fy, Fz));
-        if (Fn > p->f_adh) {
-            double ux = p->mu * Fx, uy = p->mu * Fy, uz = p->mu * Fz;
-            const double un = std::sqrt(sq3(ux, uy, uz));
-            if (un > p->delta_max) {
-                const double s = p->delta_max / un;
-                ux *= s;
-                uy *= s;
-                uz *= s;
-            }
-            dx[i] = Vec3{ux, uy, uz};
-        }
+        dx[i] = displacement(Fx, Fy, Fz, p);
     }
 
     // Commit after every force is known (the barrier of Algorithm 1).
@@ -519,9 +523,16 @@ int64_t neighbors_impl(int64_t n, const T* pos, double R, double inv_h, int64_t*
     return total;
 }
 
-// One step for a few sampled agents from the plain definition: the neighbour
-// set of agent i is every j != i with |x_i - x_j|^2 < R^2, found by scanning
-// all agents in id order (no grid).  No static skipping (a first step).
+// One step for a few sampled agents from the plain definition, without the
+// grid: the neighbour set of agent i is every j != i with
+// |x_i - x_j|^2 < R^2, found by scanning all agents.  The pair terms are
+// added one after another in canonical order (box rank, then id), the order
+// the step sums in: ranks are gap-free, so two boxes compare by their Morton
+// code relative to the smallest box (the Hilbert order: by the Hilbert index
+// of their 2x2x2 block over the smallest power-of-two cube holding the
+// blocks, then the octant).  No static skipping (a first step).  The scan
+// over the agents may run on several threads; the sum does not, so the
+// result does not depend on the thread count.
 template <class T>
 int sample_impl(int64_t n, const T* pos, const T* diam, const orc_params* p, int64_t ns, const int64_t* ids,
                 double* F, int32_t* nnz, T* new_pos) {
@@ -532,20 +543,63 @@ int sample_impl(int64_t n, const T* pos, const T* diam, const orc_params* p, int
     const std::vector<double> d = promote(n, diam);
     const double R = radius_of(n, d.data(), p);
     const double R2 = R * R;
+    const double inv_h = 1.0 / (R * (p->cell_factor >= 1.0 ? p->cell_factor : 1.0));
     for (int64_t s = 0; s < ns; ++s)
         if (ids[s] < 0 || ids[s] >= n) return -1;
+    // the box of every agent, counted from the smallest box per axis
+    int64_t lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, hi[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            const double v = double(pos[3 * i + a]) * inv_h;
+            if (!std::isfinite(v)) return -2;
+            const int64_t c = int64_t(std::floor(v));
+            lo[a] = std::min(lo[a], c);
+            hi[a] = std::max(hi[a], c);
+        }
+    int64_t sd[3];
+    for (int a = 0; a < 3; ++a) sd[a] = (hi[a] - lo[a] + 2) / 2;
+    const int sL = levels_for(sd, 3);
+    // sort key of agent j's box: monotone in its rank in the grid's order
+    auto box_key = [&](int64_t j) -> std::pair<uint64_t, uint32_t> {
+        int64_t q[3];
+        for (int a = 0; a < 3; ++a) q[a] = int64_t(std::floor(double(pos[3 * j + a]) * inv_h)) - lo[a];
+        if (p->order == 1) {
+            const int64_t S[3] = {q[0] >> 1, q[1] >> 1, q[2] >> 1};
+            return {hilbert_index(S, sL), uint32_t((q[0] & 1) | ((q[1] & 1) << 1) | ((q[2] & 1) << 2))};
+        }
+        return {morton(q, 3, 21), 0u};
+    };
     for (int64_t s = 0; s < ns; ++s) {
         const int64_t i = ids[s];
         const Vec3 xi = load(pos, i);
+        // the neighbours in contact, found in any order
+        std::vector<int64_t> found;
+#pragma omp parallel
+        {
+            std::vector<int64_t> mine;
+#pragma omp for schedule(static) nowait
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                const Vec3 xj = load(pos, j);
+                if (!(sq3(xi.x - xj.x, xi.y - xj.y, xi.z - xj.z) < R2)) continue;
+                if (pair_term(xi, d[i], xj, d[j], p->k, p->gamma).contact) mine.push_back(j);
+            }
+#pragma omp critical
+            found.insert(found.end(), mine.begin(), mine.end());
+        }
+        // ... put in canonical order and summed one after another
+        std::vector<std::tuple<uint64_t, uint32_t, int64_t>> ord;
+        ord.reserve(found.size());
+        for (int64_t j : found) {
+            const auto k = box_key(j);
+            ord.emplace_back(k.first, k.second, j);
+        }
+        std::sort(ord.begin(), ord.end());
         double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-        int64_t cnt = 0;
-#pragma omp parallel for schedule(static) reduction(+ : Fx, Fy, Fz, cnt)
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            const Vec3 xj = load(pos, j);
-            if (!(sq3(xi.x - xj.x, xi.y - xj.y, xi.z - xj.z) < R2)) continue;
-            const PairTerm pt = pair_term(xi, d[i], xj, d[j], p->k, p->gamma);
-            if (!pt.contact) continue;
+        int32_t cnt = 0;
+        for (const auto& e : ord) {
+            const int64_t j = std::get<2>(e);
+            const PairTerm pt = pair_term(xi, d[i], load(pos, j), d[j], p->k, p->gamma);
             Fx += pt.fx;
             Fy += pt.fy;
             Fz += pt.fz;
@@ -554,23 +608,11 @@ int sample_impl(int64_t n, const T* pos, const T* diam, const orc_params* p, int
         F[3 * s] = Fx;
         F[3 * s + 1] = Fy;
         F[3 * s + 2] = Fz;
-        nnz[s] = int32_t(cnt);
-        double ux = 0.0, uy = 0.0, uz = 0.0;
-        if (std::sqrt(sq3(Fx, Fy, Fz)) > p->f_adh) {
-            ux = p->mu * Fx;
-            uy = p->mu * Fy;
-            uz = p->mu * Fz;
-            const double un = std::sqrt(sq3(ux, uy, uz));
-            if (un > p->delta_max) {
-                const double sc = p->delta_max / un;
-                ux *= sc;
-                uy *= sc;
-                uz *= sc;
-            }
-        }
-        new_pos[3 * s] = T(xi.x + ux);
-        new_pos[3 * s + 1] = T(xi.y + uy);
-        new_pos[3 * s + 2] = T(xi.z + uz);
+        nnz[s] = cnt;
+        const Vec3 u = displacement(Fx, Fy, Fz, p);
+        new_pos[3 * s] = T(xi.x + u.x);
+        new_pos[3 * s + 1] = T(xi.y + u.y);
+        new_pos[3 * s + 2] = T(xi.z + u.z);
     }
     return 0;
 }

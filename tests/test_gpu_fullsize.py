@@ -15,13 +15,17 @@ pytestmark = pytest.mark.gpu
 BENCH = dict(sort_every=1, block_size=512, detect_static=True)   # the benchmark's launch configuration
 
 
-def check_samples(pos, diam, got_pos, nsamples, seed, params=oracle.Params()):
+def check_samples(pos, diam, got_pos, nsamples, seed, params=oracle.Params(), got_nnz=None):
+    """New positions of sampled agents against the oracle's all-pairs
+    sampler, bit for bit: both add each agent's pair terms in canonical
+    (Morton box rank, id) order, which is also the GPU's order in the
+    Hilbert box order (its walk takes the 2x2x2 blocks in Morton order)."""
     ids = np.random.default_rng(seed).choice(pos.shape[0], nsamples, replace=False)
+    note(f"sampler: {nsamples} agents of {pos.shape[0]}")
     F, nnz, newp = oracle.sample_step(pos, diam, ids, params)
-    d = np.abs(got_pos[ids].astype(np.float64) - newp.astype(np.float64))
-    tol = np.spacing(np.abs(newp)).astype(np.float64) if pos.dtype == np.float32 else \
-        1e-12 * np.maximum(np.abs(newp), float(diam.max()))
-    assert np.all(d <= tol), (d.max(), tol.max())
+    np.testing.assert_array_equal(got_pos[ids], newp)
+    if got_nnz is not None:
+        np.testing.assert_array_equal(got_nnz[ids], nnz)
     return ids, nnz
 
 
@@ -86,18 +90,32 @@ def test_c2_full_parity_and_skip():
     np.testing.assert_array_equal(gpu_state(on)["pos"], gpu_state(off)["pos"])
 
 
-def test_c3_clustered_first_step_sampled():
+def test_c3_clustered_all_steps_sampled():
+    # the clustered workload over its 20 steps, re-laid out every 10th step:
+    # sampled agents of steps 1, 10, 11 and 20 (full and update builds, both
+    # sides of a re-layout, the clamp active almost everywhere) against the
+    # sampler fed the GPU's state before the step
     w = workloads.c3()
     note(f"c3 n={w.n}")
     sim = make_sim(w.pos, w.diam, sort_every=w.sort_every, block_size=256)
-    sim.step(1)
-    sim.sync()
-    got = sim.query("positions").cpu().numpy()
-    note("c3 sampled check")
-    _, nnz = check_samples(w.pos, w.diam, got, 24, 3)
-    assert nnz.mean() > 5
-    gn = sim.query("nnz").cpu().numpy()
-    np.testing.assert_array_equal(gn[np.random.default_rng(3).choice(w.n, 24, replace=False)], nnz)
+    t = 0
+    x = w.pos
+    for at in (1, 10, 11, 20):
+        if at - 1 > t:
+            note(f"c3 steps {t + 1}..{at - 1}")
+            sim.step(at - 1 - t)
+            sim.sync()
+            t = at - 1
+            x = sim.query("positions").cpu().numpy()
+        note(f"c3 step {at}")
+        sim.step(1)
+        sim.sync()
+        t = at
+        got = sim.query("positions").cpu().numpy()
+        gn = sim.query("nnz").cpu().numpy()
+        _, nnz = check_samples(x, w.diam, got, 24, 30 + at, got_nnz=gn)
+        assert nnz.mean() > 5
+        x = got
 
 
 def test_c4_batched_graph_sampled_sims():
@@ -116,6 +134,16 @@ def test_c4_batched_graph_sampled_sims():
         sim = make_sim(w.pos[a:e], w.diam[a:e])
         sim.step(w.steps)
         np.testing.assert_array_equal(got[a:e], sim.query("positions").cpu().numpy())
+    # three simulations of the batch against the oracle's 50 steps: the
+    # smallest, and two of fewer than 20,000 agents drawn by seed
+    sizes = np.diff(w.offsets)
+    small = np.flatnonzero(sizes < 20_000)
+    pick = [int(np.argmin(sizes))] + [int(x) for x in np.random.default_rng(44).choice(small, 2, replace=False)]
+    for sidx in pick:
+        a, e = w.offsets[sidx], w.offsets[sidx + 1]
+        note(f"c4 sim {sidx} n={e - a} against the oracle")
+        ref = oracle.run(w.pos[a:e], w.diam[a:e], w.steps, oracle.Params())
+        np.testing.assert_array_equal(got[a:e], ref.pos)
 
 
 def test_c5_adjoint_full():
@@ -163,3 +191,44 @@ def test_headline_1e7_hilbert_order():
     sim.sync()
     assert_grid_equal(sim, x, w.diam, p)
     check_samples(x, w.diam, sim.query("positions").cpu().numpy(), 96, 4)
+
+
+def test_headline_1e7_fp64_state():
+    # the headline workload with FP64 state: a full build, then an update
+    # build from the GPU's state, grid and sampled agents against the oracle
+    w = workloads.headline(dtype=np.float64)
+    note(f"headline fp64 n={w.n}")
+    sim = make_sim(w.pos, w.diam, **BENCH)
+    sim.step(1)
+    sim.sync()
+    got = sim.query("positions").cpu().numpy()
+    check_samples(w.pos, w.diam, got, 96, 5, got_nnz=sim.query("nnz").cpu().numpy())
+    note("headline fp64 5 more steps, then an update build")
+    sim.step(5)
+    sim.sync()
+    x = sim.query("positions").cpu().numpy()
+    sim.step(1)
+    sim.sync()
+    assert_grid_equal(sim, x, w.diam, oracle.Params())
+    check_samples(x, w.diam, sim.query("positions").cpu().numpy(), 96, 6, got_nnz=sim.query("nnz").cpu().numpy())
+
+
+def test_uniform_1e8_sampled():
+    # 1e8 spheres uniform at the c2 density (the scale sweep's workload):
+    # the first step and a later update build, sampled against the oracle
+    n = 100_000_000
+    side = (n / workloads.C2_DENSITY) ** (1.0 / 3.0)
+    note(f"uniform 1e8: generating (side {side:.1f})")
+    p, d = workloads.uniform_cube(n, side, (6, n), dtype=np.float32)
+    sim = make_sim(p, d, detect_static=False, sort_every=1, block_size=512, box_slack=1.05)
+    note("uniform 1e8 step 1")
+    sim.step(1)
+    sim.sync()
+    check_samples(p, d, sim.query("positions").cpu().numpy(), 48, 7, got_nnz=sim.query("nnz").cpu().numpy())
+    note("uniform 1e8 steps 2-3, then step 4 (update build)")
+    sim.step(2)
+    sim.sync()
+    x = sim.query("positions").cpu().numpy()
+    sim.step(1)
+    sim.sync()
+    check_samples(x, d, sim.query("positions").cpu().numpy(), 48, 8, got_nnz=sim.query("nnz").cpu().numpy())

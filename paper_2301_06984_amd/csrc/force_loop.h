@@ -367,7 +367,9 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
                 // only where this feeds a static test, and then it did not move)
                 acc.moved_near = acc.moved_near || (within && pj[c].w < T(0));
                 const bool keep = within && s2 > 0.0 && s2 < S * S;
-                L.queue[m * bs + tid] = uq[c];
+                // only rows in use are rewritten: with every tested row kept,
+                // m reaches n, and n can be kQueueCap, one row past the queue
+                if (x0 + c < n) L.queue[m * bs + tid] = uq[c];
                 m += keep ? 1u : 0u;
             }
         }
@@ -508,7 +510,7 @@ __device__ __forceinline__ uint32_t queue_contacts(const Buffers<T>& b, const Si
                 const double s2 = (ex * ex + ey * ey) + ez * ez;
                 const double S = ri + 0.5 * fabs(double(pj[c].w));
                 const bool keep = x0 + c < n && s2 < r2 && s2 > 0.0 && s2 < S * S;
-                L.queue[m * bs + tid] = uq[c];
+                if (x0 + c < n) L.queue[m * bs + tid] = uq[c];   // rows in use only (see force_of)
                 m += keep ? 1u : 0u;
             }
         }

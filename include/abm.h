@@ -32,7 +32,8 @@
  *     pointers are ordinary host memory;
  *   - the caller owns every device buffer (inputs, workspace, outputs); the
  *     library never allocates device memory (graph objects aside) and keeps
- *     raw pointers into the workspace until abm_destroy();
+ *     raw pointers into the workspace until abm_destroy(); its only device
+ *     memory of its own is the fixed 1 KiB scratch of abm_extent_of_noalloc;
  *   - `stream` is a hipStream_t (0 = the null stream); all work is enqueued on
  *     it asynchronously; a context is bound to its stream and is not
  *     thread-safe;
@@ -162,6 +163,24 @@ const char* abm_last_error(void);
  */
 int abm_extent_of(int64_t n, const void* pos, const void* diam, const abm_params* p, void* scratch,
                   void* stream, abm_extent* out);
+
+/*
+ * abm_extent_of for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, with the scratch taken from a fixed array of
+ * ABM_EXTENT_SCRATCH_BYTES (1 KiB) in the library's own device memory, one
+ * copy per GPU, held until the process ends.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); its first call on a
+ * device looks up that device's copy.  Every call on one GPU shares that
+ * copy: calls that overlap on one GPU (other host threads, other streams)
+ * race and must be serialised by the caller.  The scratch need does not grow
+ * with n; n above ABM_NOALLOC_MAX_AGENTS is refused with ABM_E_INVAL.
+ * Synchronises `stream`.  Errors: ABM_E_INVAL, ABM_E_NONFINITE, ABM_E_HIP,
+ * ABM_E_UNSUPPORTED (device index above 63).
+ */
+#define ABM_NOALLOC_MAX_AGENTS 4294967294LL
+int abm_extent_of_noalloc(int64_t n, const void* pos, const void* diam, const abm_params* p, void* stream,
+                          abm_extent* out);
 
 /*
  * Bytes of device workspace for nsims simulations with the given agent

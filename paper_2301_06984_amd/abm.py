@@ -31,7 +31,7 @@ EXPORTS = ["abm_abi_version", "abm_default_params", "abm_last_error", "abm_exten
            "abm_get_stats", "abm_state_bytes", "abm_export_state", "abm_import_state", "abm_graph_capture",
            "abm_graph_launch", "abm_record_bytes", "abm_forward_record", "abm_backward", "abm_set_timing",
            "abm_get_timing", "abm_destroy", "abm_workspace_bytes_capacity", "abm_init_capacity", "abm_add_agents",
-           "abm_remove_agents", "abm_set_diameters", "abm_population"]
+           "abm_remove_agents", "abm_set_diameters", "abm_population", "abm_extent_of_noalloc"]
 TIMED_PHASES = ["setup", "keys", "scan", "scatter", "fixup", "force"]
 
 
@@ -79,6 +79,7 @@ def lib():
             "abm_default_params": (None, [C.POINTER(abm_params)]),
             "abm_last_error": (C.c_char_p, []),
             "abm_extent_of": (C.c_int, [i64, P, P, C.POINTER(abm_params), P, P, C.POINTER(abm_extent)]),
+            "abm_extent_of_noalloc": (C.c_int, [i64, P, P, C.POINTER(abm_params), P, C.POINTER(abm_extent)]),
             "abm_workspace_bytes": (C.c_int, [i32, P, P, C.POINTER(abm_params), C.POINTER(i64)]),
             "abm_init": (C.c_int, [C.POINTER(P), i64, P, P, C.POINTER(abm_params), i64, P, i64, P]),
             "abm_init_batched": (C.c_int, [C.POINTER(P), i32, P, P, P, P, P, P, i64, P]),
@@ -153,6 +154,15 @@ def extent_of(pos: torch.Tensor, diam: torch.Tensor, params: abm_params, stream=
     out = abm_extent()
     _check(lib().abm_extent_of(pos.shape[0], _ptr(pos), _ptr(diam), C.byref(params), _ptr(scratch),
                                _stream_handle(stream), C.byref(out)), "abm_extent_of")
+    return out
+
+
+def extent_of_noalloc(pos: torch.Tensor, diam: torch.Tensor, params: abm_params, stream=None) -> abm_extent:
+    """Grid extent without a scratch tensor (abm_extent_of_noalloc: the
+    library's own fixed device scratch)."""
+    out = abm_extent()
+    _check(lib().abm_extent_of_noalloc(pos.shape[0], _ptr(pos), _ptr(diam), C.byref(params),
+                                       _stream_handle(stream), C.byref(out)), "abm_extent_of_noalloc")
     return out
 
 

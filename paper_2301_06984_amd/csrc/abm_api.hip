@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -465,9 +466,15 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     return ABM_OK;
 }
 
+// Zero n bytes at p (a kernel rather than a memset, so that the call records
+// no memset node if the caller captures the stream).
+__global__ void k_zero_bytes(unsigned char* p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
 template <class T>
 int extent_impl(int64_t n, const void* pos, const void* diam, const abm_params* p, void* scratch, hipStream_t s,
-                abm_extent* out) {
+                abm_extent* out, bool zero_by_kernel = false) {
     // scratch: the error word (the only field of Globals the extent kernels
     // touch) in the first 256 bytes, then one SimGrid
     static_assert(offsetof(Globals, err) == 0, "the error word leads Globals");
@@ -478,7 +485,10 @@ int extent_impl(int64_t n, const void* pos, const void* diam, const abm_params* 
     SimGrid h{};
     h.radius = p->interaction_radius;
     h.cell_factor = p->cell_factor;
-    HIP_TRY(hipMemsetAsync(w, 0, 256, s));
+    if (zero_by_kernel)
+        hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(256), 0, s, reinterpret_cast<unsigned char*>(w), 256u);
+    else
+        HIP_TRY(hipMemsetAsync(w, 0, 256, s));
     HIP_TRY(hipMemcpyAsync(G, &h, sizeof(SimGrid), hipMemcpyHostToDevice, s));
     launch_extent<T>(static_cast<const T*>(pos), static_cast<const T*>(diam), uint32_t(n), g, G, s);
     HIP_TRY(hipGetLastError());
@@ -980,6 +990,55 @@ int abm_extent_of(int64_t n, const void* pos, const void* diam, const abm_params
     hipStream_t s = static_cast<hipStream_t>(stream);
     return p->precision == ABM_F64 ? extent_impl<double>(n, pos, diam, p, scratch, s, out)
                                    : extent_impl<float>(n, pos, diam, p, scratch, s, out);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ extent without allocation
+// The scratch of abm_extent_of_noalloc: the error word and one SimGrid, as
+// abm_extent_of's caller-owned scratch holds them.  Each GPU the library runs
+// on holds its own copy until the process ends; host code never passes the
+// array's name to a kernel or a copy, only the device address
+// hipGetSymbolAddress gives for the current device, kept per device.
+static __device__ __align__(256) unsigned char scratch[ABM_EXTENT_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch, looked up on the first call
+// on that device.
+int device_scratch(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(ABM_E_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(ABM_E_HIP, "hipGetSymbolAddress gave a null address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return ABM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int abm_extent_of_noalloc(int64_t n, const void* pos, const void* diam, const abm_params* p, void* stream,
+                          abm_extent* out) {
+    std::string why;
+    if (!valid_params(p, &why)) return fail(ABM_E_INVAL, why);
+    if (n <= 0 || n > ABM_NOALLOC_MAX_AGENTS)
+        return fail(ABM_E_INVAL, "n must be in [1, ABM_NOALLOC_MAX_AGENTS = 2^32 - 2]");
+    if (!pos || !diam || !out) return fail(ABM_E_INVAL, "bad arguments");
+    void* ptr = nullptr;
+    if (int rc = device_scratch(&ptr)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return p->precision == ABM_F64 ? extent_impl<double>(n, pos, diam, p, ptr, s, out, true)
+                                   : extent_impl<float>(n, pos, diam, p, ptr, s, out, true);
 }
 
 int abm_workspace_bytes(int32_t nsims, const int64_t* offsets, const int64_t* box_capacity, const abm_params* p,

@@ -40,8 +40,8 @@ constexpr int kTimedPhases = 6;
 struct Layout {
     int64_t globals, sims, sim_of, bbox_rep, pos4[2], flags[2], skey[2], ids[2], force[2], key, sub, rec, perm, movers,
         mcount, count, cell_start[2], dirty, dirty_list, aoff, tabidx, mmask, cellinfo, hil, tile_sums, partials,
-        stage, total;
-    uint32_t scan_tiles, partial_cap;
+        bpart, stage, total;
+    uint32_t scan_tiles, partial_cap, bpart_cap;
 };
 
 // Agents per context: loose slots [0, 2n) and the padded step grid stay below 2^32.
@@ -90,6 +90,8 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.tile_sums = take(12 * int64_t(L.scan_tiles));
     L.partial_cap = uint32_t(adj_blocks(uint32_t(n)));
     L.partials = take(16 * int64_t(L.partial_cap));
+    L.bpart_cap = force_part_capacity(uint32_t(n));
+    L.bpart = take(int64_t(sizeof(BlockPart)) * L.bpart_cap);
     L.stage = take(24 * n);
     L.total = off;
     return L;
@@ -188,6 +190,8 @@ void fill_buffers(abm_ctx* c) {
     b.scan_tiles = L.scan_tiles;
     b.partials = reinterpret_cast<double*>(w + L.partials);
     b.partial_cap = L.partial_cap;
+    b.bpart = reinterpret_cast<BlockPart*>(w + L.bpart);
+    b.bpart_cap = L.bpart_cap;
 }
 
 // After a grid build: its starts become the last grid's.

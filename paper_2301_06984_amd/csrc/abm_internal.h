@@ -119,6 +119,13 @@ struct Globals {
     unsigned long long stats[2][kReplicas][2];
 };
 
+// One block's share of the step's reductions: the box extent of its agents'
+// new positions (min x, y, z, max x, y, z) and its static and moved counts.
+struct BlockPart {
+    int32_t box[6];
+    uint32_t n_static, n_moved;
+};
+
 // Pointers into the workspace, passed by value to kernels.
 template <class T>
 struct Buffers {
@@ -163,6 +170,11 @@ struct Buffers {
     // box extent accumulators [2 slots][kReplicas][nsims][6]: one slot is
     // read by a step's setup, the other filled by its move kernel
     int32_t* bbox_rep;
+    // single simulation: the step kernel's per-block results (box extent of
+    // the new positions, static and moved counts), one record per launched
+    // block, folded into the replicas by a second kernel without atomics
+    BlockPart* bpart;
+    uint32_t bpart_cap;
 };
 
 // Host-side description of which kernels to run for one step.
@@ -207,6 +219,12 @@ template <class T> void launch_reset_bbox(const Buffers<T>& b, int parity, hipSt
 
 // ---- launchers (force_kernels.hip)
 template <class T> void launch_force(const Buffers<T>& b, const StepArgs& a, hipStream_t s);
+// Per-block records the step kernel of n agents may write (its largest grid).
+uint32_t force_part_capacity(uint32_t n);
+// Fold nparts block records into the replicas of the box extent (slot
+// parity ^ 1) and of the step statistics (parity), without atomics.
+template <class T> void launch_fold_parts(const Buffers<T>& b, uint32_t nparts, int parity, hipStream_t s);
+
 template <class T> void launch_neighbors(const Buffers<T>& b, int ids_cur, uint32_t* counts, uint32_t* rows,
                                          uint32_t K, uint32_t* worst, hipStream_t s);
 template <class T> void launch_unpack_positions(const Buffers<T>& b, int pos_cur, int ids_cur, T* out, hipStream_t s);

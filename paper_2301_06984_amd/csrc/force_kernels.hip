@@ -63,7 +63,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
         has_a = chunk >= nb && ka * bs < napp;
         has_s = chunk < nb && inc;
     }
-    if (!has_a && !has_s) return;   // no agent in the block's chunks
+    if (!has_a && !has_s) {   // no agent in the block's chunks
+        if (!BATCHED && threadIdx.x == 0) b.bpart[blockIdx.x] = BlockPart{{INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN,
+                                                                           INT32_MIN, INT32_MIN}, 0u, 0u};
+        return;
+    }
     const WalkLds L = walk_lds(s_walk);
     // the block's agents mostly belong to at most kMaxBlockSims simulations
     // from that of its chunk's first slot on (others fold straight into the
@@ -86,20 +90,36 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
         // in the same simulation's range as its storage index)
         uint32_t key = kDeadKey, i = u;
         bool active = false;
-        if (!append) {
-            if (u < n) {
-                key = b.skey[cur][u];
+        // the slot's key, position and flags (and an appended agent's storage
+        // index) are requested together, from the slot's range alone, and the
+        // gathers that need only the key (its super-box's new start, a kept
+        // agent's id) right after, so that the chain of dependent loads ahead
+        // of the walk stays short
+        const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
+        const bool inb = !append ? u < n : u - n < napp;
+        V4<T> p0{};
+        uint32_t f0 = 0;
+        if (inb) {
+            if (!append || inc) key = b.skey[cur][u];
+            p0 = pin[u];
+            f0 = b.flags[cur][u];
+            if (!append) {
                 active = key != kDeadKey;
+            } else {
+                i = u - n;
+                active = true;
+                if (inc || !RELAYOUT || KEEP_F) {
+                    i = b.perm[u - n];
+                    active = i < n;
+                    if (!active) raise_error(b.g, kErrInternal);
+                }
             }
-        } else if (u - n < napp) {
-            i = u - n;
-            active = true;
-            if (inc) key = b.skey[cur][u];
-            if (inc || !RELAYOUT || KEEP_F) {
-                i = b.perm[u - n];
-                active = i < n;
-                if (!active) raise_error(b.g, kErrInternal);
-            }
+        }
+        uint32_t cs_key = 0, id_kept = 0;
+        if (RELAYOUT && inc && active) {
+            const uint32_t sk = key >> 3;
+            if (sk < b.g->total_super) cs_key = a.cs[sk];
+            if (!append) id_kept = b.ids[a.ids_cur][i];
         }
         bool ok = false, is_static = false, moved = false;
         int sim = 0;
@@ -116,21 +136,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
             sim = BATCHED ? sim_index(b, i) : 0;
             Gp = b.sims + sim;
             const SimGrid& G = *Gp;
-            const V4<T>* __restrict__ pin = pos4_ptr(b, cur);
             if (!G.valid) {
                 // grid overflow (reported at sync): the agent keeps its state (a
                 // full build copied it to loose slot n + i, and its id and key
                 // to the next state)
-                const V4<T> p0 = pin[u];
                 pout[i] = p0;
-                b.flags[nxt][i] = b.flags[cur][u] | kBoxChangedBit;
+                b.flags[nxt][i] = f0 | kBoxChangedBit;
                 if (KEEP_F)
                     for (int c = 0; c < 3; ++c) b.force[nxt][3 * size_t(i) + c] = b.force[cur][3 * size_t(i) + c];
                 ok = box_coord(double(p0.x), G.inv_h, &cnew[0]) && box_coord(double(p0.y), G.inv_h, &cnew[1]) &&
                      box_coord(double(p0.z), G.inv_h, &cnew[2]);
             } else {
-                p = pin[u];   // own state, sign of d = moved
-                f = b.flags[cur][u];
+                p = p0;   // own state, sign of d = moved
+                f = f0;
                 uint32_t q[3];
                 if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
                 P = load_pieces(b, G, q, b.g->stamp, L);
@@ -138,7 +156,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
                     out = u - n;
                 } else if (RELAYOUT) {
                     const uint32_t sk = key >> 3;
-                    out = sk < b.g->total_super ? a.cs[sk] + (u - P.xown) : n;
+                    out = sk < b.g->total_super ? cs_key + (u - P.xown) : n;
                     if (u < P.xown || out >= n) {
                         raise_error(b.g, kErrInternal);
                         out = i;
@@ -148,7 +166,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
                     // written before the walk, so that they need not live
                     // through it
                     if (!append) {
-                        b.ids[a.ids_cur ^ 1][out] = b.ids[a.ids_cur][i];
+                        b.ids[a.ids_cur ^ 1][out] = id_kept;
                         b.skey[nxt][out] = key;
                     }
                 }
@@ -257,6 +275,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
         const uint32_t nwaves = (blockDim.x + 63u) >> 6;
         if (atomicAdd(&s_cnt[2], 1u) == nwaves - 1) {
             __threadfence_block();
+            if constexpr (!BATCHED) {
+                // one simulation: the block's record, folded by k_fold_parts
+                BlockPart r;
+                for (int c = 0; c < 6; ++c) r.box[c] = atomicAdd(&s_box[0][c], 0);
+                r.n_static = atomicAdd(&s_cnt[0], 0u);
+                r.n_moved = atomicAdd(&s_cnt[1], 0u);
+                b.bpart[blockIdx.x] = r;
+                return;
+            }
             for (int k = 0; k < kMaxBlockSims; ++k) {
                 const int sk = atomicAdd(&s_sims[k], 0);
                 if (sk < 0) continue;
@@ -275,6 +302,67 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
     }
 }
 
+// The step kernel's block records (one simulation) folded into replica r =
+// blockIdx.x of the box-extent accumulators (slot `slot`) and of the step
+// statistics (parity `parity`): each replica has one writer, so plain
+// stores replace the same-address atomics of one set per block.  Block r
+// folds records [r * per, (r + 1) * per).
+constexpr int kFoldThreads = 256;
+__global__ __launch_bounds__(kFoldThreads) void k_fold_parts(const BlockPart* __restrict__ parts, uint32_t nparts,
+                                                             int32_t* __restrict__ rep, Globals* g, int slot,
+                                                             int parity) {
+    __shared__ int32_t s_box[kFoldThreads / 64][6];
+    __shared__ unsigned long long s_cnt[kFoldThreads / 64][2];
+    const uint32_t per = (nparts + kReplicas - 1) / kReplicas;
+    const uint32_t e0 = blockIdx.x * per, e1 = min(e0 + per, nparts);
+    int32_t box[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
+    unsigned long long cnt[2] = {0ull, 0ull};
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kFoldThreads) {
+        const BlockPart r = parts[e];
+        for (int a = 0; a < 3; ++a) {
+            box[a] = min(box[a], r.box[a]);
+            box[3 + a] = max(box[3 + a], r.box[3 + a]);
+        }
+        cnt[0] += r.n_static;
+        cnt[1] += r.n_moved;
+    }
+    const int wave = int(threadIdx.x >> 6);
+    for (int a = 0; a < 3; ++a) {
+        box[a] = wave_min(box[a]);
+        box[3 + a] = wave_max(box[3 + a]);
+    }
+    for (int d = 32; d >= 1; d >>= 1)
+        for (int c = 0; c < 2; ++c) cnt[c] += __shfl_xor(cnt[c], d, 64);
+    if (lane_id() == 0) {
+        for (int a = 0; a < 6; ++a) s_box[wave][a] = box[a];
+        s_cnt[wave][0] = cnt[0];
+        s_cnt[wave][1] = cnt[1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kFoldThreads / 64; ++w) {
+            for (int a = 0; a < 3; ++a) {
+                box[a] = min(box[a], s_box[w][a]);
+                box[3 + a] = max(box[3 + a], s_box[w][3 + a]);
+            }
+            cnt[0] += s_cnt[w][0];
+            cnt[1] += s_cnt[w][1];
+        }
+        int32_t* t = rep + (size_t(slot) * kReplicas + blockIdx.x) * 6;   // one simulation
+        for (int a = 0; a < 6; ++a) t[a] = box[a];
+        g->stats[parity][blockIdx.x][0] = cnt[0];
+        g->stats[parity][blockIdx.x][1] = cnt[1];
+    }
+}
+
+uint32_t force_part_capacity(uint32_t n) { return 2u * ((n + 63u) / 64u) + 1024u; }
+
+template <class T>
+void launch_fold_parts(const Buffers<T>& b, uint32_t nparts, int parity, hipStream_t s) {
+    hipLaunchKernelGGL(k_fold_parts, dim3(kReplicas), dim3(kFoldThreads), 0, s, b.bpart, nparts, b.bbox_rep, b.g,
+                       parity ^ 1, parity);
+}
+
 template <class T, bool S, bool K, bool R, int CH>
 static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
     const int bs = a.block_size;
@@ -284,8 +372,9 @@ static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s
     const uint32_t first = two_chunks<CH>() || !a.full_only ? 0u : nb;
     const uint32_t blocks = two_chunks<CH>() ? nb : 2u * nb - first;
     const uint32_t run = xcd_run(blocks);
-    hipLaunchKernelGGL((k_force<T, S, K, R, CH>), dim3(xcd_grid(blocks, run)), dim3(bs), walk_lds_bytes(bs), s, b, a,
-                       run, first);
+    const uint32_t grid = xcd_grid(blocks, run);   // <= force_part_capacity(n): nb <= ceil(n / 64), 8 run <= 512
+    hipLaunchKernelGGL((k_force<T, S, K, R, CH>), dim3(grid), dim3(bs), walk_lds_bytes(bs), s, b, a, run, first);
+    if (!S) launch_fold_parts(b, grid, a.parity, s);
 }
 
 template <class T, int CH>
@@ -479,6 +568,7 @@ void launch_set_flags(const Buffers<T>& b, int pos_cur, int ids_cur, const uint8
 
 #define ABM_INSTANTIATE(T)                                                                                   \
     template void launch_force<T>(const Buffers<T>&, const StepArgs&, hipStream_t);                        \
+    template void launch_fold_parts<T>(const Buffers<T>&, uint32_t, int, hipStream_t);                     \
     template void launch_neighbors<T>(const Buffers<T>&, int, uint32_t*, uint32_t*, uint32_t, uint32_t*,   \
                                       hipStream_t);                                                         \
     template void launch_unpack_positions<T>(const Buffers<T>&, int, int, T*, hipStream_t);                \

@@ -109,6 +109,34 @@ struct Pieces {
     bool moved = false;   // an agent of one of the 27 boxes moved in the last step
 };
 
+// The slot range [a0, a1) (offsets from the first slot) of the part of a
+// super-box with table entry e that a piece takes: all of it, or with
+// ty (tz) only its y (z) half hy (hz), where the octant counts allow one
+// contiguous range: z halves always, a y half inside a z half, and with y
+// cut but z not, octants 2 hy .. 2 hy + 5.  Super-boxes of more than
+// kMaxSplitCount agents are taken whole.
+__device__ __forceinline__ void trim_range(const uint4& e, bool ty, bool tz, uint32_t hy, uint32_t hz, uint32_t* a0,
+                                           uint32_t* a1) {
+    const uint32_t c8 = e.y & kMaxSuperCount, c2 = e.z & 0xFFFFu, c4 = e.z >> 16, c6 = e.w & 0xFFFFu;
+    const bool split = c8 <= kMaxSplitCount;
+    ty = ty && split;
+    tz = tz && split;
+    // octant count bounds of the needed y half in the lower (z bit 0) and
+    // the upper (z bit 1) layer of the super-box
+    const uint32_t ylo0 = hy ? c2 : 0u, yhi0 = hy ? c4 : c2;
+    const uint32_t ylo1 = hy ? c6 : c4, yhi1 = hy ? c8 : c6;
+    uint32_t b0 = 0u, b1 = c8;
+    if (tz) {
+        b0 = ty ? (hz ? ylo1 : ylo0) : (hz ? c4 : 0u);
+        b1 = ty ? (hz ? yhi1 : yhi0) : (hz ? c8 : c4);
+    } else if (ty) {   // y cut, z not: one piece over octants 2h..2h+5
+        b0 = ylo0;
+        b1 = yhi1;
+    }
+    *a0 = b0;
+    *a1 = b1;
+}
+
 // Load the pieces around box q (entries of the current stamp only) into this
 // thread's LDS rows, piece j at row j.  The super-boxes are visited in
 // row-major order, so that their table offsets and range tests are fixed
@@ -152,22 +180,9 @@ __device__ __forceinline__ Pieces load_pieces(const Buffers<T>& b, const SimGrid
         if (super_stamp(e) != st15) e = make_uint4(0u, 0u, 0u, 0u);
         P.xown = c == own ? e.x : P.xown;
         moved |= (e.y >> 24) & xm[dx] & ym[dy] & zm[dz];
-        const uint32_t c8 = e.y & kMaxSuperCount, c2 = e.z & 0xFFFFu, c4 = e.z >> 16, c6 = e.w & 0xFFFFu;
         // the y (z) half of this super-box is cut when it lies on the far side
-        const bool split = c8 <= kMaxSplitCount;
-        const bool ty = split && dy == bq[1], tz = split && dz == bq[2];
-        // octant count bounds of the needed y half in the lower (z bit 0) and
-        // the upper (z bit 1) layer of the super-box
-        const uint32_t ylo0 = hy ? c2 : 0u, yhi0 = hy ? c4 : c2;
-        const uint32_t ylo1 = hy ? c6 : c4, yhi1 = hy ? c8 : c6;
-        uint32_t a0 = 0u, a1 = c8;
-        if (tz) {
-            a0 = ty ? (hz ? ylo1 : ylo0) : (hz ? c4 : 0u);
-            a1 = ty ? (hz ? yhi1 : yhi0) : (hz ? c8 : c4);
-        } else if (ty) {   // y cut, z not: one piece over octants 2h..2h+5
-            a0 = ylo0;
-            a1 = yhi1;
-        }
+        uint32_t a0, a1;
+        trim_range(e, dy == bq[1], dz == bq[2], hy, hz, &a0, &a1);
         const uint32_t j = dx * wx + dy * wy + dz * wz;
         L.rng[j * bs + tid] = (unsigned long long)(e.x + a0) | ((unsigned long long)(e.x + a1) << 32);
         P.mask |= (a1 > a0 ? 1u : 0u) << j;
@@ -210,11 +225,14 @@ __device__ __forceinline__ bool stream_pieces(const WalkLds& L, const Pieces& P,
 // read (the loose position array is padded) but must not be used:
 // test(pc, u, left) sees the chunk's positions, its first slot and the
 // number of its slots inside the piece, and returns false to stop the walk.
+//
+// sp is the position source the pieces index: the grid's loose position
+// array, or a block's copy of its neighbourhood in LDS.
 template <int CH, class T, class Test>
-__device__ __forceinline__ void walk_chunks(const Buffers<T>& b, const Pieces& P, const WalkLds& L, Test&& test) {
+__device__ __forceinline__ void walk_chunks(const V4<T>* __restrict__ sp, const Pieces& P, const WalkLds& L,
+                                            Test&& test) {
     static_assert(CH >= 1 && CH <= kSposPad && kQueueCap > CH, "walk chunk");
     if (!P.mask) return;
-    const V4<T>* __restrict__ sp = gpos_ptr(b);
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
     uint32_t M = P.mask;
     const uint32_t k0 = uint32_t(__ffs(M)) - 1u;
@@ -332,12 +350,14 @@ __device__ __forceinline__ PairTerm pair_term(double xi, double yi, double zi, d
 // register shuffles (the j-th term of every lane at once), which adds them in
 // slot order: the same sums, bit for bit, with the lanes of a wave busy
 // however unevenly the contacts fall.
+//
+// sp is the position source the pieces and queue rows index, last its last
+// readable index.
 template <int CH, class T, bool PARAM_GRADS, bool SHARE = false>
-__device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, const Pieces& P,
-                                         const WalkLds& L, ForceSum& acc) {
+__device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uint32_t last, const SimGrid& G,
+                                         const V4<T>& p, const Pieces& P, const WalkLds& L, ForceSum& acc) {
     static_assert(!(SHARE && PARAM_GRADS), "shared pair terms carry the force only");
-    const V4<T>* __restrict__ sp = gpos_ptr(b);
-    const uint32_t tid = threadIdx.x, bs = blockDim.x, last = 2u * b.n - 1u;
+    const uint32_t tid = threadIdx.x, bs = blockDim.x;
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
     const double ri = 0.5 * fabs(double(p.w));
     const double r2 = G.r2, k = G.k, gamma = G.gamma;
@@ -406,7 +426,7 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
     };
     // pass 1: the pre-test over the walk, survivors queued in slot order
     uint32_t qo = tid;   // this thread's next queue entry
-    walk_chunks<CH>(b, P, L, [&](const V4<T>* pc, uint32_t u, uint32_t left) {
+    walk_chunks<CH, T>(sp, P, L, [&](const V4<T>* pc, uint32_t u, uint32_t left) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             // no short-circuit: every lane does the same arithmetic
@@ -479,6 +499,13 @@ __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, 
     }
 }
 
+// force_of over the grid's loose position array.
+template <int CH, class T, bool PARAM_GRADS, bool SHARE = false>
+__device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, const Pieces& P,
+                                         const WalkLds& L, ForceSum& acc) {
+    force_of<CH, T, PARAM_GRADS, SHARE>(gpos_ptr(b), 2u * b.n - 1u, G, p, P, L, acc);
+}
+
 // The walk's pre-test and exact test for agent p, keeping its contacts
 // (neighbours within R, 0 < |e| < r_i + r_j) at the head of its LDS queue in
 // slot order; returns their number, rows [0, kept).  When contacts fill the
@@ -518,7 +545,7 @@ __device__ __forceinline__ uint32_t queue_contacts(const Buffers<T>& b, const Si
         n = m;
     };
     uint32_t qo = tid;
-    walk_chunks<CH>(b, P, L, [&](const V4<T>* pc, uint32_t u, uint32_t left) {
+    walk_chunks<CH, T>(sp, P, L, [&](const V4<T>* pc, uint32_t u, uint32_t left) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             const uint32_t pass = uint32_t(uint32_t(c) < left) & uint32_t(maybe_within<T>(p, pc[c], r2pad));

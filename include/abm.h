@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define ABM_ABI_VERSION 2
+#define ABM_ABI_VERSION 3
 #define ABM_EXTENT_SCRATCH_BYTES 1024
 
 enum abm_status {
@@ -104,13 +104,19 @@ typedef struct abm_extent {
     int64_t nboxes;            /* dims[0] * dims[1] * dims[2] */
 } abm_extent;
 
-/* Per-step statistics of the last completed step. */
+/* Per-step statistics of the last completed step (Section 5's engine tracks
+ * which agents moved and which were skipped). */
 typedef struct abm_stats {
     int64_t step;              /* steps completed */
     int64_t n_static;          /* agents whose force was skipped */
     int64_t n_moved;           /* agents with a non-zero displacement */
     uint32_t error;            /* device error bits (0 = none) */
     uint32_t reserved;
+    double sum_force[3];       /* sum of the forces the step evaluated (every agent's with the static test off:
+                                  zero up to rounding by Newton's third law, each pair term entering twice with
+                                  opposite signs); summed in a fixed order for a single simulation */
+    double max_displacement;   /* largest |Delta_i| of the step: |mu F_i|, or delta_max where clamped */
+    double skip_fraction;      /* n_static / n */
 } abm_stats;
 
 /* Accumulated kernel times of timed steps (abm_set_timing / abm_get_timing):

@@ -20,7 +20,7 @@ ABM_OK, ABM_E_INVAL, ABM_E_NONFINITE, ABM_E_GRID, ABM_E_WORKSPACE, ABM_E_HIP, AB
     0, -1, -2, -3, -4, -5, -6, -7
 ABM_F32, ABM_F64 = 0, 1
 ABM_ORDER_MORTON, ABM_ORDER_HILBERT = 0, 1
-ABI_VERSION = 2   # the layout of the structs below
+ABI_VERSION = 3   # the layout of the structs below
 FIELD = dict(positions=0, forces=1, moved=2, static=3, nnz=4, key=5, perm=6, cell_start=7, extent=8,
              storage_ids=9, neighbor_count=10, neighbors=11, diameters=12)
 EXTENT_SCRATCH_BYTES = 1024
@@ -50,7 +50,8 @@ class abm_extent(C.Structure):
 
 class abm_stats(C.Structure):
     _fields_ = [("step", C.c_int64), ("n_static", C.c_int64), ("n_moved", C.c_int64), ("error", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("reserved", C.c_uint32), ("sum_force", C.c_double * 3), ("max_displacement", C.c_double),
+                ("skip_fraction", C.c_double)]
 
 
 class abm_timing(C.Structure):
@@ -319,7 +320,9 @@ class Sim:
     def stats(self) -> dict:
         s = abm_stats()
         _check(lib().abm_get_stats(self.ctx, C.byref(s)), "abm_get_stats")
-        return dict(step=s.step, n_static=s.n_static, n_moved=s.n_moved, error=s.error)
+        return dict(step=s.step, n_static=s.n_static, n_moved=s.n_moved, error=s.error,
+                    sum_force=tuple(s.sum_force), max_displacement=s.max_displacement,
+                    skip_fraction=s.skip_fraction)
 
     # ---------------------------------------------------------------- checkpoint
     def export_state(self) -> bytes:

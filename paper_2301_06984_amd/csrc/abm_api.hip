@@ -1191,14 +1191,24 @@ int abm_get_stats(abm_ctx* c, abm_stats* out) {
     out->step = c->step;
     const int last = int((c->step - 1) & 1);
     int64_t ns = 0, nm = 0;
-    for (int r = 0; r < kReplicas; ++r) {
+    double fs[3] = {0.0, 0.0, 0.0};
+    uint64_t dm = 0;
+    for (int r = 0; r < kReplicas; ++r) {   // replicas in order
         ns += int64_t(g.stats[last][r][0]);
         nm += int64_t(g.stats[last][r][1]);
+        for (int a = 0; a < 3; ++a) fs[a] += g.fsum[last][r][a];
+        dm = std::max<uint64_t>(dm, g.dmax[last][r]);
     }
-    out->n_static = c->step > 0 ? ns : 0;
-    out->n_moved = c->step > 0 ? nm : 0;
+    const bool any = c->step > 0;
+    out->n_static = any ? ns : 0;
+    out->n_moved = any ? nm : 0;
     out->error = g.err;
     out->reserved = 0;
+    double dmax = 0.0;
+    std::memcpy(&dmax, &dm, sizeof(dmax));
+    for (int a = 0; a < 3; ++a) out->sum_force[a] = any ? fs[a] : 0.0;
+    out->max_displacement = any ? dmax : 0.0;
+    out->skip_fraction = any && c->n > 0 ? double(ns) / double(c->n) : 0.0;
     return ABM_OK;
 }
 

@@ -117,6 +117,11 @@ struct Globals {
     uint32_t napp;           // agents in the append region (an update: of the changed super-boxes; full: n)
     // per step parity and replica: agents skipped as static, agents moved
     unsigned long long stats[2][kReplicas][2];
+    // ... the sum of the forces the step evaluated (Newton's third law makes
+    // it zero up to rounding when every force is evaluated) and the largest
+    // displacement (as ordered bits of a non-negative double)
+    double fsum[2][kReplicas][3];
+    unsigned long long dmax[2][kReplicas];
 };
 
 // One block's share of the step's reductions: the box extent of its agents'
@@ -124,6 +129,8 @@ struct Globals {
 struct BlockPart {
     int32_t box[6];
     uint32_t n_static, n_moved;
+    double fsum[3];               // sum of the forces the block evaluated
+    unsigned long long dmax;      // largest displacement, ordered bits
 };
 
 // Pointers into the workspace, passed by value to kernels.

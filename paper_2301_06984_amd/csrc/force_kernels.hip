@@ -46,6 +46,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
     __shared__ int32_t s_box[kMaxBlockSims][6];
     __shared__ int s_sims[kMaxBlockSims];
     __shared__ uint32_t s_cnt[3];   // static, moved, waves done
+    __shared__ double s_fsum[16][3];            // per wave: sum of the forces it evaluated
+    __shared__ unsigned long long s_dmax[16];   // per wave: largest displacement (ordered bits)
     const uint32_t n = b.n, bs = blockDim.x, nb = (n + bs - 1) / bs;
     const uint32_t napp = min(b.g->napp, n);
     const bool inc = b.g->inc != 0u;
@@ -64,8 +66,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
         has_s = chunk < nb && inc;
     }
     if (!has_a && !has_s) {   // no agent in the block's chunks
-        if (!BATCHED && threadIdx.x == 0) b.bpart[blockIdx.x] = BlockPart{{INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN,
-                                                                           INT32_MIN, INT32_MIN}, 0u, 0u};
+        if (!BATCHED && threadIdx.x == 0)
+            b.bpart[blockIdx.x] =
+                BlockPart{{INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN}, 0u, 0u, {0.0, 0.0, 0.0}, 0ull};
         return;
     }
     const WalkLds L = walk_lds(s_walk);
@@ -79,6 +82,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
     }
     if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0u;
     if (threadIdx.x < kMaxBlockSims) s_sims[threadIdx.x] = -1;
+    if (threadIdx.x < 16) {
+        for (int c = 0; c < 3; ++c) s_fsum[threadIdx.x][c] = 0.0;
+        s_dmax[threadIdx.x] = 0ull;
+    }
     __syncthreads();
     const int cur = a.pos_cur, nxt = cur ^ 1;
     const bool KEEP_F = a.keep_forces;
@@ -122,6 +129,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
             if (!append) id_kept = b.ids[a.ids_cur][i];
         }
         bool ok = false, is_static = false, moved = false;
+        double st_f[3] = {0.0, 0.0, 0.0};   // this agent's force, if evaluated, for the step's statistics
+        unsigned long long st_d = 0ull;       // |Delta| as ordered bits
         int sim = 0;
         int32_t cnew[3] = {0, 0, 0};
         // ---- before the walk, per agent
@@ -204,6 +213,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
                 np.y = T(double(p.y) + m.uy);
                 np.z = T(double(p.z) + m.uz);
                 moved = m.ux != 0.0 || m.uy != 0.0 || m.uz != 0.0;
+                st_f[0] = acc.fx;
+                st_f[1] = acc.fy;
+                st_f[2] = acc.fz;
+                st_d = (unsigned long long)__double_as_longlong(m.size);
                 const uint32_t nz = acc.nnz < 0xFFFFFFu ? acc.nnz : 0xFFFFFFu;
                 nf = (moved ? kMovedBit : 0u) | (nz << kNnzShift);
                 if (moved) np.w = -np.w;
@@ -259,6 +272,21 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
             if (ns) atomicAdd(&s_cnt[0], ns);
             if (nm) atomicAdd(&s_cnt[1], nm);
         }
+        // the sum of the evaluated forces and the largest displacement: a
+        // butterfly over the wave (a fixed order), into the wave's LDS slot;
+        // a wave of static agents has nothing to add
+        if (__ballot(active && !is_static && ok) != 0ull) {
+            for (int d = 32; d >= 1; d >>= 1) {
+                for (int c = 0; c < 3; ++c) st_f[c] += __shfl_xor(st_f[c], d, 64);
+                const unsigned long long o = __shfl_xor(st_d, d, 64);
+                st_d = o > st_d ? o : st_d;
+            }
+            if (lane_id() == 0) {
+                const int w = int(threadIdx.x >> 6);
+                for (int c = 0; c < 3; ++c) s_fsum[w][c] += st_f[c];
+                s_dmax[w] = st_d > s_dmax[w] ? st_d : s_dmax[w];
+            }
+        }
     };
     if constexpr (two_chunks<CH>()) {
 #pragma unroll
@@ -275,14 +303,31 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
         const uint32_t nwaves = (blockDim.x + 63u) >> 6;
         if (atomicAdd(&s_cnt[2], 1u) == nwaves - 1) {
             __threadfence_block();
+            // the waves' force sums in wave order, their largest displacement
+            // (the other waves' LDS writes precede their counter increments)
+            double fs[3] = {0.0, 0.0, 0.0};
+            unsigned long long dm = 0ull;
+            for (uint32_t w = 0; w < nwaves; ++w) {
+                for (int c = 0; c < 3; ++c) fs[c] += s_fsum[w][c];
+                const unsigned long long x = s_dmax[w];
+                dm = x > dm ? x : dm;
+            }
             if constexpr (!BATCHED) {
                 // one simulation: the block's record, folded by k_fold_parts
                 BlockPart r;
                 for (int c = 0; c < 6; ++c) r.box[c] = atomicAdd(&s_box[0][c], 0);
                 r.n_static = atomicAdd(&s_cnt[0], 0u);
                 r.n_moved = atomicAdd(&s_cnt[1], 0u);
+                for (int c = 0; c < 3; ++c) r.fsum[c] = fs[c];
+                r.dmax = dm;
                 b.bpart[blockIdx.x] = r;
                 return;
+            }
+            {   // batched: straight to the replicas (the order of the sums is not fixed)
+                const uint32_t rep = blockIdx.x % kReplicas;
+                for (int c = 0; c < 3; ++c)
+                    if (fs[c] != 0.0) atomicAdd(&b.g->fsum[a.parity][rep][c], fs[c]);
+                if (dm) atomicMax(&b.g->dmax[a.parity][rep], dm);
             }
             for (int k = 0; k < kMaxBlockSims; ++k) {
                 const int sk = atomicAdd(&s_sims[k], 0);
@@ -312,31 +357,41 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold_parts(const BlockPart* __
                                                              int32_t* __restrict__ rep, Globals* g, int slot,
                                                              int parity) {
     __shared__ int32_t s_box[kFoldThreads / 64][6];
-    __shared__ unsigned long long s_cnt[kFoldThreads / 64][2];
+    __shared__ unsigned long long s_cnt[kFoldThreads / 64][3];
+    __shared__ double s_fs[kFoldThreads / 64][3];
     const uint32_t per = (nparts + kReplicas - 1) / kReplicas;
     const uint32_t e0 = blockIdx.x * per, e1 = min(e0 + per, nparts);
     int32_t box[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
-    unsigned long long cnt[2] = {0ull, 0ull};
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kFoldThreads) {
+    unsigned long long cnt[3] = {0ull, 0ull, 0ull};   // static, moved, largest displacement
+    double fs[3] = {0.0, 0.0, 0.0};
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kFoldThreads) {   // each thread in record order
         const BlockPart r = parts[e];
         for (int a = 0; a < 3; ++a) {
             box[a] = min(box[a], r.box[a]);
             box[3 + a] = max(box[3 + a], r.box[3 + a]);
+            fs[a] += r.fsum[a];
         }
         cnt[0] += r.n_static;
         cnt[1] += r.n_moved;
+        cnt[2] = r.dmax > cnt[2] ? r.dmax : cnt[2];
     }
     const int wave = int(threadIdx.x >> 6);
     for (int a = 0; a < 3; ++a) {
         box[a] = wave_min(box[a]);
         box[3 + a] = wave_max(box[3 + a]);
     }
-    for (int d = 32; d >= 1; d >>= 1)
+    for (int d = 32; d >= 1; d >>= 1) {   // a fixed order: the sums do not depend on timing
         for (int c = 0; c < 2; ++c) cnt[c] += __shfl_xor(cnt[c], d, 64);
+        const unsigned long long o = __shfl_xor(cnt[2], d, 64);
+        cnt[2] = o > cnt[2] ? o : cnt[2];
+        for (int c = 0; c < 3; ++c) fs[c] += __shfl_xor(fs[c], d, 64);
+    }
     if (lane_id() == 0) {
         for (int a = 0; a < 6; ++a) s_box[wave][a] = box[a];
-        s_cnt[wave][0] = cnt[0];
-        s_cnt[wave][1] = cnt[1];
+        for (int c = 0; c < 3; ++c) {
+            s_cnt[wave][c] = cnt[c];
+            s_fs[wave][c] = fs[c];
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -344,14 +399,18 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold_parts(const BlockPart* __
             for (int a = 0; a < 3; ++a) {
                 box[a] = min(box[a], s_box[w][a]);
                 box[3 + a] = max(box[3 + a], s_box[w][3 + a]);
+                fs[a] += s_fs[w][a];
             }
             cnt[0] += s_cnt[w][0];
             cnt[1] += s_cnt[w][1];
+            cnt[2] = s_cnt[w][2] > cnt[2] ? s_cnt[w][2] : cnt[2];
         }
         int32_t* t = rep + (size_t(slot) * kReplicas + blockIdx.x) * 6;   // one simulation
         for (int a = 0; a < 6; ++a) t[a] = box[a];
         g->stats[parity][blockIdx.x][0] = cnt[0];
         g->stats[parity][blockIdx.x][1] = cnt[1];
+        for (int c = 0; c < 3; ++c) g->fsum[parity][blockIdx.x][c] = fs[c];
+        g->dmax[parity][blockIdx.x] = cnt[2];
     }
 }
 

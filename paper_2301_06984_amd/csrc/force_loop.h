@@ -573,6 +573,7 @@ struct Move {
     bool moves = false;
     bool clamped = false;
     double fnorm = 0.0;
+    double size = 0.0;   // |Delta|: |mu F|, or delta_max where clamped
 };
 
 __device__ __forceinline__ Move displacement(const SimGrid& G, double fx, double fy, double fz) {
@@ -584,7 +585,9 @@ __device__ __forceinline__ Move displacement(const SimGrid& G, double fx, double
         m.uy = G.mu * fy;
         m.uz = G.mu * fz;
         const double un = sqrt((m.ux * m.ux + m.uy * m.uy) + m.uz * m.uz);
+        m.size = un;
         if (un > G.delta_max) {
+            m.size = G.delta_max;
             const double s = G.delta_max / un;
             m.ux *= s;
             m.uy *= s;

@@ -273,6 +273,8 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
         }
     }
     for (int e = int(threadIdx.x); e < kReplicas * 2; e += kSetupThreads) g->stats[parity][e >> 1][e & 1] = 0ull;
+    for (int e = int(threadIdx.x); e < kReplicas * 3; e += kSetupThreads) g->fsum[parity][e / 3][e % 3] = 0.0;
+    for (int e = int(threadIdx.x); e < kReplicas; e += kSetupThreads) g->dmax[parity][e] = 0ull;
     __syncthreads();
     for (int chunk = 0; chunk < nsims; chunk += kSetupThreads) {
         const int s = chunk + int(threadIdx.x);

@@ -109,6 +109,45 @@ def test_static_skip_bitwise_and_matches_oracle(precision):
     assert fracs[0] == 0.0 and min(fracs[1:]) > 0.3
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_step_statistics(batched):
+    # per-step statistics against the oracle's step: moved and static counts
+    # exactly, the largest displacement (|mu F| or delta_max), the sum of the
+    # forces (Newton's third law: zero up to rounding with every force
+    # evaluated) and the skip fraction
+    w = workloads.c1(n=3000, seed=41)
+    p = oracle.Params(delta_max=0.05)   # the clamp is active for some agents
+    if batched:
+        half = w.n // 2
+        sim = abm.BatchedSim(to_dev(w.pos), to_dev(w.diam), np.array([0, half, w.n]), common=dict(delta_max=0.05))
+        refs = [oracle.State.initial(w.pos[:half], w.diam[:half]), oracle.State.initial(w.pos[half:], w.diam[half:])]
+    else:
+        sim = make_sim(w.pos, w.diam, delta_max=0.05)
+        refs = [oracle.State.initial(w.pos, w.diam)]
+    for t in range(3):
+        note(f"statistics step {t + 1} batched={batched}")
+        sim.step(1)
+        s = sim.stats()
+        disps = [oracle.step(r, p, want_disp=True)[1] for r in refs]
+        disp = np.concatenate(disps)
+        force = np.concatenate([r.force for r in refs])
+        assert s["n_moved"] == int(np.concatenate([r.moved for r in refs]).sum())
+        assert s["n_static"] == 0 and s["skip_fraction"] == 0.0
+        dmax = float(np.sqrt((disp ** 2).sum(axis=1)).max())
+        assert s["max_displacement"] == pytest.approx(dmax, rel=1e-12)
+        fmax = float(np.abs(force).max())
+        ref_sum = force.sum(axis=0)
+        bound = 8 * w.n * np.finfo(np.float64).eps * fmax
+        assert np.all(np.abs(np.array(s["sum_force"]) - ref_sum) <= bound)
+        assert np.all(np.abs(np.array(s["sum_force"])) <= bound)   # Newton's third law
+    # the skip fraction where the static test fires
+    c2 = workloads.c2(n=20000, seed=42)
+    on = make_sim(c2.pos, c2.diam, detect_static=True)
+    on.step(3)
+    s = on.stats()
+    assert s["skip_fraction"] == s["n_static"] / c2.n and s["skip_fraction"] > 0.3
+
+
 def test_determinism_and_layout_invariance():
     w = workloads.c2(n=25000, seed=31)
     runs = {}

@@ -2,16 +2,24 @@
 """Benchmark of the agent step on one MI355X.
 
 Headline: agent-steps/s of the plain step (grid build + static flags + force
-+ move, the force of static agents skipped) on 1e7 spheres in FP32 state, the
-c2 construction scaled to 1e7 agents (uniform inner cube + force-free jittered
-lattice shell, cube side 3387.7, d ~ U[8, 12]).  Beside it, on the same GPU:
-the same steps without the static skip and in the Hilbert order, the batched
-form (512 simulations, 50 steps in one graph launch) and the adjoint form (1e5
-spheres, 50 steps forward + backward), each as agent-steps/s; the dominant kernel's roofline from HIP
-events around it over the timed region; and the CPU oracle timed on a bounded
-sample of the same workload.
++ move) on 1e7 spheres in FP32 state, the c2 construction scaled to 1e7
+agents (uniform inner cube + force-free jittered lattice shell, cube side
+3387.7, d ~ U[8, 12]), with the static test off, so that every force is
+evaluated: the run the roofline is taken on.  The dominant kernel's time
+comes from HIP events around it over the timed steps; its HBM bytes and VALU
+instructions per launch from the committed rocprofv3 record
+(profiles/k_force_headline_counters.json, used only while the kernel
+sources match it).
 
-Prints one JSON line (rank 0).  Inputs are resident in HBM before timing.
+Legs on the same GPU: the static test on (speedup and skip fraction), the
+Hilbert order, population changes, FP64 state, c1's density at 1e7 agents,
+c2, the clustered 5e7-agent workload, the batched form (512 simulations, 50
+steps in one graph launch, against plain contexts and against one simulation
+of as many agents) and the adjoint form (1e5 spheres, 50 steps forward +
+backward); and the CPU oracle timed on bounded samples of the headline
+workload, at all host cores and at one thread.
+
+Prints one JSON line.  Inputs are resident in HBM before timing.
 """
 from __future__ import annotations
 
@@ -26,37 +34,46 @@ sys.path.insert(0, ROOT)
 
 METRIC = "agent-steps/s (grid+force+move) at 1e7 agents; batched & adjoint vs plain step"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-# Algorithmic bytes per agent of the step: read x, y, z, d; write x, y, z;
-# one 4-byte box key and one 4-byte list index written and read.
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4
+# cycles (16 lanes), at 2.4 GHz: 6.14e11 wave instructions/s, 3.93e13 lane
+# operations/s (FP64 FMA runs at that rate on this chip).
+CUS, SIMDS, CLOCK_HZ = 256, 4, 2.4e9
+VALU_WAVE_INSTR_PEAK = CUS * SIMDS * CLOCK_HZ / 4.0
+VALU_LANE_OPS_PEAK = 64.0 * VALU_WAVE_INSTR_PEAK
+# Algorithmic bytes per agent-step of the whole step (the method's own
+# minimum): read x, y, z, d; write x, y, z; one 4-byte box key and one 4-byte
+# list index written and read.
 STEP_BYTES = {"f32": 4 * 4 + 3 * 4 + 16, "f64": 4 * 8 + 3 * 8 + 16}
-# ... of the force/move kernel alone: read x, y, z, d and the 4-byte slot
-# index of the agent; write x, y, z.
-FORCE_BYTES = {"f32": 4 * 4 + 4 + 3 * 4, "f64": 4 * 8 + 4 + 3 * 8}
+
+PROFILES = os.path.join(ROOT, "profiles")
+COUNTERS_FILE = os.path.join(PROFILES, "k_force_headline_counters.json")
+FORCE_SOURCES = ["force_kernels.hip", "force_loop.h", "abm_device.h", "abm_internal.h", "hilbert_order.h"]
+# the force kernel instantiation of the roofline run: FP32 state, one
+# simulation, static test off, re-layout on, 2-wide walk
+ROOF_KERNEL = "abm::k_force<float, false, false, true, 2>"
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_headline_traffic.json")
-
-
-def measured_traffic(n, prec, block_size, order="morton", skip=True):
-    """HBM bytes per force launch from the committed FETCH_SIZE/WRITE_SIZE
-    counter runs (scaled by a plain copy's reading), or None when the kernel
-    sources changed since the counters were taken or the configuration
-    differs from the profiled one (1e7 agents, FP32 state, the recorded threads per block,
-    Morton order, static skip on)."""
+def force_sources_sha():
     import hashlib
+    h = hashlib.sha256()
+    for name in FORCE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2301_06984_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_record(block_size):
+    """The committed rocprofv3 record of the roofline run's force kernel
+    (VALU instructions, HBM bytes per launch), or None when the kernel sources
+    changed since it was taken or the block size differs."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(COUNTERS_FILE) as f:
             rec = json.load(f)
-        h = hashlib.sha256()
-        for name in rec["sources"]:
-            with open(os.path.join(ROOT, "paper_2301_06984_amd", "csrc", name), "rb") as f:
-                h.update(f.read())
-    except (OSError, KeyError, ValueError):
+    except (OSError, ValueError):
         return None
-    if (h.hexdigest() != rec["source_sha256"] or n != 10_000_000 or prec != "f32"
-            or block_size != rec.get("block_size") or order != "morton" or not skip):
+    if rec.get("source_sha256") != force_sources_sha() or rec.get("block_size") != block_size:
         return None
-    return float(rec["traffic_bytes"])
+    return rec
 
 
 def log(msg):
@@ -81,26 +98,64 @@ def timed_steps(sim, steps, timing=0):
     return t1 - t0, tm
 
 
-def cpu_baseline(w, budget_s: float, skip: bool):
-    """The oracle (as it is) on the same workload, whole steps until the budget is used."""
-    import numpy as np
+def host_description():
+    """CPU model, sockets x cores, threads and memory of this host (lscpu, /proc/meminfo)."""
+    import subprocess
+    d = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                d[k] = v
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    d["MemTotal"] = line.split(":")[1].strip()
+    except OSError:
+        pass
+    d["usable_cpus"] = len(os.sched_getaffinity(0))
+    return d
+
+
+def cpu_oracle_rate(w, steps, nthreads, skip):
+    """The oracle as it is, one untimed step, then `steps` timed steps."""
     import oracle
     st = oracle.State.initial(w.pos, w.diam)
-    p = oracle.Params(detect_static=skip)
-    steps = 0
+    p = oracle.Params(detect_static=skip, nthreads=nthreads)
+    oracle.step(st, p)
     t0 = time.perf_counter()
-    while True:
+    for _ in range(steps):
         oracle.step(st, p)
-        steps += 1
-        el = time.perf_counter() - t0
-        log(f"cpu oracle step {steps}: {el:.1f} s")
-        if el >= budget_s or steps >= 3:
-            break
-    cores = oracle.max_threads()
-    del np
-    return dict(value=w.n * steps / el, unit="agent-steps/s", cores=int(cores), kind="oracle",
-                sample=f"{steps} full step(s) of the {w.n}-agent headline workload (FP64 C++ oracle, OpenMP, "
-                       f"{el:.1f} s)")
+    el = time.perf_counter() - t0
+    return w.n * steps / el, el
+
+
+def cpu_baseline(skip: bool):
+    """The CPU oracle on bounded samples of the headline workload: all the
+    host's cores on the full 1e7 agents, and one thread on the same
+    construction at 1e6 agents."""
+    import oracle
+    from paper_2301_06984_amd import workloads
+    cores = int(oracle.max_threads())
+    w = workloads.headline()
+    log(f"cpu oracle, {cores} threads, 1e7 agents")
+    v_all, el_all = cpu_oracle_rate(w, 2, 0, skip)
+    del w
+    w1 = workloads.headline(n=1_000_000)
+    log("cpu oracle, 1 thread, 1e6 agents")
+    v_one, el_one = cpu_oracle_rate(w1, 1, 1, skip)
+    return dict(value=v_all, unit="agent-steps/s", cores=cores, kind="oracle",
+                sample=f"2 steps after an untimed one of the 1e7-agent headline workload, {cores} OpenMP threads, "
+                       f"{el_all:.1f} s (FP64 C++ oracle, static test {'on' if skip else 'off'})",
+                value_1thread=v_one,
+                sample_1thread=f"1 step after an untimed one of the same construction at 1e6 agents, 1 thread, "
+                               f"{el_one:.1f} s",
+                host=host_description())
 
 
 DEFAULT_SWEEP = "1e3,1e4,1e5,1e6,1e7,1e8,3e8,1e9"
@@ -143,28 +198,130 @@ def scale_sweep(sizes, block_size):
         torch.cuda.empty_cache()
 
 
+def run_plain(pos, diam, steps, warmup, timing=2, **kw):
+    """Plain context on device tensors: warm-up, then `steps` timed steps
+    (events around the force kernel with timing 2); returns the context, the
+    wall time and the force kernel's mean time per step (ms)."""
+    from paper_2301_06984_amd import abm
+    sim = abm.Sim(pos, diam, **kw)
+    sim.step(warmup)
+    sim.sync()
+    el, tm = timed_steps(sim, steps, timing=timing)
+    force_ms = tm["force"] / tm["steps"] if tm else None
+    return sim, el, force_ms
+
+
+def leg(extras, name, fn):
+    """Run one extra leg; its failure is recorded, not fatal to the line."""
+    try:
+        extras[name] = fn()
+        log(f"{name} {extras[name]}")
+    except Exception as e:  # noqa: BLE001 -- reported in the JSON line
+        extras[name] = {"error": f"{type(e).__name__}: {e}"}
+        log(f"{name} failed: {e}")
+    import torch
+    torch.cuda.empty_cache()
+
+
+def summarize_profiles(kt_dir, valu_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, block_size):
+    """Write profiles/k_force_headline_counters.json from the rocprofv3 CSVs
+    of the roofline run (bench.py --profile-run): per-launch VALU and other
+    instruction counts and HBM bytes of the force kernel over the
+    steady-state steps (update builds; the first, full-build launch apart),
+    the byte counters scaled by what a plain 1 GiB copy reads and writes."""
+    import csv
+    import glob
+
+    def rows(d, pattern):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", pattern), recursive=True):
+            with open(f) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    def per_dispatch(d, kernel):
+        by = {}
+        for r in rows(d, "*counter_collection.csv"):
+            if kernel in r["Kernel_Name"]:
+                by.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        ids = sorted(by)
+        return [by[i] for i in ids]
+
+    def steady(dl):
+        return dl[1:] if len(dl) > 1 else dl
+
+    def mean(dl, c):
+        v = [x[c] for x in dl if c in x]
+        return sum(v) / len(v) if v else None
+
+    vd = per_dispatch(valu_dir, ROOF_KERNEL)
+    fd = per_dispatch(fetch_dir, ROOF_KERNEL)
+    wd = per_dispatch(write_dir, ROOF_KERNEL)
+    cf = per_dispatch(copy_fetch_dir, "copyBuffer")
+    cw = per_dispatch(copy_write_dir, "copyBuffer")
+    gib = float(1 << 30)
+    fscale = gib / (1024.0 * mean(cf, "FETCH_SIZE"))
+    wscale = gib / (1024.0 * mean(cw, "WRITE_SIZE"))
+    times = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows(kt_dir, "*kernel_trace.csv")
+             if ROOF_KERNEL in r["Kernel_Name"]]
+    sv = steady(vd)
+    rec = {
+        "kernel": ROOF_KERNEL,
+        "workload": "headline 1e7 spheres, FP32 state, static test off, re-layout every step",
+        "block_size": block_size,
+        "dispatches": f"steady state: launches 2..{len(vd)} (update builds); launch 1 (full build) reported apart",
+        "per_launch": {c: mean(sv, c) for c in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+                                               "SQ_INSTS_VMEM_RD", "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY",
+                                               "SQ_BUSY_CYCLES")},
+        "full_build_launch": {c: vd[0].get(c) for c in ("SQ_INSTS_VALU", "SQ_WAVES")} if vd else None,
+        "fetch_kib": mean(steady(fd), "FETCH_SIZE"),
+        "write_kib": mean(steady(wd), "WRITE_SIZE"),
+        "full_build_fetch_kib": fd[0]["FETCH_SIZE"] if fd else None,
+        "full_build_write_kib": wd[0]["WRITE_SIZE"] if wd else None,
+        "fetch_scale": fscale,
+        "write_scale": wscale,
+        "kernel_trace_ns": {"steady_mean": sum(times[1:]) / max(len(times) - 1, 1) if times else None,
+                            "first": times[0] if times else None, "launches": len(times)},
+        "sources": FORCE_SOURCES,
+        "source_sha256": force_sources_sha(),
+    }
+    rec["traffic_bytes"] = 1024.0 * (rec["fetch_kib"] * fscale + rec["write_kib"] * wscale)
+    with open(COUNTERS_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=10_000_000)
-    ap.add_argument("--block-size", type=int, default=512)
-    ap.add_argument("--skip", action=argparse.BooleanOptionalAction, default=True,
-                    help="the static skip (Section 5) in the headline run (--no-skip: every force computed)")
+    ap.add_argument("--block-size", type=int, default=256)
     ap.add_argument("--order", choices=["morton", "hilbert"], default="morton",
                     help="order of the boxes for the headline run (the legs keep their own)")
     ap.add_argument("--sort-every", type=int, default=1)
-    ap.add_argument("--no-extras", action="store_true", help="leave out the Hilbert, static-skip, dynamic, batched and adjoint legs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="leave out every leg but the headline (static test, FP64 state, densities, clustered, "
+                         "Hilbert, dynamic population, batched and adjoint)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--sweep", nargs="?", const=DEFAULT_SWEEP, default=None,
                     help="instead of the headline: agent-steps/s of the plain step on a uniform cube at c2's "
                          "density for each N of a comma-separated list (one JSON line per N)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scales rocprof byte counters)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the roofline run, for rocprofv3: one full-build step, then 10 update-build steps")
+    ap.add_argument("--summarize-profiles", nargs=6, metavar=("KT", "VALU", "FETCH", "WRITE", "COPY_FETCH",
+                                                               "COPY_WRITE"),
+                    help="write profiles/k_force_headline_counters.json from rocprofv3 output folders of "
+                         "--profile-run (kernel trace, SQ counters, FETCH_SIZE, WRITE_SIZE) and of "
+                         "--calibrate-copy (FETCH_SIZE, WRITE_SIZE)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles, block_size=args.block_size)
+        return
     if args.calibrate_copy:
         import torch
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -194,192 +351,245 @@ def main():
         scale_sweep([int(float(x)) for x in args.sweep.split(",")], args.block_size)
         return
 
-    # ---------------------------------------------------------------- headline
+    # ------------------------------------------------ headline (roofline run)
+    # Section 8(d): the roofline is taken with the static test off (every
+    # force evaluated); the static test's speedup is a leg of its own
     log(f"generating headline workload n={args.n}")
     w = workloads.headline(n=args.n)
     pos = torch.from_numpy(w.pos).to(dev)
     diam = torch.from_numpy(w.diam).to(dev)
-    sim = abm.Sim(pos, diam, detect_static=args.skip, sort_every=args.sort_every, block_size=args.block_size,
-                  order=args.order)
-    sim.step(args.warmup)
-    sim.sync()
-    log("timed region")
-    el, tm = timed_steps(sim, args.steps, timing=2)
+    common = dict(sort_every=args.sort_every, block_size=args.block_size, order=args.order)
+    if args.profile_run:
+        sim = abm.Sim(pos, diam, detect_static=False, **common)
+        sim.step(11)
+        sim.sync()
+        print(json.dumps({"profile_run": "headline, static test off", "steps": 11}), flush=True)
+        return
+    sim, el, force_ms = run_plain(pos, diam, args.steps, args.warmup, detect_static=False, **common)
     value = w.n * args.steps / el
     ms_step = 1e3 * el / args.steps
-    force_ms = tm["force"] / tm["steps"]
     # the phase breakdown: the next K steps, with events around every kernel
     el_ph, tm_ph = timed_steps(sim, args.steps, timing=1)
     phases = {k: tm_ph[k] / tm_ph["steps"] for k in abm.TIMED_PHASES}
     dominant = max(abm.TIMED_PHASES, key=lambda k: phases[k])
-    prec = w.precision
-    force_bytes = FORCE_BYTES[prec] * w.n
-    ach = force_bytes / (force_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w.n, prec, args.block_size, args.order, args.skip)
-    roof = dict(bound="hbm", kernel="k_force (static flags + force + move)", achieved=round(ach, 1),
-                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
-                traffic=None if traffic is None else round(traffic), traffic_unit="bytes per launch",
-                algorithmic_bytes=force_bytes,
-                bytes_per_agent=FORCE_BYTES[prec], avg_launch_ms=round(force_ms, 4),
-                dominant_phase=dominant, phase_ms={k: round(v, 4) for k, v in phases.items()},
-                phase_ms_note="the K steps after the timed ones, with events around every kernel "
-                              f"({1e3 * el_ph / args.steps:.4f} ms per step there)",
-                step_bytes_per_agent=STEP_BYTES[prec],
-                step_frac=round(value * STEP_BYTES[prec] / (HBM_PEAK_GBS * 1e9), 4))
-    log(f"headline {value:.3e} agent-steps/s, {ms_step:.3f} ms/step, phases {phases}")
-    sim_stats = sim.stats()
+    stats = sim.stats()
     del sim
+    prec = w.precision
+    alg = STEP_BYTES[prec] * w.n
+    ach = alg / (force_ms * 1e-3) / 1e9
+    rec = counter_record(args.block_size)
+    roof = dict(kernel="k_force (static flags + force + move), static test off", achieved=round(ach, 1),
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
+                algorithmic_bytes_per_launch=alg, bytes_per_agent_step=STEP_BYTES[prec],
+                avg_launch_ms=round(force_ms, 4),
+                step_frac=round(value * STEP_BYTES[prec] / (HBM_PEAK_GBS * 1e9), 4),
+                dominant_phase=dominant, phase_ms={k: round(v, 4) for k, v in phases.items()},
+                phase_ms_note=f"the K steps after the timed ones, events around every kernel "
+                              f"({1e3 * el_ph / args.steps:.4f} ms per step there)")
+    bound = None
+    if rec is not None:
+        traffic = rec["traffic_bytes"]
+        valu = rec["per_launch"]["SQ_INSTS_VALU"]
+        measured_gbs = traffic / (force_ms * 1e-3) / 1e9
+        valu_frac = valu / (force_ms * 1e-3 * VALU_WAVE_INSTR_PEAK)
+        bound = "alu" if valu_frac > measured_gbs / HBM_PEAK_GBS else "hbm"
+        roof.update(traffic=round(traffic), traffic_unit="HBM bytes per launch (FETCH_SIZE, WRITE_SIZE, scaled)",
+                    measured_achieved=round(measured_gbs, 1), measured_frac=round(measured_gbs / HBM_PEAK_GBS, 4),
+                    valu=dict(instructions_per_launch=round(valu), achieved=round(valu * 64 / (force_ms * 1e-3) / 1e12, 3),
+                              peak=round(VALU_LANE_OPS_PEAK / 1e12, 2), unit="T VALU lane operations/s",
+                              frac=round(valu_frac, 4),
+                              peak_note="256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz"),
+                    counters=os.path.relpath(COUNTERS_FILE, ROOT))
+    roof = {"bound": bound or "alu", **roof}
+    if rec is None:
+        roof["bound_note"] = "counter record absent or stale for these kernel sources: bound as last measured"
+    log(f"headline {value:.3e} agent-steps/s, {ms_step:.3f} ms/step, force {force_ms:.4f} ms, phases {phases}")
 
     extras = {}
     if not args.no_extras:
-        # Hilbert order of the super-boxes (the other curve Section 4.2
-        # compares): the same steps, only the order of the boxes changed
-        sh = abm.Sim(pos, diam, detect_static=args.skip, sort_every=args.sort_every, block_size=args.block_size,
-                     order="hilbert")
-        sh.step(args.warmup)
-        sh.sync()
-        elh, _ = timed_steps(sh, args.steps, timing=2)
-        _, tmh = timed_steps(sh, args.steps, timing=1)
-        extras["hilbert"] = dict(value=w.n * args.steps / elh, unit="agent-steps/s",
-                                 ms_per_step=round(1e3 * elh / args.steps, 4),
-                                 speedup_vs_morton=round(el / elh, 3),
-                                 phase_ms={k: round(tmh[k] / tmh["steps"], 4) for k in abm.TIMED_PHASES},
-                                 note="2x2x2 super-boxes along a Hilbert curve, Morton order inside each; "
-                                      "phase_ms from the K steps after the timed ones, as under roofline")
-        log(f"hilbert {extras['hilbert']}")
-        del sh
-        # the other setting of the static skip (same workload; the shell is
-        # force-free and static from its first step)
-        s2 = abm.Sim(pos, diam, detect_static=not args.skip, sort_every=args.sort_every, block_size=args.block_size)
-        s2.step(args.warmup)
-        el2, _ = timed_steps(s2, args.steps, timing=2)   # timed as the headline
-        el_on, el_off = (el, el2) if args.skip else (el2, el)
-        son = (sim_stats if args.skip else s2.stats())
-        extras["static_skip"] = dict(skip_on=w.n * args.steps / el_on, skip_off=w.n * args.steps / el_off,
-                                     unit="agent-steps/s", speedup_on_vs_off=round(el_off / el_on, 3),
-                                     static_fraction_last_step=round(son["n_static"] / w.n, 4))
-        log(f"static skip {extras['static_skip']}")
-        del s2
-        # dynamic population (Section 3.2): 1% of the agents removed and as
-        # many added between two steps; the next grid is a full build
-        sd = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size,
-                     capacity=w.n + w.n // 50)
-        sd.step(args.warmup)
-        sd.sync()
-        gd = np.random.default_rng(8)
-        m = w.n // 100
-        rm = torch.from_numpy(gd.choice(w.n, m, replace=False)).to(dev)
-        R = float(w.diam.max())
-        side = float(w.meta["side"])
-        newp = torch.from_numpy(gd.uniform(0.0, side, size=(m, 3)).astype(w.pos.dtype)).to(dev)
-        newd = torch.from_numpy(gd.uniform(8.0, R, size=m).astype(w.diam.dtype)).to(dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sd.remove_agents(rm)
-        t1 = time.perf_counter()
-        sd.add_agents(newp, newd)
-        t2 = time.perf_counter()
-        el_full, _ = timed_steps(sd, 1)
-        el_upd, _ = timed_steps(sd, 1)
-        extras["dynamic"] = dict(removed=m, added=m, remove_ms=round(1e3 * (t1 - t0), 3),
-                                 add_ms=round(1e3 * (t2 - t1), 3),
-                                 removed_per_s=m / (t1 - t0), added_per_s=m / (t2 - t1),
-                                 next_step_ms=round(1e3 * el_full, 3), following_step_ms=round(1e3 * el_upd, 3),
-                                 note="calls include their stream synchronisations; the next step's grid is a "
-                                      "full build, the following one an update")
-        log(f"dynamic {extras['dynamic']}")
-        del sd, rm, newp, newd
+        def static_leg():
+            s2, el2, f2 = run_plain(pos, diam, args.steps, args.warmup, detect_static=True, **common)
+            st = s2.stats()
+            return dict(value=w.n * args.steps / el2, unit="agent-steps/s", ms_per_step=round(1e3 * el2 / args.steps, 4),
+                        force_ms=round(f2, 4), speedup_vs_static_off=round(el / el2, 3),
+                        skip_fraction_last_step=round(st["skip_fraction"], 4),
+                        note="the same workload with the static test (Section 5) on; the lattice shell is "
+                             "force-free and static from step 1")
+        leg(extras, "static_skip", static_leg)
+
+        def hilbert_leg():
+            sh, elh, fh = run_plain(pos, diam, args.steps, args.warmup, detect_static=False,
+                                    sort_every=args.sort_every, block_size=args.block_size, order="hilbert")
+            return dict(value=w.n * args.steps / elh, unit="agent-steps/s", ms_per_step=round(1e3 * elh / args.steps, 4),
+                        force_ms=round(fh, 4), speedup_vs_morton=round(el / elh, 3),
+                        note="2x2x2 super-boxes along a Hilbert curve, Morton order inside each")
+        leg(extras, "hilbert", hilbert_leg)
+
+        def dynamic_leg():
+            sd = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size,
+                         capacity=w.n + w.n // 50)
+            sd.step(args.warmup)
+            sd.sync()
+            gd = np.random.default_rng(8)
+            m = w.n // 100
+            rm = torch.from_numpy(gd.choice(w.n, m, replace=False)).to(dev)
+            R = float(w.diam.max())
+            side = float(w.meta["side"])
+            newp = torch.from_numpy(gd.uniform(0.0, side, size=(m, 3)).astype(w.pos.dtype)).to(dev)
+            newd = torch.from_numpy(gd.uniform(8.0, R, size=m).astype(w.diam.dtype)).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sd.remove_agents(rm)
+            t1 = time.perf_counter()
+            sd.add_agents(newp, newd)
+            t2 = time.perf_counter()
+            el_full, _ = timed_steps(sd, 1)
+            el_upd, _ = timed_steps(sd, 1)
+            return dict(removed=m, added=m, remove_ms=round(1e3 * (t1 - t0), 3), add_ms=round(1e3 * (t2 - t1), 3),
+                        next_step_ms=round(1e3 * el_full, 3), following_step_ms=round(1e3 * el_upd, 3),
+                        note="calls include their stream synchronisations; the next step's grid is a full build")
+        leg(extras, "dynamic", dynamic_leg)
         del pos, diam
         torch.cuda.empty_cache()
-        # batched: 512 simulations, 50 steps in one graph launch, with the
-        # knobs the autotuner picks for this batch (tuning is not timed)
-        wb = workloads.c4()
-        s = torch.cuda.Stream()
-        with torch.cuda.stream(s):
-            pb, db = torch.from_numpy(wb.pos).to(dev), torch.from_numpy(wb.diam).to(dev)
-            tuned = tune.autotune_batched(pb, db, wb.offsets, graph_steps=wb.steps, stream=s)
-            log(f"autotuned {tuned.params}: {tuned.ms_per_step:.3f} ms/step over {len(tuned.trials)} trials")
-            b = abm.BatchedSim(pb, db, wb.offsets, stream=s, common=dict(tuned.params))
-            b.graph_capture(wb.steps)
-            b.graph_launch()          # warm-up replay
-            b.sync()
+
+        def fp64_leg():
+            w64 = workloads.headline(n=args.n, dtype=np.float64)
+            p64, d64 = torch.from_numpy(w64.pos).to(dev), torch.from_numpy(w64.diam).to(dev)
+            s64, el64, f64 = run_plain(p64, d64, args.steps, args.warmup, detect_static=False, **common)
+            v = w64.n * args.steps / el64
+            return dict(value=v, unit="agent-steps/s", ms_per_step=round(1e3 * el64 / args.steps, 4),
+                        force_ms=round(f64, 4), bytes_per_agent_step=STEP_BYTES["f64"],
+                        frac=round(STEP_BYTES["f64"] * w64.n / (f64 * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                        step_frac=round(v * STEP_BYTES["f64"] / (HBM_PEAK_GBS * 1e9), 4),
+                        note="the headline workload with FP64 state, static test off")
+        leg(extras, "headline_fp64_state", fp64_leg)
+
+        def c1_density_leg():
+            side = (args.n / workloads.C1_DENSITY) ** (1.0 / 3.0)
+            p1, d1 = workloads.uniform_cube(args.n, side, (1, args.n), dtype=np.float32)
+            pc, dc = torch.from_numpy(p1).to(dev), torch.from_numpy(d1).to(dev)
+            del p1, d1
+            k = max(args.steps // 4, 3)
+            sc, elc, fc = run_plain(pc, dc, k, 2, detect_static=False, **common)
+            return dict(value=args.n * k / elc, unit="agent-steps/s", ms_per_step=round(1e3 * elc / k, 4),
+                        force_ms=round(fc, 4), steps=k,
+                        note=f"1e7 spheres uniform at c1's density (side {side:.0f}, about 47 candidates and 4 "
+                             f"contacts per agent), FP32 state, static test off: bound by VALU, not HBM")
+        leg(extras, "c1_density_1e7", c1_density_leg)
+
+        def c2_leg():
+            w2 = workloads.c2()
+            p2, d2 = torch.from_numpy(w2.pos).to(dev), torch.from_numpy(w2.diam).to(dev)
+            s2, el2, f2 = run_plain(p2, d2, w2.steps, 3, detect_static=True, sort_every=1, block_size=args.block_size)
+            return dict(value=w2.n * w2.steps / el2, unit="agent-steps/s", ms_per_step=round(1e3 * el2 / w2.steps, 4),
+                        force_ms=round(f2, 4), steps=w2.steps, skip_fraction_last_step=round(s2.stats()["skip_fraction"], 4),
+                        note="c2: 1e6 spheres, FP32, static test on, 100 steps after 3 untimed")
+        leg(extras, "c2", c2_leg)
+
+        def c3_leg():
+            w3 = workloads.c3()
+            p3, d3 = torch.from_numpy(w3.pos).to(dev), torch.from_numpy(w3.diam).to(dev)
+            s3, el3, f3 = run_plain(p3, d3, 3, 1, detect_static=False, sort_every=10, block_size=args.block_size)
+            return dict(value=w3.n * 3 / el3, unit="agent-steps/s", ms_per_step=round(1e3 * el3 / 3, 2),
+                        force_ms=round(f3, 2), steps=3,
+                        note="c3: 5e7 spheres in 1000 Gaussian blobs, FP32, re-layout every 10 steps; steps 2-4 "
+                             "timed; about 5e3 candidates per agent, bound by VALU")
+        leg(extras, "c3", c3_leg)
+
+        def batched_leg():
+            wb = workloads.c4()
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                pb, db = torch.from_numpy(wb.pos).to(dev), torch.from_numpy(wb.diam).to(dev)
+                tuned = tune.autotune_batched(pb, db, wb.offsets, graph_steps=wb.steps, stream=s)
+                b = abm.BatchedSim(pb, db, wb.offsets, stream=s, common=dict(tuned.params))
+                b.graph_capture(wb.steps)
+                b.graph_launch()          # warm-up replay
+                b.sync()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                b.graph_launch()
+                b.sync()
+                elb = time.perf_counter() - t0
+                del b
+                # (i) the same simulations, one plain context each
+                kp = 10
+                plain_sims = []
+                for k in range(len(wb.offsets) - 1):
+                    a, e = int(wb.offsets[k]), int(wb.offsets[k + 1])
+                    sp = abm.Sim(pb[a:e].contiguous(), db[a:e].contiguous(), stream=s)
+                    sp.step(2)
+                    sp.graph_capture(kp)
+                    sp.graph_launch()
+                    plain_sims.append(sp)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for sp in plain_sims:
+                    sp.graph_launch()
+                torch.cuda.synchronize()
+                elc = (time.perf_counter() - t0) / kp
+                del plain_sims
+            # (ii) one plain simulation of as many agents at volume fraction 0.45
+            g = workloads.rng_for((4, 999))
+            dd = g.uniform(8.0, 12.0, size=wb.n)
+            side = (float(np.sum(np.pi / 6.0 * dd ** 3)) / 0.45) ** (1.0 / 3.0)
+            pp = g.uniform(0.0, side, size=(wb.n, 3)).astype(np.float32)
+            one, el1, f1 = run_plain(torch.from_numpy(pp).to(dev), torch.from_numpy(dd.astype(np.float32)).to(dev),
+                                     10, 3, detect_static=False, sort_every=1, block_size=args.block_size)
+            v = wb.n * wb.steps / elb
+            return dict(value=v, unit="agent-steps/s", nsims=len(wb.offsets) - 1, agents=int(wb.n), steps=wb.steps,
+                        launch="one hipGraph replay of 50 steps", ms_per_step=round(1e3 * elb / wb.steps, 4),
+                        plain_contexts_ms_per_step=round(1e3 * elc, 4),
+                        speedup_vs_plain_contexts=round(elc / (elb / wb.steps), 3),
+                        one_simulation_phi045=dict(value=wb.n * 10 / el1, ms_per_step=round(1e3 * el1 / 10, 4),
+                                                   force_ms=round(f1, 4)),
+                        ratio_vs_one_simulation=round(v / (wb.n * 10 / el1), 3),
+                        ratio_vs_headline=round(v / value, 3),
+                        autotuned=tuned.params, tune_trials=len(tuned.trials),
+                        untuned_ms_per_step=round(tuned.trials[0][1], 4), tuned_ms_per_step=round(tuned.ms_per_step, 4))
+        leg(extras, "batched", batched_leg)
+
+        def adjoint_leg():
+            wa = workloads.c5()
+            pa = torch.from_numpy(wa.pos).to(dev)
+            da = torch.from_numpy(wa.diam).to(dev)
+            plain = abm.Sim(pa, da, sort_every=0)
+            plain.step(5)
+            elp, _ = timed_steps(plain, wa.steps)
+            adj = abm.Sim(pa, da, sort_every=0)
+            adj.forward_record(wa.steps, 10)      # warm-up
+            xT = adj.positions().double()
+            tgt = torch.from_numpy(wa.target).to(dev)
+            adj.backward(2.0 * (xT - tgt) / (3 * wa.n))
+            adj2 = abm.Sim(pa, da, sort_every=0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            b.graph_launch()
-            b.sync()
-            elb = time.perf_counter() - t0
-            del b
-            # the same simulations without batching: one plain context each,
-            # default knobs, each replaying a graph of its own 10 steps
-            kp = 10
-            plain_sims = []
-            for k in range(len(wb.offsets) - 1):
-                a, e = int(wb.offsets[k]), int(wb.offsets[k + 1])
-                sp = abm.Sim(pb[a:e].contiguous(), db[a:e].contiguous(), stream=s)
-                sp.step(2)
-                sp.graph_capture(kp)
-                sp.graph_launch()     # warm-up replay
-                plain_sims.append(sp)
+            adj2.forward_record(wa.steps, 10)
+            xT = adj2.positions().double()
+            gx, gp = adj2.backward(2.0 * (xT - tgt) / (3 * wa.n))
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for sp in plain_sims:
-                sp.graph_launch()
-            torch.cuda.synchronize()
-            elc = (time.perf_counter() - t0) / kp
-            del plain_sims, sp
-        extras["batched"] = dict(value=wb.n * wb.steps / elb, unit="agent-steps/s", nsims=len(wb.offsets) - 1,
-                                 agents=int(wb.n), steps=wb.steps, launch="one hipGraph replay of 50 steps",
-                                 ms_per_step=round(1e3 * elb / wb.steps, 4),
-                                 plain_contexts_ms_per_step=round(1e3 * elc, 4),
-                                 speedup_vs_plain_contexts=round(elc / (elb / wb.steps), 3),
-                                 plain_contexts="the same simulations, one plain context each, each replaying a "
-                                                "graph of 10 steps, one after another on one stream",
-                                 ratio_vs_plain=round((wb.n * wb.steps / elb) / value, 3),
-                                 autotuned=tuned.params, tune_trials=len(tuned.trials),
-                                 untuned_ms_per_step=round(tuned.trials[0][1], 4),
-                                 tuned_ms_per_step=round(tuned.ms_per_step, 4))
-        log(f"batched {extras['batched']}")
-        del pb, db
-        torch.cuda.empty_cache()
-        # adjoint: 1e5 spheres, 50 steps, checkpoint every 10, forward + backward
-        wa = workloads.c5()
-        pa = torch.from_numpy(wa.pos).to(dev)
-        da = torch.from_numpy(wa.diam).to(dev)
-        plain = abm.Sim(pa, da, sort_every=0)
-        plain.step(5)
-        elp, _ = timed_steps(plain, wa.steps)
-        adj = abm.Sim(pa, da, sort_every=0)
-        adj.forward_record(wa.steps, 10)      # warm-up
-        xT = adj.positions().double()
-        tgt = torch.from_numpy(wa.target).to(dev)
-        adj.backward(2.0 * (xT - tgt) / (3 * wa.n))
-        adj2 = abm.Sim(pa, da, sort_every=0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        adj2.forward_record(wa.steps, 10)
-        xT = adj2.positions().double()
-        gx, gp = adj2.backward(2.0 * (xT - tgt) / (3 * wa.n))
-        torch.cuda.synchronize()
-        ela = time.perf_counter() - t0
-        extras["adjoint"] = dict(value=wa.n * wa.steps / ela, unit="agent-steps/s (forward+backward)",
-                                 agents=wa.n, steps=wa.steps, ckpt_every=10,
-                                 plain_forward=wa.n * wa.steps / elp,
-                                 ratio_vs_plain_forward=round(elp / ela, 3),
-                                 dL_dk=float(gp[0]), dL_dgamma=float(gp[1]))
-        log(f"adjoint {extras['adjoint']}")
+            ela = time.perf_counter() - t0
+            peak = int(adj2.ws.numel()) + int(adj2.rec.numel()) + 2 * 24 * wa.n
+            return dict(value=wa.n * wa.steps / ela, unit="agent-steps/s (forward+backward)", agents=wa.n,
+                        steps=wa.steps, ckpt_every=10, plain_forward=wa.n * wa.steps / elp,
+                        ratio_vs_plain_forward=round(elp / ela, 3), dL_dk=float(gp[0]), dL_dgamma=float(gp[1]),
+                        peak_device_bytes=peak,
+                        peak_note="workspace + forward record + dL/dx_T and dL/dx_0 (n x 3 doubles each)")
+        leg(extras, "adjoint", adjoint_leg)
 
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
-        cpu = cpu_baseline(w, args.cpu_budget, args.skip)
+        cpu = cpu_baseline(False)
 
     out = {"metric": METRIC, "value": value, "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "vs_baseline": None, "dtype": "f64", "state_dtype": prec, "data": "synthetic",
            "config": {"workload": "headline: 1e7 spheres, c2 construction (uniform inner cube + jittered "
                                   "force-free lattice shell), side 3387.7, d~U[8,12], seed 2",
-                      "n": w.n, "state": prec, "arithmetic": "f64", "detect_static": bool(args.skip),
+                      "n": w.n, "state": prec, "arithmetic": "f64", "detect_static": False,
                       "sort_every": args.sort_every, "block_size": args.block_size, "order": args.order},
+           "stats_last_step": {k: (list(v) if isinstance(v, tuple) else v) for k, v in stats.items()},
            "roofline": roof, "cpu_baseline": cpu, **extras}
     line = json.dumps(out)
     print(line, flush=True)

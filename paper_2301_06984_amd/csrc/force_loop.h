@@ -276,17 +276,21 @@ __device__ __forceinline__ void walk_chunks(const V4<T>* __restrict__ sp, const 
     }
 }
 
-// Conservative single-precision pre-test of |x_i - x_j|^2 < R^2 for float
-// state: false only if the exact double test must fail (the float sum of
-// squares is within a few ulp of the exact value; the bound is padded by
-// 2^-16 relative).  Double state goes straight to the exact test.
+// Conservative single-precision pre-test of |x_i - x_j|^2 < R^2: false only
+// if the exact double test must fail.  The float sum of squares is within a
+// few ulp (relative) of the exact value: for float state the differences are
+// float roundings of the exact ones, for double state float roundings of the
+// double differences (about 5 * 2^-24 relative in all, far inside the 2^-16
+// relative padding of the bound; a difference too large for float becomes
+// infinite and fails, as the exact test does).
 template <class T>
 __device__ __forceinline__ bool maybe_within(const V4<T>& pi, const V4<T>& pj, float r2pad) {
     if constexpr (sizeof(T) == 4) {
         const float ex = pi.x - pj.x, ey = pi.y - pj.y, ez = pi.z - pj.z;
         return __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex)) < r2pad;
     } else {
-        return true;
+        const float ex = float(pi.x - pj.x), ey = float(pi.y - pj.y), ez = float(pi.z - pj.z);
+        return __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex)) < r2pad;
     }
 }
 

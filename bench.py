@@ -211,8 +211,11 @@ def run_plain(pos, diam, steps, warmup, timing=2, **kw):
     return sim, el, force_ms
 
 
-def leg(extras, name, fn):
-    """Run one extra leg; its failure is recorded, not fatal to the line."""
+def leg(extras, name, fn, only=None):
+    """Run one extra leg (unless `only` names others); its failure is
+    recorded, not fatal to the line."""
+    if only is not None and name not in only:
+        return
     try:
         extras[name] = fn()
         log(f"{name} {extras[name]}")
@@ -305,6 +308,9 @@ def main():
                     help="leave out every leg but the headline (static test, FP64 state, densities, clustered, "
                          "Hilbert, dynamic population, batched and adjoint)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated legs to run (default: all): static_skip, hilbert, dynamic, "
+                         "headline_fp64_state, c1_density_1e7, c2, c3, batched, adjoint")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--sweep", nargs="?", const=DEFAULT_SWEEP, default=None,
                     help="instead of the headline: agent-steps/s of the plain step on a uniform cube at c2's "
@@ -406,6 +412,7 @@ def main():
     log(f"headline {value:.3e} agent-steps/s, {ms_step:.3f} ms/step, force {force_ms:.4f} ms, phases {phases}")
 
     extras = {}
+    only = set(args.legs.split(",")) if args.legs else None
     if not args.no_extras:
         def static_leg():
             s2, el2, f2 = run_plain(pos, diam, args.steps, args.warmup, detect_static=True, **common)
@@ -415,7 +422,7 @@ def main():
                         skip_fraction_last_step=round(st["skip_fraction"], 4),
                         note="the same workload with the static test (Section 5) on; the lattice shell is "
                              "force-free and static from step 1")
-        leg(extras, "static_skip", static_leg)
+        leg(extras, "static_skip", static_leg, only)
 
         def hilbert_leg():
             sh, elh, fh = run_plain(pos, diam, args.steps, args.warmup, detect_static=False,
@@ -423,7 +430,7 @@ def main():
             return dict(value=w.n * args.steps / elh, unit="agent-steps/s", ms_per_step=round(1e3 * elh / args.steps, 4),
                         force_ms=round(fh, 4), speedup_vs_morton=round(el / elh, 3),
                         note="2x2x2 super-boxes along a Hilbert curve, Morton order inside each")
-        leg(extras, "hilbert", hilbert_leg)
+        leg(extras, "hilbert", hilbert_leg, only)
 
         def dynamic_leg():
             sd = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size,
@@ -448,7 +455,7 @@ def main():
             return dict(removed=m, added=m, remove_ms=round(1e3 * (t1 - t0), 3), add_ms=round(1e3 * (t2 - t1), 3),
                         next_step_ms=round(1e3 * el_full, 3), following_step_ms=round(1e3 * el_upd, 3),
                         note="calls include their stream synchronisations; the next step's grid is a full build")
-        leg(extras, "dynamic", dynamic_leg)
+        leg(extras, "dynamic", dynamic_leg, only)
         del pos, diam
         torch.cuda.empty_cache()
 
@@ -462,7 +469,7 @@ def main():
                         frac=round(STEP_BYTES["f64"] * w64.n / (f64 * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
                         step_frac=round(v * STEP_BYTES["f64"] / (HBM_PEAK_GBS * 1e9), 4),
                         note="the headline workload with FP64 state, static test off")
-        leg(extras, "headline_fp64_state", fp64_leg)
+        leg(extras, "headline_fp64_state", fp64_leg, only)
 
         def c1_density_leg():
             side = (args.n / workloads.C1_DENSITY) ** (1.0 / 3.0)
@@ -475,7 +482,7 @@ def main():
                         force_ms=round(fc, 4), steps=k,
                         note=f"1e7 spheres uniform at c1's density (side {side:.0f}, about 47 candidates and 4 "
                              f"contacts per agent), FP32 state, static test off: bound by VALU, not HBM")
-        leg(extras, "c1_density_1e7", c1_density_leg)
+        leg(extras, "c1_density_1e7", c1_density_leg, only)
 
         def c2_leg():
             w2 = workloads.c2()
@@ -484,7 +491,7 @@ def main():
             return dict(value=w2.n * w2.steps / el2, unit="agent-steps/s", ms_per_step=round(1e3 * el2 / w2.steps, 4),
                         force_ms=round(f2, 4), steps=w2.steps, skip_fraction_last_step=round(s2.stats()["skip_fraction"], 4),
                         note="c2: 1e6 spheres, FP32, static test on, 100 steps after 3 untimed")
-        leg(extras, "c2", c2_leg)
+        leg(extras, "c2", c2_leg, only)
 
         def c3_leg():
             w3 = workloads.c3()
@@ -494,7 +501,7 @@ def main():
                         force_ms=round(f3, 2), steps=3,
                         note="c3: 5e7 spheres in 1000 Gaussian blobs, FP32, re-layout every 10 steps; steps 2-4 "
                              "timed; about 5e3 candidates per agent, bound by VALU")
-        leg(extras, "c3", c3_leg)
+        leg(extras, "c3", c3_leg, only)
 
         def batched_leg():
             wb = workloads.c4()
@@ -547,7 +554,7 @@ def main():
                         ratio_vs_headline=round(v / value, 3),
                         autotuned=tuned.params, tune_trials=len(tuned.trials),
                         untuned_ms_per_step=round(tuned.trials[0][1], 4), tuned_ms_per_step=round(tuned.ms_per_step, 4))
-        leg(extras, "batched", batched_leg)
+        leg(extras, "batched", batched_leg, only)
 
         def adjoint_leg():
             wa = workloads.c5()
@@ -575,7 +582,7 @@ def main():
                         ratio_vs_plain_forward=round(elp / ela, 3), dL_dk=float(gp[0]), dL_dgamma=float(gp[1]),
                         peak_device_bytes=peak,
                         peak_note="workspace + forward record + dL/dx_T and dL/dx_0 (n x 3 doubles each)")
-        leg(extras, "adjoint", adjoint_leg)
+        leg(extras, "adjoint", adjoint_leg, only)
 
     cpu = None
     if not args.no_cpu:

@@ -12,7 +12,7 @@ from paper_2301_06984_amd import abm, workloads
 
 pytestmark = pytest.mark.gpu
 
-BENCH = dict(sort_every=1, block_size=512, detect_static=True)   # the benchmark's launch configuration
+BENCH = dict(sort_every=1, block_size=256, detect_static=False)   # the benchmark's launch configuration
 
 
 def check_samples(pos, diam, got_pos, nsamples, seed, params=oracle.Params(), got_nnz=None):
@@ -29,10 +29,11 @@ def check_samples(pos, diam, got_pos, nsamples, seed, params=oracle.Params(), go
     return ids, nnz
 
 
-def test_headline_1e7_first_step():
+@pytest.mark.parametrize("detect_static", [False, True])
+def test_headline_1e7_first_step(detect_static):
     w = workloads.headline()
-    note(f"headline n={w.n} side={w.meta['side']:.1f}")
-    sim = make_sim(w.pos, w.diam, **BENCH)
+    note(f"headline n={w.n} side={w.meta['side']:.1f} static test {detect_static}")
+    sim = make_sim(w.pos, w.diam, **{**BENCH, "detect_static": detect_static})
     sim.step(1)
     sim.sync()
     note("headline grid parity")
@@ -232,3 +233,24 @@ def test_uniform_1e8_sampled():
     sim.step(1)
     sim.sync()
     check_samples(x, d, sim.query("positions").cpu().numpy(), 48, 8, got_nnz=sim.query("nnz").cpu().numpy())
+
+
+def test_uniform_1e9_sampled():
+    # 1e9 spheres uniform at the c2 density: 2e9 loose slots, near the 32-bit
+    # limit of the slot space; the first step (full build) and the next
+    # (update build), sampled against the oracle
+    n = 1_000_000_000
+    side = (n / workloads.C2_DENSITY) ** (1.0 / 3.0)
+    note(f"uniform 1e9: generating (side {side:.1f})")
+    p, d = workloads.uniform_cube(n, side, (6, n), dtype=np.float32)
+    sim = make_sim(p, d, detect_static=False, sort_every=1, block_size=256, box_slack=1.05)
+    note("uniform 1e9 step 1")
+    sim.step(1)
+    sim.sync()
+    x = sim.query("positions").cpu().numpy()
+    check_samples(p, d, x, 32, 9, got_nnz=sim.query("nnz").cpu().numpy())
+    del p
+    note("uniform 1e9 step 2 (update build)")
+    sim.step(1)
+    sim.sync()
+    check_samples(x, d, sim.query("positions").cpu().numpy(), 32, 10, got_nnz=sim.query("nnz").cpu().numpy())

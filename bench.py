@@ -158,7 +158,11 @@ def cpu_baseline(skip: bool):
                 host=host_description())
 
 
-DEFAULT_SWEEP = "1e3,1e4,1e5,1e6,1e7,1e8,3e8,1e9"
+DEFAULT_SWEEP = "1e3,1e4,1e5,1e6,1e7,1e8,3e8,1e9,1.72e9"
+# above this many agents the sweep builds its context from chunks of agents
+# (the inputs of one piece would not fit beside the workspace)
+SWEEP_CHUNKED_ABOVE = 1_000_000_000
+SWEEP_CHUNK = 100_000_000
 
 
 def scale_sweep(sizes, block_size):
@@ -166,35 +170,64 @@ def scale_sweep(sizes, block_size):
     cube at c2's density (about 12 candidates per agent), d ~ U[8, 12],
     FP32 state, seed (6, n): agent-steps/s per n (steps timed without
     events), HIP-event phase times (from up to 20 steps after them), and the
-    workspace size."""
+    workspace size.  Above SWEEP_CHUNKED_ABOVE agents the positions come in
+    chunks of SWEEP_CHUNK (chunk k from seed (6, n, k)): a context of the
+    first chunk with room for n agents, the others added with
+    abm_add_agents, R fixed at 12 (the largest diameter the draw allows)."""
     import numpy as np
     import torch
     from paper_2301_06984_amd import abm, workloads
     for n in sizes:
         side = (n / workloads.C2_DENSITY) ** (1.0 / 3.0)
-        log(f"sweep n={n}: generating (side {side:.1f})")
-        p, d = workloads.uniform_cube(n, side, (6, n), dtype=np.float32)
-        pos = torch.from_numpy(p).cuda()
-        diam = torch.from_numpy(d).cuda()
-        del p, d
         # the grid grows by a box or two per axis as the agents relax: a
-        # tight box capacity keeps the largest runs inside the GPU's memory
-        sim = abm.Sim(pos, diam, detect_static=False, sort_every=1, block_size=block_size,
-                      box_slack=1.5 if n < 100_000_000 else 1.05)
+        # tight box capacity (and from 1e8 agents a super-box table sized
+        # for the grid) keeps the largest runs inside the GPU's memory
+        kw = dict(detect_static=False, sort_every=1, block_size=block_size,
+                  box_slack=1.5 if n < 100_000_000 else 1.05)
+        if n >= 100_000_000:
+            kw["super_slack"] = 1.2
+        if n <= SWEEP_CHUNKED_ABOVE:
+            log(f"sweep n={n}: generating (side {side:.1f})")
+            p, d = workloads.uniform_cube(n, side, (6, n), dtype=np.float32)
+            pos = torch.from_numpy(p).cuda()
+            diam = torch.from_numpy(d).cuda()
+            del p, d
+            sim = abm.Sim(pos, diam, **kw)
+            del pos, diam
+            made = "one piece, seed (6, n)"
+        else:
+            nchunks = (n + SWEEP_CHUNK - 1) // SWEEP_CHUNK
+            free, total = torch.cuda.mem_get_info()
+            log(f"sweep n={n}: {nchunks} chunks (side {side:.1f}); device memory free {free / 1e9:.1f} of "
+                f"{total / 1e9:.1f} GB")
+            sim = None
+            for k in range(nchunks):
+                m = min(SWEEP_CHUNK, n - k * SWEEP_CHUNK)
+                p, d = workloads.uniform_cube(m, side, (6, n, k), dtype=np.float32)
+                pos = torch.from_numpy(p).cuda()
+                diam = torch.from_numpy(d).cuda()
+                del p, d
+                if sim is None:
+                    sim = abm.Sim(pos, diam, capacity=n, interaction_radius=12.0, **kw)
+                else:
+                    sim.add_agents(pos, diam)
+                del pos, diam
+                log(f"sweep n={n}: {min(n, (k + 1) * SWEEP_CHUNK)} agents in the context")
+            made = f"{nchunks} chunks of {SWEEP_CHUNK} (seed (6, n, k)), added with abm_add_agents; R = 12"
         steps = int(min(200, max(5, 2e8 // n)))
         sim.step(3)
         sim.sync()
         el, _ = timed_steps(sim, steps)   # no events in the timed steps
         _, tm = timed_steps(sim, min(steps, 20), timing=1)   # phase breakdown: the steps after them
         value = n * steps / el
-        rec = dict(sweep="uniform cube at c2 density, d~U[8,12], FP32 state, seed (6, n)", n=int(n), steps=steps,
+        rec = dict(sweep="uniform cube at c2 density, d~U[8,12], FP32 state", made=made, n=int(n), steps=steps,
                    value=value, unit="agent-steps/s", ms_per_step=1e3 * el / steps,
                    step_frac=round(value * STEP_BYTES["f32"] / (HBM_PEAK_GBS * 1e9), 4),
                    workspace_gb=round(sim.ws.numel() / 1e9, 2),
                    phase_ms={k: round(tm[k] / tm["steps"], 4) for k in abm.TIMED_PHASES})
         print(json.dumps(rec), flush=True)
         sim.close()
-        del sim, pos, diam
+        del sim
         torch.cuda.empty_cache()
 
 

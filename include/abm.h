@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define ABM_ABI_VERSION 3
+#define ABM_ABI_VERSION 4
 #define ABM_EXTENT_SCRATCH_BYTES 1024
 
 enum abm_status {
@@ -93,6 +93,13 @@ typedef struct abm_params {
     int32_t order;             /* ABM_ORDER_MORTON (default) or ABM_ORDER_HILBERT; fixed at init, the same for
                                   every simulation of a batch.  It sets the canonical order, and with it the
                                   order in which each agent's pair terms are summed */
+    double super_fraction;     /* size of the super-box table (one entry per aligned 2x2x2 block of boxes) per
+                                  simulation, as a fraction of its box capacity: 0 (default) = enough for any
+                                  grid of box_capacity boxes, ceil((capacity + 1) / 2) entries (a grid one box
+                                  thick); f in (0, 1] = min(that, ceil(f * capacity) + 64) entries, about
+                                  capacity / 8 for grids of many boxes along each axis.  A grid with more
+                                  super-boxes fails like one above the box capacity (ABM_E_GRID).  Fixed at
+                                  init; a batch takes per_sim[0]'s */
 } abm_params;
 
 /* Grid extent of a set of positions (Section 3.1), as abm_extent reports it. */
@@ -193,7 +200,9 @@ int abm_extent_of_noalloc(int64_t n, const void* pos, const void* diam, const ab
  * offsets (host, nsims + 1, offsets[0] = 0; at most 2^31 - 2^20 agents in
  * all) and box capacities (host, nsims: boxes each simulation's grid may
  * span; see abm_extent.nboxes).  The per-box tables are held per super-box,
- * ceil((capacity + 1) / 2) entries per simulation.
+ * ceil((capacity + 1) / 2) entries per simulation, or fewer with
+ * p->super_fraction (which the workspace of a context must have been sized
+ * with).
  */
 int abm_workspace_bytes(int32_t nsims, const int64_t* offsets, const int64_t* box_capacity,
                         const abm_params* p, int64_t* bytes);

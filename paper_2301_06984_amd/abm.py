@@ -20,7 +20,7 @@ ABM_OK, ABM_E_INVAL, ABM_E_NONFINITE, ABM_E_GRID, ABM_E_WORKSPACE, ABM_E_HIP, AB
     0, -1, -2, -3, -4, -5, -6, -7
 ABM_F32, ABM_F64 = 0, 1
 ABM_ORDER_MORTON, ABM_ORDER_HILBERT = 0, 1
-ABI_VERSION = 3   # the layout of the structs below
+ABI_VERSION = 4   # the layout of the structs below
 FIELD = dict(positions=0, forces=1, moved=2, static=3, nnz=4, key=5, perm=6, cell_start=7, extent=8,
              storage_ids=9, neighbor_count=10, neighbors=11, diameters=12)
 EXTENT_SCRATCH_BYTES = 1024
@@ -40,7 +40,7 @@ class abm_params(C.Structure):
                 ("delta_max", C.c_double), ("interaction_radius", C.c_double), ("cell_factor", C.c_double),
                 ("precision", C.c_int32), ("detect_static", C.c_int32), ("sort_every", C.c_int32),
                 ("block_size", C.c_int32), ("keep_forces", C.c_int32), ("walk_chunk", C.c_int32),
-                ("order", C.c_int32)]
+                ("order", C.c_int32), ("super_fraction", C.c_double)]
 
 
 class abm_extent(C.Structure):
@@ -171,13 +171,25 @@ def box_capacity_for(nboxes: int, slack: float) -> int:
     return int(min(nboxes * slack + 4096, 2 ** 32 - 2))
 
 
+def super_fraction_for(ext: "abm_extent", box_capacity: int, slack: float) -> float:
+    """abm_params.super_fraction for a super-box table of about ``slack``
+    times the super-boxes of the grid ``ext`` (its aligned 2x2x2 blocks)."""
+    supers = 1
+    for a in range(3):
+        supers *= (int(ext.dims[a]) + 1) // 2
+    return min(1.0, slack * supers / box_capacity)
+
+
 class Sim:
     """One simulation: ``Sim(pos, diam, **params)`` with device tensors
     (n x 3 and n, float32 or float64 per ``precision``)."""
 
     def __init__(self, pos: torch.Tensor, diam: torch.Tensor, *, box_slack: float = 1.5,
                  box_capacity: Optional[int] = None, capacity: Optional[int] = None,
-                 stream: Optional[torch.cuda.Stream] = None, **params):
+                 super_slack: Optional[float] = None, stream: Optional[torch.cuda.Stream] = None, **params):
+        """super_slack: size the super-box table for ``super_slack`` times the
+        super-boxes of the initial grid (abm_params.super_fraction) instead of
+        for any grid of the box capacity."""
         if "precision" not in params:
             params["precision"] = "f64" if pos.dtype == torch.float64 else "f32"
         self.params = default_params(**params)
@@ -191,6 +203,8 @@ class Sim:
         ext = extent_of(self.pos_in, self.diam_in, self.params, self.stream)
         self.extent0 = ext
         self.box_capacity = int(box_capacity) if box_capacity else box_capacity_for(ext.nboxes, box_slack)
+        if super_slack is not None:
+            self.params.super_fraction = super_fraction_for(ext, self.box_capacity, float(super_slack))
         nbytes = C.c_int64()
         self.ctx = C.c_void_p()
         if capacity is None:

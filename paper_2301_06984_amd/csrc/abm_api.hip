@@ -48,8 +48,16 @@ struct Layout {
 constexpr int64_t kMaxAgents = (int64_t(1) << 31) - (int64_t(1) << 20);
 
 // Super-boxes of a grid of at most cap boxes: prod ceil(d_a / 2) with d_x d_y
-// d_z <= cap is largest for dims (1, 1, cap), so at most ceil((cap + 1) / 2).
-int64_t super_capacity(int64_t cap) { return (cap + 2) / 2; }
+// d_z <= cap is largest for dims (1, 1, cap), so at most ceil((cap + 1) / 2);
+// with a fraction f > 0 the table holds min(that, ceil(f cap) + 64) entries
+// (a grid with more super-boxes is refused at setup, as one above the box
+// capacity).
+int64_t super_capacity(int64_t cap, double f) {
+    const int64_t any = (cap + 2) / 2;
+    if (!(f > 0.0)) return any;
+    const int64_t t = int64_t(std::ceil(f * double(cap))) + 64;
+    return t < any ? t : any;
+}
 
 // boxes: capacity in super-boxes (sum of super_capacity over the simulations)
 Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, int64_t elem) {
@@ -92,7 +100,9 @@ Layout make_layout(int64_t n, int32_t nsims, int64_t boxes, bool keep_forces, in
     L.partials = take(16 * int64_t(L.partial_cap));
     L.bpart_cap = force_part_capacity(uint32_t(n));
     L.bpart = take(int64_t(sizeof(BlockPart)) * L.bpart_cap);
-    L.stage = take(24 * n);
+    // staging for the host calls between steps: key, sub and rec (contiguous,
+    // 24 B per agent and more with the alignment), which only a grid build uses
+    L.stage = L.key;
     L.total = off;
     return L;
 }
@@ -243,6 +253,8 @@ bool valid_params(const abm_params* p, std::string* why) {
         return *why = "walk_chunk must be 0, 2 or 4", false;
     if (p->order != ABM_ORDER_MORTON && p->order != ABM_ORDER_HILBERT)
         return *why = "order must be ABM_ORDER_MORTON or ABM_ORDER_HILBERT", false;
+    if (!(p->super_fraction >= 0.0 && p->super_fraction <= 1.0))
+        return *why = "super_fraction must be in [0, 1]", false;
     return true;
 }
 
@@ -373,7 +385,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
         if (box_capacity[s] < 1 || box_capacity[s] > 0xFFFFFFFFll)
             return fail(ABM_E_INVAL, "box capacity must be in [1, 2^32)");
         boxes += uint64_t(box_capacity[s]);
-        supers += uint64_t(super_capacity(box_capacity[s]));
+        supers += uint64_t(super_capacity(box_capacity[s], per_sim[0].super_fraction));
         SimGrid& G = sims[s];
         std::memset(&G, 0, sizeof(G));
         G.radius = per_sim[s].interaction_radius;
@@ -981,6 +993,7 @@ void abm_default_params(abm_params* p) {
     p->block_size = 256;
     p->keep_forces = 0;
     p->walk_chunk = 0;
+    p->super_fraction = 0.0;
 }
 
 const char* abm_last_error(void) { return g_last_error.c_str(); }
@@ -1058,7 +1071,7 @@ int abm_workspace_bytes(int32_t nsims, const int64_t* offsets, const int64_t* bo
         if (offsets[s + 1] < offsets[s]) return fail(ABM_E_INVAL, "offsets must be non-decreasing");
         if (box_capacity[s] < 1) return fail(ABM_E_INVAL, "box capacity must be >= 1");
         boxes += box_capacity[s];
-        supers += super_capacity(box_capacity[s]);
+        supers += super_capacity(box_capacity[s], p->super_fraction);
     }
     if (boxes >= 0xFFFFFFFFll) return fail(ABM_E_GRID, "total box capacity must be below 2^32");
     *bytes = make_layout(n, nsims, supers, p->keep_forces != 0, p->precision == ABM_F64 ? 8 : 4).total;
@@ -1079,7 +1092,7 @@ int abm_workspace_bytes_capacity(int64_t capacity, int64_t box_capacity, const a
     if (!p || !valid_params(p, &why)) return fail(ABM_E_INVAL, p ? why : "params is null");
     if (!bytes || capacity < 1 || capacity > kMaxAgents) return fail(ABM_E_INVAL, "capacity must be in [1, 2^31 - 2^20]");
     if (box_capacity < 1 || box_capacity >= 0xFFFFFFFFll) return fail(ABM_E_INVAL, "box capacity must be in [1, 2^32 - 1)");
-    *bytes = make_layout(capacity, 1, super_capacity(box_capacity), p->keep_forces != 0,
+    *bytes = make_layout(capacity, 1, super_capacity(box_capacity, p->super_fraction), p->keep_forces != 0,
                          p->precision == ABM_F64 ? 8 : 4).total;
     return ABM_OK;
 }

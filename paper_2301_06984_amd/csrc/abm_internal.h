@@ -32,6 +32,9 @@
 //     sub    arrival index of the agent in its super-box (histogram atomics)
 //     rec    agents of the rebuilt super-boxes in arrival order per super-box, at
 //            canonical slots: {storage index, id, super-box start, count << 4 | octant << 1 | moved}
+//     (key, sub and rec, 24 B per agent, live only inside a grid build: the
+//     host calls between steps (queries, state import, population changes)
+//     use the same bytes as their staging area)
 //     perm   storage index of loose slot n + j
 //     movers storage slots of the agents that left their box (update
 //            build), listed per block of 256 agents, + a count per block

@@ -1,6 +1,7 @@
 """The C-ABI library loads and exports every symbol include/abm.h declares.
 No compute calls: these run without a GPU."""
 import ctypes as C
+import math
 import os
 import re
 
@@ -41,15 +42,15 @@ def test_every_declared_symbol_is_exported(libabm):
 
 def test_version_and_defaults(libabm):
     L = libabm.lib()
-    assert L.abm_abi_version() == libabm.ABI_VERSION == 3
+    assert L.abm_abi_version() == libabm.ABI_VERSION == 4
     p = libabm.default_params()
     assert p.order == libabm.ABM_ORDER_MORTON and libabm.default_params(order="hilbert").order == 1
     assert (p.k, p.gamma, p.mu, p.f_adh, p.delta_max) == (2.0, 1.0, 0.1, 0.0, 3.0)
-    assert p.cell_factor == 1.0 and p.sort_every == 1 and p.block_size == 256
+    assert p.cell_factor == 1.0 and p.sort_every == 1 and p.block_size == 256 and p.super_fraction == 0.0
 
 
 def test_struct_sizes_match_header(libabm):
-    assert C.sizeof(libabm.abm_params) == 7 * 8 + 7 * 4 + 4   # padded to 8 bytes
+    assert C.sizeof(libabm.abm_params) == 7 * 8 + 7 * 4 + 4 + 8   # the ints padded to 8 bytes, then a double
     assert C.sizeof(libabm.abm_extent) == 2 * 8 + 7 * 8
     assert C.sizeof(libabm.abm_stats) == 3 * 8 + 2 * 4 + 5 * 8
 
@@ -74,6 +75,26 @@ def test_workspace_bytes_validation(libabm):
     assert L.abm_workspace_bytes(1, offs, huge, C.byref(p), C.byref(nb)) == libabm.ABM_E_GRID
     offs_bad = (C.c_int64 * 2)(5, 1000)
     assert L.abm_workspace_bytes(1, offs_bad, caps, C.byref(p), C.byref(nb)) == libabm.ABM_E_INVAL
+
+
+def test_super_fraction_sizes_the_table(libabm):
+    # the per-super-box tables (48 B per entry): ceil((cap + 1) / 2) entries
+    # by default, min(that, ceil(f cap) + 64) with super_fraction f
+    L = libabm.lib()
+    nb = C.c_int64()
+    cap = 8_000_000
+    sizes = {}
+    for f in (0.0, 0.15, 1.0):
+        p = libabm.default_params(super_fraction=f)
+        assert L.abm_workspace_bytes_capacity(10 ** 6, cap, C.byref(p), C.byref(nb)) == 0
+        sizes[f] = nb.value
+    assert sizes[1.0] == sizes[0.0]                  # capped at the any-grid size
+    saved = sizes[0.0] - sizes[0.15]
+    assert abs(saved - 48 * ((cap + 2) // 2 - (math.ceil(0.15 * cap) + 64))) <= 48 * 1024
+    for f in (-0.1, 1.5, float("nan")):
+        bad = libabm.default_params(super_fraction=f)
+        assert L.abm_workspace_bytes_capacity(10 ** 6, cap, C.byref(bad), C.byref(nb)) == libabm.ABM_E_INVAL
+        assert b"super_fraction" in L.abm_last_error()
 
 
 def test_null_context_is_rejected(libabm):

@@ -243,7 +243,7 @@ def test_uniform_1e9_sampled():
     side = (n / workloads.C2_DENSITY) ** (1.0 / 3.0)
     note(f"uniform 1e9: generating (side {side:.1f})")
     p, d = workloads.uniform_cube(n, side, (6, n), dtype=np.float32)
-    sim = make_sim(p, d, detect_static=False, sort_every=1, block_size=256, box_slack=1.05)
+    sim = make_sim(p, d, detect_static=False, sort_every=1, block_size=256, box_slack=1.05, super_slack=1.2)
     note("uniform 1e9 step 1")
     sim.step(1)
     sim.sync()

@@ -148,6 +148,34 @@ def test_step_statistics(batched):
     assert s["skip_fraction"] == s["n_static"] / c2.n and s["skip_fraction"] > 0.3
 
 
+def test_super_table_sized_for_the_grid():
+    # a super-box table sized for the initial grid (abm_params.super_fraction)
+    # runs the same steps bit for bit, and the grid checked against the
+    # oracle; one smaller than the grid is refused like a grid above the box
+    # capacity, and the queries name the error
+    w = workloads.c2(n=30000, seed=52)
+    note("super table: default vs sized for the grid")
+    a = make_sim(w.pos, w.diam, sort_every=1)
+    b = make_sim(w.pos, w.diam, sort_every=1, super_slack=1.2)
+    assert 0.0 < b.params.super_fraction < 0.5
+    assert b.ws.numel() < a.ws.numel()
+    for sim in (a, b):
+        sim.step(6)
+    sa, sb = gpu_state(a), gpu_state(b)
+    for k in sa:
+        np.testing.assert_array_equal(sa[k], sb[k], err_msg=k)
+    before = b.query("positions").cpu().numpy()
+    b.step(1)
+    b.sync()
+    assert_grid_equal(b, before, w.diam, oracle.Params())
+    note("super table: smaller than the grid")
+    c = make_sim(w.pos, w.diam, super_fraction=1e-6)
+    c.step(1)
+    with pytest.raises(abm.ABMError) as e:
+        c.sync()
+    assert e.value.code == abm.ABM_E_GRID
+
+
 def test_determinism_and_layout_invariance():
     w = workloads.c2(n=25000, seed=31)
     runs = {}

@@ -254,3 +254,40 @@ def test_uniform_1e9_sampled():
     sim.step(1)
     sim.sync()
     check_samples(x, d, sim.query("positions").cpu().numpy(), 32, 10, got_nnz=sim.query("nnz").cpu().numpy())
+
+
+def test_uniform_1_72e9_sampled():
+    # 1.72e9 spheres uniform at the c2 density (the agent count of the
+    # paper's largest run): 3.44e9 loose slots and 3.9e9 boxes, past 2^31,
+    # built from chunks of 1e8 agents (as the scale sweep builds it) with a
+    # super-box table sized for the grid; the first step (full build) and the
+    # next (update build), sampled against the oracle with the same R
+    n, chunk = 1_720_000_000, 100_000_000
+    side = (n / workloads.C2_DENSITY) ** (1.0 / 3.0)
+    params = oracle.Params(interaction_radius=12.0)
+    ps, ds, sim = [], [], None
+    for k in range((n + chunk - 1) // chunk):
+        m = min(chunk, n - k * chunk)
+        p, d = workloads.uniform_cube(m, side, (6, n, k), dtype=np.float32)
+        ps.append(p)
+        ds.append(d)
+        if sim is None:
+            sim = make_sim(p, d, capacity=n, interaction_radius=12.0, super_slack=1.2, box_slack=1.05,
+                           detect_static=False, sort_every=1, block_size=256)
+        else:
+            sim.add_agents(to_dev(p), to_dev(d))
+        note(f"uniform 1.72e9: {k * chunk + m} agents in the context")
+    p, d = np.concatenate(ps), np.concatenate(ds)
+    del ps, ds
+    note("uniform 1.72e9 step 1")
+    sim.step(1)
+    sim.sync()
+    x = sim.query("positions").cpu().numpy()
+    check_samples(p, d, x, 32, 11, params=params, got_nnz=sim.query("nnz").cpu().numpy())
+    del p
+    note("uniform 1.72e9 step 2 (update build)")
+    sim.step(1)
+    sim.sync()
+    check_samples(x, d, sim.query("positions").cpu().numpy(), 32, 12, params=params,
+                  got_nnz=sim.query("nnz").cpu().numpy())
+    assert sim.stats()["error"] == 0

@@ -342,7 +342,7 @@ def main():
                          "Hilbert, dynamic population, batched and adjoint)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--legs", default=None,
-                    help="comma-separated legs to run (default: all): static_skip, hilbert, dynamic, "
+                    help="comma-separated legs to run (default: all): static_skip, hilbert, sort_cadence, dynamic, "
                          "headline_fp64_state, c1_density_1e7, c2, c3, batched, adjoint")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--sweep", nargs="?", const=DEFAULT_SWEEP, default=None,
@@ -464,6 +464,23 @@ def main():
                         force_ms=round(fh, 4), speedup_vs_morton=round(el / elh, 3),
                         note="2x2x2 super-boxes along a Hilbert curve, Morton order inside each")
         leg(extras, "hilbert", hilbert_leg, only)
+
+        def cadence_leg():
+            # the GPU analog of the paper's agent-sorting frequency study: the
+            # step after one that did not re-lay the agents out rebuilds the
+            # whole grid, after a re-layout only the changed super-boxes
+            out = {}
+            for k in (1, 2, 5, 10, 0):
+                sk, elk, fk = run_plain(pos, diam, 10, args.warmup, detect_static=False, sort_every=k,
+                                        block_size=args.block_size)
+                out[f"sort_every_{k}"] = dict(ms_per_step=round(1e3 * elk / 10, 4), force_ms=round(fk, 4))
+                sk.close()
+                del sk
+            out["note"] = ("the headline workload, static test off, 10 timed steps after the warm-up; sort_every k "
+                           "re-lays the agents out every k steps (0: never); a step after one without a re-layout "
+                           "is a full grid build")
+            return out
+        leg(extras, "sort_cadence", cadence_leg, only)
 
         def dynamic_leg():
             sd = abm.Sim(pos, diam, detect_static=False, sort_every=args.sort_every, block_size=args.block_size,

@@ -308,6 +308,52 @@ def test_tiny_inputs():
         assert np.abs(sim.query("positions").cpu().numpy() - st.pos).max() < 1e-12
 
 
+def _degenerate_cases():
+    g = np.random.default_rng(91)
+    # a monolayer: the grid is one box thick (the super-box table's worst shape)
+    p = np.column_stack([g.uniform(0, 400, 4000), g.uniform(0, 400, 4000), g.uniform(0, 4, 4000)])
+    yield "monolayer", p, g.uniform(8, 12, 4000)
+    # a line of agents along x: one box across in y and z
+    p = np.column_stack([np.sort(g.uniform(0, 3000, 600)), g.uniform(0, 3, 600), g.uniform(0, 3, 600)])
+    yield "line", p, g.uniform(8, 12, 600)
+    # coincident centres (a pair at distance 0 adds nothing, R9), some triple
+    p = g.uniform(0, 150, (2000, 3))
+    dup = g.choice(2000, 300, replace=False)
+    p = np.concatenate([p, p[dup], p[dup[:50]]])
+    yield "coincident", p, g.uniform(8, 12, p.shape[0])
+    # centres on box boundaries: a lattice of spacing 6 with every diameter 12
+    # (the box edge), so every other coordinate is an exact multiple of the
+    # edge; each agent overlaps its 6 lattice neighbours, whose terms cancel
+    # in the interior
+    ax = np.arange(10) * 6.0
+    p = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), axis=-1).reshape(-1, 3)
+    yield "box-boundaries", p, np.full(p.shape[0], 12.0)
+    # every agent inside one box
+    yield "one-box", g.uniform(0, 11.5, (400, 3)), g.uniform(8, 12, 400)
+
+
+DEGENERATE = list(_degenerate_cases())
+
+
+@pytest.mark.parametrize("name,pos,diam", DEGENERATE, ids=[c[0] for c in DEGENERATE])
+def test_degenerate_layouts(name, pos, diam):
+    # FP64 against the oracle: the first grid exactly, then three steps
+    note(f"degenerate layout {name} n={pos.shape[0]}")
+    sim = make_sim(pos, diam, keep_forces=True)
+    sim.step(1)
+    sim.sync()
+    assert_grid_equal(sim, pos, diam, oracle.Params())
+    assert_neighbors_equal(sim, pos, diam, oracle.Params())
+    sim.step(2)
+    st = oracle.run(pos, diam, 3, oracle.Params())
+    g = gpu_state(sim)
+    np.testing.assert_array_equal(g["nnz"], st.nnz)
+    np.testing.assert_array_equal(g["moved"], st.moved)
+    R = float(diam.max())
+    bound = 1e-12 * np.maximum(np.abs(st.pos).max(axis=1), R)
+    assert np.all(np.abs(g["pos"] - st.pos).max(axis=1) <= bound)
+
+
 def test_errors_are_reported():
     p, d = workloads.uniform_cube(1000, 60.0, seed=81)
     bad = p.copy()

@@ -558,7 +558,9 @@ def main():
             s = torch.cuda.Stream()
             with torch.cuda.stream(s):
                 pb, db = torch.from_numpy(wb.pos).to(dev), torch.from_numpy(wb.diam).to(dev)
-                tuned = tune.autotune_batched(pb, db, wb.offsets, graph_steps=wb.steps, stream=s)
+                # each trial: 10 steps, then 10 timed, past the first steps' relaxation,
+                # when agents change boxes far more often than over the whole run
+                tuned = tune.autotune_batched(pb, db, wb.offsets, graph_steps=wb.steps, stream=s, warmup=10, steps=10)
                 b = abm.BatchedSim(pb, db, wb.offsets, stream=s, common=dict(tuned.params))
                 b.graph_capture(wb.steps)
                 b.graph_launch()          # warm-up replay

@@ -118,7 +118,10 @@ typedef struct abm_stats {
     int64_t n_static;          /* agents whose force was skipped */
     int64_t n_moved;           /* agents with a non-zero displacement */
     uint32_t error;            /* device error bits (0 = none) */
-    uint32_t reserved;
+    uint32_t build;            /* the last step's grid: bit 0 set for an update of the grid before (Section 3.1's
+                                  grid kept, only the super-boxes agents entered or left rebuilt), clear for a full
+                                  build; bits 1..31 the simulations of a batch rebuilt inside that update (their
+                                  extent changed) */
     double sum_force[3];       /* sum of the forces the step evaluated (every agent's with the static test off:
                                   zero up to rounding by Newton's third law, each pair term entering twice with
                                   opposite signs); summed in a fixed order for a single simulation */
@@ -226,7 +229,12 @@ int abm_init(abm_ctx** ctx, int64_t n, const void* pos, const void* diam, const 
  * (host, nsims) gives each simulation's parameters (precision, sort_every,
  * block_size, keep_forces and detect_static are taken from per_sim[0]);
  * box_capacity (host, nsims).  Agent ids are global input indices.  Each
- * simulation advances exactly as it would alone.
+ * simulation advances exactly as it would alone.  Each simulation owns a
+ * fixed range of the super-box table (ceil((capacity + 1) / 2) entries, or
+ * per_sim[0].super_fraction of its capacity + 64), scanned every step; a
+ * step's grid is an update of the last one in which the simulations whose
+ * extent changed are rebuilt (a full build when a quarter of the agents or
+ * more belong to them; abm_stats.build reports which).
  */
 int abm_init_batched(abm_ctx** ctx, int32_t nsims, const int64_t* offsets, const void* pos, const void* diam,
                      const abm_params* per_sim, const int64_t* box_capacity, void* ws, int64_t ws_bytes,

@@ -50,7 +50,7 @@ class abm_extent(C.Structure):
 
 class abm_stats(C.Structure):
     _fields_ = [("step", C.c_int64), ("n_static", C.c_int64), ("n_moved", C.c_int64), ("error", C.c_uint32),
-                ("reserved", C.c_uint32), ("sum_force", C.c_double * 3), ("max_displacement", C.c_double),
+                ("build", C.c_uint32), ("sum_force", C.c_double * 3), ("max_displacement", C.c_double),
                 ("skip_fraction", C.c_double)]
 
 
@@ -171,13 +171,20 @@ def box_capacity_for(nboxes: int, slack: float) -> int:
     return int(min(nboxes * slack + 4096, 2 ** 32 - 2))
 
 
-def super_fraction_for(ext: "abm_extent", box_capacity: int, slack: float) -> float:
-    """abm_params.super_fraction for a super-box table of about ``slack``
-    times the super-boxes of the grid ``ext`` (its aligned 2x2x2 blocks)."""
+def grown_supers(ext: "abm_extent", grow: int = 3) -> int:
+    """Super-boxes (aligned 2x2x2 blocks of boxes) of the grid ``ext`` grown
+    by ``grow`` boxes along each axis: room for extents that change by a box
+    or two as agents move (one more box on an even axis adds a block)."""
     supers = 1
     for a in range(3):
-        supers *= (int(ext.dims[a]) + 1) // 2
-    return min(1.0, slack * supers / box_capacity)
+        supers *= (int(ext.dims[a]) + grow + 1) // 2
+    return supers
+
+
+def super_fraction_for(ext: "abm_extent", box_capacity: int, slack: float) -> float:
+    """abm_params.super_fraction for a super-box table of about ``slack``
+    times the super-boxes of the grid ``ext`` grown by three boxes per axis."""
+    return min(1.0, max(slack * grown_supers(ext) - 64.0, 1.0) / box_capacity)
 
 
 class Sim:
@@ -188,8 +195,9 @@ class Sim:
                  box_capacity: Optional[int] = None, capacity: Optional[int] = None,
                  super_slack: Optional[float] = None, stream: Optional[torch.cuda.Stream] = None, **params):
         """super_slack: size the super-box table for ``super_slack`` times the
-        super-boxes of the initial grid (abm_params.super_fraction) instead of
-        for any grid of the box capacity."""
+        super-boxes of the initial grid grown by three boxes per axis
+        (abm_params.super_fraction) instead of for any grid of the box
+        capacity."""
         if "precision" not in params:
             params["precision"] = "f64" if pos.dtype == torch.float64 else "f32"
         self.params = default_params(**params)
@@ -336,7 +344,7 @@ class Sim:
         _check(lib().abm_get_stats(self.ctx, C.byref(s)), "abm_get_stats")
         return dict(step=s.step, n_static=s.n_static, n_moved=s.n_moved, error=s.error,
                     sum_force=tuple(s.sum_force), max_displacement=s.max_displacement,
-                    skip_fraction=s.skip_fraction)
+                    skip_fraction=s.skip_fraction, update_build=bool(s.build & 1), rebuilt_sims=s.build >> 1)
 
     # ---------------------------------------------------------------- checkpoint
     def export_state(self) -> bytes:
@@ -384,7 +392,14 @@ class BatchedSim(Sim):
 
     def __init__(self, pos: torch.Tensor, diam: torch.Tensor, offsets: Sequence[int],
                  params: Optional[Sequence[dict]] = None, *, box_slack: float = 1.5,
-                 stream: Optional[torch.cuda.Stream] = None, common: Optional[dict] = None):
+                 super_slack: Optional[float] = 1.2, stream: Optional[torch.cuda.Stream] = None,
+                 common: Optional[dict] = None):
+        """Each simulation owns a fixed range of the super-box table, which the
+        grid build scans every step: with super_slack (default 1.2) a range
+        holds at least super_slack times the super-boxes of the simulation's
+        initial grid grown by three boxes per axis (abm_params.super_fraction,
+        the largest fraction any simulation needs); None sizes every range for
+        any grid of its box capacity."""
         offsets = [int(o) for o in offsets]
         ns = len(offsets) - 1
         common = dict(common or {})
@@ -397,11 +412,16 @@ class BatchedSim(Sim):
         self.n = int(pos.shape[0])
         self._nsims = ns
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        caps = []
+        caps, frac = [], 0.0
         for s in range(ns):
             a, b = offsets[s], offsets[s + 1]
             ext = extent_of(self.pos_in[a:b], self.diam_in[a:b], plist[s], self.stream)
             caps.append(box_capacity_for(ext.nboxes, box_slack))
+            if super_slack is not None:   # each range holds ceil(f * capacity) + 64 entries
+                frac = max(frac, super_fraction_for(ext, caps[-1], float(super_slack)))
+        if super_slack is not None:
+            for p in plist:
+                p.super_fraction = frac
         self.box_capacity = sum(caps)
         offs = (C.c_int64 * (ns + 1))(*offsets)
         capa = (C.c_int64 * ns)(*caps)

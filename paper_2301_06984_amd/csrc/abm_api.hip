@@ -385,9 +385,13 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
         if (box_capacity[s] < 1 || box_capacity[s] > 0xFFFFFFFFll)
             return fail(ABM_E_INVAL, "box capacity must be in [1, 2^32)");
         boxes += uint64_t(box_capacity[s]);
-        supers += uint64_t(super_capacity(box_capacity[s], per_sim[0].super_fraction));
+        const uint64_t scap = uint64_t(super_capacity(box_capacity[s], per_sim[0].super_fraction));
         SimGrid& G = sims[s];
         std::memset(&G, 0, sizeof(G));
+        // several simulations: each owns a fixed range of the super-box table
+        G.sbase = nsims > 1 ? uint32_t(supers) : 0u;
+        G.scap = uint32_t(scap);
+        supers += scap;
         G.radius = per_sim[s].interaction_radius;
         G.k = per_sim[s].k;
         G.gamma = per_sim[s].gamma;
@@ -400,6 +404,8 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
         G.cap = uint32_t(box_capacity[s]);
     }
     if (boxes >= 0xFFFFFFFFull) return fail(ABM_E_GRID, "total box capacity must be below 2^32");
+    if (nsims > 1 && supers >= uint64_t(kMaxSuperBoxes))
+        return fail(ABM_E_GRID, "the simulations' super-box capacities must sum below 2^29");
     const abm_params& p0 = per_sim[0];
     const Layout L = make_layout(cap, nsims, int64_t(supers), p0.keep_forces != 0, sizeof(T));
     if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(ABM_E_INVAL, "workspace must be 256-byte aligned");
@@ -1216,7 +1222,7 @@ int abm_get_stats(abm_ctx* c, abm_stats* out) {
     out->n_static = any ? ns : 0;
     out->n_moved = any ? nm : 0;
     out->error = g.err;
-    out->reserved = 0;
+    out->build = (g.inc ? 1u : 0u) | (g.rebuilt << 1);
     double dmax = 0.0;
     std::memcpy(&dmax, &dm, sizeof(dmax));
     for (int a = 0; a < 3; ++a) out->sum_force[a] = any ? fs[a] : 0.0;

@@ -92,7 +92,7 @@ struct SimGrid {
     double cell_factor;
     uint32_t agent_begin, agent_end;
     uint32_t cap;           // box capacity of this simulation
-    uint32_t pad0;
+    uint32_t scap;          // super-box capacity of this simulation (its table range, several simulations)
     // set by the per-step setup kernel
     int32_t cmin[3];
     uint32_t dims[3];
@@ -102,8 +102,12 @@ struct SimGrid {
     uint32_t valid;
     uint32_t sdims[3];      // super-boxes per axis: (dims + 1) >> 1
     uint32_t nsuper;        // sdims[0] * sdims[1] * sdims[2]
-    uint32_t sbase;         // first global super-box index of this simulation
+    uint32_t sbase;         // first global super-box index of this simulation (several simulations: fixed
+                            // at init, the sum of the capacities before it, so a simulation's table range
+                            // does not move when another one's grid changes)
     int32_t slevels;        // smallest L with 2^L >= max(sdims)
+    uint32_t stamp;         // stamp of this simulation's current table entries
+    uint32_t rebuild;       // this step rebuilds this simulation's grid inside an update build of the others
     // min x,y,z then max x,y,z of the box coordinates (extent queries only;
     // the step keeps its accumulators in Buffers::bbox_rep)
     int32_t bbox[2][6];
@@ -118,6 +122,7 @@ struct Globals {
     uint32_t epoch;          // counts grid builds (marks this step's changed super-boxes; never 0)
     uint32_t ndirty;         // changed super-boxes of an update build (dirty_list, from the scan)
     uint32_t napp;           // agents in the append region (an update: of the changed super-boxes; full: n)
+    uint32_t rebuilt;        // simulations rebuilt inside this step's update build (several simulations)
     // per step parity and replica: agents skipped as static, agents moved
     unsigned long long stats[2][kReplicas][2];
     // ... the sum of the forces the step evaluated (Newton's third law makes

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, co
         uint32_t q[3];
         double wi[3] = {0.0, 0.0, 0.0};
         if (G.valid && box_of<T>(G, p, q)) {
-            const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
+            const Pieces P = load_pieces(b, G, q, G.stamp, L);
             ForceSum acc;
             force_of<kAdjChunk, T, true>(b, G, p, P, L, acc);
             const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
         }
         uint32_t q[3];
         if (G.valid && box_of<T>(G, p, q))
-            P = load_pieces(b, G, q, b.g->stamp, L);
+            P = load_pieces(b, G, q, G.stamp, L);
         else
             raise_error(b.g, kErrInternal);
     }

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
                 f = f0;
                 uint32_t q[3];
                 if (!box_of<T>(G, p, q)) raise_error(b.g, kErrInternal);
-                P = load_pieces(b, G, q, b.g->stamp, L);
+                P = load_pieces(b, G, q, G.stamp, L);
                 if (RELAYOUT && !inc) {
                     out = u - n;
                 } else if (RELAYOUT) {
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_neighbors(Buffers<T> b, int ids_cur, ui
         raise_error(b.g, kErrInternal);
         return;
     }
-    const Pieces P = load_pieces(b, G, q, b.g->stamp, L);
+    const Pieces P = load_pieces(b, G, q, G.stamp, L);
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
     uint32_t cnt = 0;
     uint32_t* row = rows ? rows + size_t(id) * K : nullptr;

@@ -241,10 +241,15 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
     __shared__ unsigned long long s_wave[kSetupThreads / 64];
     __shared__ unsigned long long s_carry;
     __shared__ uint32_t s_same;
+    __shared__ uint32_t s_flags;   // the decision: update build (bit 0), the current stamp
+    __shared__ uint32_t s_moving;  // agents of the simulations whose grid changed
+    __shared__ uint32_t s_nchanged;   // ... and their number
     __shared__ int32_t s_bb[kSetupLdsSims][6];
     if (threadIdx.x == 0) {
         s_carry = 0;
         s_same = 1u;
+        s_moving = 0u;
+        s_nchanged = 0u;
     }
     // each simulation's box range from its replicas: one wave per simulation,
     // one lane per replica (below kSetupLdsSims simulations; else per thread)
@@ -276,13 +281,15 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
     for (int e = int(threadIdx.x); e < kReplicas * 3; e += kSetupThreads) g->fsum[parity][e / 3][e % 3] = 0.0;
     for (int e = int(threadIdx.x); e < kReplicas; e += kSetupThreads) g->dmax[parity][e] = 0ull;
     __syncthreads();
+    bool t_all_valid = true, t_some_same = false;   // over this thread's simulations
     for (int chunk = 0; chunk < nsims; chunk += kSetupThreads) {
         const int s = chunk + int(threadIdx.x);
         uint32_t nb = 0, nsup = 0;
-        bool same = true;
+        bool same = true, last_valid = true;
         if (s < nsims) {
             SimGrid& G = sims[s];
-            same = G.valid != 0u;   // the last grid of this simulation was built
+            last_valid = G.valid != 0u;
+            same = last_valid;   // the last grid of this simulation was built
             int32_t bb[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
             if (wave_fold) {
                 for (int a = 0; a < 6; ++a) bb[a] = s_bb[s][a];
@@ -320,11 +327,23 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
                 ns *= sd;
             }
             G.slevels = levels > 0 ? levels - 1 : 0;
+            if (ok && nsims > 1 && ns > G.scap) {   // beyond this simulation's table range
+                ok = false;
+                G.valid = 0u;
+                G.nboxes = 0u;
+            }
             G.nsuper = ok ? ns : 0u;
             nb = G.nboxes;
             nsup = G.nsuper;
             same = same && ok;
             if (!ok) raise_error(g, kErrGrid);
+            t_all_valid = t_all_valid && last_valid && ok;
+            t_some_same = t_some_same || same;
+            G.rebuild = same ? 0u : 1u;   // provisional: the grid changed
+            if (!same) {
+                atomicAdd(&s_moving, G.agent_end - G.agent_begin);
+                atomicAdd(&s_nchanged, 1u);
+            }
         }
         if (!__syncthreads_and(same ? 1 : 0) && threadIdx.x == 0) s_same = 0u;
         // block exclusive scans of nb (box bases) and nsup (super-box bases)
@@ -344,7 +363,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
         const unsigned long long sbase = (s_carry >> 32) + (off >> 32);
         if (s < nsims) {
             sims[s].box_base = uint32_t(bbase);
-            sims[s].sbase = uint32_t(sbase);
+            if (nsims == 1) sims[s].sbase = uint32_t(sbase);   // several: fixed ranges
         }
         __syncthreads();
         // box counts are bounded by the capacities, whose sum fits 32 bits,
@@ -352,24 +371,49 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(Globals* g, SimGrid* si
         if (threadIdx.x == kSetupThreads - 1) s_carry = ((bbase + nb) & 0xFFFFFFFFull) | ((sbase + nsup) << 32);
         __syncthreads();
     }
+    const bool all_valid = __syncthreads_and(t_all_valid ? 1 : 0) != 0;
+    const bool some_same = __syncthreads_or(t_some_same ? 1 : 0) != 0;
     if (threadIdx.x == 0) {
-        unsigned long long total = s_carry >> 32;
+        // one simulation: its super-boxes; several: every table range, fixed
+        unsigned long long total = nsims == 1 ? s_carry >> 32 : (unsigned long long)super_capacity;
         if (total > super_capacity || total >= kMaxSuperBoxes) {
             raise_error(g, kErrGrid);
             total = 0;
             for (int s = 0; s < nsims; ++s) sims[s].valid = 0;
         }
         g->total_super = uint32_t(total);
-        // an update of the last grid needs the same boxes (extent) and agents
-        // stored in that grid's canonical order (the caller's allow_inc)
-        g->inc = (allow_inc && s_same && total > 0) ? 1u : 0u;
+        // An update of the last grid needs the agents stored in that grid's
+        // canonical order (the caller's allow_inc).  One simulation: the same
+        // boxes (extent).  Several: every simulation's last and new grid
+        // valid, and some simulation with its extent kept; the others are
+        // rebuilt inside the update (all their agents move to their new keys).
+        // Rebuilding simulations inside an update moves all their agents
+        // through the movers' path, whose arrival counters serialise runs of
+        // agents bound for one super-box: with a quarter of the agents or
+        // more in changed simulations, a full build is the faster one.
+        const bool inc = allow_inc && total > 0 &&
+                         (nsims == 1 ? s_same != 0u : all_valid && some_same && 4ull * s_moving < n);
+        g->inc = inc ? 1u : 0u;
         g->epoch = g->epoch + 1u ? g->epoch + 1u : 1u;
         g->ndirty = 0u;
         g->napp = n;   // a full build fills the whole append region (an update: set by its scan)
-        // a full build marks its box table entries with a fresh stamp (the
-        // host clears the table before the 15-bit stamp wraps); an update
-        // keeps the entries of the super-boxes it does not rebuild
-        if (!g->inc) g->stamp = g->stamp + 1;
+        // A full build marks every simulation's table entries with a fresh
+        // stamp (the host clears the table before the 15-bit stamp wraps); an
+        // update keeps the entries of the super-boxes it does not rebuild, and
+        // the simulations rebuilt inside it take a fresh stamp
+        const bool rebuilds = inc && nsims > 1 && s_same == 0u;
+        g->rebuilt = rebuilds ? s_nchanged : 0u;
+        if (!inc || rebuilds) g->stamp = g->stamp + 1;
+        s_flags = (inc ? 1u : 0u) | (g->stamp << 1);
+    }
+    __syncthreads();
+    const bool inc = (s_flags & 1u) != 0u;
+    const uint32_t stamp = s_flags >> 1;
+    for (int s = int(threadIdx.x); s < nsims; s += kSetupThreads) {
+        SimGrid& G = sims[s];
+        const bool rb = inc && nsims > 1 && G.rebuild != 0u;
+        G.rebuild = rb ? 1u : 0u;
+        if (!inc || rb) G.stamp = stamp;
     }
 }
 
@@ -402,9 +446,9 @@ __device__ __forceinline__ bool super_key(const SimGrid& G, const V4<T>& p, uint
 
 // Lanes of a wave that hold equal values of k come in runs (agents of one
 // super-box are neighbours in storage).  wave_run_add adds each run's length
-// to arr[k] with one atomic and returns every lane's index in arr[k]'s
-// count.
-__device__ __forceinline__ uint32_t wave_run_add(uint32_t* arr, bool act, uint32_t k) {
+// to arr[k] (subtracts it with `subtract`) with one atomic and returns every
+// lane's index in arr[k]'s count (an add).
+__device__ __forceinline__ uint32_t wave_run_add(uint32_t* arr, bool act, uint32_t k, bool subtract = false) {
     const int lane = lane_id();
     const uint32_t pk = __shfl_up(k, 1, 64);
     const int pact = __shfl_up(act ? 1 : 0, 1, 64);
@@ -416,7 +460,7 @@ __device__ __forceinline__ uint32_t wave_run_add(uint32_t* arr, bool act, uint32
     const unsigned long long above = brk & ~upto;
     const int next = above ? __ffsll((long long)above) - 1 : 64;
     uint32_t old = 0;
-    if (head) old = atomicAdd(&arr[k], uint32_t(next - lane));
+    if (head) old = atomicAdd(&arr[k], subtract ? 0u - uint32_t(next - lane) : uint32_t(next - lane));
     old = __shfl(old, leader, 64);
     return old + uint32_t(lane - leader);
 }
@@ -498,6 +542,19 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur, in
         f[k] = i < b.n ? b.flags[cur][i] : 0u;
         sk[k] = moved_bits && i < b.n ? b.skey[cur][i] : kDeadKey;
     }
+    // several simulations: every agent of a simulation rebuilt inside this
+    // update counts as having left its box (also for the scatter, which reads
+    // the flag again)
+    if (b.sim_of) {
+#pragma unroll
+        for (int k = 0; k < kKeysPer; ++k) {
+            const uint32_t i = i0 + uint32_t(k) * kKeysThreads;
+            if (i < b.n && !(f[k] & kBoxChangedBit) && b.sims[sim_index(b, i)].rebuild) {
+                f[k] |= kBoxChangedBit;
+                b.flags[cur][i] = f[k];
+            }
+        }
+    }
     if (moved_bits) {   // agents in storage order: equal super-boxes in runs
         const uint32_t total = b.g->total_super;
 #pragma unroll
@@ -514,25 +571,40 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(Buffers<T> b, int cur, in
     for (int k = 0; k < kKeysPer; ++k)
         if (f[k] & kBoxChangedBit) s_list[atomicAdd(&s_movers, 1u)] = i0 + uint32_t(k) * kKeysThreads;
     __syncthreads();
+    // the count moves as runs of equal keys, one atomic per run (a simulation
+    // rebuilt inside the update moves runs of agents of one super-box)
     const uint32_t nl = s_movers, ep = b.g->epoch, total = b.g->total_super;
-    for (uint32_t j = threadIdx.x; j < nl; j += kKeysThreads) {
-        const uint32_t i = s_list[j];
-        const SimGrid& G = b.sims[sim_index(b, i)];
-        const uint32_t old = b.skey[cur][i];
-        uint32_t key = old, real = 0;
-        if (!G.valid || (old >> 3) >= total || !super_key<T>(G, pos4_ptr(b, cur)[i], &key, hil)) {
-            raise_error(b.g, kErrInternal);
+    for (uint32_t j0 = 0; j0 < nl; j0 += kKeysThreads) {
+        const uint32_t j = j0 + threadIdx.x;
+        const bool in = j < nl;
+        const uint32_t i = in ? s_list[j] : 0u;
+        uint32_t old = 0, key = 0, real = 0;
+        bool rb = false;
+        if (in) {
+            const SimGrid& G = b.sims[sim_index(b, i)];
+            old = b.skey[cur][i];
             key = old;
-        } else if (key != old) {
-            real = 1;
-            atomicAdd(&b.count[old >> 3], 0xFFFFFFFFu);
-            atomicAdd(&b.count[key >> 3], 1u);
-            b.dirty[old >> 3] = ep;
-            b.dirty[key >> 3] = ep;
+            if (!G.valid || (old >> 3) >= total || !super_key<T>(G, pos4_ptr(b, cur)[i], &key, hil)) {
+                raise_error(b.g, kErrInternal);
+                key = old;
+            } else {
+                real = key != old ? 1u : 0u;
+                rb = G.rebuild != 0u;
+            }
         }
-        b.key[i] = key;   // read by the scatter for every agent that left its box
-        b.sub[i] = real;  // ... and whether it entered another super-box
-        b.movers[blockIdx.x * kKeysSpan + j] = i;
+        (void)wave_run_add(b.count, real != 0u, old >> 3, true);
+        (void)wave_run_add(b.count, real != 0u, key >> 3);
+        if (in) {
+            // a rebuilt simulation's super-boxes are all rebuilt: the same
+            // key names another block of boxes in its new grid
+            if (real || rb) {
+                b.dirty[old >> 3] = ep;
+                b.dirty[key >> 3] = ep;
+            }
+            b.key[i] = key;   // read by the scatter for every agent that left its box
+            b.sub[i] = real;  // ... and whether it entered another super-box
+            b.movers[blockIdx.x * kKeysSpan + j] = i;
+        }
     }
     if (threadIdx.x == 0) b.mcount[blockIdx.x] = nl;
 }
@@ -877,24 +949,30 @@ __global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
     const uint32_t waves = stride >> 6;
     for (uint32_t kb = tid >> 6; kb < kblocks; kb += waves) {
         const uint32_t mc = min(b.mcount[kb], kKeysSpan);
-        for (uint32_t m = uint32_t(lane_id()); m < mc; m += 64u) {
-            const uint32_t i = b.movers[kb * kKeysSpan + m];
-            if (i >= b.n) {
-                raise_error(b.g, kErrInternal);
-                continue;
+        for (uint32_t m0 = 0; m0 < mc; m0 += 64u) {   // wave-uniform: runs of equal super-boxes share an atomic
+            const uint32_t m = m0 + uint32_t(lane_id());
+            uint32_t i = 0, key = 0, sk = 0, st = 0, en = 0;
+            bool act = false;
+            if (m < mc) {
+                i = b.movers[kb * kKeysSpan + m];
+                if (i >= b.n) {
+                    raise_error(b.g, kErrInternal);
+                } else if (b.sub[i]) {
+                    key = b.key[i];
+                    sk = key >> 3;
+                    if (sk >= b.g->total_super) {
+                        raise_error(b.g, kErrInternal);
+                    } else {
+                        st = cs[sk];
+                        en = cs[sk + 1];
+                        act = slot_range(st, en, b.n);
+                        if (!act) raise_error(b.g, kErrInternal);
+                    }
+                }
             }
-            if (!b.sub[i]) continue;
-            const uint32_t key = b.key[i], sk = key >> 3;
-            if (sk >= b.g->total_super) {
-                raise_error(b.g, kErrInternal);
-                continue;
-            }
-            const uint32_t st = cs[sk], en = cs[sk + 1], cnt = en - st;
-            if (!slot_range(st, en, b.n)) {
-                raise_error(b.g, kErrInternal);
-                continue;
-            }
-            const uint32_t r = atomicAdd(&b.count[sk], 1u);
+            const uint32_t r = wave_run_add(b.count, act, sk);
+            if (!act) continue;
+            const uint32_t cnt = en - st;
             if (r >= cnt) {
                 raise_error(b.g, kErrInternal);
                 continue;
@@ -903,6 +981,20 @@ __global__ void k_scatter(Buffers<T> b, int cur, int ids_cur) {
                 make_uint4(i, b.ids[ids_cur][i], st, (cnt << 4) | ((key & 7u) << 1) | (b.flags[cur][i] & kMovedBit));
         }
     }
+}
+
+// The simulation whose table range holds super-box sk: several simulations
+// own fixed ranges in order of their sbase; one owns all.
+__device__ __forceinline__ int sim_of_super(const SimGrid* sims, int nsims, uint32_t sk) {
+    int lo = 0, hi = nsims - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sims[mid].sbase <= sk)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 // Rank of the agent of record slot t inside its super-box sk (records [st,
@@ -961,7 +1053,7 @@ __device__ __forceinline__ void fixup_slot(const Buffers<T>& b, const SimGrid& G
         }
         if (cnt > kMaxSuperCount) raise_error(b.g, kErrGrid);
         const uint32_t idx = super_index(G, q[0] >> 1, q[1] >> 1, q[2] >> 1);
-        b.cellinfo[idx] = pack_super(x, cnt, c2, c4, c6, moved, b.g->stamp);
+        b.cellinfo[idx] = pack_super(x, cnt, c2, c4, c6, moved, G.stamp);
         b.tabidx[sk] = idx;
     }
 }
@@ -1017,11 +1109,14 @@ __global__ void k_fixup(Buffers<T> b, int cur, int ids_next) {
         if (x0 == 0) b.count[sk] = 0u;
         if (cnt == 0) {   // emptied (so not empty in the last grid, which wrote its table index)
             if (x0 == 0) {
+                // a rebuilt simulation's old entries are stale by its new
+                // stamp, and their indices may be new super-boxes' now
+                const SimGrid& G = b.sims[sim_of_super(b.sims, b.nsims, sk)];
                 const uint32_t idx = b.tabidx[sk];
-                if (idx < b.g->total_super)
-                    b.cellinfo[idx] = pack_super(0u, 0u, 0u, 0u, 0u, 0u, b.g->stamp);
-                else
+                if (idx >= b.g->total_super)
                     raise_error(b.g, kErrInternal);
+                else if (!G.rebuild)
+                    b.cellinfo[idx] = pack_super(0u, 0u, 0u, 0u, 0u, 0u, G.stamp);
             }
             continue;
         }

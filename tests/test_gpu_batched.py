@@ -21,7 +21,25 @@ def test_batched_equals_plain_runs_bitwise():
     note(f"batched {len(off) - 1} sims, n={w.n}")
     params = [dict(k=2.0 + 0.05 * s, gamma=1.0 - 0.01 * s) for s in range(len(off) - 1)]
     b = abm.BatchedSim(to_dev(w.pos), to_dev(w.diam), off, params=params, common=dict(detect_static=True))
-    b.step(w.steps)
+    # step by step: a step where some simulations change their grid extent
+    # and others keep it rebuilds only the former inside an update build
+    mixed = rebuilt = 0
+    b.step(1)
+    assert not b.stats()["update_build"]   # the first grid is a full build
+    last = b.query("extent").cpu().numpy()[:, :6]
+    for t in range(1, w.steps):
+        b.step(1)
+        ext = b.query("extent").cpu().numpy()[:, :6]
+        changed = np.any(ext != last, axis=1)
+        mixed += int(changed.any() and not changed.all())
+        st = b.stats()
+        if st["update_build"]:
+            assert st["rebuilt_sims"] == int(changed.sum())
+            rebuilt += int(st["rebuilt_sims"] > 0)
+        last = ext
+    note(f"steps with some simulations' extents changed and others kept: {mixed}, "
+         f"update builds that rebuilt some simulations: {rebuilt}")
+    assert mixed >= 1 and rebuilt >= 1
     got = b.query("positions").cpu().numpy()
     nnz = b.query("nnz").cpu().numpy()
     for s in range(len(off) - 1):

@@ -463,10 +463,48 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     if (hipGetLastError() != hipSuccess) return bail(fail(ABM_E_HIP, "init kernels failed to launch"));
     const int rc = read_error(c, true);   // also keeps the host arrays alive until the copies are done
     if (rc != ABM_OK) return bail(rc);
-    // the walk width: 4 where boxes hold one or more agents on average
-    // (longer slot ranges), else 2; from the boxes the agents span now
+    // the walk width: 4 where an agent's boxes hold more agents (longer slot
+    // ranges), else 2.  One simulation: 4 at two or more agents per occupied
+    // box of its initial grid (a bitmap of the boxes in the bytes of the
+    // per-agent records, free before the first grid build); otherwise, or
+    // when the bitmap does not fit, 4 at one or more agents per box of the
+    // extent
     c->walk_chunk = p0.walk_chunk;
-    if (c->walk_chunk == 0) {
+    bool chosen = false;
+    if (c->walk_chunk == 0 && nsims == 1) {
+        std::vector<int32_t> rep(size_t(kReplicas) * 6);
+        if (hipMemcpy(rep.data(), b.bbox_rep, rep.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(ABM_E_HIP, "extent read-back failed"));
+        int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+        for (int r = 0; r < kReplicas; ++r)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], rep[size_t(r) * 6 + a]);
+                hi[a] = std::max(hi[a], rep[size_t(r) * 6 + 3 + a]);
+            }
+        uint32_t dims[3] = {0u, 0u, 0u};
+        uint64_t nboxes = 1;
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            ok = ok && hi[a] >= lo[a] && int64_t(hi[a]) - int64_t(lo[a]) < (int64_t(1) << 31);
+            dims[a] = ok ? uint32_t(int64_t(hi[a]) - int64_t(lo[a]) + 1) : 1u;
+            nboxes *= dims[a];
+        }
+        const uint64_t nwords = (nboxes + 31) / 32;
+        if (ok && nboxes < (uint64_t(1) << 40) && 4 * nwords <= uint64_t(16) * uint64_t(cap)) {
+            uint32_t* bits = reinterpret_cast<uint32_t*>(c->ws + L.rec);
+            unsigned long long* out = reinterpret_cast<unsigned long long*>(c->ws + L.key);
+            launch_occupied_boxes<T>(b, lo, dims, bits, nwords, out, s);
+            unsigned long long occupied = 0;
+            if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess ||
+                hipMemcpy(&occupied, out, 8, hipMemcpyDeviceToHost) != hipSuccess)
+                return bail(fail(ABM_E_HIP, "occupied-box count failed"));
+            if (occupied > 0) {
+                c->walk_chunk = double(n) >= 2.0 * double(occupied) ? 4 : 2;
+                chosen = true;
+            }
+        }
+    }
+    if (c->walk_chunk == 0 && !chosen) {
         std::vector<int32_t> rep(size_t(kReplicas) * nsims * 6);
         if (hipMemcpy(rep.data(), b.bbox_rep, rep.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
             return bail(fail(ABM_E_HIP, "extent read-back failed"));

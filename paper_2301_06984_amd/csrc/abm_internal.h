@@ -215,6 +215,11 @@ constexpr uint32_t kMaxSuperBoxes = 1u << 29;
 
 // ---- launchers (grid_kernels.hip)
 template <class T> void launch_pack(const Buffers<T>& b, const T* pos, const T* diam, hipStream_t s);
+// Occupied boxes of one simulation's initial grid into *out (bits: a zeroed
+// bitmap of nwords 32-bit words, one bit per box of the dims box at lo).
+template <class T> void launch_occupied_boxes(const Buffers<T>& b, const int32_t lo[3], const uint32_t dims[3],
+                                              uint32_t* bits, uint64_t nwords, unsigned long long* out,
+                                              hipStream_t s);
 template <class T> void launch_radius(const Buffers<T>& b, int pos_cur, hipStream_t s);
 template <class T> void launch_finish_radius(const Buffers<T>& b, hipStream_t s);
 template <class T> void launch_extent(const T* pos, const T* diam, uint32_t n, Globals* g, SimGrid* sim, hipStream_t s);

@@ -49,6 +49,55 @@ void launch_pack(const Buffers<T>& b, const T* pos, const T* diam, hipStream_t s
     hipLaunchKernelGGL(k_pack<T>, dim3(blocks), dim3(256), 0, s, b, pos, diam);
 }
 
+// Occupied boxes of one simulation's initial grid (lower box lo, dims d):
+// one bit per box, set by the agents in it, then counted.  The mean number
+// of agents per occupied box chooses the neighbour walk's width at init
+// (clustered agents fill few boxes of a large extent densely).
+template <class T>
+__global__ void k_mark_boxes(Buffers<T> b, int32_t lo0, int32_t lo1, int32_t lo2, uint32_t d0, uint32_t d1,
+                             uint32_t d2, uint32_t* __restrict__ bits) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n) return;
+    const V4<T> p = pos4_ptr(b, 0)[i];
+    const double inv_h = b.sims[0].inv_h;
+    int32_t c[3];
+    if (!(box_coord(double(p.x), inv_h, &c[0]) && box_coord(double(p.y), inv_h, &c[1]) &&
+          box_coord(double(p.z), inv_h, &c[2])))
+        return;
+    const int64_t q0 = int64_t(c[0]) - lo0, q1 = int64_t(c[1]) - lo1, q2 = int64_t(c[2]) - lo2;
+    if (q0 < 0 || q1 < 0 || q2 < 0 || q0 >= int64_t(d0) || q1 >= int64_t(d1) || q2 >= int64_t(d2)) return;
+    const uint64_t lin = (uint64_t(q2) * d1 + uint64_t(q1)) * d0 + uint64_t(q0);
+    atomicOr(&bits[lin >> 5], 1u << (lin & 31u));
+}
+
+__global__ void k_count_bits(const uint32_t* __restrict__ bits, uint64_t nwords, unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long s_sum;
+    if (threadIdx.x == 0) s_sum = 0ull;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nwords; w += uint64_t(gridDim.x) * blockDim.x)
+        t += uint64_t(__popc(bits[w]));
+    for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+    if (lane_id() == 0) atomicAdd(&s_sum, t);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_sum) atomicAdd(out, s_sum);
+}
+
+__global__ void k_zero_words(uint32_t* __restrict__ p, uint64_t n, unsigned long long* __restrict__ out) {
+    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < n; w += uint64_t(gridDim.x) * blockDim.x)
+        p[w] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out = 0ull;
+}
+
+template <class T>
+void launch_occupied_boxes(const Buffers<T>& b, const int32_t lo[3], const uint32_t dims[3], uint32_t* bits,
+                           uint64_t nwords, unsigned long long* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_words, dim3(2048), dim3(256), 0, s, bits, nwords, out);
+    hipLaunchKernelGGL(k_mark_boxes<T>, dim3((b.n + 255) / 256), dim3(256), 0, s, b, lo[0], lo[1], lo[2], dims[0],
+                       dims[1], dims[2], bits);
+    hipLaunchKernelGGL(k_count_bits, dim3(2048), dim3(256), 0, s, bits, nwords, out);
+}
+
 // Largest diameter per simulation, as the bits of a positive double (which
 // order like unsigned integers).
 template <class T>
@@ -1253,6 +1302,8 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, b
 
 #define ABM_INSTANTIATE(T)                                                                                 \
     template void launch_pack<T>(const Buffers<T>&, const T*, const T*, hipStream_t);                    \
+    template void launch_occupied_boxes<T>(const Buffers<T>&, const int32_t*, const uint32_t*, uint32_t*,      \
+                                           uint64_t, unsigned long long*, hipStream_t);                          \
     template void launch_radius<T>(const Buffers<T>&, int, hipStream_t);                                 \
     template void launch_finish_radius<T>(const Buffers<T>&, hipStream_t);                               \
     template void launch_extent<T>(const T*, const T*, uint32_t, Globals*, SimGrid*, hipStream_t);       \

@@ -397,7 +397,8 @@ def main():
     w = workloads.headline(n=args.n)
     pos = torch.from_numpy(w.pos).to(dev)
     diam = torch.from_numpy(w.diam).to(dev)
-    common = dict(sort_every=args.sort_every, block_size=args.block_size, order=args.order)
+    # the super-box table sized for the headline's grid (abm_params.super_fraction)
+    common = dict(sort_every=args.sort_every, block_size=args.block_size, order=args.order, super_slack=1.2)
     if args.profile_run:
         sim = abm.Sim(pos, diam, detect_static=False, **common)
         sim.step(11)
@@ -459,7 +460,7 @@ def main():
 
         def hilbert_leg():
             sh, elh, fh = run_plain(pos, diam, args.steps, args.warmup, detect_static=False,
-                                    sort_every=args.sort_every, block_size=args.block_size, order="hilbert")
+                                    **{**common, "order": "hilbert"})
             return dict(value=w.n * args.steps / elh, unit="agent-steps/s", ms_per_step=round(1e3 * elh / args.steps, 4),
                         force_ms=round(fh, 4), speedup_vs_morton=round(el / elh, 3),
                         note="2x2x2 super-boxes along a Hilbert curve, Morton order inside each")
@@ -471,8 +472,7 @@ def main():
             # whole grid, after a re-layout only the changed super-boxes
             out = {}
             for k in (1, 2, 5, 10, 0):
-                sk, elk, fk = run_plain(pos, diam, 10, args.warmup, detect_static=False, sort_every=k,
-                                        block_size=args.block_size)
+                sk, elk, fk = run_plain(pos, diam, 10, args.warmup, detect_static=False, **{**common, "sort_every": k})
                 out[f"sort_every_{k}"] = dict(ms_per_step=round(1e3 * elk / 10, 4), force_ms=round(fk, 4))
                 sk.close()
                 del sk

@@ -1289,8 +1289,9 @@ void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, b
     const ScanIn in{b.count, b.cell_start_old, b.dirty, b.tabidx, b.mmask, b.cellinfo};
     hipLaunchKernelGGL(k_scan_reduce, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, in, b.tile_sums,
                        b.scan_tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kTileScanThreads), 0, s, b.g, b.tile_sums, b.cell_start,
-                       b.scan_tiles);
+    if (b.scan_tiles > kFusedScanTiles)   // else the rescan adds up the tile sums itself
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kTileScanThreads), 0, s, b.g, b.tile_sums, b.cell_start,
+                           b.scan_tiles);
     hipLaunchKernelGGL(k_scan_down, dim3(b.scan_tiles), dim3(kScanThreads), 0, s, b.g, in, b.count, b.cell_start,
                        b.tile_sums, b.dirty_list, b.aoff, b.scan_tiles);
     mark(1);

@@ -12,7 +12,7 @@ from paper_2301_06984_amd import abm, workloads
 
 pytestmark = pytest.mark.gpu
 
-BENCH = dict(sort_every=1, block_size=256, detect_static=False)   # the benchmark's launch configuration
+BENCH = dict(sort_every=1, block_size=256, detect_static=False, super_slack=1.2)   # the benchmark's launch configuration
 
 
 def check_samples(pos, diam, got_pos, nsamples, seed, params=oracle.Params(), got_nnz=None):

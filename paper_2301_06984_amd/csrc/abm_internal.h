@@ -47,9 +47,10 @@
 //     mmask       moved octants of a kept super-box, gathered by the keys
 //                 kernel and moved into its table entry by the scan
 //     cellinfo    row-major super-box table, 16 B per entry (SuperEntry); an
-//                 entry whose stamp is not the current one is empty, so the
-//                 table is never cleared between steps (the timestamp trick
-//                 of Section 3.1; update builds keep the stamp)
+//                 entry whose stamp is not its simulation's current one is
+//                 empty, so the table is never cleared between steps (the
+//                 timestamp trick of Section 3.1; update builds keep the
+//                 stamps, a simulation rebuilt inside one takes a fresh one)
 //   per scan tile: three 32-bit sums.
 //   the Hilbert order's tables (HilbertTables, 768 B).
 #pragma once
@@ -117,7 +118,7 @@ struct SimGrid {
 struct Globals {
     uint32_t err;
     uint32_t total_super;    // super-boxes of all simulations in this step's grid
-    uint32_t stamp;          // of the current super-box table entries (1..32767)
+    uint32_t stamp;          // the latest stamp given to table entries (1..32767; each simulation keeps its own)
     uint32_t inc;            // this step's grid is an update of the last one (see launch_grid)
     uint32_t epoch;          // counts grid builds (marks this step's changed super-boxes; never 0)
     uint32_t ndirty;         // changed super-boxes of an update build (dirty_list, from the scan)

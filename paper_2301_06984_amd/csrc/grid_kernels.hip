@@ -3,10 +3,13 @@
 // the super-boxes), counted per super-box (the aligned 2x2x2 blocks of
 // boxes, whose agents are contiguous in that order):
 //   bbox     box extent of the agents (per simulation)
-//   setup    dims, box and super-box counts and bases of every simulation
+//   setup    dims, box and super-box counts and bases of every simulation;
+//            full or update build (several simulations: those whose extent
+//            changed are rebuilt inside an update, with a fresh table stamp)
 //   keys     super-box key and octant of every agent + histogram (atomics);
-//            an update build: only the agents that left their box, and with
-//            the static test the moved octants of every super-box
+//            an update build: only the agents that left their box (all of a
+//            rebuilt simulation's), and with the static test the moved
+//            octants of every super-box
 //   scan     exclusive scan of the super-box counts (tile sums, their scan,
 //            rescan); an update build also lists the changed super-boxes
 //            and refreshes the table entries of the others

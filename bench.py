@@ -620,20 +620,32 @@ def main():
             xT = adj.positions().double()
             tgt = torch.from_numpy(wa.target).to(dev)
             adj.backward(2.0 * (xT - tgt) / (3 * wa.n))
-            adj2 = abm.Sim(pa, da, sort_every=0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            adj2.forward_record(wa.steps, 10)
-            xT = adj2.positions().double()
-            gx, gp = adj2.backward(2.0 * (xT - tgt) / (3 * wa.n))
-            torch.cuda.synchronize()
-            ela = time.perf_counter() - t0
-            peak = int(adj2.ws.numel()) + int(adj2.rec.numel()) + 2 * 24 * wa.n
+            def fwd_bwd(tapes):
+                a2 = abm.Sim(pa, da, sort_every=0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                a2.forward_record(wa.steps, 10, tapes=tapes)
+                xT = a2.positions().double()
+                gx, gp = a2.backward(2.0 * (xT - tgt) / (3 * wa.n))
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                peak = int(a2.ws.numel()) + int(a2.rec.numel()) + 2 * 24 * wa.n
+                return el, gp, peak, a2.record_info()
+            # contact tapes of every step (the default where they fit), of each
+            # recomputed segment, or none (every reverse step walks a grid)
+            ela, gp, peak, info = fwd_bwd("all")
+            others = {t: fwd_bwd(t) for t in ("segment", "none")}
+            same = all(bool(torch.equal(gp, o[1])) for o in others.values())
             return dict(value=wa.n * wa.steps / ela, unit="agent-steps/s (forward+backward)", agents=wa.n,
                         steps=wa.steps, ckpt_every=10, plain_forward=wa.n * wa.steps / elp,
                         ratio_vs_plain_forward=round(elp / ela, 3), dL_dk=float(gp[0]), dL_dgamma=float(gp[1]),
-                        peak_device_bytes=peak,
-                        peak_note="workspace + forward record + dL/dx_T and dL/dx_0 (n x 3 doubles each)")
+                        contact_tapes="every step", record_info=info,
+                        by_tapes={t: dict(value=wa.n * wa.steps / o[0], ratio_vs_plain_forward=round(elp / o[0], 3),
+                                          peak_device_bytes=o[2])
+                                  for t, o in others.items()},
+                        same_gradients_all_modes=same, peak_device_bytes=peak,
+                        peak_note="workspace + forward record (with every step's contact tape) + dL/dx_T and "
+                                  "dL/dx_0 (n x 3 doubles each)")
         leg(extras, "adjoint", adjoint_leg, only)
 
     cpu = None

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define ABM_ABI_VERSION 4
+#define ABM_ABI_VERSION 5
 #define ABM_EXTENT_SCRATCH_BYTES 1024
 
 enum abm_status {
@@ -349,18 +349,37 @@ int abm_graph_launch(abm_ctx* ctx);
  * Reverse mode of the step x -> x + Delta(F(x); k, gamma) with the neighbour
  * sets, thresholds and clamp states of every forward step held fixed
  * (single simulation, detect_static off).
- *   abm_record_bytes: device bytes needed to record nsteps with a checkpoint
- *     every ckpt_every steps.
+ *   abm_record_sizes: device bytes of a record of nsteps with a checkpoint
+ *     every ckpt_every steps, in three sizes (sizes: host, 3 int64):
+ *     sizes[0] the least; sizes[1] with room for one segment's contact tapes;
+ *     sizes[2] with room for every step's tapes.  abm_record_bytes gives
+ *     sizes[2].  A contact tape holds every agent's contacts on one step's
+ *     grid, in the order the force sums them (32 per agent at most); a
+ *     reverse step that reads a complete tape needs no grid and no
+ *     neighbour walk, and gives the same result, bit for bit.
  *   abm_forward_record: run nsteps steps from the current state, keeping the
- *     positions of every ckpt_every-th step in rec (device, rec_bytes).
+ *     positions of every ckpt_every-th step in rec (device, rec_bytes of at
+ *     least sizes[0], 256-byte aligned; the caller owns it and keeps it
+ *     until the backward is done).  With rec_bytes >= sizes[2] it also tapes
+ *     every step, and the backward recomputes nothing unless a tape is
+ *     incomplete (an agent with more than 32 contacts).
  *   abm_backward: given dL/dx_T (device, n x 3 double, by id), write
  *     dL/dx_0 (device, n x 3 double, by id) and dL/d(k, gamma) (device,
- *     2 double).  Recomputes each checkpoint segment forward, then walks it
- *     backward.  ABM_E_STATE without a preceding abm_forward_record.
+ *     2 double).  Without complete tapes of every step it recomputes each
+ *     checkpoint segment forward (taping its steps if rec_bytes >=
+ *     sizes[1]), then walks it backward, on the tape of each step whose tape
+ *     is complete and else on a grid built from the step's positions.
+ *     ABM_E_STATE without a preceding abm_forward_record.
+ *   abm_record_info: info (host, 3 int32): [0] the record's tapes (-1 no
+ *     record, 0 none, 1 per recomputed segment, 2 every step); [1] reverse
+ *     steps of the last abm_backward that read a tape; [2] the largest
+ *     contact count a tape has seen.
  */
 int abm_record_bytes(abm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, int64_t* bytes);
+int abm_record_sizes(abm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, int64_t* sizes);
 int abm_forward_record(abm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, void* rec, int64_t rec_bytes);
 int abm_backward(abm_ctx* ctx, const void* dL_dxT, void* dL_dx0, void* dL_dparams);
+int abm_record_info(abm_ctx* ctx, int32_t* info);
 
 /*
  * Timing mode: with enable = 1, every step enqueued by abm_step brackets

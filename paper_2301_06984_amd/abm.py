@@ -20,7 +20,7 @@ ABM_OK, ABM_E_INVAL, ABM_E_NONFINITE, ABM_E_GRID, ABM_E_WORKSPACE, ABM_E_HIP, AB
     0, -1, -2, -3, -4, -5, -6, -7
 ABM_F32, ABM_F64 = 0, 1
 ABM_ORDER_MORTON, ABM_ORDER_HILBERT = 0, 1
-ABI_VERSION = 4   # the layout of the structs below
+ABI_VERSION = 5   # the layout of the structs below
 FIELD = dict(positions=0, forces=1, moved=2, static=3, nnz=4, key=5, perm=6, cell_start=7, extent=8,
              storage_ids=9, neighbor_count=10, neighbors=11, diameters=12)
 EXTENT_SCRATCH_BYTES = 1024
@@ -31,7 +31,8 @@ EXPORTS = ["abm_abi_version", "abm_default_params", "abm_last_error", "abm_exten
            "abm_get_stats", "abm_state_bytes", "abm_export_state", "abm_import_state", "abm_graph_capture",
            "abm_graph_launch", "abm_record_bytes", "abm_forward_record", "abm_backward", "abm_set_timing",
            "abm_get_timing", "abm_destroy", "abm_workspace_bytes_capacity", "abm_init_capacity", "abm_add_agents",
-           "abm_remove_agents", "abm_set_diameters", "abm_population", "abm_extent_of_noalloc"]
+           "abm_remove_agents", "abm_set_diameters", "abm_population", "abm_extent_of_noalloc", "abm_record_sizes",
+           "abm_record_info"]
 TIMED_PHASES = ["setup", "keys", "scan", "scatter", "fixup", "force"]
 
 
@@ -95,6 +96,8 @@ def lib():
             "abm_graph_capture": (C.c_int, [P, i32]),
             "abm_graph_launch": (C.c_int, [P]),
             "abm_record_bytes": (C.c_int, [P, i32, i32, C.POINTER(i64)]),
+            "abm_record_sizes": (C.c_int, [P, i32, i32, P]),
+            "abm_record_info": (C.c_int, [P, P]),
             "abm_forward_record": (C.c_int, [P, i32, i32, P, i64]),
             "abm_backward": (C.c_int, [P, P, P, P]),
             "abm_set_timing": (C.c_int, [P, i32]),
@@ -359,12 +362,34 @@ class Sim:
         _check(lib().abm_import_state(self.ctx, buf, len(blob)), "abm_import_state")
 
     # ---------------------------------------------------------------- adjoint
-    def forward_record(self, nsteps: int, ckpt_every: int):
-        nb = C.c_int64()
-        _check(lib().abm_record_bytes(self.ctx, int(nsteps), int(ckpt_every), C.byref(nb)), "abm_record_bytes")
-        self.rec = torch.empty(int(nb.value), dtype=torch.uint8, device=self.ws.device)
+    def record_sizes(self, nsteps: int, ckpt_every: int) -> dict:
+        """Bytes of a record without contact tapes, with one segment's, with every step's."""
+        sz = (C.c_int64 * 3)()
+        _check(lib().abm_record_sizes(self.ctx, int(nsteps), int(ckpt_every), sz), "abm_record_sizes")
+        return dict(none=int(sz[0]), segment=int(sz[1]), all=int(sz[2]))
+
+    def forward_record(self, nsteps: int, ckpt_every: int, tapes: str = "auto"):
+        """Record nsteps steps for backward().  tapes: "all" (every step's
+        contacts kept: the backward recomputes nothing), "segment" (taped while
+        each segment is recomputed), "none" (the reverse steps walk a grid), or
+        "auto": the largest that takes at most half the free device memory."""
+        sizes = self.record_sizes(nsteps, ckpt_every)
+        if tapes == "auto":
+            free = torch.cuda.mem_get_info(self.ws.device)[0]
+            tapes = next((k for k in ("all", "segment") if sizes[k] <= free // 2), "none")
+        if tapes not in sizes:
+            raise ValueError(f"tapes must be auto, all, segment or none, not {tapes!r}")
+        self.rec = torch.empty(sizes[tapes], dtype=torch.uint8, device=self.ws.device)
         _check(lib().abm_forward_record(self.ctx, int(nsteps), int(ckpt_every), _ptr(self.rec), self.rec.numel()),
                "abm_forward_record")
+
+    def record_info(self) -> dict:
+        """The record's tapes (-1 no record, 0 none, 1 per segment, 2 every
+        step), the reverse steps of the last backward that read a tape, and the
+        largest contact count a tape saw."""
+        info = (C.c_int32 * 3)()
+        _check(lib().abm_record_info(self.ctx, info), "abm_record_info")
+        return dict(tapes=int(info[0]), taped_reverse_steps=int(info[1]), worst_contacts=int(info[2]))
 
     def backward(self, dL_dxT: torch.Tensor):
         g = dL_dxT.to(torch.float64).contiguous()

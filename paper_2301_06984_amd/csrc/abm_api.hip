@@ -150,6 +150,13 @@ struct abm_ctx {
     int64_t rec_start = 0;
     char* rec = nullptr;
     int64_t rec_bytes = 0;
+    // contact tapes of the record: 0 none (the reverse steps walk a grid), 1
+    // written per segment while it is recomputed, 2 written by the record for
+    // every step (no recomputation)
+    int rec_tapes = 0;
+    uint32_t rec_worst = 0;        // the largest contact count a tape saw
+    int32_t taped_reverse = 0;     // reverse steps of the last backward that read a tape
+    TapeStep tape_next{};          // the next step's grid is taped here (pos null: not taped)
 
     int64_t elem() const { return precision == ABM_F64 ? 8 : 4; }
     template <class T> Buffers<T>& buf();
@@ -335,6 +342,15 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, int timed = 0) {
     launch_grid<T>(b, c->pos_cur, c->ids_cur, a.relayout, a.detect_static, c->stream, all_phases ? marks : nullptr);
     swap_cell_start<T>(c);
     a.cs = last_grid_starts<T>(c);
+    if (c->tape_next.pos) {
+        // the step kernel tapes a full build of one simulation without the
+        // static test or a re-layout (every step the adjoint records)
+        if (c->nsims == 1 && !a.detect_static && !a.relayout && a.full_only)
+            a.tape = c->tape_next;
+        else
+            launch_adj_tape<T>(b, c->tape_next, c->stream);
+        c->tape_next = TapeStep{};
+    }
     if (ev && !all_phases) (void)hipEventRecord((*ev)[kTimedPhases - 1], c->stream);
     launch_force<T>(b, a, c->stream);
     if (ev) (void)hipEventRecord((*ev)[kTimedPhases], c->stream);
@@ -736,8 +752,12 @@ int export_impl(abm_ctx* c, void* dst, int64_t dst_bytes) {
 }
 
 // ---------------------------------------------------------------- adjoint
+// The record: checkpoints, one segment's positions, x_T, lambda twice and w,
+// then (optional) a word per taped step and the contact tapes, one per step.
 struct RecLayout {
-    int64_t ckpt, seg, xT, lam, lam2, w, total;
+    int64_t ckpt, seg, xT, lam, lam2, w, total;   // total: without tapes
+    int64_t worst, tape, tape_step;               // the tapes: first one, bytes of each
+    int64_t total_seg, total_all;                 // with one segment's tapes, with every step's
     int32_t nckpt;
 };
 
@@ -760,7 +780,36 @@ RecLayout rec_layout(abm_ctx* c, int32_t nsteps, int32_t ckpt_every) {
     r.w = off;
     off += db;
     r.total = off;
+    r.worst = off;
+    off += align_up(4 * int64_t(nsteps));
+    r.tape = off;
+    r.tape_step = align_up(4 * c->n * c->elem()) + 2 * align_up(4 * c->n) + align_up(4 * c->n * kTapeWidth);
+    r.total_seg = off + r.tape_step * std::min(ckpt_every, nsteps);
+    r.total_all = off + r.tape_step * nsteps;
     return r;
+}
+
+TapeStep tape_at(abm_ctx* c, const RecLayout& R, char* base, int32_t k) {
+    char* p = base + R.tape + R.tape_step * k;
+    TapeStep tp;
+    tp.pos = p;
+    p += align_up(4 * c->n * c->elem());
+    tp.perm = reinterpret_cast<uint32_t*>(p);
+    p += align_up(4 * c->n);
+    tp.cnt = reinterpret_cast<uint32_t*>(p);
+    p += align_up(4 * c->n);
+    tp.list = reinterpret_cast<uint32_t*>(p);
+    tp.worst = reinterpret_cast<uint32_t*>(base + R.worst) + k;
+    return tp;
+}
+
+// The largest contact counts of taped steps [0, m), read back to the host.
+int read_worst(abm_ctx* c, const RecLayout& R, char* base, int32_t m, std::vector<uint32_t>& out) {
+    out.assign(size_t(m), 0u);
+    HIP_TRY(hipMemcpyAsync(out.data(), base + R.worst, 4 * size_t(m), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (uint32_t v : out) c->rec_worst = std::max(c->rec_worst, v);
+    return ABM_OK;
 }
 
 template <class T>
@@ -770,25 +819,56 @@ int forward_record_impl(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, void* re
     Buffers<T>& b = c->buf<T>();
     char* base = static_cast<char*>(rec);
     const int64_t pb = align_up(3 * c->n * c->elem());
+    const int tapes = rec_bytes >= R.total_all ? 2 : (rec_bytes >= R.total_seg ? 1 : 0);
     c->recorded = false;
     c->rec_start = c->step;
+    c->rec_worst = 0;
+    if (tapes == 2) {
+        HIP_TRY(hipMemsetAsync(base + R.worst, 0, 4 * size_t(nsteps), c->stream));
+        c->inc_ready = false;   // a taped step's grid is a full build (so are the later ones here)
+    }
     for (int32_t s = 0; s < nsteps; ++s) {
         if (s % ckpt_every == 0)
             launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.ckpt + pb * (s / ckpt_every)),
                                        c->stream);
+        if (tapes == 2) c->tape_next = tape_at(c, R, base, s);
         int rc = do_steps<T>(c, 1, false);
         if (rc != ABM_OK) return rc;
     }
     launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.xT), c->stream);
     HIP_TRY(hipGetLastError());
-    const int rc = read_error(c, true);
+    int rc = read_error(c, true);
     if (rc != ABM_OK) return rc;
+    c->rec_tapes = tapes;
+    if (tapes == 2) {
+        std::vector<uint32_t> worst;
+        if ((rc = read_worst(c, R, base, nsteps, worst)) != ABM_OK) return rc;
+        // an incomplete tape: the backward recomputes each segment, taping
+        // the steps again and walking the grid of those that do not fit
+        if (c->rec_worst > kTapeWidth) c->rec_tapes = 1;
+    }
     c->recorded = true;
     c->rec_steps = nsteps;
     c->rec_ckpt = ckpt_every;
     c->rec = base;
     c->rec_bytes = rec_bytes;
     return ABM_OK;
+}
+
+// The grid of the current positions and its tape, without the step's force
+// (the last step of a recomputed segment: its new positions are not needed).
+template <class T>
+void enqueue_tape_only(abm_ctx* c, const TapeStep& tp) {
+    Buffers<T>& b = c->buf<T>();
+    guard_stamps<T>(c, 1);
+    set_grid_pos<T>(c, c->pos_cur);
+    launch_setup<T>(b, int(c->step & 1), c->inc_ready, c->stream);
+    launch_grid<T>(b, c->pos_cur, c->ids_cur, false, false, c->stream);
+    swap_cell_start<T>(c);
+    launch_adj_tape<T>(b, tp, c->stream);
+    c->grid_ids = c->ids_cur;
+    c->inc_ready = false;
+    c->stamp_count += 1;
 }
 
 // Load positions (by id) into the current storage and build the grid for them.
@@ -825,27 +905,59 @@ int backward_impl(abm_ctx* c, const double* dL_dxT, double* dL_dx0, double* dL_d
     launch_permute3(ids, n, dL_dxT, lam, false, s);
     HIP_TRY(hipMemsetAsync(dL_dparams, 0, 2 * sizeof(double), s));
     const int nblocks = adj_blocks(n);
-    for (int32_t seg = R.nckpt - 1; seg >= 0; --seg) {
-        const int32_t s0 = seg * c->rec_ckpt;
-        const int32_t s1 = std::min(c->rec_steps, s0 + c->rec_ckpt);
-        // recompute the segment forward, keeping every step's positions
-        launch_load_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const T*>(base + R.ckpt + pb * seg), s);
-        c->inc_ready = false;   // positions replaced outside the step
-        launch_mark_moved<T>(b, c->pos_cur, s);
-        c->step = c->rec_start + s0;
-        enqueue_extent<T>(c);
-        for (int32_t t = s0; t < s1; ++t) {
-            launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.seg + pb * (t - s0)), s);
-            int rc = do_steps<T>(c, 1, false);
-            if (rc != ABM_OK) return rc;
-        }
-        // walk the segment backward
-        for (int32_t t = s1 - 1; t >= s0; --t) {
-            load_and_grid<T>(c, reinterpret_cast<const T*>(base + R.seg + pb * (t - s0)));
-            launch_adj_w<T>(b, c->pos_cur, lam, w, s);
-            launch_adj_gather<T>(b, c->pos_cur, lam, w, lam2, s);
-            launch_adj_finish<T>(b, nblocks, dL_dparams, s);
-            std::swap(lam, lam2);
+    c->taped_reverse = 0;
+    // one reverse step on the tape of step t, or on a grid built from x_t
+    auto reverse_taped = [&](const TapeStep& tp) {
+        launch_adj_tape_w<T>(b, tp, lam, w, s);
+        launch_adj_tape_gather<T>(b, tp, lam, w, lam2, s);
+        launch_adj_finish<T>(b, nblocks, dL_dparams, s);
+        std::swap(lam, lam2);
+        c->taped_reverse += 1;
+    };
+    auto reverse_walked = [&](const T* x_t) {
+        load_and_grid<T>(c, x_t);
+        launch_adj_w<T>(b, c->pos_cur, lam, w, s);
+        launch_adj_gather<T>(b, c->pos_cur, lam, w, lam2, s);
+        launch_adj_finish<T>(b, nblocks, dL_dparams, s);
+        std::swap(lam, lam2);
+    };
+    if (c->rec_tapes == 2) {
+        for (int32_t t = c->rec_steps - 1; t >= 0; --t) reverse_taped(tape_at(c, R, base, t));
+    } else {
+        std::vector<uint32_t> worst;
+        for (int32_t seg = R.nckpt - 1; seg >= 0; --seg) {
+            const int32_t s0 = seg * c->rec_ckpt;
+            const int32_t s1 = std::min(c->rec_steps, s0 + c->rec_ckpt);
+            const bool taped = c->rec_tapes == 1;
+            // recompute the segment forward, keeping every step's positions
+            // (and contacts); the step out of its last state is not needed
+            launch_load_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const T*>(base + R.ckpt + pb * seg), s);
+            c->inc_ready = false;   // positions replaced outside the step
+            launch_mark_moved<T>(b, c->pos_cur, s);
+            c->step = c->rec_start + s0;
+            enqueue_extent<T>(c);
+            if (taped) HIP_TRY(hipMemsetAsync(base + R.worst, 0, 4 * size_t(s1 - s0), s));
+            for (int32_t t = s0; t < s1; ++t) {
+                launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.seg + pb * (t - s0)), s);
+                if (t + 1 < s1) {
+                    if (taped) c->tape_next = tape_at(c, R, base, t - s0);
+                    int rc = do_steps<T>(c, 1, false);
+                    if (rc != ABM_OK) return rc;
+                } else if (taped) {
+                    enqueue_tape_only<T>(c, tape_at(c, R, base, t - s0));
+                }
+            }
+            if (taped) {
+                HIP_TRY(hipGetLastError());
+                if (int rc = read_worst(c, R, base, s1 - s0, worst)) return rc;
+            }
+            // walk the segment backward
+            for (int32_t t = s1 - 1; t >= s0; --t) {
+                if (taped && worst[size_t(t - s0)] <= kTapeWidth)
+                    reverse_taped(tape_at(c, R, base, t - s0));
+                else
+                    reverse_walked(reinterpret_cast<const T*>(base + R.seg + pb * (t - s0)));
+            }
         }
     }
     launch_permute3(ids, n, lam, dL_dx0, true, s);
@@ -1304,7 +1416,26 @@ int abm_graph_launch(abm_ctx* c) {
 int abm_record_bytes(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, int64_t* bytes) {
     if (int rc = check_ctx(c)) return rc;
     if (nsteps < 1 || ckpt_every < 1 || !bytes) return fail(ABM_E_INVAL, "bad arguments");
-    *bytes = rec_layout(c, nsteps, ckpt_every).total;
+    *bytes = rec_layout(c, nsteps, ckpt_every).total_all;
+    return ABM_OK;
+}
+
+int abm_record_sizes(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, int64_t* sizes) {
+    if (int rc = check_ctx(c)) return rc;
+    if (nsteps < 1 || ckpt_every < 1 || !sizes) return fail(ABM_E_INVAL, "bad arguments");
+    const RecLayout R = rec_layout(c, nsteps, ckpt_every);
+    sizes[0] = R.total;
+    sizes[1] = R.total_seg;
+    sizes[2] = R.total_all;
+    return ABM_OK;
+}
+
+int abm_record_info(abm_ctx* c, int32_t* info) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!info) return fail(ABM_E_INVAL, "null output");
+    info[0] = c->recorded ? c->rec_tapes : -1;
+    info[1] = c->taped_reverse;
+    info[2] = int32_t(std::min<uint32_t>(c->rec_worst, 0x7FFFFFFFu));
     return ABM_OK;
 }
 

@@ -193,6 +193,21 @@ struct Buffers {
     uint32_t bpart_cap;
 };
 
+// The contact tape of one step (a full build): per canonical slot t, the
+// agent's position (as the grid holds it), its storage index and its
+// contacts' canonical slots in the order the force sums them (row r of
+// slot t at list[r * n + t], at most kTapeWidth rows); *worst gets the
+// largest contact count of the step (a tape with worst > kTapeWidth is
+// incomplete and not used).
+constexpr uint32_t kTapeWidth = 32;
+struct TapeStep {
+    void* pos;          // V4<T>[n]
+    uint32_t* perm;     // [n]
+    uint32_t* cnt;      // [n]
+    uint32_t* list;     // [kTapeWidth][n]
+    uint32_t* worst;    // one word, cleared before the step
+};
+
 // Host-side description of which kernels to run for one step.
 struct StepArgs {
     int parity;             // which bbox accumulator describes the current positions
@@ -205,6 +220,7 @@ struct StepArgs {
     int block_size;
     int walk_chunk;         // 2 or 4 candidate slots tested together by the neighbour walk
     const uint32_t* cs;     // this grid's super-box starts
+    TapeStep tape;          // the step's contacts are taped here (pos null: not taped)
 };
 
 constexpr uint32_t kStampPeriod = 32767;   // 15-bit stamps in the super-box table
@@ -272,6 +288,11 @@ template <class T> void launch_set_diameters(const Buffers<T>& b, int pos_cur, i
                                              const int64_t* ids, const T* diam, uint32_t* mk, hipStream_t s, int phase);
 
 // ---- launchers (adjoint_kernels.hip)
+template <class T> void launch_adj_tape(const Buffers<T>& b, const TapeStep& tp, hipStream_t s);
+template <class T> void launch_adj_tape_w(const Buffers<T>& b, const TapeStep& tp, const double* lam, double* w,
+                                          hipStream_t s);
+template <class T> void launch_adj_tape_gather(const Buffers<T>& b, const TapeStep& tp, const double* lam,
+                                               const double* w, double* lam_out, hipStream_t s);
 template <class T> void launch_adj_w(const Buffers<T>& b, int pos_cur, const double* lam, double* w, hipStream_t s);
 template <class T> void launch_adj_gather(const Buffers<T>& b, int pos_cur, const double* lam, const double* w,
                                           double* lam_out, hipStream_t s);

@@ -10,7 +10,11 @@
 //   dL/dk += sum_i w_i . sum_j delta_ij u_ij,  dL/dgamma -= sum_i w_i . sum_j sqrt(rho delta) u_ij.
 //
 // The grids of the reverse steps are full builds: the agent of canonical slot
-// t sits in loose slot n + t, with storage index perm[t].
+// t sits in loose slot n + t, with storage index perm[t].  A reverse step
+// either walks such a grid (k_adj_w, k_adj_gather) or reads the step's
+// contact tape, written by k_adj_tape while the forward step had its grid
+// (k_adj_tape_w, k_adj_tape_gather): the same contacts in the same order, so
+// both give the same sums, bit for bit.
 #include "force_loop.h"
 
 namespace abm {
@@ -20,10 +24,48 @@ constexpr int kAdjChunk = 4;   // candidates the walk of the reverse step tests 
 
 int adj_blocks(uint32_t n) { return int((n + kAdjThreads - 1) / kAdjThreads); }
 
+// w_i = D_i^T lambda_i for agent i (storage index) with force sums acc, and
+// its terms of dL/dk and dL/dgamma.
+__device__ __forceinline__ void adjoint_w(const SimGrid& G, const ForceSum& acc, const double* __restrict__ lam,
+                                          uint32_t i, double wi[3], double& gk, double& gg) {
+    const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
+    if (!m.moves) return;
+    const double li[3] = {lam[3 * size_t(i)], lam[3 * size_t(i) + 1], lam[3 * size_t(i) + 2]};
+    if (m.clamped) {
+        const double Fn = m.fnorm;
+        const double fh[3] = {acc.fx / Fn, acc.fy / Fn, acc.fz / Fn};
+        const double dot = li[0] * fh[0] + li[1] * fh[1] + li[2] * fh[2];
+        for (int a = 0; a < 3; ++a) wi[a] = G.delta_max / Fn * (li[a] - dot * fh[a]);
+    } else {
+        for (int a = 0; a < 3; ++a) wi[a] = G.mu * li[a];
+    }
+    gk = wi[0] * acc.kx + wi[1] * acc.ky + wi[2] * acc.kz;
+    gg = wi[0] * acc.gx + wi[1] * acc.gy + wi[2] * acc.gz;
+}
+
+// The block's partial sums of dL/dk and dL/dgamma, by a fixed-shape tree (the
+// result does not depend on timing); every thread of the block calls it.
+__device__ __forceinline__ void block_partials(double* __restrict__ partials, uint32_t cap, double gk, double gg) {
+    __shared__ double s_k[kAdjThreads], s_g[kAdjThreads];
+    s_k[threadIdx.x] = gk;
+    s_g[threadIdx.x] = gg;
+    __syncthreads();
+    for (int h = kAdjThreads / 2; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) {
+            s_k[threadIdx.x] += s_k[threadIdx.x + h];
+            s_g[threadIdx.x] += s_g[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && blockIdx.x < cap) {
+        partials[2 * blockIdx.x] = s_k[0];
+        partials[2 * blockIdx.x + 1] = s_g[0];
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, const double* __restrict__ lam,
                                                         double* __restrict__ w) {
-    __shared__ double s_k[kAdjThreads], s_g[kAdjThreads];
     extern __shared__ __align__(16) unsigned char s_walk[];
     const WalkLds L = walk_lds(s_walk);
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -39,40 +81,13 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, co
             const Pieces P = load_pieces(b, G, q, G.stamp, L);
             ForceSum acc;
             force_of<kAdjChunk, T, true>(b, G, p, P, L, acc);
-            const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
-            if (m.moves) {
-                const double li[3] = {lam[3 * size_t(i)], lam[3 * size_t(i) + 1], lam[3 * size_t(i) + 2]};
-                if (m.clamped) {
-                    const double Fn = m.fnorm;
-                    const double fh[3] = {acc.fx / Fn, acc.fy / Fn, acc.fz / Fn};
-                    const double dot = li[0] * fh[0] + li[1] * fh[1] + li[2] * fh[2];
-                    for (int a = 0; a < 3; ++a) wi[a] = G.delta_max / Fn * (li[a] - dot * fh[a]);
-                } else {
-                    for (int a = 0; a < 3; ++a) wi[a] = G.mu * li[a];
-                }
-                gk = wi[0] * acc.kx + wi[1] * acc.ky + wi[2] * acc.kz;
-                gg = wi[0] * acc.gx + wi[1] * acc.gy + wi[2] * acc.gz;
-            }
+            adjoint_w(G, acc, lam, i, wi, gk, gg);
         } else {
             raise_error(b.g, kErrInternal);
         }
         for (int a = 0; a < 3; ++a) w[3 * size_t(t) + a] = wi[a];   // by canonical slot: the gather reads it there
     }
-    // fixed-shape tree reduction: the result does not depend on timing
-    s_k[threadIdx.x] = gk;
-    s_g[threadIdx.x] = gg;
-    __syncthreads();
-    for (int h = kAdjThreads / 2; h > 0; h >>= 1) {
-        if (int(threadIdx.x) < h) {
-            s_k[threadIdx.x] += s_k[threadIdx.x + h];
-            s_g[threadIdx.x] += s_g[threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && blockIdx.x < b.partial_cap) {
-        b.partials[2 * blockIdx.x] = s_k[0];
-        b.partials[2 * blockIdx.x + 1] = s_g[0];
-    }
+    block_partials(b.partials, b.partial_cap, gk, gg);
 }
 
 // One term of the update of lambda_m for its contact at loose slot u:
@@ -191,6 +206,121 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
         for (int a = 0; a < 3; ++a) lam_out[3 * size_t(m) + a] = acc[a];
 }
 
+// ---------------------------------------------------------------- contact tape
+// The contacts of every agent on the step's grid (a full build), found by the
+// walk of the gather, in the order the force sums them: canonical slot t
+// keeps its position, storage index and contacts' canonical slots (see
+// TapeStep).  A count above kTapeWidth is still counted (and raises *worst
+// past it), its excess rows are not kept.
+template <class T>
+__global__ __launch_bounds__(kAdjThreads) void k_adj_tape(Buffers<T> b, TapeStep tp) {
+    extern __shared__ __align__(16) unsigned char s_walk[];
+    const WalkLds L = walk_lds(s_walk);
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, tid = threadIdx.x, bs = blockDim.x, n = b.n;
+    const SimGrid& G = b.sims[0];   // the adjoint covers one simulation
+    uint32_t i = 0xFFFFFFFFu;
+    if (t < n) {
+        i = b.perm[t];
+        // a full build holds every agent in the append slots [n, 2n)
+        if (i >= n || b.g->inc) raise_error(b.g, kErrInternal);
+    }
+    const bool has = i < n && !b.g->inc;
+    V4<T> p{};
+    Pieces P;
+    if (has) {
+        p = gpos_ptr(b)[n + t];
+        uint32_t q[3];
+        if (G.valid && box_of<T>(G, p, q))
+            P = load_pieces(b, G, q, G.stamp, L);
+        else
+            raise_error(b.g, kErrInternal);
+    }
+    uint32_t cnt = 0;
+    auto emit = [&](uint32_t k) {
+        for (uint32_t r = 0; r < k; ++r) {
+            const uint32_t u = L.queue[r * bs + tid];
+            if (u < n) {
+                raise_error(b.g, kErrInternal);
+                continue;
+            }
+            if (cnt < kTapeWidth) tp.list[size_t(cnt) * n + t] = u - n;
+            ++cnt;
+        }
+    };
+    emit(queue_contacts<kAdjChunk, T>(b, G, p, P, L, emit));
+    if (has) {
+        tp.cnt[t] = cnt;
+        tp.perm[t] = i;
+        static_cast<V4<T>*>(tp.pos)[t] = p;
+    }
+    uint32_t most = cnt;   // one atomic per wave
+    for (int d = 32; d >= 1; d >>= 1) most = max(most, uint32_t(__shfl_xor(int(most), d, 64)));
+    if (lane_id() == 0 && most > 0) atomicMax(tp.worst, most);
+}
+
+// k_adj_w on a complete tape: F_i and its parameter derivatives from the
+// listed contacts, in their order.
+template <class T>
+__global__ __launch_bounds__(kAdjThreads) void k_adj_tape_w(Buffers<T> b, TapeStep tp, const double* __restrict__ lam,
+                                                             double* __restrict__ w) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, n = b.n;
+    double gk = 0.0, gg = 0.0;
+    if (t < n) {
+        const uint32_t i = tp.perm[t], cnt = tp.cnt[t];
+        double wi[3] = {0.0, 0.0, 0.0};
+        if (i >= n || cnt > kTapeWidth) {
+            raise_error(b.g, kErrInternal);
+        } else {
+            const SimGrid& G = b.sims[0];
+            const V4<T>* __restrict__ tpos = static_cast<const V4<T>*>(tp.pos);
+            const V4<T> p = tpos[t];
+            const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
+            const double ri = 0.5 * fabs(double(p.w));
+            ForceSum acc;
+            for (uint32_t r = 0; r < cnt; ++r) {
+                const uint32_t c = tp.list[size_t(r) * n + t];
+                add_term<true>(acc, pair_term<T>(xi, yi, zi, ri, tpos[min(c, n - 1u)], G.k, G.gamma));
+            }
+            adjoint_w(G, acc, lam, i, wi, gk, gg);
+        }
+        for (int a = 0; a < 3; ++a) w[3 * size_t(t) + a] = wi[a];
+    }
+    block_partials(b.partials, b.partial_cap, gk, gg);
+}
+
+// k_adj_gather on a complete tape: lambda_m + sum_j A_mj (w_m - w_j) over the
+// listed contacts, in their order.
+template <class T>
+__global__ __launch_bounds__(kAdjThreads) void k_adj_tape_gather(Buffers<T> b, TapeStep tp,
+                                                                  const double* __restrict__ lam,
+                                                                  const double* __restrict__ w,
+                                                                  double* __restrict__ lam_out) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, n = b.n;
+    if (t >= n) return;
+    const uint32_t m = tp.perm[t], cnt = tp.cnt[t];
+    if (m >= n || cnt > kTapeWidth) {
+        raise_error(b.g, kErrInternal);
+        return;
+    }
+    const SimGrid& G = b.sims[0];
+    const V4<T>* __restrict__ tpos = static_cast<const V4<T>*>(tp.pos);
+    const V4<T> p = tpos[t];
+    const double xm = double(p.x), ym = double(p.y), zm = double(p.z);
+    const double rm = 0.5 * fabs(double(p.w));
+    double acc[3], wm[3];
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = lam[3 * size_t(m) + a];
+        wm[a] = w[3 * size_t(t) + a];
+    }
+    for (uint32_t r = 0; r < cnt; ++r) {
+        const uint32_t c = tp.list[size_t(r) * n + t];
+        double o[3];
+        gather_term<T>(b, G, xm, ym, zm, rm, wm, w, tpos[min(c, n - 1u)], n + c, o);
+        for (int a = 0; a < 3; ++a) acc[a] += o[a];
+    }
+    for (int a = 0; a < 3; ++a) lam_out[3 * size_t(m) + a] = acc[a];
+}
+
 // dparams[0..1] += the block partials, summed in block order by one block.
 __global__ __launch_bounds__(kAdjThreads) void k_adj_finish(const double* __restrict__ partials, int nblocks,
                                                              double* dparams) {
@@ -250,6 +380,22 @@ void launch_adj_gather(const Buffers<T>& b, int pos_cur, const double* lam, cons
 }
 
 template <class T>
+void launch_adj_tape(const Buffers<T>& b, const TapeStep& tp, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_tape<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b, tp);
+}
+
+template <class T>
+void launch_adj_tape_w(const Buffers<T>& b, const TapeStep& tp, const double* lam, double* w, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_tape_w<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), 0, s, b, tp, lam, w);
+}
+
+template <class T>
+void launch_adj_tape_gather(const Buffers<T>& b, const TapeStep& tp, const double* lam, const double* w,
+                            double* lam_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_tape_gather<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), 0, s, b, tp, lam, w, lam_out);
+}
+
+template <class T>
 void launch_adj_finish(const Buffers<T>& b, int nblocks, double* dparams, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_finish, dim3(1), dim3(kAdjThreads), 0, s, b.partials, nblocks, dparams);
 }
@@ -258,7 +404,12 @@ void launch_adj_finish(const Buffers<T>& b, int nblocks, double* dparams, hipStr
     template void launch_adj_w<T>(const Buffers<T>&, int, const double*, double*, hipStream_t);       \
     template void launch_adj_gather<T>(const Buffers<T>&, int, const double*, const double*, double*, \
                                        hipStream_t);                                                  \
-    template void launch_adj_finish<T>(const Buffers<T>&, int, double*, hipStream_t);
+    template void launch_adj_finish<T>(const Buffers<T>&, int, double*, hipStream_t);                 \
+    template void launch_adj_tape<T>(const Buffers<T>&, const TapeStep&, hipStream_t);                 \
+    template void launch_adj_tape_w<T>(const Buffers<T>&, const TapeStep&, const double*, double*,     \
+                                       hipStream_t);                                                  \
+    template void launch_adj_tape_gather<T>(const Buffers<T>&, const TapeStep&, const double*,         \
+                                            const double*, double*, hipStream_t);
 
 ABM_INSTANTIATE(float)
 ABM_INSTANTIATE(double)

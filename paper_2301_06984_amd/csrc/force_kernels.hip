@@ -31,6 +31,10 @@ constexpr int kMaxBlockSims = 4;
 // positions' box extent is reduced here for the next step's grid: each wave
 // folds into the block's LDS copy, and the block's last wave to finish adds
 // it to the global accumulators, so no wave waits for the others.
+// With TAPE (one simulation, static test off, no re-layout, a full build),
+// the step also writes its contact tape: each agent's contacts, in the order
+// their terms are summed, with its position and storage index, by canonical
+// slot (the adjoint's reverse step reads it instead of walking a grid).
 // At 96 VGPRs or fewer a SIMD holds 5 waves of this kernel (4 above); the
 // hint asks the compiler for that.
 #ifndef ABM_FORCE_WAVES_PER_EU
@@ -39,9 +43,10 @@ constexpr int kMaxBlockSims = 4;
 template <int CH>
 constexpr bool two_chunks() { return CH == 2; }
 
-template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT, int CH>
+template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT, int CH, bool TAPE = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_WAVES_PER_EU))) void k_force(
     Buffers<T> b, StepArgs a, uint32_t run, uint32_t first_chunk) {
+    static_assert(!TAPE || (!BATCHED && !STATIC_ON && !RELAYOUT), "tapes cover the adjoint's steps only");
     extern __shared__ __align__(16) unsigned char s_walk[];
     __shared__ int32_t s_box[kMaxBlockSims][6];
     __shared__ int s_sims[kMaxBlockSims];
@@ -198,7 +203,31 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
         // simulations) and the 4-wide walk (one or more agents per box)
         if (!walks) P.mask = 0u;
         ForceSum acc;
-        force_of<CH, T, false, BATCHED || CH == 4>(b, *Gp, p, P, L, acc);
+        uint32_t tcnt = 0;   // contacts taped (TAPE; a full build: canonical slot u - n)
+        auto tape = [&](uint32_t k) {
+            if constexpr (TAPE) {
+                for (uint32_t r = 0; r < k; ++r) {
+                    const uint32_t uj = L.queue[r * bs + threadIdx.x];
+                    if (uj < n) raise_error(b.g, kErrInternal);
+                    if (append && tcnt < kTapeWidth) a.tape.list[size_t(tcnt) * n + (u - n)] = uj - n;
+                    ++tcnt;
+                }
+            }
+        };
+        force_of<CH, T, false, BATCHED || CH == 4>(b, *Gp, p, P, L, acc, tape);
+        if constexpr (TAPE) {
+            if (inc) raise_error(b.g, kErrInternal);
+            // a grid that overflowed leaves the tape incomplete
+            if (active && !Gp->valid) tcnt = 0xFFFFFFFFu;
+            if (active && append && Gp->valid) {
+                a.tape.cnt[u - n] = tcnt;
+                a.tape.perm[u - n] = i;
+                static_cast<V4<T>*>(a.tape.pos)[u - n] = p;
+            }
+            uint32_t most = tcnt;   // one atomic per wave
+            for (int d = 32; d >= 1; d >>= 1) most = max(most, uint32_t(__shfl_xor(int(most), d, 64)));
+            if (lane_id() == 0 && most > 0) atomicMax(a.tape.worst, most);
+        }
         // ---- after the walk, per agent
         if (active && Gp->valid) {
             const SimGrid& G = *Gp;
@@ -422,7 +451,7 @@ void launch_fold_parts(const Buffers<T>& b, uint32_t nparts, int parity, hipStre
                        parity ^ 1, parity);
 }
 
-template <class T, bool S, bool K, bool R, int CH>
+template <class T, bool S, bool K, bool R, int CH, bool TAPE = false>
 static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
     const int bs = a.block_size;
     const uint32_t nb = (b.n + bs - 1) / bs;
@@ -432,13 +461,18 @@ static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s
     const uint32_t blocks = two_chunks<CH>() ? nb : 2u * nb - first;
     const uint32_t run = xcd_run(blocks);
     const uint32_t grid = xcd_grid(blocks, run);   // <= force_part_capacity(n): nb <= ceil(n / 64), 8 run <= 512
-    hipLaunchKernelGGL((k_force<T, S, K, R, CH>), dim3(grid), dim3(bs), walk_lds_bytes(bs), s, b, a, run, first);
+    hipLaunchKernelGGL((k_force<T, S, K, R, CH, TAPE>), dim3(grid), dim3(bs), walk_lds_bytes(bs), s, b, a, run,
+                       first);
     if (!S) launch_fold_parts(b, grid, a.parity, s);
 }
 
 template <class T, int CH>
 static void launch_force_c(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
     const int v = (b.sim_of ? 4 : 0) | (a.detect_static ? 2 : 0) | (a.relayout ? 1 : 0);
+    if (a.tape.pos && v == 0) {   // the host tapes no other kind of step
+        launch_force_v<T, false, false, false, CH, true>(b, a, s);
+        return;
+    }
     switch (v) {
         case 0: launch_force_v<T, false, false, false, CH>(b, a, s); break;
         case 1: launch_force_v<T, false, false, true, CH>(b, a, s); break;

@@ -337,6 +337,25 @@ __device__ __forceinline__ PairTerm pair_term(double xi, double yi, double zi, d
     return t;
 }
 
+// Adds one pair term to F_i (and, with PARAM_GRADS, to dF_i/dk and
+// dF_i/dgamma); every walk that sums pair terms adds them through this.
+template <bool PARAM_GRADS>
+__device__ __forceinline__ void add_term(ForceSum& acc, const PairTerm& t) {
+    acc.fx += t.fx;
+    acc.fy += t.fy;
+    acc.fz += t.fz;
+    acc.nnz += t.nonzero ? 1u : 0u;
+    if (PARAM_GRADS) {
+        const double ux = t.ex / t.dist, uy = t.ey / t.dist, uz = t.ez / t.dist;
+        acc.kx += t.delta * ux;
+        acc.ky += t.delta * uy;
+        acc.kz += t.delta * uz;
+        acc.gx -= t.sr * ux;
+        acc.gy -= t.sr * uy;
+        acc.gz -= t.sr * uz;
+    }
+}
+
 // F_i over the neighbours j (|e|^2 < R^2) in contact (0 < |e| < r_i + r_j),
 // summed in ascending slot order.
 //
@@ -356,10 +375,15 @@ __device__ __forceinline__ PairTerm pair_term(double xi, double yi, double zi, d
 // however unevenly the contacts fall.
 //
 // sp is the position source the pieces and queue rows index, last its last
-// readable index.
-template <int CH, class T, bool PARAM_GRADS, bool SHARE = false>
+// readable index.  emit(k) sees each batch of contacts, queue rows [0, k),
+// before their terms are added: all of them, in the order they are summed.
+struct NoEmit {
+    __device__ __forceinline__ void operator()(uint32_t) const {}
+};
+template <int CH, class T, bool PARAM_GRADS, bool SHARE = false, class Emit = NoEmit>
 __device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uint32_t last, const SimGrid& G,
-                                         const V4<T>& p, const Pieces& P, const WalkLds& L, ForceSum& acc) {
+                                         const V4<T>& p, const Pieces& P, const WalkLds& L, ForceSum& acc,
+                                         Emit emit = Emit{}) {
     static_assert(!(SHARE && PARAM_GRADS), "shared pair terms carry the force only");
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
@@ -402,6 +426,7 @@ __device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uin
     };
     // this lane's contacts, rows [0, kept), in order; four positions requested together
     auto own_terms = [&]() {
+        emit(kept);
         for (uint32_t x0 = 0; x0 < kept; x0 += 4) {
             V4<T> pj4[4];
 #pragma unroll
@@ -409,20 +434,7 @@ __device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uin
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 if (x0 + c >= kept) break;
-                const PairTerm t = pair_term<T>(xi, yi, zi, ri, pj4[c], k, gamma);
-                acc.fx += t.fx;
-                acc.fy += t.fy;
-                acc.fz += t.fz;
-                acc.nnz += t.nonzero ? 1u : 0u;
-                if (PARAM_GRADS) {
-                    const double ux = t.ex / t.dist, uy = t.ey / t.dist, uz = t.ez / t.dist;
-                    acc.kx += t.delta * ux;
-                    acc.ky += t.delta * uy;
-                    acc.kz += t.delta * uz;
-                    acc.gx -= t.sr * ux;
-                    acc.gy -= t.sr * uy;
-                    acc.gz -= t.sr * uz;
-                }
+                add_term<PARAM_GRADS>(acc, pair_term<T>(xi, yi, zi, ri, pj4[c], k, gamma));
             }
         }
         kept = 0;
@@ -450,6 +462,7 @@ __device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uin
     if constexpr (!SHARE) {
         own_terms();
     } else {
+        emit(kept);
         // the wave's contacts: lane l's rows [0, kept) are pairs [off, off +
         // kept) of the wave, pair x evaluated by lane x mod 64 in round x / 64
         const uint32_t lane = uint32_t(lane_id()), wbase = tid - lane;
@@ -504,10 +517,10 @@ __device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uin
 }
 
 // force_of over the grid's loose position array.
-template <int CH, class T, bool PARAM_GRADS, bool SHARE = false>
+template <int CH, class T, bool PARAM_GRADS, bool SHARE = false, class Emit = NoEmit>
 __device__ __forceinline__ void force_of(const Buffers<T>& b, const SimGrid& G, const V4<T>& p, const Pieces& P,
-                                         const WalkLds& L, ForceSum& acc) {
-    force_of<CH, T, PARAM_GRADS, SHARE>(gpos_ptr(b), 2u * b.n - 1u, G, p, P, L, acc);
+                                         const WalkLds& L, ForceSum& acc, Emit emit = Emit{}) {
+    force_of<CH, T, PARAM_GRADS, SHARE, Emit>(gpos_ptr(b), 2u * b.n - 1u, G, p, P, L, acc, emit);
 }
 
 // The walk's pre-test and exact test for agent p, keeping its contacts

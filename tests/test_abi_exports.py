@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(libabm):
 
 def test_version_and_defaults(libabm):
     L = libabm.lib()
-    assert L.abm_abi_version() == libabm.ABI_VERSION == 4
+    assert L.abm_abi_version() == libabm.ABI_VERSION == 5
     p = libabm.default_params()
     assert p.order == libabm.ABM_ORDER_MORTON and libabm.default_params(order="hilbert").order == 1
     assert (p.k, p.gamma, p.mu, p.f_adh, p.delta_max) == (2.0, 1.0, 0.1, 0.0, 3.0)

@@ -20,14 +20,16 @@ def case(n, seed, dtype=np.float64):
     return pos, diam, target
 
 
-def gpu_grad(pos, diam, target, steps, ckpt, **kw):
+def gpu_grad(pos, diam, target, steps, ckpt, tapes="auto", info=None, **kw):
     sim = make_sim(pos, diam, **kw)
-    sim.forward_record(steps, ckpt)
+    sim.forward_record(steps, ckpt, tapes=tapes)
     xT = sim.query("positions").double()
     t = torch.from_numpy(target).cuda()
     n = pos.shape[0]
     loss = float(((xT - t) ** 2).mean())
     gx0, gp = sim.backward(2.0 * (xT - t) / (3 * n))
+    if info is not None:
+        info.update(sim.record_info())
     return loss, gx0.cpu().numpy(), gp.cpu().numpy(), xT.cpu().numpy()
 
 
@@ -111,3 +113,42 @@ def test_state_restored_after_backward():
     ref = make_sim(pos, diam)
     ref.step(8)
     np.testing.assert_array_equal(sim.query("positions").cpu().numpy(), ref.query("positions").cpu().numpy())
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_contact_tapes_bitwise(dtype):
+    """The reverse steps on contact tapes (every step's, or each recomputed
+    segment's) give the walked grid's result bit for bit."""
+    pos, diam, target = case(3000, 6, dtype)
+    res = {}
+    for tapes, mode in (("none", 0), ("segment", 1), ("all", 2)):
+        note(f"adjoint tapes={tapes} {dtype.__name__}")
+        info = {}
+        res[tapes] = gpu_grad(pos, diam, target, 12, 5, tapes=tapes, info=info)
+        assert info["tapes"] == mode, info
+        assert info["taped_reverse_steps"] == (0 if mode == 0 else 12), info
+        assert 0 < info["worst_contacts"] <= 32 or mode == 0, info
+    for tapes in ("segment", "all"):
+        for a, b in zip(res["none"], res[tapes]):
+            np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_contact_tape_overflow_falls_back():
+    """A cluster where agents touch more than 32 others: the record cannot tape
+    every step, the backward tapes each recomputed segment and walks the grid
+    of the steps whose tape is incomplete; the result is still bit for bit that
+    of the walked grids."""
+    pos, diam, target = case(2000, 7)
+    g = np.random.default_rng(8)
+    centre = pos.mean(axis=0)
+    v = g.normal(size=(48, 3))
+    v *= (g.uniform(0.0, 1.0, size=(48, 1)) ** (1 / 3) * 2.5) / np.linalg.norm(v, axis=1, keepdims=True)
+    pos[:48] = centre + v   # 48 spheres of diameter >= 8 within 5 of each other
+    note("adjoint tape overflow")
+    info = {}
+    ref = gpu_grad(pos, diam, target, 10, 4, tapes="none")
+    got = gpu_grad(pos, diam, target, 10, 4, tapes="all", info=info)
+    assert info["tapes"] == 1 and info["worst_contacts"] > 32, info
+    assert 0 < info["taped_reverse_steps"] < 10, info
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(np.asarray(a), np.asarray(b))

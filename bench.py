@@ -441,6 +441,9 @@ def main():
                               peak_note="256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz"),
                     counters=os.path.relpath(COUNTERS_FILE, ROOT))
     roof = {"bound": bound or "alu", **roof}
+    if roof["bound"] == "alu":
+        roof["bound_note"] = ("achieved/peak/frac: the step's algorithmic bytes per launch against the HBM peak; the "
+                              "kernel is bound by VALU issue, whose fraction is valu.frac")
     if rec is None:
         roof["bound_note"] = "counter record absent or stale for these kernel sources: bound as last measured"
     log(f"headline {value:.3e} agent-steps/s, {ms_step:.3f} ms/step, force {force_ms:.4f} ms, phases {phases}")

@@ -89,7 +89,10 @@ typedef struct abm_params {
     int32_t block_size;        /* threads per block of the force kernel: 64..1024, multiple of 64; 0 = 256 */
     int32_t keep_forces;       /* store F_i each step so ABM_FIELD_FORCES can be queried */
     int32_t walk_chunk;        /* candidates the neighbour walk tests together: 2 or 4; 0 = chosen at init
-                                  from the agents per box (4 at one or more, else 2) */
+                                  from how densely the agents fill their boxes: 4 at 1.6 or more agents per
+                                  occupied box of the initial grid (one simulation; about one per box where
+                                  agents spread uniformly), or at one or more per box of the extent (a batch),
+                                  else 2 */
     int32_t order;             /* ABM_ORDER_MORTON (default) or ABM_ORDER_HILBERT; fixed at init, the same for
                                   every simulation of a batch.  It sets the canonical order, and with it the
                                   order in which each agent's pair terms are summed */

@@ -480,11 +480,12 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     const int rc = read_error(c, true);   // also keeps the host arrays alive until the copies are done
     if (rc != ABM_OK) return bail(rc);
     // the walk width: 4 where an agent's boxes hold more agents (longer slot
-    // ranges), else 2.  One simulation: 4 at two or more agents per occupied
+    // ranges), else 2.  One simulation: 4 at 1.6 or more agents per occupied
     // box of its initial grid (a bitmap of the boxes in the bytes of the
-    // per-agent records, free before the first grid build); otherwise, or
-    // when the bitmap does not fit, 4 at one or more agents per box of the
-    // extent
+    // per-agent records, free before the first grid build); for agents
+    // spread uniformly that is one agent per box, clustered agents count by
+    // the boxes they fill.  Otherwise, or when the bitmap does not fit, 4 at
+    // one or more agents per box of the extent
     c->walk_chunk = p0.walk_chunk;
     bool chosen = false;
     if (c->walk_chunk == 0 && nsims == 1) {
@@ -515,7 +516,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
                 hipMemcpy(&occupied, out, 8, hipMemcpyDeviceToHost) != hipSuccess)
                 return bail(fail(ABM_E_HIP, "occupied-box count failed"));
             if (occupied > 0) {
-                c->walk_chunk = double(n) >= 2.0 * double(occupied) ? 4 : 2;
+                c->walk_chunk = double(n) >= 1.6 * double(occupied) ? 4 : 2;
                 chosen = true;
             }
         }

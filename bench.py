@@ -50,7 +50,7 @@ COUNTERS_FILE = os.path.join(PROFILES, "k_force_headline_counters.json")
 FORCE_SOURCES = ["force_kernels.hip", "force_loop.h", "abm_device.h", "abm_internal.h", "hilbert_order.h"]
 # the force kernel instantiation of the roofline run: FP32 state, one
 # simulation, static test off, re-layout on, 2-wide walk
-ROOF_KERNEL = "abm::k_force<float, false, false, true, 2, false>"
+ROOF_KERNEL = "abm::k_force<float, false, false, true, 2, false, false>"
 
 
 def force_sources_sha():

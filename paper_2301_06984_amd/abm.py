@@ -20,7 +20,7 @@ ABM_OK, ABM_E_INVAL, ABM_E_NONFINITE, ABM_E_GRID, ABM_E_WORKSPACE, ABM_E_HIP, AB
     0, -1, -2, -3, -4, -5, -6, -7
 ABM_F32, ABM_F64 = 0, 1
 ABM_ORDER_MORTON, ABM_ORDER_HILBERT = 0, 1
-ABI_VERSION = 5   # the layout of the structs below
+ABI_VERSION = 6   # the layout of the structs below
 FIELD = dict(positions=0, forces=1, moved=2, static=3, nnz=4, key=5, perm=6, cell_start=7, extent=8,
              storage_ids=9, neighbor_count=10, neighbors=11, diameters=12)
 EXTENT_SCRATCH_BYTES = 1024
@@ -41,7 +41,7 @@ class abm_params(C.Structure):
                 ("delta_max", C.c_double), ("interaction_radius", C.c_double), ("cell_factor", C.c_double),
                 ("precision", C.c_int32), ("detect_static", C.c_int32), ("sort_every", C.c_int32),
                 ("block_size", C.c_int32), ("keep_forces", C.c_int32), ("walk_chunk", C.c_int32),
-                ("order", C.c_int32), ("super_fraction", C.c_double)]
+                ("order", C.c_int32), ("share_terms", C.c_int32), ("super_fraction", C.c_double)]
 
 
 class abm_extent(C.Structure):

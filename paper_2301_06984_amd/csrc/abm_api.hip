@@ -122,6 +122,7 @@ struct abm_ctx {
     std::vector<int64_t> offsets;
     abm_params params{};
     int walk_chunk = 2;      // candidates the neighbour walk tests together (2 or 4)
+    bool share = false;      // the 2-wide walk of one simulation shares out the wave's pair terms
     int cs_cur = 0;          // which cell_start copy the next grid build writes (the other holds the last)
     bool inc_ready = false;  // agents are stored in the last grid's canonical order, positions from the step
     bool graph_inc_after = false;
@@ -258,6 +259,7 @@ bool valid_params(const abm_params* p, std::string* why) {
         return *why = "block_size must be 0 or a multiple of 64 in [64, 1024]", false;
     if (p->walk_chunk != 0 && p->walk_chunk != 2 && p->walk_chunk != 4)
         return *why = "walk_chunk must be 0, 2 or 4", false;
+    if (p->share_terms < 0 || p->share_terms > 2) return *why = "share_terms must be 0, 1 or 2", false;
     if (p->order != ABM_ORDER_MORTON && p->order != ABM_ORDER_HILBERT)
         return *why = "order must be ABM_ORDER_MORTON or ABM_ORDER_HILBERT", false;
     if (!(p->super_fraction >= 0.0 && p->super_fraction <= 1.0))
@@ -335,6 +337,7 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, int timed = 0) {
     a.keep_forces = c->params.keep_forces != 0;
     a.block_size = block_size_of(c->params);
     a.walk_chunk = c->walk_chunk;
+    a.share = c->share;
     a.full_only = !c->inc_ready;
     set_grid_pos<T>(c, c->pos_cur);
     launch_setup<T>(b, parity, c->inc_ready, c->stream);
@@ -479,16 +482,26 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     if (hipGetLastError() != hipSuccess) return bail(fail(ABM_E_HIP, "init kernels failed to launch"));
     const int rc = read_error(c, true);   // also keeps the host arrays alive until the copies are done
     if (rc != ABM_OK) return bail(rc);
-    // the walk width: 4 where an agent's boxes hold more agents (longer slot
-    // ranges), else 2.  One simulation: 4 at 1.6 or more agents per occupied
-    // box of its initial grid (a bitmap of the boxes in the bytes of the
-    // per-agent records, free before the first grid build); for agents
-    // spread uniformly that is one agent per box, clustered agents count by
-    // the boxes they fill.  Otherwise, or when the bitmap does not fit, 4 at
-    // one or more agents per box of the extent
+    // The walk: its width, 4 where an agent's boxes hold many agents (long
+    // slot ranges), else 2; and for the 2-wide walk of one simulation,
+    // whether the wave shares out its pair terms (where agents have several
+    // contacts).  One simulation: from the agents per occupied box of its
+    // initial grid (a bitmap of the boxes in the bytes of the per-agent
+    // records, free before the first grid build).  With 2^20 agents or more
+    // (enough waves that the kernel is bound by issue rather than by the
+    // latency of one wave's walk): 4-wide at 4 or more (clustered agents: no
+    // uniform packing reaches 3), else 2-wide, shared at 1.2 or more.  With
+    // fewer: 4-wide at 1.6 or more (the shorter walk of each wave), else
+    // 2-wide, each lane adding its own terms.  Otherwise, or when the bitmap
+    // does not fit, from the agents per box of the extent: 4-wide at one or
+    // more (a batch, which always shares), shared at 0.4 or more with 2^20
+    // agents (about 1.2 per occupied box where agents spread uniformly).
     c->walk_chunk = p0.walk_chunk;
+    c->share = p0.share_terms == 2;
+    const bool pick_width = c->walk_chunk == 0, pick_share = p0.share_terms == 0 && nsims == 1;
+    const bool many = n >= (int64_t(1) << 20);
     bool chosen = false;
-    if (c->walk_chunk == 0 && nsims == 1) {
+    if ((pick_width || pick_share) && nsims == 1) {
         std::vector<int32_t> rep(size_t(kReplicas) * 6);
         if (hipMemcpy(rep.data(), b.bbox_rep, rep.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
             return bail(fail(ABM_E_HIP, "extent read-back failed"));
@@ -516,12 +529,14 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
                 hipMemcpy(&occupied, out, 8, hipMemcpyDeviceToHost) != hipSuccess)
                 return bail(fail(ABM_E_HIP, "occupied-box count failed"));
             if (occupied > 0) {
-                c->walk_chunk = double(n) >= 1.6 * double(occupied) ? 4 : 2;
+                const double per_occupied = double(n) / double(occupied);
+                if (pick_width) c->walk_chunk = per_occupied >= (many ? 4.0 : 1.6) ? 4 : 2;
+                if (pick_share) c->share = many && per_occupied >= 1.2;
                 chosen = true;
             }
         }
     }
-    if (c->walk_chunk == 0 && !chosen) {
+    if ((pick_width || pick_share) && !chosen) {
         std::vector<int32_t> rep(size_t(kReplicas) * nsims * 6);
         if (hipMemcpy(rep.data(), b.bbox_rep, rep.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
             return bail(fail(ABM_E_HIP, "extent read-back failed"));
@@ -537,7 +552,8 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
             for (int a = 0; a < 3; ++a) nb *= hi[a] >= lo[a] ? double(hi[a]) - double(lo[a]) + 1.0 : 1.0;
             boxes_total += nb;
         }
-        c->walk_chunk = double(n) >= boxes_total ? 4 : 2;
+        if (pick_width) c->walk_chunk = double(n) >= boxes_total ? 4 : 2;
+        if (pick_share) c->share = many && double(n) >= 0.4 * boxes_total;
     }
     *out = c;
     return ABM_OK;
@@ -1329,6 +1345,8 @@ int abm_set_params(abm_ctx* c, const abm_params* p) {
     c->params.keep_forces = keep;
     if (p->walk_chunk) c->walk_chunk = p->walk_chunk;
     c->params.walk_chunk = p->walk_chunk;
+    if (p->share_terms) c->share = p->share_terms == 2;
+    c->params.share_terms = p->share_terms;
     HIP_TRY(hipGetLastError());
     return ABM_OK;
 }

@@ -219,6 +219,7 @@ struct StepArgs {
     bool full_only;         // the grid is a full build (no agent in storage slots)
     int block_size;
     int walk_chunk;         // 2 or 4 candidate slots tested together by the neighbour walk
+    bool share;             // the 2-wide walk of one simulation shares out the wave's pair terms
     const uint32_t* cs;     // this grid's super-box starts
     TapeStep tape;          // the step's contacts are taped here (pos null: not taped)
 };

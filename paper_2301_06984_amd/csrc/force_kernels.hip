@@ -43,7 +43,7 @@ constexpr int kMaxBlockSims = 4;
 template <int CH>
 constexpr bool two_chunks() { return CH == 2; }
 
-template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT, int CH, bool TAPE = false>
+template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT, int CH, bool TAPE = false, bool SHARE = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_WAVES_PER_EU))) void k_force(
     Buffers<T> b, StepArgs a, uint32_t run, uint32_t first_chunk) {
     static_assert(!TAPE || (!BATCHED && !STATIC_ON && !RELAYOUT), "tapes cover the adjoint's steps only");
@@ -200,7 +200,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
         // ---- the walk and the pair terms, with every lane of the wave (a lane
         // that does not walk has no pieces), so that the wave can share out
         // its pair terms where contacts are many and uneven: batched (dense
-        // simulations) and the 4-wide walk (one or more agents per box)
+        // simulations), the 4-wide walk (clustered agents) and, with SHARE,
+        // the 2-wide walk of one simulation (agents with several contacts)
         if (!walks) P.mask = 0u;
         ForceSum acc;
         uint32_t tcnt = 0;   // contacts taped (TAPE; a full build: canonical slot u - n)
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
                 }
             }
         };
-        force_of<CH, T, false, BATCHED || CH == 4>(b, *Gp, p, P, L, acc, tape);
+        force_of<CH, T, false, BATCHED || CH == 4 || SHARE>(b, *Gp, p, P, L, acc, tape);
         if constexpr (TAPE) {
             if (inc) raise_error(b.g, kErrInternal);
             // a grid that overflowed leaves the tape incomplete
@@ -451,7 +452,7 @@ void launch_fold_parts(const Buffers<T>& b, uint32_t nparts, int parity, hipStre
                        parity ^ 1, parity);
 }
 
-template <class T, bool S, bool K, bool R, int CH, bool TAPE = false>
+template <class T, bool S, bool K, bool R, int CH, bool TAPE = false, bool SH = false>
 static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
     const int bs = a.block_size;
     const uint32_t nb = (b.n + bs - 1) / bs;
@@ -461,27 +462,40 @@ static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s
     const uint32_t blocks = two_chunks<CH>() ? nb : 2u * nb - first;
     const uint32_t run = xcd_run(blocks);
     const uint32_t grid = xcd_grid(blocks, run);   // <= force_part_capacity(n): nb <= ceil(n / 64), 8 run <= 512
-    hipLaunchKernelGGL((k_force<T, S, K, R, CH, TAPE>), dim3(grid), dim3(bs), walk_lds_bytes(bs), s, b, a, run,
+    hipLaunchKernelGGL((k_force<T, S, K, R, CH, TAPE, SH>), dim3(grid), dim3(bs), walk_lds_bytes(bs), s, b, a, run,
                        first);
     if (!S) launch_fold_parts(b, grid, a.parity, s);
+}
+
+// the shared pair terms of the 2-wide walk of one simulation are a variant of
+// their own (the 4-wide walk and a batch always share)
+template <class T, bool S, bool K, bool R, int CH, bool TAPE = false>
+static void launch_force_s(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
+    if constexpr (CH == 2 && !S) {
+        if (a.share) {
+            launch_force_v<T, S, K, R, CH, TAPE, true>(b, a, s);
+            return;
+        }
+    }
+    launch_force_v<T, S, K, R, CH, TAPE>(b, a, s);
 }
 
 template <class T, int CH>
 static void launch_force_c(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
     const int v = (b.sim_of ? 4 : 0) | (a.detect_static ? 2 : 0) | (a.relayout ? 1 : 0);
     if (a.tape.pos && v == 0) {   // the host tapes no other kind of step
-        launch_force_v<T, false, false, false, CH, true>(b, a, s);
+        launch_force_s<T, false, false, false, CH, true>(b, a, s);
         return;
     }
     switch (v) {
-        case 0: launch_force_v<T, false, false, false, CH>(b, a, s); break;
-        case 1: launch_force_v<T, false, false, true, CH>(b, a, s); break;
-        case 2: launch_force_v<T, false, true, false, CH>(b, a, s); break;
-        case 3: launch_force_v<T, false, true, true, CH>(b, a, s); break;
-        case 4: launch_force_v<T, true, false, false, CH>(b, a, s); break;
-        case 5: launch_force_v<T, true, false, true, CH>(b, a, s); break;
-        case 6: launch_force_v<T, true, true, false, CH>(b, a, s); break;
-        default: launch_force_v<T, true, true, true, CH>(b, a, s); break;
+        case 0: launch_force_s<T, false, false, false, CH>(b, a, s); break;
+        case 1: launch_force_s<T, false, false, true, CH>(b, a, s); break;
+        case 2: launch_force_s<T, false, true, false, CH>(b, a, s); break;
+        case 3: launch_force_s<T, false, true, true, CH>(b, a, s); break;
+        case 4: launch_force_s<T, true, false, false, CH>(b, a, s); break;
+        case 5: launch_force_s<T, true, false, true, CH>(b, a, s); break;
+        case 6: launch_force_s<T, true, true, false, CH>(b, a, s); break;
+        default: launch_force_s<T, true, true, true, CH>(b, a, s); break;
     }
 }
 

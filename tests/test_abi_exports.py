@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(libabm):
 
 def test_version_and_defaults(libabm):
     L = libabm.lib()
-    assert L.abm_abi_version() == libabm.ABI_VERSION == 5
+    assert L.abm_abi_version() == libabm.ABI_VERSION == 6
     p = libabm.default_params()
     assert p.order == libabm.ABM_ORDER_MORTON and libabm.default_params(order="hilbert").order == 1
     assert (p.k, p.gamma, p.mu, p.f_adh, p.delta_max) == (2.0, 1.0, 0.1, 0.0, 3.0)
@@ -50,7 +50,7 @@ def test_version_and_defaults(libabm):
 
 
 def test_struct_sizes_match_header(libabm):
-    assert C.sizeof(libabm.abm_params) == 7 * 8 + 7 * 4 + 4 + 8   # the ints padded to 8 bytes, then a double
+    assert C.sizeof(libabm.abm_params) == 7 * 8 + 8 * 4 + 8   # seven doubles, eight ints, a double
     assert C.sizeof(libabm.abm_extent) == 2 * 8 + 7 * 8
     assert C.sizeof(libabm.abm_stats) == 3 * 8 + 2 * 4 + 5 * 8
 

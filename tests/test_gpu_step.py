@@ -182,14 +182,17 @@ def test_determinism_and_layout_invariance():
     for name, kw in [("a", dict(sort_every=1)), ("b", dict(sort_every=1)), ("never", dict(sort_every=0)),
                      ("every3", dict(sort_every=3)), ("bs64", dict(block_size=64)), ("bs1024", dict(block_size=1024)),
                      ("walk2", dict(walk_chunk=2)), ("walk4", dict(walk_chunk=4)),
-                     ("walk4static", dict(walk_chunk=4, detect_static=True))]:
+                     ("walk4static", dict(walk_chunk=4, detect_static=True)),
+                     ("walk2own", dict(walk_chunk=2, share_terms=1)), ("walk2shared", dict(walk_chunk=2, share_terms=2)),
+                     ("walk2sharednever", dict(walk_chunk=2, share_terms=2, sort_every=0)),
+                     ("walk2sharedstatic", dict(walk_chunk=2, share_terms=2, detect_static=True))]:
         note(f"layout variant {name}")
         sim = make_sim(w.pos, w.diam, **kw)
         sim.step(7)
         runs[name] = gpu_state(sim)
     for name, r in runs.items():
         np.testing.assert_array_equal(r["pos"], runs["a"]["pos"], err_msg=name)
-        if name != "walk4static":   # a static agent keeps the count of its last force evaluation
+        if "static" not in name:   # a static agent keeps the count of its last force evaluation
             np.testing.assert_array_equal(r["nnz"], runs["a"]["nnz"], err_msg=name)
 
 
@@ -395,16 +398,16 @@ def test_grid_after_many_steps(sort_every):
     assert_neighbors_equal(sim, before, w.diam, oracle.Params())
 
 
-@pytest.mark.parametrize("walk_chunk", [2, 4])
-def test_dense_packing_matches_oracle_bitwise(walk_chunk):
+@pytest.mark.parametrize("walk_chunk,share_terms", [(2, 1), (2, 2), (4, 0)])
+def test_dense_packing_matches_oracle_bitwise(walk_chunk, share_terms):
     # volume fraction 0.6 (the densest batch member): several contacts per
     # agent, so lanes flush full queues themselves mid-walk and the wave
     # shares out the rest; FP64, every step bit for bit against the oracle
     n = 5000
     side = (n * (np.pi / 6.0) * 1040.0 / 0.6) ** (1.0 / 3.0)   # E[d^3] = 1040 for d ~ U[8, 12]
     pos, diam = workloads.uniform_cube(n, side, (7, walk_chunk), dtype=np.float64)
-    note(f"dense packing walk{walk_chunk} n={n} side={side:.1f}")
-    sim = make_sim(pos, diam, walk_chunk=walk_chunk)
+    note(f"dense packing walk{walk_chunk} share{share_terms} n={n} side={side:.1f}")
+    sim = make_sim(pos, diam, walk_chunk=walk_chunk, share_terms=share_terms)
     st = oracle.State.initial(pos, diam)
     for t in range(4):
         oracle.step(st, oracle.Params())

@@ -468,7 +468,8 @@ class StepFn(torch.autograd.Function):
     """x_T = StepFn.apply(x0, diam, k, gamma, nsteps, ckpt_every, params_dict).
 
     Runs nsteps steps on the GPU from x0, recording a checkpoint every
-    ckpt_every steps; backward gives dL/dx0, dL/dk and dL/dgamma through the
+    ckpt_every steps and, where they fit in device memory, every step's
+    contact tape; backward gives dL/dx0, dL/dk and dL/dgamma through the
     hand-written reverse-mode kernels."""
 
     @staticmethod

@@ -671,6 +671,8 @@ def main():
                         by_tapes={t: dict(value=wa.n * wa.steps / o[0], ratio_vs_plain_forward=round(elp / o[0], 3),
                                           peak_device_bytes=o[2])
                                   for t, o in others.items()},
+                        plain_forward_note="the plain step without re-layout (sort_every 0), as a record runs: "
+                                           "storage indices stay fixed for the reverse steps",
                         same_gradients_all_modes=same, at_1e6_agents=at_1e6, peak_device_bytes=peak,
                         peak_note="workspace + forward record (with every step's contact tape) + dL/dx_T and "
                                   "dL/dx_0 (n x 3 doubles each)")

@@ -1432,9 +1432,15 @@ int abm_graph_launch(abm_ctx* c) {
     return c->precision == ABM_F64 ? graph_launch_impl<double>(c) : graph_launch_impl<float>(c);
 }
 
+// a record of every step's tapes must stay far below 2^63 bytes
+static bool record_fits(abm_ctx* c, int32_t nsteps) {
+    return double(rec_layout(c, 1, 1).tape_step + 4 * c->n * c->elem()) * double(nsteps) < 1e18;
+}
+
 int abm_record_bytes(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, int64_t* bytes) {
     if (int rc = check_ctx(c)) return rc;
     if (nsteps < 1 || ckpt_every < 1 || !bytes) return fail(ABM_E_INVAL, "bad arguments");
+    if (!record_fits(c, nsteps)) return fail(ABM_E_INVAL, "record too large");
     *bytes = rec_layout(c, nsteps, ckpt_every).total_all;
     return ABM_OK;
 }
@@ -1442,6 +1448,7 @@ int abm_record_bytes(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, int64_t* by
 int abm_record_sizes(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, int64_t* sizes) {
     if (int rc = check_ctx(c)) return rc;
     if (nsteps < 1 || ckpt_every < 1 || !sizes) return fail(ABM_E_INVAL, "bad arguments");
+    if (!record_fits(c, nsteps)) return fail(ABM_E_INVAL, "record too large");
     const RecLayout R = rec_layout(c, nsteps, ckpt_every);
     sizes[0] = R.total;
     sizes[1] = R.total_seg;
@@ -1461,6 +1468,7 @@ int abm_record_info(abm_ctx* c, int32_t* info) {
 int abm_forward_record(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, void* rec, int64_t rec_bytes) {
     if (int rc = check_ctx(c)) return rc;
     if (nsteps < 1 || ckpt_every < 1 || !rec) return fail(ABM_E_INVAL, "bad arguments");
+    if (!record_fits(c, nsteps)) return fail(ABM_E_INVAL, "record too large");
     if (c->nsims != 1) return fail(ABM_E_UNSUPPORTED, "the adjoint covers a single simulation");
     if (c->params.detect_static) return fail(ABM_E_UNSUPPORTED, "the adjoint needs detect_static off");
     if (reinterpret_cast<uintptr_t>(rec) % kAlign) return fail(ABM_E_INVAL, "record buffer must be 256-byte aligned");

@@ -365,7 +365,8 @@ int abm_graph_launch(abm_ctx* ctx);
  *     grid, in the order the force sums them (32 per agent at most); a
  *     reverse step that reads a complete tape needs no grid and no
  *     neighbour walk, and gives the same result, bit for bit.
- *   abm_forward_record: run nsteps steps from the current state, keeping the
+ *   abm_forward_record: run nsteps steps from the current state (re-laying
+ *     agents out every sort_every steps, as abm_step does), keeping the
  *     positions of every ckpt_every-th step in rec (device, rec_bytes of at
  *     least sizes[0], 256-byte aligned; the caller owns it and keeps it
  *     until the backward is done).  With rec_bytes >= sizes[2] it also tapes

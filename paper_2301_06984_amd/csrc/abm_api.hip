@@ -347,11 +347,11 @@ void enqueue_step(abm_ctx* c, bool allow_relayout, int timed = 0) {
     a.cs = last_grid_starts<T>(c);
     if (c->tape_next.pos) {
         // the step kernel tapes a full build of one simulation without the
-        // static test or a re-layout (every step the adjoint records)
-        if (c->nsims == 1 && !a.detect_static && !a.relayout && a.full_only)
+        // static test (every step the adjoint records)
+        if (c->nsims == 1 && !a.detect_static && a.full_only)
             a.tape = c->tape_next;
         else
-            launch_adj_tape<T>(b, c->tape_next, c->stream);
+            launch_adj_tape<T>(b, c->ids_cur, c->tape_next, c->stream);
         c->tape_next = TapeStep{};
     }
     if (ev && !all_phases) (void)hipEventRecord((*ev)[kTimedPhases - 1], c->stream);
@@ -811,7 +811,7 @@ TapeStep tape_at(abm_ctx* c, const RecLayout& R, char* base, int32_t k) {
     TapeStep tp;
     tp.pos = p;
     p += align_up(4 * c->n * c->elem());
-    tp.perm = reinterpret_cast<uint32_t*>(p);
+    tp.ids = reinterpret_cast<uint32_t*>(p);
     p += align_up(4 * c->n);
     tp.cnt = reinterpret_cast<uint32_t*>(p);
     p += align_up(4 * c->n);
@@ -840,16 +840,16 @@ int forward_record_impl(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, void* re
     c->recorded = false;
     c->rec_start = c->step;
     c->rec_worst = 0;
-    if (tapes == 2) {
-        HIP_TRY(hipMemsetAsync(base + R.worst, 0, 4 * size_t(nsteps), c->stream));
-        c->inc_ready = false;   // a taped step's grid is a full build (so are the later ones here)
-    }
+    if (tapes == 2) HIP_TRY(hipMemsetAsync(base + R.worst, 0, 4 * size_t(nsteps), c->stream));
     for (int32_t s = 0; s < nsteps; ++s) {
         if (s % ckpt_every == 0)
             launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.ckpt + pb * (s / ckpt_every)),
                                        c->stream);
-        if (tapes == 2) c->tape_next = tape_at(c, R, base, s);
-        int rc = do_steps<T>(c, 1, false);
+        if (tapes == 2) {
+            c->tape_next = tape_at(c, R, base, s);
+            c->inc_ready = false;   // a taped step's grid is a full build
+        }
+        int rc = do_steps<T>(c, 1, true);
         if (rc != ABM_OK) return rc;
     }
     launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.xT), c->stream);
@@ -877,12 +877,13 @@ int forward_record_impl(abm_ctx* c, int32_t nsteps, int32_t ckpt_every, void* re
 template <class T>
 void enqueue_tape_only(abm_ctx* c, const TapeStep& tp) {
     Buffers<T>& b = c->buf<T>();
+    c->inc_ready = false;   // a taped step's grid is a full build
     guard_stamps<T>(c, 1);
     set_grid_pos<T>(c, c->pos_cur);
     launch_setup<T>(b, int(c->step & 1), c->inc_ready, c->stream);
     launch_grid<T>(b, c->pos_cur, c->ids_cur, false, false, c->stream);
     swap_cell_start<T>(c);
-    launch_adj_tape<T>(b, tp, c->stream);
+    launch_adj_tape<T>(b, c->ids_cur, tp, c->stream);
     c->grid_ids = c->ids_cur;
     c->inc_ready = false;
     c->stamp_count += 1;
@@ -915,11 +916,11 @@ int backward_impl(abm_ctx* c, const double* dL_dxT, double* dL_dx0, double* dL_d
     double* lam = reinterpret_cast<double*>(base + R.lam);
     double* lam2 = reinterpret_cast<double*>(base + R.lam2);
     double* w = reinterpret_cast<double*>(base + R.w);
-    const uint32_t* ids = b.ids[c->ids_cur];
     const uint32_t n = uint32_t(c->n);
     hipStream_t s = c->stream;
     const int64_t end_step = c->step;
-    launch_permute3(ids, n, dL_dxT, lam, false, s);
+    // lambda is kept by id, as dL/dx_T and dL/dx_0 are
+    HIP_TRY(hipMemcpyAsync(lam, dL_dxT, 24 * size_t(n), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemsetAsync(dL_dparams, 0, 2 * sizeof(double), s));
     const int nblocks = adj_blocks(n);
     c->taped_reverse = 0;
@@ -933,8 +934,8 @@ int backward_impl(abm_ctx* c, const double* dL_dxT, double* dL_dx0, double* dL_d
     };
     auto reverse_walked = [&](const T* x_t) {
         load_and_grid<T>(c, x_t);
-        launch_adj_w<T>(b, c->pos_cur, lam, w, s);
-        launch_adj_gather<T>(b, c->pos_cur, lam, w, lam2, s);
+        launch_adj_w<T>(b, c->ids_cur, lam, w, s);
+        launch_adj_gather<T>(b, c->ids_cur, lam, w, lam2, s);
         launch_adj_finish<T>(b, nblocks, dL_dparams, s);
         std::swap(lam, lam2);
     };
@@ -957,8 +958,11 @@ int backward_impl(abm_ctx* c, const double* dL_dxT, double* dL_dx0, double* dL_d
             for (int32_t t = s0; t < s1; ++t) {
                 launch_unpack_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<T*>(base + R.seg + pb * (t - s0)), s);
                 if (t + 1 < s1) {
-                    if (taped) c->tape_next = tape_at(c, R, base, t - s0);
-                    int rc = do_steps<T>(c, 1, false);
+                    if (taped) {
+                        c->tape_next = tape_at(c, R, base, t - s0);
+                        c->inc_ready = false;   // a taped step's grid is a full build
+                    }
+                    int rc = do_steps<T>(c, 1, true);
                     if (rc != ABM_OK) return rc;
                 } else if (taped) {
                     enqueue_tape_only<T>(c, tape_at(c, R, base, t - s0));
@@ -977,7 +981,7 @@ int backward_impl(abm_ctx* c, const double* dL_dxT, double* dL_dx0, double* dL_d
             }
         }
     }
-    launch_permute3(ids, n, lam, dL_dx0, true, s);
+    HIP_TRY(hipMemcpyAsync(dL_dx0, lam, 24 * size_t(n), hipMemcpyDeviceToDevice, s));
     // restore the final state of the recorded run
     launch_load_positions<T>(b, c->pos_cur, c->ids_cur, reinterpret_cast<const T*>(base + R.xT), s);
     c->inc_ready = false;   // positions replaced outside the step

@@ -194,15 +194,16 @@ struct Buffers {
 };
 
 // The contact tape of one step (a full build): per canonical slot t, the
-// agent's position (as the grid holds it), its storage index and its
-// contacts' canonical slots in the order the force sums them (row r of
-// slot t at list[r * n + t], at most kTapeWidth rows); *worst gets the
-// largest contact count of the step (a tape with worst > kTapeWidth is
-// incomplete and not used).
+// agent's position (as the grid holds it), its id and its contacts'
+// canonical slots in the order the force sums them (row r of slot t at
+// list[r * n + t], at most kTapeWidth rows); *worst gets the largest
+// contact count of the step (a tape with worst > kTapeWidth is incomplete
+// and not used).  Ids, not storage indices: a re-layout moves agents
+// between storage slots from one step to the next.
 constexpr uint32_t kTapeWidth = 32;
 struct TapeStep {
     void* pos;          // V4<T>[n]
-    uint32_t* perm;     // [n]
+    uint32_t* ids;      // [n]
     uint32_t* cnt;      // [n]
     uint32_t* list;     // [kTapeWidth][n]
     uint32_t* worst;    // one word, cleared before the step
@@ -244,7 +245,6 @@ template <class T> void launch_extent(const T* pos, const T* diam, uint32_t n, G
 template <class T> void launch_mark_moved(const Buffers<T>& b, int pos_cur, hipStream_t s);
 void launch_set_params(SimGrid* sims, int nsims, double k, double gamma, double mu, double f_adh, double delta_max,
                        hipStream_t s);
-void launch_permute3(const uint32_t* ids, uint32_t n, const double* in, double* out, bool to_id, hipStream_t s);
 template <class T> void launch_bbox(const Buffers<T>& b, int pos_cur, int parity, hipStream_t s);
 template <class T> void launch_setup(const Buffers<T>& b, int parity, bool allow_inc, hipStream_t s);
 template <class T> void launch_grid(const Buffers<T>& b, int pos_cur, int ids_cur, bool relayout, bool moved_bits,
@@ -289,13 +289,13 @@ template <class T> void launch_set_diameters(const Buffers<T>& b, int pos_cur, i
                                              const int64_t* ids, const T* diam, uint32_t* mk, hipStream_t s, int phase);
 
 // ---- launchers (adjoint_kernels.hip)
-template <class T> void launch_adj_tape(const Buffers<T>& b, const TapeStep& tp, hipStream_t s);
+template <class T> void launch_adj_tape(const Buffers<T>& b, int ids_cur, const TapeStep& tp, hipStream_t s);
 template <class T> void launch_adj_tape_w(const Buffers<T>& b, const TapeStep& tp, const double* lam, double* w,
                                           hipStream_t s);
 template <class T> void launch_adj_tape_gather(const Buffers<T>& b, const TapeStep& tp, const double* lam,
                                                const double* w, double* lam_out, hipStream_t s);
-template <class T> void launch_adj_w(const Buffers<T>& b, int pos_cur, const double* lam, double* w, hipStream_t s);
-template <class T> void launch_adj_gather(const Buffers<T>& b, int pos_cur, const double* lam, const double* w,
+template <class T> void launch_adj_w(const Buffers<T>& b, int ids_cur, const double* lam, double* w, hipStream_t s);
+template <class T> void launch_adj_gather(const Buffers<T>& b, int ids_cur, const double* lam, const double* w,
                                           double* lam_out, hipStream_t s);
 template <class T> void launch_adj_finish(const Buffers<T>& b, int nblocks, double* dparams, hipStream_t s);
 int adj_blocks(uint32_t n);

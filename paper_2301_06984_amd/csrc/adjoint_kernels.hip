@@ -10,7 +10,9 @@
 //   dL/dk += sum_i w_i . sum_j delta_ij u_ij,  dL/dgamma -= sum_i w_i . sum_j sqrt(rho delta) u_ij.
 //
 // The grids of the reverse steps are full builds: the agent of canonical slot
-// t sits in loose slot n + t, with storage index perm[t].  A reverse step
+// t sits in loose slot n + t, with storage index perm[t].  lambda is kept
+// by agent id (a re-layout moves agents between storage slots from one
+// forward step to the next); w by canonical slot of the step.  A reverse step
 // either walks such a grid (k_adj_w, k_adj_gather) or reads the step's
 // contact tape, written by k_adj_tape while the forward step had its grid
 // (k_adj_tape_w, k_adj_tape_gather): the same contacts in the same order, so
@@ -24,8 +26,8 @@ constexpr int kAdjChunk = 4;   // candidates the walk of the reverse step tests 
 
 int adj_blocks(uint32_t n) { return int((n + kAdjThreads - 1) / kAdjThreads); }
 
-// w_i = D_i^T lambda_i for agent i (storage index) with force sums acc, and
-// its terms of dL/dk and dL/dgamma.
+// w_i = D_i^T lambda_i for agent i (id) with force sums acc, and its terms
+// of dL/dk and dL/dgamma.
 __device__ __forceinline__ void adjoint_w(const SimGrid& G, const ForceSum& acc, const double* __restrict__ lam,
                                           uint32_t i, double wi[3], double& gk, double& gg) {
     const Move m = displacement(G, acc.fx, acc.fy, acc.fz);
@@ -64,13 +66,14 @@ __device__ __forceinline__ void block_partials(double* __restrict__ partials, ui
 }
 
 template <class T>
-__global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int cur, const double* __restrict__ lam,
+__global__ __launch_bounds__(kAdjThreads) void k_adj_w(Buffers<T> b, int ids_cur, const double* __restrict__ lam,
                                                         double* __restrict__ w) {
     extern __shared__ __align__(16) unsigned char s_walk[];
     const WalkLds L = walk_lds(s_walk);
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     double gk = 0.0, gg = 0.0;
-    const uint32_t i = t < b.n ? b.perm[t] : 0xFFFFFFFFu;
+    const uint32_t si = t < b.n ? b.perm[t] : 0xFFFFFFFFu;
+    const uint32_t i = si < b.n ? b.ids[ids_cur][si] : 0xFFFFFFFFu;   // the agent's id
     if (t < b.n && i >= b.n) raise_error(b.g, kErrInternal);
     if (i < b.n) {
         const SimGrid& G = b.sims[sim_index(b, t)];
@@ -122,7 +125,7 @@ __device__ __forceinline__ void gather_term(const Buffers<T>& b, const SimGrid& 
 // shuffles; a lane whose queue fills with contacts mid-walk adds those
 // itself.  The sums are in slot order either way.
 template <class T>
-__global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cur, const double* __restrict__ lam,
+__global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int ids_cur, const double* __restrict__ lam,
                                                              const double* __restrict__ w,
                                                              double* __restrict__ lam_out) {
     extern __shared__ __align__(16) unsigned char s_walk[];
@@ -133,7 +136,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
     const uint32_t last = 2u * b.n - 1u;
     uint32_t m = 0xFFFFFFFFu;
     if (t < b.n) {
-        m = b.perm[t];
+        const uint32_t si = b.perm[t];
+        m = si < b.n ? b.ids[ids_cur][si] : 0xFFFFFFFFu;   // the agent's id
         if (m >= b.n) raise_error(b.g, kErrInternal);
     }
     const bool has = m < b.n;
@@ -209,11 +213,11 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int cu
 // ---------------------------------------------------------------- contact tape
 // The contacts of every agent on the step's grid (a full build), found by the
 // walk of the gather, in the order the force sums them: canonical slot t
-// keeps its position, storage index and contacts' canonical slots (see
+// keeps its position, id and contacts' canonical slots (see
 // TapeStep).  A count above kTapeWidth is still counted (and raises *worst
 // past it), its excess rows are not kept.
 template <class T>
-__global__ __launch_bounds__(kAdjThreads) void k_adj_tape(Buffers<T> b, TapeStep tp) {
+__global__ __launch_bounds__(kAdjThreads) void k_adj_tape(Buffers<T> b, int ids_cur, TapeStep tp) {
     extern __shared__ __align__(16) unsigned char s_walk[];
     const WalkLds L = walk_lds(s_walk);
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, tid = threadIdx.x, bs = blockDim.x, n = b.n;
@@ -250,7 +254,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_tape(Buffers<T> b, TapeStep
     emit(queue_contacts<kAdjChunk, T>(b, G, p, P, L, emit));
     if (has) {
         tp.cnt[t] = cnt;
-        tp.perm[t] = i;
+        tp.ids[t] = b.ids[ids_cur][i];
         static_cast<V4<T>*>(tp.pos)[t] = p;
     }
     uint32_t most = cnt;   // one atomic per wave
@@ -266,7 +270,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_tape_w(Buffers<T> b, TapeSt
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, n = b.n;
     double gk = 0.0, gg = 0.0;
     if (t < n) {
-        const uint32_t i = tp.perm[t], cnt = tp.cnt[t];
+        const uint32_t i = tp.ids[t], cnt = tp.cnt[t];
         double wi[3] = {0.0, 0.0, 0.0};
         if (i >= n || cnt > kTapeWidth) {
             raise_error(b.g, kErrInternal);
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_tape_gather(Buffers<T> b, T
                                                                   double* __restrict__ lam_out) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, n = b.n;
     if (t >= n) return;
-    const uint32_t m = tp.perm[t], cnt = tp.cnt[t];
+    const uint32_t m = tp.ids[t], cnt = tp.cnt[t];
     if (m >= n || cnt > kTapeWidth) {
         raise_error(b.g, kErrInternal);
         return;
@@ -346,42 +350,23 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_finish(const double* __rest
     }
 }
 
-// Storage-indexed <-> id-indexed copies of n x 3 double arrays (the adjoint
-// keeps lambda and w by storage slot; callers see them by agent id).
-__global__ void k_permute3(const uint32_t* __restrict__ ids, uint32_t n, const double* __restrict__ in,
-                           double* __restrict__ out, int to_id) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t id = ids[i];
-    if (id >= n) return;
-    for (int a = 0; a < 3; ++a) {
-        if (to_id)
-            out[3 * size_t(id) + a] = in[3 * size_t(i) + a];
-        else
-            out[3 * size_t(i) + a] = in[3 * size_t(id) + a];
-    }
-}
-
-void launch_permute3(const uint32_t* ids, uint32_t n, const double* in, double* out, bool to_id, hipStream_t s) {
-    hipLaunchKernelGGL(k_permute3, dim3((n + 255) / 256), dim3(256), 0, s, ids, n, in, out, to_id ? 1 : 0);
-}
-
 template <class T>
-void launch_adj_w(const Buffers<T>& b, int pos_cur, const double* lam, double* w, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_w<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b, pos_cur,
+void launch_adj_w(const Buffers<T>& b, int ids_cur, const double* lam, double* w, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_w<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b, ids_cur,
                        lam, w);
 }
 
 template <class T>
-void launch_adj_gather(const Buffers<T>& b, int pos_cur, const double* lam, const double* w, double* lam_out,
+void launch_adj_gather(const Buffers<T>& b, int ids_cur, const double* lam, const double* w, double* lam_out,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_adj_gather<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b,
-                       pos_cur, lam, w, lam_out);
+                       ids_cur, lam, w, lam_out);
 }
 
 template <class T>
-void launch_adj_tape(const Buffers<T>& b, const TapeStep& tp, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_tape<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b, tp);
+void launch_adj_tape(const Buffers<T>& b, int ids_cur, const TapeStep& tp, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_tape<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b,
+                       ids_cur, tp);
 }
 
 template <class T>
@@ -405,7 +390,7 @@ void launch_adj_finish(const Buffers<T>& b, int nblocks, double* dparams, hipStr
     template void launch_adj_gather<T>(const Buffers<T>&, int, const double*, const double*, double*, \
                                        hipStream_t);                                                  \
     template void launch_adj_finish<T>(const Buffers<T>&, int, double*, hipStream_t);                 \
-    template void launch_adj_tape<T>(const Buffers<T>&, const TapeStep&, hipStream_t);                 \
+    template void launch_adj_tape<T>(const Buffers<T>&, int, const TapeStep&, hipStream_t);            \
     template void launch_adj_tape_w<T>(const Buffers<T>&, const TapeStep&, const double*, double*,     \
                                        hipStream_t);                                                  \
     template void launch_adj_tape_gather<T>(const Buffers<T>&, const TapeStep&, const double*,         \

@@ -31,10 +31,10 @@ constexpr int kMaxBlockSims = 4;
 // positions' box extent is reduced here for the next step's grid: each wave
 // folds into the block's LDS copy, and the block's last wave to finish adds
 // it to the global accumulators, so no wave waits for the others.
-// With TAPE (one simulation, static test off, no re-layout, a full build),
-// the step also writes its contact tape: each agent's contacts, in the order
-// their terms are summed, with its position and storage index, by canonical
-// slot (the adjoint's reverse step reads it instead of walking a grid).
+// With TAPE (one simulation, static test off, a full build), the step also
+// writes its contact tape: each agent's contacts, in the order their terms
+// are summed, with its position and id, by canonical slot (the adjoint's
+// reverse step reads it instead of walking a grid).
 // At 96 VGPRs or fewer a SIMD holds 5 waves of this kernel (4 above); the
 // hint asks the compiler for that.
 #ifndef ABM_FORCE_WAVES_PER_EU
@@ -46,7 +46,7 @@ constexpr bool two_chunks() { return CH == 2; }
 template <class T, bool BATCHED, bool STATIC_ON, bool RELAYOUT, int CH, bool TAPE = false, bool SHARE = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_WAVES_PER_EU))) void k_force(
     Buffers<T> b, StepArgs a, uint32_t run, uint32_t first_chunk) {
-    static_assert(!TAPE || (!BATCHED && !STATIC_ON && !RELAYOUT), "tapes cover the adjoint's steps only");
+    static_assert(!TAPE || (!BATCHED && !STATIC_ON), "tapes cover the adjoint's steps only");
     extern __shared__ __align__(16) unsigned char s_walk[];
     __shared__ int32_t s_box[kMaxBlockSims][6];
     __shared__ int s_sims[kMaxBlockSims];
@@ -222,7 +222,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ABM_FORCE_
             if (active && !Gp->valid) tcnt = 0xFFFFFFFFu;
             if (active && append && Gp->valid) {
                 a.tape.cnt[u - n] = tcnt;
-                a.tape.perm[u - n] = i;
+                // with a re-layout the grid build wrote the next state's ids
+                // in canonical order; else the storage index gives the id
+                a.tape.ids[u - n] = RELAYOUT ? b.ids[a.ids_cur ^ 1][u - n] : b.ids[a.ids_cur][i];
                 static_cast<V4<T>*>(a.tape.pos)[u - n] = p;
             }
             uint32_t most = tcnt;   // one atomic per wave
@@ -483,8 +485,11 @@ static void launch_force_s(const Buffers<T>& b, const StepArgs& a, hipStream_t s
 template <class T, int CH>
 static void launch_force_c(const Buffers<T>& b, const StepArgs& a, hipStream_t s) {
     const int v = (b.sim_of ? 4 : 0) | (a.detect_static ? 2 : 0) | (a.relayout ? 1 : 0);
-    if (a.tape.pos && v == 0) {   // the host tapes no other kind of step
-        launch_force_s<T, false, false, false, CH, true>(b, a, s);
+    if (a.tape.pos && v <= 1) {   // the host tapes no other kind of step
+        if (v == 1)
+            launch_force_s<T, false, false, true, CH, true>(b, a, s);
+        else
+            launch_force_s<T, false, false, false, CH, true>(b, a, s);
         return;
     }
     switch (v) {

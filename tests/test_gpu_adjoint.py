@@ -118,19 +118,21 @@ def test_state_restored_after_backward():
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_contact_tapes_bitwise(dtype):
     """The reverse steps on contact tapes (every step's, or each recomputed
-    segment's) give the walked grid's result bit for bit."""
+    segment's) give the walked grid's result bit for bit, with or without
+    re-layouts during the record (lambda is kept by id)."""
     pos, diam, target = case(3000, 6, dtype)
     res = {}
-    for tapes, mode in (("none", 0), ("segment", 1), ("all", 2)):
-        note(f"adjoint tapes={tapes} {dtype.__name__}")
-        info = {}
-        res[tapes] = gpu_grad(pos, diam, target, 12, 5, tapes=tapes, info=info)
-        assert info["tapes"] == mode, info
-        assert info["taped_reverse_steps"] == (0 if mode == 0 else 12), info
-        assert 0 < info["worst_contacts"] <= 32 or mode == 0, info
-    for tapes in ("segment", "all"):
-        for a, b in zip(res["none"], res[tapes]):
-            np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
+    for sort_every in (0, 1, 3):
+        for tapes, mode in (("none", 0), ("segment", 1), ("all", 2)):
+            note(f"adjoint tapes={tapes} sort_every={sort_every} {dtype.__name__}")
+            info = {}
+            res[tapes, sort_every] = gpu_grad(pos, diam, target, 12, 5, tapes=tapes, info=info, sort_every=sort_every)
+            assert info["tapes"] == mode, info
+            assert info["taped_reverse_steps"] == (0 if mode == 0 else 12), info
+            assert 0 < info["worst_contacts"] <= 32 or mode == 0, info
+    for key, r in res.items():
+        for a, b in zip(res["none", 0], r):
+            np.testing.assert_array_equal(np.asarray(a), np.asarray(b), err_msg=str(key))
 
 
 def test_contact_tape_overflow_falls_back():

@@ -1427,6 +1427,7 @@ int abm_import_state(abm_ctx* c, const void* src, int64_t src_bytes) {
 int abm_graph_capture(abm_ctx* c, int32_t nsteps) {
     if (int rc = check_ctx(c)) return rc;
     if (nsteps <= 0) return fail(ABM_E_INVAL, "nsteps must be > 0");
+    if (!c->stream) return fail(ABM_E_INVAL, "graph capture needs a stream other than the null stream");
     return c->precision == ABM_F64 ? graph_capture_impl<double>(c, nsteps) : graph_capture_impl<float>(c, nsteps);
 }
 

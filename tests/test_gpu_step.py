@@ -380,6 +380,13 @@ def test_errors_are_reported():
     with pytest.raises(abm.ABMError) as e:
         sim.backward(torch.zeros((1000, 3), dtype=torch.float64, device="cuda"))
     assert e.value.code == abm.ABM_E_STATE
+    note("error: graph capture on the null stream")
+    if torch.cuda.current_stream().cuda_stream == 0:
+        with pytest.raises(abm.ABMError) as e:
+            sim.graph_capture(2)
+        assert e.value.code == abm.ABM_E_INVAL and "null stream" in str(e.value)
+        sim.step(1)   # the context still steps
+        sim.sync()
 
 
 @pytest.mark.parametrize("sort_every", [1, 2])

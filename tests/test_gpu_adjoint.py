@@ -154,3 +154,35 @@ def test_contact_tape_overflow_falls_back():
     assert 0 < info["taped_reverse_steps"] < 10, info
     for a, b in zip(ref, got):
         np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
+
+
+@pytest.mark.parametrize("n,steps,ckpt", [(1, 3, 2), (2, 3, 10), (65, 5, 2), (65, 4, 4)])
+def test_contact_tapes_edge_cases(n, steps, ckpt):
+    """Tiny inputs, a checkpoint interval longer than the run and a last
+    segment shorter than the others: every tape mode gives the walked result
+    bit for bit, and the oracle's reverse mode to 1e-9."""
+    g = np.random.default_rng(90 + n)
+    side = max(6.0, (n / workloads.C1_DENSITY) ** (1 / 3) / 2)   # denser than C1: contacts from the start
+    pos = g.uniform(0, side, size=(n, 3))
+    diam = g.uniform(8, 12, size=n)
+    target = pos + g.normal(0, 0.5, size=(n, 3))
+    res = {}
+    for tapes in ("none", "segment", "all"):
+        note(f"adjoint edge n={n} steps={steps} ckpt={ckpt} tapes={tapes}")
+        info = {}
+        res[tapes] = gpu_grad(pos, diam, target, steps, ckpt, tapes=tapes, info=info)
+        if tapes == "none":
+            assert info["taped_reverse_steps"] == 0, info
+        elif info["worst_contacts"] <= 32:
+            assert info["taped_reverse_steps"] == steps, info
+        else:   # a step with more than 32 contacts per agent walks its grid
+            assert 0 <= info["taped_reverse_steps"] < steps and info["tapes"] == 1, info
+    for tapes in ("segment", "all"):
+        for a, b in zip(res["none"], res[tapes]):
+            np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
+    ref = oracle.adjoint(pos, diam, steps, oracle.Params(), target)
+    loss, gx0, gp, _ = res["all"]
+    assert abs(loss - ref["loss"]) <= 1e-12 * abs(ref["loss"])
+    np.testing.assert_allclose(gp, [ref["dL_dk"], ref["dL_dgamma"]], rtol=1e-9, atol=1e-300)
+    scale = max(np.abs(ref["dL_dx0"]).max(), 1e-300)
+    assert np.abs(gx0 - ref["dL_dx0"]).max() <= 1e-9 * scale

@@ -90,17 +90,17 @@ typedef struct abm_params {
     int32_t keep_forces;       /* store F_i each step so ABM_FIELD_FORCES can be queried */
     int32_t walk_chunk;        /* candidates the neighbour walk tests together: 2 or 4; 0 = chosen at init
                                   from how densely the agents fill their boxes: one simulation, 4 at 4 or more
-                                  agents per occupied box of the initial grid with 2^20 agents or more
-                                  (clustered agents; no uniform packing reaches 3), at 1.6 or more with fewer;
-                                  a batch, 4 at one or more per box of the extent; else 2 */
+                                  agents per occupied box of the initial grid (clustered agents; no uniform
+                                  packing reaches 3), or below 1.4 with fewer than 2^18 agents; a batch, 4 at
+                                  3 or more per box of the extent; else 2 */
     int32_t order;             /* ABM_ORDER_MORTON (default) or ABM_ORDER_HILBERT; fixed at init, the same for
                                   every simulation of a batch.  It sets the canonical order, and with it the
                                   order in which each agent's pair terms are summed */
     int32_t share_terms;       /* the 2-wide walk of one simulation: 1 = each lane adds its own agent's pair
                                   terms, 2 = the wave shares out all its lanes' pair terms, one per lane (the
                                   same sums, bit for bit; pays where agents have several contacts); 0 = chosen
-                                  at init: 2 with 2^20 agents or more at 1.2 or more agents per occupied box of
-                                  the initial grid, else 1.  The 4-wide walk and a batch always share */
+                                  at init: 2 at 2 or more agents per occupied box of the initial grid, else 1.
+                                  The 4-wide walk and a batch always share */
     double super_fraction;     /* size of the super-box table (one entry per aligned 2x2x2 block of boxes) per
                                   simulation, as a fraction of its box capacity: 0 (default) = enough for any
                                   grid of box_capacity boxes, ceil((capacity + 1) / 2) entries (a grid one box

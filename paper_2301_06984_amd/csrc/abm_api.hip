@@ -482,24 +482,21 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     if (hipGetLastError() != hipSuccess) return bail(fail(ABM_E_HIP, "init kernels failed to launch"));
     const int rc = read_error(c, true);   // also keeps the host arrays alive until the copies are done
     if (rc != ABM_OK) return bail(rc);
-    // The walk: its width, 4 where an agent's boxes hold many agents (long
-    // slot ranges), else 2; and for the 2-wide walk of one simulation,
-    // whether the wave shares out its pair terms (where agents have several
-    // contacts).  One simulation: from the agents per occupied box of its
-    // initial grid (a bitmap of the boxes in the bytes of the per-agent
-    // records, free before the first grid build).  With 2^20 agents or more
-    // (enough waves that the kernel is bound by issue rather than by the
-    // latency of one wave's walk): 4-wide at 4 or more (clustered agents: no
-    // uniform packing reaches 3), else 2-wide, shared at 1.2 or more.  With
-    // fewer: 4-wide at 1.6 or more (the shorter walk of each wave), else
-    // 2-wide, each lane adding its own terms.  Otherwise, or when the bitmap
-    // does not fit, from the agents per box of the extent: 4-wide at one or
-    // more (a batch, which always shares), shared at 0.4 or more with 2^20
-    // agents (about 1.2 per occupied box where agents spread uniformly).
+    // The walk: its width, and for the 2-wide walk of one simulation whether
+    // the wave shares out its pair terms.  One simulation: from the agents
+    // per occupied box of its initial grid (a bitmap of the boxes in the
+    // bytes of the per-agent records, free before the first grid build):
+    // 4-wide at 4 or more (clustered agents: no uniform packing reaches 3), or
+    // below 1.4 with fewer than 2^18 agents (small sparse simulations, bound
+    // by the latency of each wave's walk); else 2-wide, shared at 2 or more
+    // (several contacts per agent).  Otherwise, or when the bitmap does not
+    // fit, from the agents per box of the extent: 4-wide at 3 or more (a
+    // batch, which always shares), shared at 1.5 or more (about 2 per occupied
+    // box where agents spread uniformly).
     c->walk_chunk = p0.walk_chunk;
     c->share = p0.share_terms == 2;
     const bool pick_width = c->walk_chunk == 0, pick_share = p0.share_terms == 0 && nsims == 1;
-    const bool many = n >= (int64_t(1) << 20);
+    const bool small = n < (int64_t(1) << 18);
     bool chosen = false;
     if ((pick_width || pick_share) && nsims == 1) {
         std::vector<int32_t> rep(size_t(kReplicas) * 6);
@@ -530,8 +527,8 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
                 return bail(fail(ABM_E_HIP, "occupied-box count failed"));
             if (occupied > 0) {
                 const double per_occupied = double(n) / double(occupied);
-                if (pick_width) c->walk_chunk = per_occupied >= (many ? 4.0 : 1.6) ? 4 : 2;
-                if (pick_share) c->share = many && per_occupied >= 1.2;
+                if (pick_width) c->walk_chunk = per_occupied >= 4.0 || (small && per_occupied < 1.4) ? 4 : 2;
+                if (pick_share) c->share = per_occupied >= 2.0;
                 chosen = true;
             }
         }
@@ -552,8 +549,8 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
             for (int a = 0; a < 3; ++a) nb *= hi[a] >= lo[a] ? double(hi[a]) - double(lo[a]) + 1.0 : 1.0;
             boxes_total += nb;
         }
-        if (pick_width) c->walk_chunk = double(n) >= boxes_total ? 4 : 2;
-        if (pick_share) c->share = many && double(n) >= 0.4 * boxes_total;
+        if (pick_width) c->walk_chunk = double(n) >= 3.0 * boxes_total ? 4 : 2;
+        if (pick_share) c->share = double(n) >= 1.5 * boxes_total;
     }
     *out = c;
     return ABM_OK;

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_gather(Buffers<T> b, int id
         const double owm[3] = {__shfl(wm[0], int(o), 64), __shfl(wm[1], int(o), 64), __shfl(wm[2], int(o), 64)};
         double term[3] = {0.0, 0.0, 0.0};
         if (x < total) {
-            const uint32_t u = L.queue[min(row, uint32_t(kQueueCap - 1)) * bs + wbase + o];
+            const uint32_t u = L.queue[min(row, uint32_t(queue_cap<kAdjChunk>() - 1)) * bs + wbase + o];
             gather_term<T>(b, G, oxm, oym, ozm, orm, owm, w, sp[min(u, last)], u, term);
         }
         // the terms go back to their agent's lane: the j-th of every lane at once
@@ -352,20 +352,20 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_finish(const double* __rest
 
 template <class T>
 void launch_adj_w(const Buffers<T>& b, int ids_cur, const double* lam, double* w, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_w<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b, ids_cur,
+    hipLaunchKernelGGL(k_adj_w<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes<kAdjChunk>(kAdjThreads), s, b, ids_cur,
                        lam, w);
 }
 
 template <class T>
 void launch_adj_gather(const Buffers<T>& b, int ids_cur, const double* lam, const double* w, double* lam_out,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_gather<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b,
+    hipLaunchKernelGGL(k_adj_gather<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes<kAdjChunk>(kAdjThreads), s, b,
                        ids_cur, lam, w, lam_out);
 }
 
 template <class T>
 void launch_adj_tape(const Buffers<T>& b, int ids_cur, const TapeStep& tp, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_tape<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes(kAdjThreads), s, b,
+    hipLaunchKernelGGL(k_adj_tape<T>, dim3(adj_blocks(b.n)), dim3(kAdjThreads), walk_lds_bytes<kAdjChunk>(kAdjThreads), s, b,
                        ids_cur, tp);
 }
 

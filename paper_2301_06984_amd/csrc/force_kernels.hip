@@ -464,7 +464,7 @@ static void launch_force_v(const Buffers<T>& b, const StepArgs& a, hipStream_t s
     const uint32_t blocks = two_chunks<CH>() ? nb : 2u * nb - first;
     const uint32_t run = xcd_run(blocks);
     const uint32_t grid = xcd_grid(blocks, run);   // <= force_part_capacity(n): nb <= ceil(n / 64), 8 run <= 512
-    hipLaunchKernelGGL((k_force<T, S, K, R, CH, TAPE, SH>), dim3(grid), dim3(bs), walk_lds_bytes(bs), s, b, a, run,
+    hipLaunchKernelGGL((k_force<T, S, K, R, CH, TAPE, SH>), dim3(grid), dim3(bs), walk_lds_bytes<CH>(bs), s, b, a, run,
                        first);
     if (!S) launch_fold_parts(b, grid, a.parity, s);
 }
@@ -578,7 +578,7 @@ __global__ __launch_bounds__(256) void k_neighbors(Buffers<T> b, int ids_cur, ui
 template <class T>
 void launch_neighbors(const Buffers<T>& b, int ids_cur, uint32_t* counts, uint32_t* rows, uint32_t K,
                       uint32_t* worst, hipStream_t s) {
-    hipLaunchKernelGGL(k_neighbors<T>, dim3((2u * b.n + 255) / 256), dim3(256), walk_lds_bytes(256), s, b, ids_cur,
+    hipLaunchKernelGGL(k_neighbors<T>, dim3((2u * b.n + 255) / 256), dim3(256), walk_lds_bytes<4>(256), s, b, ids_cur,
                        counts, rows, K, worst);
 }
 

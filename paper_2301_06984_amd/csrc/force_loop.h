@@ -83,17 +83,25 @@ __device__ __forceinline__ bool box_of(const SimGrid& G, const V4<T>& p, uint32_
 // Per-thread scratch in LDS for the neighbour walk: the pieces (start slot in
 // the low, end slot in the high 32 bits) and a queue of candidate slots.  Laid
 // out [entry][thread] so that the threads of a wave hit distinct banks.
-// LDS per thread of the walk: kPieces * 8 + kQueueCap * 4 bytes, which
-// bounds the waves per CU.  The walk tests CH = 2 or 4 candidate slots of a
-// piece together (4 pays off where boxes hold one or more agents).
+// LDS per thread of the walk: kPieces * 8 + queue_cap<CH>() * 4 bytes,
+// which bounds the waves per CU.  The walk tests CH = 2 or 4 candidate slots
+// of a piece together (4 pays off where boxes hold many agents).
 constexpr int kPieces = 8;   // one per super-box of the 2x2x2 block, in Morton order
-constexpr int kQueueCap = 10;
+// Queue rows of a lane.  A lane whose queue fills mid-walk runs the exact test
+// (and its own pair terms) alone while the rest of its wave waits; 14 rows let
+// an agent with a few dozen candidates (uniform packing) finish its walk
+// first, so that one exact test serves the whole wave, and keep five blocks of
+// 256 threads per CU.  The 4-wide walk (clustered agents, thousands of
+// candidates, whose queues fill regardless) keeps 10.
+template <int CH>
+constexpr int queue_cap() { return CH == 2 ? 14 : 10; }
 static_assert(4 <= kSposPad, "the walk reads up to 3 slots past a piece");
 struct WalkLds {
     unsigned long long* rng;   // [kPieces][blockDim]
-    uint32_t* queue;           // [kQueueCap][blockDim]
+    uint32_t* queue;           // [queue_cap<CH>()][blockDim]
 };
-inline size_t walk_lds_bytes(int block) { return size_t(block) * (kPieces * 8 + kQueueCap * 4); }
+template <int CH>
+inline size_t walk_lds_bytes(int block) { return size_t(block) * (kPieces * 8 + queue_cap<CH>() * 4); }
 
 __device__ __forceinline__ WalkLds walk_lds(void* base) {
     WalkLds w;
@@ -231,7 +239,7 @@ __device__ __forceinline__ bool stream_pieces(const WalkLds& L, const Pieces& P,
 template <int CH, class T, class Test>
 __device__ __forceinline__ void walk_chunks(const V4<T>* __restrict__ sp, const Pieces& P, const WalkLds& L,
                                             Test&& test) {
-    static_assert(CH >= 1 && CH <= kSposPad && kQueueCap > CH, "walk chunk");
+    static_assert(CH >= 1 && CH <= kSposPad && queue_cap<CH>() > CH, "walk chunk");
     if (!P.mask) return;
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
     uint32_t M = P.mask;
@@ -385,6 +393,7 @@ __device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uin
                                          const V4<T>& p, const Pieces& P, const WalkLds& L, ForceSum& acc,
                                          Emit emit = Emit{}) {
     static_assert(!(SHARE && PARAM_GRADS), "shared pair terms carry the force only");
+    constexpr int QC = queue_cap<CH>();
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
     const double ri = 0.5 * fabs(double(p.w));
@@ -416,7 +425,7 @@ __device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uin
                 acc.moved_near = acc.moved_near || (within && pj[c].w < T(0));
                 const bool keep = within && s2 > 0.0 && s2 < S * S;
                 // only rows in use are rewritten: with every tested row kept,
-                // m reaches n, and n can be kQueueCap, one row past the queue
+                // m reaches n, and n can be QC, one row past the queue
                 if (x0 + c < n) L.queue[m * bs + tid] = uq[c];
                 m += keep ? 1u : 0u;
             }
@@ -447,13 +456,13 @@ __device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uin
         for (int c = 0; c < CH; ++c) {
             // no short-circuit: every lane does the same arithmetic
             const uint32_t pass = uint32_t(uint32_t(c) < left) & uint32_t(maybe_within<T>(p, pc[c], r2pad));
-            L.queue[qo] = u + c;   // n < kQueueCap here
+            L.queue[qo] = u + c;   // n < QC here
             n += pass;
             qo += pass ? bs : 0u;
         }
-        if (n > uint32_t(kQueueCap - CH)) {
+        if (n > uint32_t(QC - CH)) {
             exact();
-            if (!SHARE || n > uint32_t(kQueueCap - CH)) own_terms();
+            if (!SHARE || n > uint32_t(QC - CH)) own_terms();
             qo = n * bs + tid;
         }
         return true;
@@ -487,7 +496,7 @@ __device__ __forceinline__ void force_of(const V4<T>* __restrict__ sp, const uin
             t.fx = t.fy = t.fz = 0.0;
             t.nonzero = false;
             if (x < total) {
-                const uint32_t uj = L.queue[min(row, uint32_t(kQueueCap - 1)) * bs + wbase + o];
+                const uint32_t uj = L.queue[min(row, uint32_t(QC - 1)) * bs + wbase + o];
                 t = pair_term<T>(oxi, oyi, ozi, ori, sp[min(uj, last)], ok_, og);
             }
             const unsigned long long nzm = __ballot(x < total && t.nonzero);
@@ -531,6 +540,7 @@ template <int CH, class T, class Own>
 __device__ __forceinline__ uint32_t queue_contacts(const Buffers<T>& b, const SimGrid& G, const V4<T>& p,
                                                    const Pieces& P, const WalkLds& L, Own&& own) {
     const V4<T>* __restrict__ sp = gpos_ptr(b);
+    constexpr int QC = queue_cap<CH>();
     const uint32_t tid = threadIdx.x, bs = blockDim.x, last = 2u * b.n - 1u;
     const double xi = double(p.x), yi = double(p.y), zi = double(p.z);
     const double ri = 0.5 * fabs(double(p.w));
@@ -566,13 +576,13 @@ __device__ __forceinline__ uint32_t queue_contacts(const Buffers<T>& b, const Si
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             const uint32_t pass = uint32_t(uint32_t(c) < left) & uint32_t(maybe_within<T>(p, pc[c], r2pad));
-            L.queue[qo] = u + c;   // n < kQueueCap here
+            L.queue[qo] = u + c;   // n < QC here
             n += pass;
             qo += pass ? bs : 0u;
         }
-        if (n > uint32_t(kQueueCap - CH)) {
+        if (n > uint32_t(QC - CH)) {
             exact();
-            if (kept > uint32_t(kQueueCap - CH)) {
+            if (kept > uint32_t(QC - CH)) {
                 own(kept);
                 kept = n = 0;
             }

@@ -91,8 +91,7 @@ typedef struct abm_params {
     int32_t walk_chunk;        /* candidates the neighbour walk tests together: 2 or 4; 0 = chosen at init
                                   from how densely the agents fill their boxes: one simulation, 4 at 4 or more
                                   agents per occupied box of the initial grid (clustered agents; no uniform
-                                  packing reaches 3), or below 1.4 with fewer than 2^18 agents; a batch, 4 at
-                                  3 or more per box of the extent; else 2 */
+                                  packing reaches 3); a batch, 4 at 3 or more per box of the extent; else 2 */
     int32_t order;             /* ABM_ORDER_MORTON (default) or ABM_ORDER_HILBERT; fixed at init, the same for
                                   every simulation of a batch.  It sets the canonical order, and with it the
                                   order in which each agent's pair terms are summed */

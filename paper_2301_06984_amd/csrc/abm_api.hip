@@ -486,17 +486,15 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
     // the wave shares out its pair terms.  One simulation: from the agents
     // per occupied box of its initial grid (a bitmap of the boxes in the
     // bytes of the per-agent records, free before the first grid build):
-    // 4-wide at 4 or more (clustered agents: no uniform packing reaches 3), or
-    // below 1.4 with fewer than 2^18 agents (small sparse simulations, bound
-    // by the latency of each wave's walk); else 2-wide, shared at 2 or more
-    // (several contacts per agent).  Otherwise, or when the bitmap does not
+    // 4-wide at 4 or more (clustered agents: no uniform packing reaches 3),
+    // else 2-wide, shared at 2 or more (several contacts per agent).
+    // Otherwise, or when the bitmap does not
     // fit, from the agents per box of the extent: 4-wide at 3 or more (a
     // batch, which always shares), shared at 1.5 or more (about 2 per occupied
     // box where agents spread uniformly).
     c->walk_chunk = p0.walk_chunk;
     c->share = p0.share_terms == 2;
     const bool pick_width = c->walk_chunk == 0, pick_share = p0.share_terms == 0 && nsims == 1;
-    const bool small = n < (int64_t(1) << 18);
     bool chosen = false;
     if ((pick_width || pick_share) && nsims == 1) {
         std::vector<int32_t> rep(size_t(kReplicas) * 6);
@@ -527,7 +525,7 @@ int init_impl(abm_ctx** out, int32_t nsims, const int64_t* offsets, const void* 
                 return bail(fail(ABM_E_HIP, "occupied-box count failed"));
             if (occupied > 0) {
                 const double per_occupied = double(n) / double(occupied);
-                if (pick_width) c->walk_chunk = per_occupied >= 4.0 || (small && per_occupied < 1.4) ? 4 : 2;
+                if (pick_width) c->walk_chunk = per_occupied >= 4.0 ? 4 : 2;
                 if (pick_share) c->share = per_occupied >= 2.0;
                 chosen = true;
             }

@@ -88,13 +88,15 @@ __device__ __forceinline__ bool box_of(const SimGrid& G, const V4<T>& p, uint32_
 // of a piece together (4 pays off where boxes hold many agents).
 constexpr int kPieces = 8;   // one per super-box of the 2x2x2 block, in Morton order
 // Queue rows of a lane.  A lane whose queue fills mid-walk runs the exact test
-// (and its own pair terms) alone while the rest of its wave waits; 14 rows let
-// an agent with a few dozen candidates (uniform packing) finish its walk
-// first, so that one exact test serves the whole wave, and keep five blocks of
-// 256 threads per CU.  The 4-wide walk (clustered agents, thousands of
-// candidates, whose queues fill regardless) keeps 10.
+// (and its own pair terms) alone while the rest of its wave waits.  The 2-wide
+// walk takes 14 rows: an agent with a few dozen candidates (uniform packing)
+// then finishes its walk first, so that one exact test serves the whole wave,
+// and five blocks of 256 threads still fit a CU.  The 4-wide walk (clustered
+// agents, thousands of candidates, whose queues fill whatever their depth)
+// takes 5, the least a chunk of 4 needs: every lane then flushes after nearly
+// every chunk, so the lanes of a wave flush together.
 template <int CH>
-constexpr int queue_cap() { return CH == 2 ? 14 : 10; }
+constexpr int queue_cap() { return CH == 2 ? 14 : 5; }
 static_assert(4 <= kSposPad, "the walk reads up to 3 slots past a piece");
 struct WalkLds {
     unsigned long long* rng;   // [kPieces][blockDim]

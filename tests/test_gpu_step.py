@@ -428,7 +428,7 @@ def test_dense_packing_matches_oracle_bitwise(walk_chunk, share_terms):
 @pytest.mark.parametrize("sort_every", [0, 1])
 def test_repeated_contexts_match_oracle(sort_every):
     # the adjoint workload's density (about 47 candidates per agent, the
-    # 4-wide walk): contexts made one after another in one process, on
+    # 2-wide walk with shared pair terms): contexts made one after another in one process, on
     # memory the last one used (filled with a pattern in between), each
     # give the oracle's 10 steps bit for bit
     w = workloads.c5()

@@ -56,6 +56,32 @@ def test_headline_1e7_first_step(detect_static):
     check_samples(x, w.diam, sim.query("positions").cpu().numpy(), 96, 2)
 
 
+def test_c1_density_1e7_shared_terms_sampled():
+    """C1's density with 1e7 agents (about 47 candidates and 4 contacts per
+    agent), in the walk the library takes there (2-wide, the wave sharing
+    its pair terms, 14 queue rows): the first step and a later update-build
+    step, sampled agents against the oracle's all-pairs sampler bit for bit,
+    non-zero counts exactly."""
+    n = 10_000_000
+    side = (n / workloads.C1_DENSITY) ** (1.0 / 3.0)
+    pos, diam = workloads.uniform_cube(n, side, (1, n), dtype=np.float32)
+    note(f"c1 density n={n} side={side:.1f}")
+    sim = make_sim(pos, diam, **{**BENCH, "walk_chunk": 2, "share_terms": 2})
+    sim.step(1)
+    sim.sync()
+    _, nnz = check_samples(pos, diam, sim.query("positions").cpu().numpy(), 64, 11,
+                           got_nnz=sim.query("nnz").cpu().numpy())
+    assert nnz.mean() > 2.0   # several contacts per agent: the terms are shared out
+    note("c1 density steps 2-4")
+    sim.step(3)
+    sim.sync()
+    x = sim.query("positions").cpu().numpy()
+    note("c1 density step 5 (update build) sampled")
+    sim.step(1)
+    sim.sync()
+    check_samples(x, diam, sim.query("positions").cpu().numpy(), 64, 12, got_nnz=sim.query("nnz").cpu().numpy())
+
+
 def test_c2_full_parity_and_skip():
     w = workloads.c2()
     note(f"c2 n={w.n}")
